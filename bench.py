@@ -1,0 +1,214 @@
+"""Benchmark: Gauss-Chebyshev bilateral filter on one MI355X.
+
+Workload (the headline configuration): one 4096 x 4096 edge-rich synthetic
+image (0/255 checkerboard with 64-pixel cells, 512 random star polygons,
+N(0, 5^2) noise, clipped), sigma_s = 10 (W = 30), sigma_r = 30, degree N = 28
+(30 stack planes), FP32 stack. A step is one full forward filter
+(bf_gc_forward: parameters, stack build, column pass, row pass + combine) with
+the image already resident in HBM.
+
+Prints one JSON line. Besides the contract fields it carries
+  roofline      dominant kernel, timed with HIP events on its launch stream
+  cpu_baseline  the plain-C FP64 oracle on the host cores
+  fp16_stack    the same workload with an FP16 stack, at the smallest degree
+                whose error against the direct filter is no worse than FP32's
+  accuracy      max-abs errors on crops against both FP64 oracles
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s at 4096², σs=10 (FP32 vs FP16 stack, same error); HBM GB/s % peak"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_VALU_TFS = 78.6      # 256 CU x 64 lanes x 2 flop x 2.4 GHz, FP64 FMA at full rate
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch):
+    """Algorithmic bytes and flops of one launch of `name` and the bound it
+    sits against (see the design doc for the per-pixel figures)."""
+    px = H * Wd
+    taps = 2 * W + 1
+    if name == "k_stack_build":
+        byts = px * (4 + P * esize)
+        return {"bound": "hbm", "achieved": byts / ms_per_launch / 1e6, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "bytes_per_launch": byts}
+    if name in ("k_vpass", "k_hpass", "k_hpass_combine"):
+        flops = 2.0 * taps * P * px
+        byts = px * P * 2 * esize if name != "k_hpass_combine" else px * (P * esize + 8)
+        return {"bound": "alu", "achieved": flops / ms_per_launch / 1e9, "peak": PEAK_FP64_VALU_TFS,
+                "unit": "TFLOP/s", "flops_per_launch": flops, "bytes_per_launch": byts,
+                "hbm_gbs_algorithmic": byts / ms_per_launch / 1e6}
+    if name == "k_combine":
+        byts = px * (P * esize + 8)
+        return {"bound": "hbm", "achieved": byts / ms_per_launch / 1e6, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "bytes_per_launch": byts}
+    return None
+
+
+def profile_read(lib):
+    import ctypes
+    out = {}
+    for i in range(lib.bf_profile_count()):
+        name = ctypes.create_string_buffer(64)
+        cnt = ctypes.c_longlong()
+        tot = ctypes.c_double()
+        lib.bf_profile_entry(i, name, 64, ctypes.byref(cnt), ctypes.byref(tot))
+        out[name.value.decode()] = (cnt.value, tot.value)
+    return out
+
+
+def time_forward(bf, f, out, ws, sigma_s, sigma_r, N, stack, steps, warmup, profile=True):
+    import torch
+    for _ in range(warmup):
+        bf.gc_filter(f, sigma_s, sigma_r, N, stack_dtype=stack, out=out, workspace=ws)
+    torch.cuda.synchronize()
+    lib = bf._lib.load()
+    if profile:
+        lib.bf_profile_start()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        bf.gc_filter(f, sigma_s, sigma_r, N, stack_dtype=stack, out=out, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    prof = {}
+    if profile:
+        lib.bf_profile_stop(None)
+        prof = profile_read(lib)
+    return ms, prof
+
+
+def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
+    """Plain-C FP64 oracle (OpenMP over rows) on rows [0, rows) of the image."""
+    from oracle import native as C
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    t = time.perf_counter()
+    C.gcf(f64, sigma_s, sigma_r, N, region=(0, rows, 0, f64.shape[1]))
+    dt = time.perf_counter() - t
+    px = rows * f64.shape[1]
+    return {"value": px / 1e6 / dt, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
+            "sample": f"rows 0..{rows} of the {f64.shape[0]}x{f64.shape[1]} image ({px} px, all {N + 2} planes), "
+                      f"{dt:.1f} s", "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--sigma-s", type=float, default=10.0)
+    ap.add_argument("--sigma-r", type=float, default=30.0)
+    ap.add_argument("--degree", type=int, default=28)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-stack comparison")
+    ap.add_argument("--cpu-rows", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding is design-only, "
+              "see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1605_02178_amd as bf
+    from synth import edge_rich
+
+    H = Wd = args.size
+    ss, sr, N = args.sigma_s, args.sigma_r, args.degree
+    W = bf.radius(ss)
+    P = N + 2
+    log(f"bench: generating {H}x{Wd} edge-rich image")
+    f64 = edge_rich(H, Wd, seed=3).astype(np.float32).astype(np.float64)
+    f = torch.tensor(f64, dtype=torch.float32, device="cuda:0")
+    out = torch.empty_like(f)
+    ws = torch.empty(bf.workspace_bytes(H, Wd, ss, N, "f32"), dtype=torch.uint8, device="cuda:0")
+
+    log(f"bench: FP32 stack, {args.warmup} warmup + {args.steps} timed steps")
+    ms, prof = time_forward(bf, f, out, ws, ss, sr, N, "f32", args.steps, args.warmup)
+    value = H * Wd / 1e6 / (ms / 1e3)
+    kernels = {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
+    dom = max((k for k in kernels if k != "k_put_params"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    roof = kernel_roofline(dom, H, Wd, W, P, 4, kernels[dom]["avg_ms"])
+    roof = {"kernel": dom, **roof}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["avg_ms"] = kernels[dom]["avg_ms"]
+    log(f"bench: FP32 {ms:.3f} ms/step, {value:.1f} Mpx/s; kernels {kernels}")
+
+    # accuracy on crops against both oracles
+    from oracle import native as C
+    y = out.cpu().double().numpy()
+    c0 = H // 2 - 128
+    reg = (c0, c0 + 256, c0, c0 + 256)
+    gc_ref = C.gcf(f64, ss, sr, N, region=reg)
+    d0 = H // 2 - 32
+    dreg = (d0, d0 + 64, d0, d0 + 64)
+    direct_ref = C.direct_bf(f64, ss, sr, region=dreg)
+    acc32 = {"max_abs_vs_gc_oracle_256c": float(np.abs(y[c0:c0 + 256, c0:c0 + 256] - gc_ref).max()),
+             "max_abs_vs_direct_64c": float(np.abs(y[d0:d0 + 64, d0:d0 + 64] - direct_ref).max())}
+
+    result = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"edge-rich {H}x{Wd}, sigma_s={ss:g} (W={W}), sigma_r={sr:g}, N={N} "
+                               f"({P} planes), FP32 stack, FP64 accumulation",
+                   "image": f"{H}x{Wd}", "sigma_s": ss, "sigma_r": sr, "degree": N, "stack": "f32",
+                   "path": "fused: build | column pass | row pass + combine"},
+        "roofline": roof,
+        "kernels": kernels,
+        "accuracy": acc32,
+    }
+
+    if not args.no_fp16:
+        # smallest N' >= N whose error against the direct filter (64^2 crop) is
+        # no worse than the FP32 stack's at N
+        target = acc32["max_abs_vs_direct_64c"] * 1.05
+        ws16 = None
+        chosen = None
+        for N16 in range(N, N + 9, 2):
+            ws16 = torch.empty(bf.workspace_bytes(H, Wd, ss, N16, "f16"), dtype=torch.uint8, device="cuda:0")
+            o16 = torch.empty_like(f)
+            bf.gc_filter(f, ss, sr, N16, stack_dtype="f16", out=o16, workspace=ws16)
+            e = float(np.abs(o16.cpu().double().numpy()[d0:d0 + 64, d0:d0 + 64] - direct_ref).max())
+            chosen = (N16, e, o16)
+            if e <= target:
+                break
+        N16, e16, o16 = chosen
+        ms16, prof16 = time_forward(bf, f, o16, ws16, ss, sr, N16, "f16", args.steps, args.warmup)
+        gc16 = C.gcf(f64, ss, sr, N16, region=reg)
+        result["fp16_stack"] = {
+            "degree": N16, "value": round(H * Wd / 1e6 / (ms16 / 1e3), 2), "unit": "Mpixel/s",
+            "ms_per_step": round(ms16, 4), "max_abs_vs_direct_64c": e16, "fp32_max_abs_vs_direct_64c": target / 1.05,
+            "same_error": e16 <= target,
+            "max_abs_vs_gc_oracle_256c": float(np.abs(o16.cpu().double().numpy()[c0:c0 + 256, c0:c0 + 256] - gc16).max()),
+            "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof16.items()},
+        }
+        log(f"bench: FP16 N={N16} {ms16:.3f} ms/step")
+
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        result["cpu_baseline"] = cpu_baseline(f64, ss, sr, N, min(args.cpu_rows, H))
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

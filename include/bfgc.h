@@ -1,0 +1,188 @@
+/*
+ * bfgc: Gauss-Chebyshev bilateral filter on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Ghosh & Chaudhury, "Fast and High-Quality Bilateral Filtering Using
+ * Gauss-Chebyshev Approximation", 2016):
+ *
+ *   B[f](i) = sum_j g_s(j) g_r(f(i-j) - f(i)) f(i-j) / sum_j g_s(j) g_r(f(i-j) - f(i))
+ *
+ * over the square Omega = [-W, W]^2, W = ceil(3 sigma_s), with the image
+ * extended outside its rectangle by symmetry (Section I, eq. 1). The range
+ * kernel is factored (eq. 2) and its cross term exp(x), x in [-mu, mu],
+ * mu = (U-L)^2 / (4 sigma_r^2), is replaced by the degree-N polynomial that
+ * interpolates it at the scaled zeros of T_{N+1} (Section III, eq. 16 rescaled,
+ * eq. 19). The filter then becomes (Section II, eqs. 6-10, centring eq. 17):
+ *
+ *   1. a stack of N+2 pointwise images of the centred input,
+ *   2. the same truncated spatial Gaussian applied to every image,
+ *   3. a per-pixel combine into numerator P and denominator Q, and P/Q.
+ *
+ * The library computes in the scaled variables s = (f - t_c)/t_h,
+ * t_c = t_h = 127.5 ([L, U] = [0, 255]), H_n = exp(-mu s^2/2) s^n,
+ * b_n = c_n mu^n; F_n of eq. (6) equals mu^{n/2} H_n, and
+ *   y = t_c + t_h * (sum_n b_n s^n Hbar_{n+1}) / (sum_n b_n s^n Hbar_n),
+ * which is eq. (10) with the centring undone.
+ *
+ * Conventions for every entry point below:
+ *   - Images are FP32, row-major, row stride `ld` >= width (elements).
+ *   - Device pointers are HIP device memory owned by the caller; the library
+ *     never allocates device memory in these calls.
+ *   - `stream` is a hipStream_t (NULL = the null stream). All GPU work is
+ *     enqueued on it asynchronously; a returned BF_OK means the work was
+ *     enqueued, not that it has finished.
+ *   - Host-side argument checks run before anything is enqueued; on an error
+ *     nothing is enqueued and bf_last_error() holds a message (per thread).
+ *   - Inputs are expected in [0, 255]. A pixel outside it (or NaN) is not
+ *     corrected; it sets bit BF_DEVFLAG_RANGE in the workspace flag word.
+ *   - No entry point aborts or throws.
+ */
+#ifndef BFGC_H
+#define BFGC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BF_OK = 0,
+    BF_ERR_INVALID_ARG = 1,      /* null pointer, bad size, sigma <= 0 or not finite, N out of range, overlap */
+    BF_ERR_UNSUPPORTED = 2,      /* radius W above BF_MAX_RADIUS, size beyond the index range */
+    BF_ERR_ILL_CONDITIONED = 3,  /* (sigma_r, N, stack type) outside the numerically usable domain */
+    BF_ERR_WORKSPACE = 4,        /* workspace null or smaller than bf_gc_workspace_bytes() */
+    BF_ERR_DEVICE = 5            /* a HIP call failed; bf_last_error() has the HIP message */
+} bf_status;
+
+typedef enum {
+    BF_STACK_F32 = 0,            /* stack planes stored in FP32 */
+    BF_STACK_F16 = 1,            /* FP16, each plane scaled by a power of two 2^k_n */
+    BF_STACK_BF16 = 2            /* BF16 */
+} bf_stack_dtype;
+
+/* flags */
+#define BF_FLAG_ALLOW_ILL_CONDITIONED 0x1u  /* compute even where the conditioning check fails */
+#define BF_FLAG_STAGED                0x2u  /* materialise the stack: build | filter | combine (one kernel each) */
+
+/* device flag word bits (read with bf_gc_read_flags) */
+#define BF_DEVFLAG_RANGE 0x1u               /* some input pixel was outside [0, 255] or not finite */
+
+#define BF_MAX_DEGREE 320                   /* largest N accepted */
+#define BF_MAX_RADIUS 96                    /* largest W = ceil(3 sigma_s) accepted */
+
+/*
+ * Degree for a given sigma_r when the caller has none. The paper fixes N per
+ * experiment (N = 28 at sigma_r = 30, Table 2) and states no rule; this one
+ * keeps that point and scales it through the first neglected Chebyshev
+ * coefficient of exp(mu y): the smallest N with 2 I_{N+1}(mu) <= eps0, eps0 =
+ * sqrt(2 I_28(mu30) 2 I_29(mu30)), I_k the modified Bessel function.
+ * Returns N >= 1, or -1 for sigma_r <= 0 / not finite / N above BF_MAX_DEGREE.
+ */
+int bf_gc_degree_rule(double sigma_r);
+
+/*
+ * Monomial coefficients b_n = c_n mu^n, n = 0..N, of the interpolant of
+ * exp(mu y) at the zeros of T_{N+1} (Section III-B, eq. 19 with the mu^-n
+ * moved into the scaled variables). b_out: host array of N+1 doubles.
+ * mu_out: host double (may be NULL).
+ */
+bf_status bf_gc_coefficients(double sigma_r, int N, double *b_out, double *mu_out);
+
+/*
+ * Conditioning of the approximation for (sigma_r, N): kernel_err = max over
+ * y in [-1,1] of exp(-mu|y|) |p_N(mu y) - exp(mu y)| (largest error of the
+ * approximate range kernel, relative to its peak 1) and kappa = max over y of
+ * exp(-mu|y|) sum_n |b_n| |y|^n (how much a relative rounding of the stack
+ * grows in the kernel). Either output pointer may be NULL. stack_dtype is
+ * accepted for symmetry and does not change the values.
+ */
+bf_status bf_gc_query(double sigma_r, int N, int stack_dtype, double *kernel_err, double *kappa);
+
+/*
+ * Workspace bytes needed by bf_gc_forward (for_backward = 0) or
+ * bf_gc_backward (for_backward = 1) for one height x width image. Includes
+ * the parameter block, the device flag word and N+2 stack planes (twice that
+ * with BF_FLAG_STAGED or for the backward). Returns 0 for invalid arguments.
+ */
+size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype,
+                             int for_backward);
+
+/*
+ * Forward filter (Section III-B procedure: centre, fast algorithm with the
+ * coefficients of eq. 19, undo the centring).
+ *   f      device, height x width FP32 with row stride ld, read only
+ *   out    device, height x width FP32 with row stride ld; must not overlap f
+ *   height, width >= 0 (0 means nothing to do, BF_OK); ld >= width
+ *   sigma_s > 0: spatial std. dev.; W = ceil(3 sigma_s) <= BF_MAX_RADIUS
+ *   sigma_r > 0: range std. dev.
+ *   N: degree, 1 <= N <= BF_MAX_DEGREE (bf_gc_degree_rule gives the default)
+ *   stack_dtype: bf_stack_dtype
+ *   flags: BF_FLAG_*
+ *   ws, ws_bytes: device workspace of at least bf_gc_workspace_bytes(..., 0)
+ *     bytes, 256-byte aligned; its contents on entry are ignored.
+ * The device flag word inside ws is cleared, then set by the kernels.
+ */
+bf_status bf_gc_forward(const float *f, float *out, int height, int width, int ld,
+                        double sigma_s, double sigma_r, int N, int stack_dtype, unsigned flags,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Stages of the forward filter, for callers that want the stack itself. These
+ * are the kernels bf_gc_forward runs with BF_FLAG_STAGED. The stack is N+2
+ * planes of height x width, plane stride `plane_stride` and row stride `lds`
+ * elements, element type per stack_dtype; plane n holds 2^k_n H_n (k_n = 0
+ * except for FP16, see bf_gc_plane_scales).
+ *
+ * bf_gc_stack_build: H_n = exp(-mu s^2/2) s^n, n = 0..N+1 (eq. 6 scaled,
+ *   centring eq. 17). Sets the range flag in *devflag (device unsigned, may
+ *   be NULL).
+ * bf_gc_gauss_planes: Hbar_n = G H_n for every plane (eq. 7, separable,
+ *   taps normalised to sum 1), in place; tmp is a second stack of the same
+ *   layout used between the row and the column pass.
+ * bf_gc_combine: y = t_c + t_h P/Q from the filtered planes (eqs. 8-10);
+ *   P_out and Q_out (device FP32 height x width with row stride ld, may be
+ *   NULL) receive the scaled P' = sum b_n s^n Hbar_{n+1} and
+ *   Q' = sum b_n s^n Hbar_n, P = t_h S P', Q = S Q' with S the sum of the
+ *   unnormalised 2-D spatial weights.
+ * prm is a device buffer of bf_gc_param_bytes() bytes that the call fills and
+ * the kernels read; it must stay untouched until the kernels have run.
+ */
+size_t bf_gc_param_bytes(double sigma_s, int N);
+bf_status bf_gc_plane_scales(double sigma_r, int N, int stack_dtype, int *k_out);
+bf_status bf_gc_stack_build(const float *f, int height, int width, int ld, double sigma_r, int N,
+                            int stack_dtype, void *stack, long long plane_stride, int lds,
+                            unsigned *devflag, void *prm, void *stream);
+bf_status bf_gc_gauss_planes(void *stack, void *tmp, int planes, int height, int width,
+                             long long plane_stride, int lds, double sigma_s, int stack_dtype,
+                             void *prm, void *stream);
+bf_status bf_gc_combine(const float *f, const void *stack, int height, int width, int ld,
+                        long long plane_stride, int lds, double sigma_r, int N, int stack_dtype,
+                        float *out, float *P_out, float *Q_out, void *prm, void *stream);
+
+/* Reads the device flag word of a workspace used by bf_gc_forward; waits for
+ * `stream` first. flags_out: host unsigned. */
+bf_status bf_gc_read_flags(const void *ws, unsigned *flags_out, void *stream);
+
+/*
+ * Kernel timing for profiling. bf_profile_start() turns it on for every later
+ * launch of this library (all streams): each kernel is bracketed by two HIP
+ * events on the stream it runs on. bf_profile_stop() turns it off, waits for
+ * the recorded events and sums the elapsed times per kernel name; read the
+ * sums with bf_profile_count() and bf_profile_entry(i, ...), which copies the
+ * name (NUL-terminated, at most name_len bytes), the launch count and the
+ * total milliseconds. `stream` is unused (kept for symmetry).
+ */
+bf_status bf_profile_start(void);
+bf_status bf_profile_stop(void *stream);
+int bf_profile_count(void);
+bf_status bf_profile_entry(int i, char *name, int name_len, long long *count, double *total_ms);
+
+/* Text for a status code; the last error message of the calling thread. */
+const char *bf_status_string(int status);
+const char *bf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFGC_H */

@@ -1,0 +1,207 @@
+"""Gauss-Chebyshev bilateral filter (Ghosh & Chaudhury, 2016) on AMD MI355X.
+
+Thin torch-facing layer over the C ABI in include/bfgc.h (libbfgc.so, HIP
+kernels for gfx950). torch provides device memory and the current HIP stream;
+all arithmetic of the filter runs in the library.
+
+    y = gc_filter(f, sigma_s=10.0, sigma_r=30.0)               # N from the degree rule
+    y = gc_filter(f, 10.0, 30.0, degree=28, stack_dtype="f16")
+
+The module imports without a GPU; the functions need the built library and a
+CUDA (HIP) device tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+from . import _lib
+from ._lib import BFError
+
+__all__ = [
+    "BFError", "STACK_DTYPES", "FLAG_ALLOW_ILL_CONDITIONED", "FLAG_STAGED", "DEVFLAG_RANGE",
+    "degree_rule", "coefficients", "query", "plane_scales", "workspace_bytes", "param_bytes",
+    "gc_filter", "stack_build", "gauss_planes", "combine", "read_flags", "radius", "StackLayout",
+]
+
+STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+FLAG_ALLOW_ILL_CONDITIONED = 0x1
+FLAG_STAGED = 0x2
+DEVFLAG_RANGE = 0x1
+MAX_DEGREE = 320
+MAX_RADIUS = 96
+
+
+def _dtype_code(stack_dtype) -> int:
+    if isinstance(stack_dtype, int):
+        return stack_dtype
+    import torch
+    table = {torch.float32: 0, torch.float16: 1, torch.bfloat16: 2}
+    if stack_dtype in table:
+        return table[stack_dtype]
+    return STACK_DTYPES[str(stack_dtype)]
+
+
+def radius(sigma_s: float) -> int:
+    """W = ceil(3 sigma_s), the half-width of the spatial window."""
+    return int(math.ceil(3.0 * sigma_s - 1e-12))
+
+
+def degree_rule(sigma_r: float) -> int:
+    n = _lib.load().bf_gc_degree_rule(float(sigma_r))
+    if n < 0:
+        raise ValueError(f"no degree for sigma_r={sigma_r}")
+    return n
+
+
+def coefficients(sigma_r: float, N: int):
+    """(b_n list, mu) as the library's planner computes them."""
+    b = (ctypes.c_double * (N + 1))()
+    mu = ctypes.c_double()
+    _lib.check(_lib.load().bf_gc_coefficients(float(sigma_r), int(N), b, ctypes.byref(mu)), "bf_gc_coefficients")
+    return list(b), mu.value
+
+
+def query(sigma_r: float, N: int, stack_dtype="f32"):
+    """(kernel_err, kappa) for (sigma_r, N)."""
+    e, k = ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().bf_gc_query(float(sigma_r), int(N), _dtype_code(stack_dtype), ctypes.byref(e),
+                                        ctypes.byref(k)), "bf_gc_query")
+    return e.value, k.value
+
+
+def plane_scales(sigma_r: float, N: int, stack_dtype="f32"):
+    k = (ctypes.c_int * (N + 2))()
+    _lib.check(_lib.load().bf_gc_plane_scales(float(sigma_r), int(N), _dtype_code(stack_dtype), k),
+               "bf_gc_plane_scales")
+    return list(k)
+
+
+def workspace_bytes(height, width, sigma_s, N, stack_dtype="f32", for_backward=False) -> int:
+    return int(_lib.load().bf_gc_workspace_bytes(int(height), int(width), float(sigma_s), int(N),
+                                                 _dtype_code(stack_dtype), int(bool(for_backward))))
+
+
+def param_bytes(sigma_s, N) -> int:
+    return int(_lib.load().bf_gc_param_bytes(float(sigma_s), int(N)))
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_image(f, name="f"):
+    import torch
+    if not isinstance(f, torch.Tensor) or not f.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if f.dtype != torch.float32 or f.dim() != 2:
+        raise TypeError(f"{name} must be a 2-D float32 tensor")
+    if f.numel() and f.stride(1) != 1:
+        raise ValueError(f"{name} must have unit column stride")
+
+
+def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
+              staged: bool = False, allow_ill_conditioned: bool = False, out=None, workspace=None,
+              stream=None):
+    """Gauss-Chebyshev bilateral filter of a 2-D float32 image in [0, 255]
+    (Section III-B). Returns a new tensor (or writes `out`)."""
+    import torch
+    _check_image(f)
+    H, Wd = f.shape
+    N = degree_rule(sigma_r) if degree is None else int(degree)
+    code = _dtype_code(stack_dtype)
+    if out is None:
+        out = torch.empty_like(f, memory_format=torch.contiguous_format)
+    _check_image(out, "out")
+    if out.stride(0) != f.stride(0) and H > 1:
+        raise ValueError("out must have the row stride of f")
+    ld = f.stride(0) if H > 1 else Wd
+    need = workspace_bytes(H, Wd, sigma_s, N, code)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    flags = (FLAG_STAGED if staged else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
+    st = _lib.load().bf_gc_forward(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), H, Wd,
+                                   max(ld, Wd), float(sigma_s), float(sigma_r), N, code, flags,
+                                   ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                   _stream_ptr(stream))
+    _lib.check(st, "bf_gc_forward")
+    return out
+
+
+class StackLayout:
+    """Device stack of N+2 planes as the stage functions use it."""
+
+    def __init__(self, height, width, N, stack_dtype="f32", device="cuda"):
+        import torch
+        self.height, self.width, self.N = int(height), int(width), int(N)
+        self.code = _dtype_code(stack_dtype)
+        self.lds = (self.width + 63) // 64 * 64
+        self.planes = self.N + 2
+        self.plane_stride = self.height * self.lds
+        tdtype = {0: torch.float32, 1: torch.float16, 2: torch.bfloat16}[self.code]
+        self.data = torch.empty((self.planes, self.height, self.lds), dtype=tdtype, device=device)
+
+    def view(self):
+        """(N+2, height, width) view of the planes."""
+        return self.data[:, :, : self.width]
+
+
+def stack_build(f, sigma_r, N, stack_dtype="f32", stack: StackLayout | None = None, prm=None, devflag=None,
+                stream=None) -> StackLayout:
+    import torch
+    _check_image(f)
+    H, Wd = f.shape
+    stack = stack or StackLayout(H, Wd, N, stack_dtype, f.device)
+    prm = prm if prm is not None else torch.empty(param_bytes(1.0, N) + 8 * 64, dtype=torch.uint8, device=f.device)
+    st = _lib.load().bf_gc_stack_build(ctypes.c_void_p(f.data_ptr()), H, Wd, max(f.stride(0), Wd), float(sigma_r),
+                                       int(N), stack.code, ctypes.c_void_p(stack.data.data_ptr()),
+                                       stack.plane_stride, stack.lds,
+                                       ctypes.c_void_p(devflag.data_ptr() if devflag is not None else 0),
+                                       ctypes.c_void_p(prm.data_ptr()), _stream_ptr(stream))
+    _lib.check(st, "bf_gc_stack_build")
+    stack._prm = prm
+    return stack
+
+
+def gauss_planes(stack: StackLayout, sigma_s, tmp: StackLayout | None = None, prm=None, stream=None):
+    import torch
+    tmp = tmp or StackLayout(stack.height, stack.width, stack.N, stack.code, stack.data.device)
+    prm = prm if prm is not None else torch.empty(param_bytes(sigma_s, 1) + 8 * 64, dtype=torch.uint8,
+                                                  device=stack.data.device)
+    st = _lib.load().bf_gc_gauss_planes(ctypes.c_void_p(stack.data.data_ptr()), ctypes.c_void_p(tmp.data.data_ptr()),
+                                        stack.planes, stack.height, stack.width, stack.plane_stride, stack.lds,
+                                        float(sigma_s), stack.code, ctypes.c_void_p(prm.data_ptr()),
+                                        _stream_ptr(stream))
+    _lib.check(st, "bf_gc_gauss_planes")
+    stack._tmp, stack._prm2 = tmp, prm
+    return stack
+
+
+def combine(f, stack: StackLayout, sigma_r, out=None, want_pq=False, prm=None, stream=None):
+    """Returns y, or (y, P', Q') with want_pq."""
+    import torch
+    _check_image(f)
+    H, Wd = f.shape
+    out = out if out is not None else torch.empty_like(f)
+    P = torch.empty_like(f) if want_pq else None
+    Q = torch.empty_like(f) if want_pq else None
+    prm = prm if prm is not None else torch.empty(param_bytes(1.0, stack.N) + 8 * 64, dtype=torch.uint8,
+                                                  device=f.device)
+    st = _lib.load().bf_gc_combine(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(stack.data.data_ptr()), H, Wd,
+                                   max(f.stride(0), Wd), stack.plane_stride, stack.lds, float(sigma_r), stack.N,
+                                   stack.code, ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.c_void_p(P.data_ptr() if want_pq else 0),
+                                   ctypes.c_void_p(Q.data_ptr() if want_pq else 0),
+                                   ctypes.c_void_p(prm.data_ptr()), _stream_ptr(stream))
+    _lib.check(st, "bf_gc_combine")
+    out._prm = prm
+    return (out, P, Q) if want_pq else out
+
+
+def read_flags(workspace, stream=None) -> int:
+    v = ctypes.c_uint()
+    _lib.check(_lib.load().bf_gc_read_flags(ctypes.c_void_p(workspace.data_ptr()), ctypes.byref(v),
+                                            _stream_ptr(stream)), "bf_gc_read_flags")
+    return v.value

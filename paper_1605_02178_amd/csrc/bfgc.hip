@@ -1,0 +1,651 @@
+// Gauss-Chebyshev bilateral filter: HIP kernels for gfx950 and the C ABI
+// declared in include/bfgc.h.
+//
+// Forward pipeline (Section III-B procedure over the fast algorithm of
+// Section II):
+//   k_put_params    parameter block (taps, b_n, plane scales) into device memory
+//   k_stack_build   H_n = e^{-mu s^2/2} s^n, n = 0..N+1        (eq. 6, eq. 17)
+//   k_vpass         column pass of the separable Gaussian      (eq. 7)
+//   k_hpass<true>   row pass fused with the combine and divide (eqs. 7-10)
+// With BF_FLAG_STAGED the last step is k_hpass<false> (row pass back into the
+// stack) followed by k_combine, one kernel per stage.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bfgc.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+namespace bfgc {
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_put_params(double *__restrict__ prm, unsigned *__restrict__ flag,
+                                                    ParamChunk chunk) {
+    for (int i = threadIdx.x; i < chunk.count; i += blockDim.x) prm[chunk.offset + i] = chunk.v[i];
+    if (chunk.clear_flag && threadIdx.x == 0 && flag) *flag = 0u;
+}
+
+// One thread per pixel; planes written one after another, coalesced along rows.
+template <class S>
+__global__ __launch_bounds__(256) void k_stack_build(const float *__restrict__ f, int H, int Wd, int ld,
+                                                      typename S::T *__restrict__ stack, long long ps, int lds,
+                                                      int P, const double *__restrict__ scale, double mu,
+                                                      unsigned *__restrict__ flag) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = blockIdx.y; r < H; r += gridDim.y) {
+        bool bad = false;
+        if (c < Wd) {
+            const float fv = f[(long long)r * ld + c];
+            bad = !(fv >= 0.0f && fv <= 255.0f);
+            const double s = ((double)fv - kTc) * (1.0 / kTh);           // eq. (17), scaled
+            double v = exp(-0.5 * mu * s * s);                           // H_0 = e^{-mu s^2/2}
+            typename S::T *dst = stack + (long long)r * lds + c;
+            for (int n = 0; n < P; ++n) {
+                dst[n * ps] = S::enc(v * scale[n]);
+                v *= s;                                                  // H_{n+1} = H_n s
+            }
+        }
+        if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1)
+            atomicOr(flag, BF_DEVFLAG_RANGE);
+    }
+}
+
+// Column pass: lane = column, each wave R consecutive output rows, one plane
+// per blockIdx.z. Each input row j of the window [r0-W, r0+R+W) is read once
+// (coalesced across the wave) and multiplied into the R accumulators it
+// touches; taps outside |k| <= W are zeros of the padded tap array.
+template <class S, int R>
+__global__ __launch_bounds__(256) void k_vpass(const typename S::T *__restrict__ in,
+                                                typename S::T *__restrict__ out, int H, int Wd, long long ps,
+                                                int lds, const double *__restrict__ taps, int W) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + lane;
+    const int r0 = (blockIdx.y * 4 + wave) * R;
+    const long long n = blockIdx.z;
+    if (r0 >= H) return;
+    const int cl = c < Wd ? c : Wd - 1;
+    const typename S::T *src = in + n * ps + cl;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    const int span = R + 2 * W;
+    for (int j = 0; j < span; ++j) {
+        const int rr = mirror(r0 - W + j, H);
+        const double x = (double)S::dec(src[(long long)rr * lds]);
+        const double *t = taps + j + (kTapPad - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = fma(t[-r], x, acc[r]);
+    }
+    if (c < Wd) {
+        typename S::T *dst = out + n * ps + c;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r0 + r < H) dst[(long long)(r0 + r) * lds] = S::enc(acc[r]);
+    }
+}
+
+// Row pass over a tile of 64 rows x 4R columns staged in LDS (lane = row,
+// wave w = columns [4R-block + wR, +R)). The LDS row pitch is odd, so the 64
+// lanes of a wave reading one column each hit distinct banks.
+// COMBINE = false: filtered planes go back to a stack.
+// COMBINE = true : the filtered planes are combined as they come out,
+//   Q += cq_n s^n Hbar_n (n <= N),  P += cp_{n-1} s^{n-1} Hbar_n (n >= 1)
+//   y  = t_c + t_h P / Q                                        (eqs. 8-10)
+template <class S, int R, bool COMBINE>
+__global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__ in,
+                                                typename S::T *__restrict__ out_stack,
+                                                const float *__restrict__ f, float *__restrict__ out,
+                                                float *__restrict__ Pout, float *__restrict__ Qout, int H,
+                                                int Wd, int ld, long long ps, int lds, int P, int N,
+                                                const double *__restrict__ taps, const double *__restrict__ cq,
+                                                const double *__restrict__ cp, int W, int pitch) {
+    extern __shared__ float tile[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int span = 4 * R + 2 * W;
+    int *colidx = (int *)(tile + 64 * pitch);
+    const int c0 = blockIdx.x * (4 * R);
+    const int rbase = blockIdx.y * 64;
+    const int r = rbase + lane;
+    const int cw = c0 + wave * R;
+    for (int i = threadIdx.x; i < span; i += blockDim.x) colidx[i] = mirror(c0 - W + i, Wd);
+
+    double s[R], sp[R], Qa[R], Pa[R];
+    if (COMBINE) {
+        const int rl = r < H ? r : H - 1;
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int cc = cw + q < Wd ? cw + q : Wd - 1;
+            s[q] = ((double)f[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
+            sp[q] = 1.0;
+            Qa[q] = 0.0;
+            Pa[q] = 0.0;
+        }
+    }
+    __syncthreads();
+    for (int n = 0; n < P; ++n) {
+        const typename S::T *src = in + (long long)n * ps;
+        for (int row = wave; row < 64; row += 4) {
+            const int gr = rbase + row < H ? rbase + row : H - 1;
+            const typename S::T *srow = src + (long long)gr * lds;
+            for (int i = lane; i < span; i += 64) tile[row * pitch + i] = S::dec(srow[colidx[i]]);
+        }
+        __syncthreads();
+        double acc[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] = 0.0;
+        const float *trow = tile + lane * pitch + wave * R;
+        const int wspan = R + 2 * W;
+        for (int j = 0; j < wspan; ++j) {
+            const double x = (double)trow[j];
+            const double *t = taps + j + (kTapPad - 1);
+#pragma unroll
+            for (int q = 0; q < R; ++q) acc[q] = fma(t[-q], x, acc[q]);
+        }
+        __syncthreads();
+        if (COMBINE) {
+            const double cqn = n <= N ? cq[n] : 0.0;
+            const double cpn = n >= 1 ? cp[n - 1] : 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const double spn = n >= 1 ? sp[q] * s[q] : 1.0;   // s^n; sp holds s^{n-1}
+                Pa[q] = fma(cpn * sp[q], acc[q], Pa[q]);
+                Qa[q] = fma(cqn * spn, acc[q], Qa[q]);
+                sp[q] = spn;
+            }
+        } else if (r < H) {
+            typename S::T *dst = out_stack + (long long)n * ps + (long long)r * lds;
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                if (cw + q < Wd) dst[cw + q] = S::enc(acc[q]);
+        }
+    }
+    if (COMBINE && r < H) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (cw + q < Wd) {
+                const long long o = (long long)r * ld + cw + q;
+                out[o] = (float)(kTc + kTh * (Pa[q] / Qa[q]));
+                if (Pout) Pout[o] = (float)Pa[q];
+                if (Qout) Qout[o] = (float)Qa[q];
+            }
+        }
+    }
+}
+
+// Staged combine: one thread per pixel, planes read in order (eqs. 8-10).
+template <class S>
+__global__ __launch_bounds__(256) void k_combine(const float *__restrict__ f, const typename S::T *__restrict__ stack,
+                                                  int H, int Wd, int ld, long long ps, int lds, int N,
+                                                  const double *__restrict__ cq, const double *__restrict__ cp,
+                                                  float *__restrict__ out, float *__restrict__ Pout,
+                                                  float *__restrict__ Qout) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int r = blockIdx.y; r < H; r += gridDim.y) {
+        if (c >= Wd) continue;
+        const long long o = (long long)r * ld + c;
+        const double s = ((double)f[o] - kTc) * (1.0 / kTh);
+        const typename S::T *src = stack + (long long)r * lds + c;
+        double Q = 0.0, Pn = 0.0, sn = 1.0;                    // sn = s^n
+        for (int n = 0; n <= N; ++n) {
+            Q = fma(cq[n] * sn, (double)S::dec(src[n * ps]), Q);
+            Pn = fma(cp[n] * sn, (double)S::dec(src[(n + 1) * ps]), Pn);
+            sn *= s;
+        }
+        out[o] = (float)(kTc + kTh * (Pn / Q));
+        if (Pout) Pout[o] = (float)Pn;
+        if (Qout) Qout[o] = (float)Q;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_err;
+
+static bf_status fail(bf_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+static bf_status check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return BF_OK;
+}
+
+// Optional per-kernel timing: when enabled, every launch is bracketed by a
+// pair of HIP events on its own stream; bf_profile_stop waits for them and
+// sums the elapsed times per kernel name.
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+struct ProfStat {
+    std::string name;
+    long long count;
+    double total_ms;
+};
+static std::mutex g_prof_mtx;
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof_recs;
+static std::vector<hipEvent_t> g_prof_pool;
+static std::vector<ProfStat> g_prof_stats;
+
+static hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    const char *name;
+    hipStream_t stream;
+    hipEvent_t a = nullptr;
+    ProfScope(const char *n, hipStream_t s) : name(n), stream(s) {
+        std::lock_guard<std::mutex> lock(g_prof_mtx);
+        if (!g_prof_on) return;
+        a = prof_event();
+        if (a) (void)hipEventRecord(a, stream);
+    }
+    ~ProfScope() {
+        if (!a) return;
+        std::lock_guard<std::mutex> lock(g_prof_mtx);
+        hipEvent_t b = prof_event();
+        if (!b) return;
+        (void)hipEventRecord(b, stream);
+        g_prof_recs.push_back({name, a, b});
+    }
+};
+
+constexpr int kVR = 16;   // rows per wave in k_vpass
+constexpr int kHR = 8;    // columns per thread in k_hpass
+constexpr size_t kFlagBytes = 256;
+
+static size_t esize(int dtype) { return dtype == BF_STACK_F32 ? 4 : 2; }
+static int lds_of(int width) { return (width + 63) & ~63; }
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool finite_pos(double x) { return x > 0.0 && std::isfinite(x); }
+
+static bf_status check_common(int height, int width, double sigma_s, double sigma_r, int N, int dtype) {
+    if (height < 0 || width < 0) return fail(BF_ERR_INVALID_ARG, "height and width must be >= 0");
+    if (!finite_pos(sigma_s)) return fail(BF_ERR_INVALID_ARG, "sigma_s must be positive and finite");
+    if (!finite_pos(sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be positive and finite");
+    if (N < 1 || N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N out of [1, BF_MAX_DEGREE]");
+    if (dtype < BF_STACK_F32 || dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
+    if (radius_of(sigma_s) > BF_MAX_RADIUS) return fail(BF_ERR_UNSUPPORTED, "radius ceil(3 sigma_s) above BF_MAX_RADIUS");
+    if ((long long)height * lds_of(width) > (1LL << 40)) return fail(BF_ERR_UNSUPPORTED, "image too large");
+    return BF_OK;
+}
+
+// Storage rounding unit of each stack type.
+static double unit_roundoff(int dtype) {
+    return dtype == BF_STACK_F32 ? std::ldexp(1.0, -24) : dtype == BF_STACK_F16 ? std::ldexp(1.0, -11)
+                                                                                : std::ldexp(1.0, -8);
+}
+
+static bf_status check_conditioning(double sigma_r, int N, int dtype, unsigned flags) {
+    if (flags & BF_FLAG_ALLOW_ILL_CONDITIONED) return BF_OK;
+    const Fit &F = fit(sigma_r, N);
+    if (!std::isfinite(F.kappa) || F.kappa * unit_roundoff(dtype) > 1e-2) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "ill-conditioned: kappa=%.3g times the stack rounding unit exceeds 1e-2 "
+                                  "(sigma_r=%g, N=%d)", F.kappa, sigma_r, N);
+        return fail(BF_ERR_ILL_CONDITIONED, buf);
+    }
+    return BF_OK;
+}
+
+static bf_status upload_params(double *prm, unsigned *flag, double sigma_s, double sigma_r, int N, int dtype,
+                               hipStream_t stream, ParamLayout *Lout) {
+    const int W = radius_of(sigma_s);
+    ParamLayout L = param_layout(W, N);
+    std::vector<double> host;
+    fill_params(L, sigma_s, sigma_r, dtype, host);
+    ParamChunk ch;
+    int off = 0;
+    do {
+        std::memset(&ch, 0, sizeof ch);
+        ch.offset = off;
+        ch.count = std::min(400, L.total - off);
+        ch.clear_flag = off == 0 ? 1 : 0;
+        for (int i = 0; i < ch.count; ++i) ch.v[i] = host[off + i];
+        ProfScope prof_("k_put_params", stream);
+        hipLaunchKernelGGL(k_put_params, dim3(1), dim3(256), 0, stream, prm, flag, ch);
+        off += 400;
+    } while (off < L.total);
+    *Lout = L;
+    return check_launch("k_put_params");
+}
+
+struct Plan {
+    int W = 0, N = 0, P = 0;
+    double mu = 0.0;
+    ParamLayout L;
+};
+
+template <class S>
+static bf_status launch_build(const float *f, int H, int Wd, int ld, void *stack, long long ps, int lds, int P,
+                              const double *prm, const ParamLayout &L, double mu, unsigned *flag,
+                              hipStream_t stream) {
+    dim3 grid((Wd + 255) / 256, std::min(H, 65535));
+    ProfScope prof_("k_stack_build", stream);
+    hipLaunchKernelGGL(k_stack_build<S>, grid, dim3(256), 0, stream, f, H, Wd, ld,
+                       (typename S::T *)stack, ps, lds, P, prm + L.off_scale, mu, flag);
+    return check_launch("k_stack_build");
+}
+
+template <class S>
+static bf_status launch_gauss(void *stack, void *tmp, int planes, int H, int Wd, long long ps, int lds,
+                              const double *prm, const ParamLayout &L, hipStream_t stream) {
+    dim3 gv((Wd + 63) / 64, (H + 4 * kVR - 1) / (4 * kVR), planes);
+    {
+    ProfScope prof_("k_vpass", stream);
+    hipLaunchKernelGGL((k_vpass<S, kVR>), gv, dim3(256), 0, stream, (const typename S::T *)stack,
+                       (typename S::T *)tmp, H, Wd, ps, lds, prm + L.off_taps, L.W);
+    }
+    bf_status st = check_launch("k_vpass");
+    if (st != BF_OK) return st;
+    const int span = 4 * kHR + 2 * L.W;
+    const int pitch = span | 1;
+    const size_t shm = (size_t)64 * pitch * sizeof(float) + (size_t)span * sizeof(int);
+    dim3 gh((Wd + 4 * kHR - 1) / (4 * kHR), (H + 63) / 64);
+    ProfScope prof_("k_hpass", stream);
+    hipLaunchKernelGGL((k_hpass<S, kHR, false>), gh, dim3(256), shm, stream, (const typename S::T *)tmp,
+                       (typename S::T *)stack, (const float *)nullptr, (float *)nullptr, (float *)nullptr,
+                       (float *)nullptr, H, Wd, 0, ps, lds, planes, 0, prm + L.off_taps, prm + L.off_cq,
+                       prm + L.off_cp, L.W, pitch);
+    return check_launch("k_hpass");
+}
+
+template <class S>
+static bf_status launch_hpass_combine(const void *tmp, const float *f, float *out, float *Pout, float *Qout, int H,
+                                      int Wd, int ld, long long ps, int lds, const double *prm,
+                                      const ParamLayout &L, hipStream_t stream) {
+    const int span = 4 * kHR + 2 * L.W;
+    const int pitch = span | 1;
+    const size_t shm = (size_t)64 * pitch * sizeof(float) + (size_t)span * sizeof(int);
+    dim3 gh((Wd + 4 * kHR - 1) / (4 * kHR), (H + 63) / 64);
+    ProfScope prof_("k_hpass_combine", stream);
+    hipLaunchKernelGGL((k_hpass<S, kHR, true>), gh, dim3(256), shm, stream, (const typename S::T *)tmp,
+                       (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, ps, lds, L.N + 2, L.N,
+                       prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W, pitch);
+    return check_launch("k_hpass(combine)");
+}
+
+template <class S>
+static bf_status launch_combine(const float *f, const void *stack, int H, int Wd, int ld, long long ps, int lds,
+                                const double *prm, const ParamLayout &L, float *out, float *Pout, float *Qout,
+                                hipStream_t stream) {
+    dim3 grid((Wd + 255) / 256, std::min(H, 65535));
+    ProfScope prof_("k_combine", stream);
+    hipLaunchKernelGGL(k_combine<S>, grid, dim3(256), 0, stream, f, (const typename S::T *)stack, H, Wd, ld, ps,
+                       lds, L.N, prm + L.off_cq, prm + L.off_cp, out, Pout, Qout);
+    return check_launch("k_combine");
+}
+
+template <class S>
+static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
+                             int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    ParamLayout L;
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L);
+    if (st != BF_OK) return st;
+    const int lds = lds_of(Wd);
+    const long long ps = (long long)H * lds;
+    const int P = N + 2;
+    char *stackA = ws + kFlagBytes + align256(sizeof(double) * L.total);
+    char *stackB = stackA + align256((size_t)P * ps * sizeof(typename S::T));
+    const double mu = fit(sigma_r, N).mu;
+    if ((st = launch_build<S>(f, H, Wd, ld, stackA, ps, lds, P, prm, L, mu, flag, stream)) != BF_OK) return st;
+    if (flags & BF_FLAG_STAGED) {
+        if ((st = launch_gauss<S>(stackA, stackB, P, H, Wd, ps, lds, prm, L, stream)) != BF_OK) return st;
+        return launch_combine<S>(f, stackA, H, Wd, ld, ps, lds, prm, L, out, nullptr, nullptr, stream);
+    }
+    dim3 gv((Wd + 63) / 64, (H + 4 * kVR - 1) / (4 * kVR), P);
+    {
+        ProfScope prof_("k_vpass", stream);
+        hipLaunchKernelGGL((k_vpass<S, kVR>), gv, dim3(256), 0, stream, (const typename S::T *)stackA,
+                           (typename S::T *)stackB, H, Wd, ps, lds, prm + L.off_taps, L.W);
+    }
+    if ((st = check_launch("k_vpass")) != BF_OK) return st;
+    return launch_hpass_combine<S>(stackB, f, out, nullptr, nullptr, H, Wd, ld, ps, lds, prm, L, stream);
+}
+
+static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+}  // namespace bfgc
+
+using namespace bfgc;
+
+extern "C" {
+
+int bf_gc_degree_rule(double sigma_r) { return degree_rule(sigma_r, BF_MAX_DEGREE); }
+
+bf_status bf_gc_coefficients(double sigma_r, int N, double *b_out, double *mu_out) {
+    if (!finite_pos(sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be positive and finite");
+    if (N < 1 || N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N out of [1, BF_MAX_DEGREE]");
+    if (!b_out) return fail(BF_ERR_INVALID_ARG, "b_out is null");
+    const Fit &F = fit(sigma_r, N);
+    for (int n = 0; n <= N; ++n) b_out[n] = F.b[n];
+    if (mu_out) *mu_out = F.mu;
+    return BF_OK;
+}
+
+bf_status bf_gc_query(double sigma_r, int N, int stack_dtype, double *kernel_err, double *kappa) {
+    if (!finite_pos(sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be positive and finite");
+    if (N < 1 || N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N out of [1, BF_MAX_DEGREE]");
+    if (stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
+    const Fit &F = fit(sigma_r, N);
+    if (kernel_err) *kernel_err = F.kernel_err;
+    if (kappa) *kappa = F.kappa;
+    return BF_OK;
+}
+
+size_t bf_gc_param_bytes(double sigma_s, int N) {
+    if (!finite_pos(sigma_s) || N < 1 || N > BF_MAX_DEGREE || radius_of(sigma_s) > BF_MAX_RADIUS) return 0;
+    return sizeof(double) * (size_t)param_layout(radius_of(sigma_s), N).total;
+}
+
+size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype, int for_backward) {
+    (void)for_backward;
+    if (check_common(height, width, sigma_s, 30.0, N, stack_dtype) != BF_OK) return 0;
+    const size_t planes = (size_t)(N + 2) * height * lds_of(width) * esize(stack_dtype);
+    return kFlagBytes + align256(bf_gc_param_bytes(sigma_s, N)) + 2 * align256(planes);
+}
+
+bf_status bf_gc_forward(const float *f, float *out, int height, int width, int ld, double sigma_s,
+                        double sigma_r, int N, int stack_dtype, unsigned flags, void *ws, size_t ws_bytes,
+                        void *stream) {
+    bf_status st = check_common(height, width, sigma_s, sigma_r, N, stack_dtype);
+    if (st != BF_OK) return st;
+    if (height == 0 || width == 0) return BF_OK;
+    if (!f || !out) return fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    const size_t img = ((size_t)(height - 1) * ld + width) * sizeof(float);
+    if (overlaps(f, img, out, img)) return fail(BF_ERR_INVALID_ARG, "out overlaps f");
+    if ((st = check_conditioning(sigma_r, N, stack_dtype, flags)) != BF_OK) return st;
+    const size_t need = bf_gc_workspace_bytes(height, width, sigma_s, N, stack_dtype, 0);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
+    hipStream_t s = (hipStream_t)stream;
+    switch (stack_dtype) {
+    case BF_STACK_F32: return run_forward<StF32>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    case BF_STACK_F16: return run_forward<StF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    default: return run_forward<StBF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    }
+}
+
+bf_status bf_gc_plane_scales(double sigma_r, int N, int stack_dtype, int *k_out) {
+    if (!finite_pos(sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be positive and finite");
+    if (N < 1 || N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N out of [1, BF_MAX_DEGREE]");
+    if (!k_out) return fail(BF_ERR_INVALID_ARG, "k_out is null");
+    const std::vector<int> k = plane_exponents(fit(sigma_r, N).mu, N, stack_dtype);
+    for (int n = 0; n <= N + 1; ++n) k_out[n] = k[n];
+    return BF_OK;
+}
+
+static bf_status check_stack_args(const void *stack, int height, int width, long long plane_stride, int lds,
+                                  int planes, const void *prm) {
+    if (!stack || !prm) return fail(BF_ERR_INVALID_ARG, "stack and prm must be non-null");
+    if (lds < width) return fail(BF_ERR_INVALID_ARG, "lds must be >= width");
+    if (plane_stride < (long long)height * lds) return fail(BF_ERR_INVALID_ARG, "plane_stride < height * lds");
+    if (planes < 1) return fail(BF_ERR_INVALID_ARG, "planes must be >= 1");
+    return BF_OK;
+}
+
+bf_status bf_gc_stack_build(const float *f, int height, int width, int ld, double sigma_r, int N, int stack_dtype,
+                            void *stack, long long plane_stride, int lds, unsigned *devflag, void *prm,
+                            void *stream) {
+    bf_status st = check_common(height, width, 1.0, sigma_r, N, stack_dtype);
+    if (st != BF_OK) return st;
+    if (height == 0 || width == 0) return BF_OK;
+    if (!f) return fail(BF_ERR_INVALID_ARG, "f must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    if ((st = check_stack_args(stack, height, width, plane_stride, lds, N + 2, prm)) != BF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    ParamLayout L;
+    if ((st = upload_params((double *)prm, devflag, 1.0, sigma_r, N, stack_dtype, s, &L)) != BF_OK) return st;
+    const double mu = fit(sigma_r, N).mu;
+    switch (stack_dtype) {
+    case BF_STACK_F32: return launch_build<StF32>(f, height, width, ld, stack, plane_stride, lds, N + 2, (double *)prm, L, mu, devflag, s);
+    case BF_STACK_F16: return launch_build<StF16>(f, height, width, ld, stack, plane_stride, lds, N + 2, (double *)prm, L, mu, devflag, s);
+    default: return launch_build<StBF16>(f, height, width, ld, stack, plane_stride, lds, N + 2, (double *)prm, L, mu, devflag, s);
+    }
+}
+
+bf_status bf_gc_gauss_planes(void *stack, void *tmp, int planes, int height, int width, long long plane_stride,
+                             int lds, double sigma_s, int stack_dtype, void *prm, void *stream) {
+    bf_status st = check_common(height, width, sigma_s, 30.0, 1, stack_dtype);
+    if (st != BF_OK) return st;
+    if (height == 0 || width == 0) return BF_OK;
+    if ((st = check_stack_args(stack, height, width, plane_stride, lds, planes, prm)) != BF_OK) return st;
+    if (!tmp) return fail(BF_ERR_INVALID_ARG, "tmp must be non-null");
+    hipStream_t s = (hipStream_t)stream;
+    ParamLayout L;
+    if ((st = upload_params((double *)prm, nullptr, sigma_s, 30.0, 1, stack_dtype, s, &L)) != BF_OK) return st;
+    switch (stack_dtype) {
+    case BF_STACK_F32: return launch_gauss<StF32>(stack, tmp, planes, height, width, plane_stride, lds, (double *)prm, L, s);
+    case BF_STACK_F16: return launch_gauss<StF16>(stack, tmp, planes, height, width, plane_stride, lds, (double *)prm, L, s);
+    default: return launch_gauss<StBF16>(stack, tmp, planes, height, width, plane_stride, lds, (double *)prm, L, s);
+    }
+}
+
+bf_status bf_gc_combine(const float *f, const void *stack, int height, int width, int ld, long long plane_stride,
+                        int lds, double sigma_r, int N, int stack_dtype, float *out, float *P_out, float *Q_out,
+                        void *prm, void *stream) {
+    bf_status st = check_common(height, width, 1.0, sigma_r, N, stack_dtype);
+    if (st != BF_OK) return st;
+    if (height == 0 || width == 0) return BF_OK;
+    if (!f || !out) return fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    if ((st = check_stack_args(stack, height, width, plane_stride, lds, N + 2, prm)) != BF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    ParamLayout L;
+    if ((st = upload_params((double *)prm, nullptr, 1.0, sigma_r, N, stack_dtype, s, &L)) != BF_OK) return st;
+    switch (stack_dtype) {
+    case BF_STACK_F32: return launch_combine<StF32>(f, stack, height, width, ld, plane_stride, lds, (double *)prm, L, out, P_out, Q_out, s);
+    case BF_STACK_F16: return launch_combine<StF16>(f, stack, height, width, ld, plane_stride, lds, (double *)prm, L, out, P_out, Q_out, s);
+    default: return launch_combine<StBF16>(f, stack, height, width, ld, plane_stride, lds, (double *)prm, L, out, P_out, Q_out, s);
+    }
+}
+
+bf_status bf_gc_read_flags(const void *ws, unsigned *flags_out, void *stream) {
+    if (!ws || !flags_out) return fail(BF_ERR_INVALID_ARG, "ws and flags_out must be non-null");
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemcpy(flags_out, ws, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("bf_gc_read_flags: ") + hipGetErrorString(e));
+    return BF_OK;
+}
+
+bf_status bf_profile_start(void) {
+    std::lock_guard<std::mutex> lock(g_prof_mtx);
+    g_prof_stats.clear();
+    g_prof_on = true;
+    return BF_OK;
+}
+
+bf_status bf_profile_stop(void *stream) {
+    (void)stream;
+    std::vector<ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lock(g_prof_mtx);
+        g_prof_on = false;
+        recs.swap(g_prof_recs);
+    }
+    bf_status st = BF_OK;
+    std::vector<ProfStat> stats;
+    for (const ProfRec &r : recs) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) {
+            st = fail(BF_ERR_DEVICE, std::string("bf_profile_stop: ") + hipGetErrorString(e));
+            continue;
+        }
+        bool found = false;
+        for (ProfStat &p : stats)
+            if (p.name == r.name) {
+                p.count += 1;
+                p.total_ms += ms;
+                found = true;
+            }
+        if (!found) stats.push_back({r.name, 1, (double)ms});
+    }
+    std::lock_guard<std::mutex> lock(g_prof_mtx);
+    for (const ProfRec &r : recs) {
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_stats = stats;
+    return st;
+}
+
+int bf_profile_count(void) {
+    std::lock_guard<std::mutex> lock(g_prof_mtx);
+    return (int)g_prof_stats.size();
+}
+
+bf_status bf_profile_entry(int i, char *name, int name_len, long long *count, double *total_ms) {
+    std::lock_guard<std::mutex> lock(g_prof_mtx);
+    if (i < 0 || i >= (int)g_prof_stats.size() || !name || name_len < 1 || !count || !total_ms)
+        return fail(BF_ERR_INVALID_ARG, "bf_profile_entry: bad index or null output");
+    snprintf(name, name_len, "%s", g_prof_stats[i].name.c_str());
+    *count = g_prof_stats[i].count;
+    *total_ms = g_prof_stats[i].total_ms;
+    return BF_OK;
+}
+
+const char *bf_status_string(int status) {
+    switch (status) {
+    case BF_OK: return "BF_OK";
+    case BF_ERR_INVALID_ARG: return "BF_ERR_INVALID_ARG";
+    case BF_ERR_UNSUPPORTED: return "BF_ERR_UNSUPPORTED";
+    case BF_ERR_ILL_CONDITIONED: return "BF_ERR_ILL_CONDITIONED";
+    case BF_ERR_WORKSPACE: return "BF_ERR_WORKSPACE";
+    case BF_ERR_DEVICE: return "BF_ERR_DEVICE";
+    default: return "BF_UNKNOWN_STATUS";
+    }
+}
+
+const char *bf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,178 @@
+// Host planning: coefficient fit (Section III), taps (Section I), plane
+// scales and the parameter block. Pure C++, no HIP.
+#include "plan.hpp"
+
+#include <quadmath.h>
+
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
+
+namespace bfgc {
+
+int radius_of(double sigma_s) { return (int)std::ceil(3.0 * sigma_s - 1e-12); }
+
+// Modified Bessel function of the first kind, I_nu(x) for integer nu >= 0 and
+// x >= 0, by its power series sum_k (x/2)^{2k+nu} / (k! (k+nu)!). All terms
+// are positive, so the sum carries no cancellation.
+static long double bessel_i(int nu, long double x) {
+    if (x == 0.0L) return nu == 0 ? 1.0L : 0.0L;
+    const long double h = 0.5L * x;
+    long double term = std::exp((long double)nu * std::log(h) - std::lgamma((long double)nu + 1.0L));
+    long double sum = term;
+    for (int k = 1; k < 100000; ++k) {
+        term *= h * h / ((long double)k * (long double)(k + nu));
+        sum += term;
+        if (term < 1e-22L * sum && k > h) break;
+    }
+    return sum;
+}
+
+int degree_rule(double sigma_r, int max_degree) {
+    if (!(sigma_r > 0.0) || !std::isfinite(sigma_r)) return -1;
+    const long double mu30 = (long double)kTh * kTh / (30.0L * 30.0L);
+    const long double eps0 = std::sqrt(2.0L * bessel_i(28, mu30) * 2.0L * bessel_i(29, mu30));
+    const long double mu = (long double)kTh * kTh / ((long double)sigma_r * sigma_r);
+    for (int N = 1; N <= max_degree; ++N)
+        if (2.0L * bessel_i(N + 1, mu) <= eps0) return N;
+    return -1;
+}
+
+// The fit of exp(mu y), y in [-1, 1], at the N+1 zeros of T_{N+1}:
+//   xi_k = cos(pi (2k-1) / (2(N+1))),  k = 1..N+1
+//   d_0 = 1/(N+1) sum_k e^{mu xi_k},  d_l = 2/(N+1) sum_k e^{mu xi_k} T_l(xi_k)
+// (eq. 16 in its rescaled form), T_l(xi_k) = cos(l theta_k) (eq. 11); then the
+// monomial coefficients of T_l from T_{l+1} = 2x T_l - T_{l-1} (eqs. 12-13) and
+// b_n = sum_{l >= n} d_l a_{l,n} (eq. 19 with mu^n folded into y = x/mu).
+// The last sum cancels heavily (its terms reach I_0(mu) 2^{N-1} while b_n can
+// be tiny), so the fit runs in binary128 and is rounded to double at the end.
+static Fit compute_fit(double sigma_r, int N) {
+    typedef __float128 qd;
+    Fit F;
+    const qd mu = (qd)kTh * (qd)kTh / ((qd)sigma_r * (qd)sigma_r);
+    F.mu = (double)mu;
+    const int K = N + 1;
+    std::vector<qd> theta(K), e(K);
+    for (int k = 1; k <= K; ++k) {
+        theta[k - 1] = M_PIq * (qd)(2 * k - 1) / (qd)(2 * K);
+        e[k - 1] = expq(mu * cosq(theta[k - 1]));
+    }
+    std::vector<qd> d(K);
+    for (int l = 0; l <= N; ++l) {
+        qd s = 0;
+        for (int k = 0; k < K; ++k) s += e[k] * cosq((qd)l * theta[k]);
+        d[l] = (l == 0 ? (qd)1 : (qd)2) * s / (qd)K;
+    }
+    // a[l][n] row by row; three rows are enough to accumulate b_n.
+    std::vector<qd> bq(K, (qd)0), am1(K, (qd)0), a0(K, (qd)0), ap1(K, (qd)0);
+    a0[0] = 1;                                     // T_0 = 1
+    for (int n = 0; n < K; ++n) bq[n] += d[0] * a0[n];
+    if (N >= 1) {
+        am1 = a0;
+        std::fill(a0.begin(), a0.end(), (qd)0);
+        a0[1] = 1;                                 // T_1 = x
+        for (int n = 0; n < K; ++n) bq[n] += d[1] * a0[n];
+        for (int l = 1; l < N; ++l) {              // T_{l+1} = 2x T_l - T_{l-1}
+            for (int n = 0; n < K; ++n) ap1[n] = (n >= 1 ? 2 * a0[n - 1] : (qd)0) - am1[n];
+            for (int n = 0; n < K; ++n) bq[n] += d[l + 1] * ap1[n];
+            am1.swap(a0);
+            a0.swap(ap1);
+        }
+    }
+    F.b.resize(K);
+    for (int n = 0; n < K; ++n) F.b[n] = (double)bq[n];
+
+    // Conditioning of the double coefficients the kernels use, on a grid of y.
+    typedef long double ld;
+    std::vector<ld> b(K);
+    for (int n = 0; n < K; ++n) b[n] = F.b[n];
+    const ld mul = (ld)F.mu;
+    // Conditioning on a grid of y (with its endpoints and 0).
+    const int M = 4000;
+    ld kerr = 0.0L, kap = 0.0L;
+    for (int m = 0; m <= M; ++m) {
+        const ld y = -1.0L + 2.0L * m / M;
+        ld p = 0.0L, q = 0.0L;
+        const ld ay = std::fabs(y);
+        for (int n = N; n >= 0; --n) {
+            p = p * y + b[n];
+            q = q * ay + std::fabs(b[n]);
+        }
+        const ld wgt = std::exp(-mul * ay);
+        const ld err = wgt * std::fabs(p - std::exp(mul * y));
+        if (err > kerr) kerr = err;
+        if (wgt * q > kap) kap = wgt * q;
+    }
+    F.kernel_err = (double)kerr;
+    F.kappa = (double)kap;
+    return F;
+}
+
+const Fit &fit(double sigma_r, int N) {
+    static std::mutex mtx;
+    static std::map<std::pair<double, int>, Fit> cache;
+    std::lock_guard<std::mutex> lock(mtx);
+    auto key = std::make_pair(sigma_r, N);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    return cache.emplace(key, compute_fit(sigma_r, N)).first->second;
+}
+
+std::vector<double> spatial_taps(double sigma_s) {
+    const int W = radius_of(sigma_s);
+    std::vector<long double> w(2 * W + 1);
+    long double sum = 0.0L;
+    for (int k = -W; k <= W; ++k) {
+        w[k + W] = std::exp(-(long double)k * k / (2.0L * sigma_s * sigma_s));
+        sum += w[k + W];
+    }
+    std::vector<double> out(2 * W + 1);
+    for (int i = 0; i < 2 * W + 1; ++i) out[i] = (double)(w[i] / sum);
+    return out;
+}
+
+std::vector<int> plane_exponents(double mu, int N, int stack_dtype) {
+    std::vector<int> k(N + 2, 0);
+    if (stack_dtype != 1) return k;                 // FP16 only
+    for (int n = 0; n <= N + 1; ++n) {
+        double lg;                                   // log2 of the plane's largest |value|
+        if (n == 0) lg = 0.0;
+        else if (n <= mu) lg = 0.5 * n * std::log2(n / (M_E * mu));
+        else lg = -0.5 * mu / M_LN2;
+        int kn = (int)std::floor(14.0 - lg);
+        if (kn < 0) kn = 0;
+        if (kn > 120) kn = 120;
+        k[n] = kn;
+    }
+    return k;
+}
+
+ParamLayout param_layout(int W, int N) {
+    ParamLayout L;
+    L.W = W;
+    L.N = N;
+    L.off_taps = 0;
+    L.n_taps = 2 * W + 1 + 2 * (kTapPad - 1);
+    L.off_cq = L.off_taps + ((L.n_taps + 7) & ~7);
+    L.off_cp = L.off_cq + ((N + 1 + 7) & ~7);
+    L.off_scale = L.off_cp + ((N + 1 + 7) & ~7);
+    L.total = L.off_scale + ((N + 2 + 7) & ~7);
+    return L;
+}
+
+void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack_dtype,
+                 std::vector<double> &out) {
+    out.assign(L.total, 0.0);
+    const std::vector<double> w = spatial_taps(sigma_s);
+    for (int t = 0; t <= 2 * L.W; ++t) out[L.off_taps + t + (kTapPad - 1)] = w[t];
+    const Fit &F = fit(sigma_r, L.N);
+    const std::vector<int> k = plane_exponents(F.mu, L.N, stack_dtype);
+    for (int n = 0; n <= L.N; ++n) {
+        out[L.off_cq + n] = std::ldexp(F.b[n], -k[n]);
+        out[L.off_cp + n] = std::ldexp(F.b[n], -k[n + 1]);
+    }
+    for (int n = 0; n <= L.N + 1; ++n) out[L.off_scale + n] = std::ldexp(1.0, k[n]);
+}
+
+}  // namespace bfgc

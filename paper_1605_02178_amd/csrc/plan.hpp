@@ -1,0 +1,61 @@
+// Host-side planning for the Gauss-Chebyshev bilateral filter: radius and
+// spatial taps, the Chebyshev coefficient fit, conditioning figures, FP16
+// plane scales, and the parameter block the kernels read.
+#pragma once
+
+#include <cstddef>
+#include <vector>
+
+namespace bfgc {
+
+// Intensity range of an 8-bit image, [L, U] = [0, 255] (Section II); the
+// centring of eq. (17) uses t_c = (L + U)/2 and the half range t_h = (U - L)/2.
+constexpr double kTc = 127.5;
+constexpr double kTh = 127.5;
+
+// Largest register block the kernels use; the padded tap array carries this
+// many zeros minus one on each side.
+constexpr int kTapPad = 16;
+
+// W = 3 sigma_s (Section I), rounded up for non-integer sigma_s.
+int radius_of(double sigma_s);
+
+// Degree rule (see bf_gc_degree_rule in bfgc.h). -1 if none <= max_degree.
+int degree_rule(double sigma_r, int max_degree);
+
+struct Fit {
+    double mu = 0.0;              // t_h^2 / sigma_r^2
+    std::vector<double> b;        // b_n = c_n mu^n, n = 0..N
+    double kernel_err = 0.0;      // max_y e^{-mu|y|} |p(mu y) - e^{mu y}|
+    double kappa = 0.0;           // max_y e^{-mu|y|} sum |b_n| |y|^n
+};
+
+// Chebyshev fit of exp(mu y) at the zeros of T_{N+1} (Section III), in the
+// monomial basis. Cached per (sigma_r, N); thread safe.
+const Fit &fit(double sigma_r, int N);
+
+// Normalised spatial taps exp(-k^2/2 sigma_s^2) / sum, k = -W..W.
+std::vector<double> spatial_taps(double sigma_s);
+
+// Power-of-two exponents k_n, n = 0..N+1: plane n is stored as 2^k_n H_n.
+// Non-zero only for FP16, where they keep every plane's largest value near
+// 2^14 (max over |s| <= 1 of e^{-mu s^2/2}|s|^n is (n/(e mu))^{n/2} for
+// n <= mu, else e^{-mu/2}).
+std::vector<int> plane_exponents(double mu, int N, int stack_dtype);
+
+// Parameter block layout (all doubles) in device memory.
+struct ParamLayout {
+    int W = 0, N = 0;
+    int off_taps = 0, n_taps = 0;   // taps padded: index u <-> tap t = u - (kTapPad-1) - W, zero outside |t| <= W
+    int off_cq = 0;                 // cq_n = b_n 2^-k_n        (weight of Hbar_n in Q), n = 0..N
+    int off_cp = 0;                 // cp_n = b_n 2^-k_{n+1}    (weight of Hbar_{n+1} in P), n = 0..N
+    int off_scale = 0;              // 2^k_n, n = 0..N+1
+    int total = 0;                  // doubles
+};
+ParamLayout param_layout(int W, int N);
+
+// Fills `out` (layout.total doubles).
+void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack_dtype,
+                 std::vector<double> &out);
+
+}  // namespace bfgc

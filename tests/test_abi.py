@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point the header declares, its planner agrees with the oracle, and
+argument errors come back as status codes before anything touches a device."""
+import ctypes
+import math
+import os
+import re
+
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import coeffs as K
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfgc.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1605_02178_amd import _lib
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bf_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1605_02178_amd._lib import SIGNATURES
+    assert set(SIGNATURES) == set(names)
+
+
+def test_degree_rule_matches_oracle(lib):
+    for sr in (10.0, 15.0, 20.0, 25.0, 29.8, 30.0, 30.2, 40.0, 50.0, 60.0, 120.0):
+        assert lib.bf_gc_degree_rule(sr) == K.degree_rule(sr), sr
+    assert lib.bf_gc_degree_rule(-1.0) == -1
+    assert lib.bf_gc_degree_rule(float("nan")) == -1
+
+
+@pytest.mark.parametrize("sigma_r,N", [(30.0, 28), (30.0, 10), (40.0, 16), (50.0, 11), (25.0, 40), (20.0, 62)])
+def test_planner_coefficients_match_oracle_at_kernel_level(sigma_r, N):
+    """The monomial coefficients are ill-conditioned individually; what the
+    filter uses is the polynomial, so compare exp(-mu|y|) p(mu y) over y."""
+    import paper_1605_02178_amd as bf
+    b, mu = bf.coefficients(sigma_r, N)
+    c, _ = K.gcf_coefficients(sigma_r, N)
+    assert mu == pytest.approx(K.gcf_params(sigma_r)[1], rel=1e-15)
+    with mpmath.workdps(50):
+        worst = 0.0
+        for y in np.linspace(-1, 1, 401):
+            pb = mpmath.fsum(mpmath.mpf(v) * mpmath.mpf(y) ** n for n, v in enumerate(b))
+            pc = mpmath.fsum(mpmath.mpf(v) * (mu * mpmath.mpf(y)) ** n for n, v in enumerate(c))
+            worst = max(worst, float(abs(pb - pc) * mpmath.exp(-mu * abs(y))))
+    assert worst < 1e-11, worst
+
+
+def test_query_values(lib):
+    import paper_1605_02178_amd as bf
+    err, kappa = bf.query(30.0, 28)
+    assert 4e-3 < err < 9e-3          # weighted kernel error at the paper's operating point
+    assert 5 < kappa < 40
+    e2, _ = bf.query(30.0, 34)
+    assert e2 < err / 100
+
+
+def test_plane_scales():
+    import paper_1605_02178_amd as bf
+    assert bf.plane_scales(30.0, 28, "f32") == [0] * 30
+    k = bf.plane_scales(30.0, 28, "f16")
+    mu = K.gcf_params(30.0)[1]
+    for n, kn in enumerate(k):
+        m = 1.0 if n == 0 else ((n / (math.e * mu)) ** (n / 2) if n <= mu else math.exp(-mu / 2))
+        assert 2 ** 13 <= m * 2 ** kn <= 2 ** 15
+
+
+def test_workspace_bytes():
+    import paper_1605_02178_amd as bf
+    a = bf.workspace_bytes(4096, 4096, 10.0, 28, "f32")
+    b = bf.workspace_bytes(4096, 4096, 10.0, 28, "f16")
+    assert a >= 2 * 30 * 4096 * 4096 * 4
+    assert b < a * 0.6
+    assert bf.workspace_bytes(10, 10, -1.0, 28) == 0
+    assert bf.workspace_bytes(10, 10, 1000.0, 28) == 0
+
+
+def _fwd(lib, f=1 << 20, out=1 << 24, H=8, Wd=8, ld=8, ss=2.0, sr=30.0, N=28, dt=0, flags=0, ws=256 * 1024, wsb=1 << 30):
+    return lib.bf_gc_forward(ctypes.c_void_p(f), ctypes.c_void_p(out), H, Wd, ld, ss, sr, N, dt, flags,
+                             ctypes.c_void_p(ws), wsb, None)
+
+
+def test_forward_argument_errors_need_no_device(lib):
+    big = 1 << 40
+    assert _fwd(lib, f=0) == 1                       # null f
+    assert _fwd(lib, H=-1) == 1
+    assert _fwd(lib, ld=4) == 1                      # ld < width
+    assert _fwd(lib, ss=0.0) == 1
+    assert _fwd(lib, sr=float("inf")) == 1
+    assert _fwd(lib, N=0) == 1 and _fwd(lib, N=400) == 1
+    assert _fwd(lib, dt=7) == 1
+    assert _fwd(lib, f=big, out=big + 16) == 1      # out overlaps f
+    assert _fwd(lib, ss=40.0) == 2                   # W = 120 > BF_MAX_RADIUS
+    assert _fwd(lib, sr=12.0, N=170) == 3            # ill-conditioned in FP32
+    assert _fwd(lib, sr=30.0, N=28, dt=2) == 3       # BF16 at sigma_r = 30
+    assert _fwd(lib, ws=0) == 4
+    assert _fwd(lib, wsb=100) == 4
+    assert _fwd(lib, ws=256 * 1024 + 8) == 4         # misaligned
+    assert _fwd(lib, H=0, f=0, out=0) == 0           # empty image: nothing to do
+    assert lib.bf_status_string(3) == b"BF_ERR_ILL_CONDITIONED"
+    _fwd(lib, ss=-1.0)
+    assert b"sigma_s" in lib.bf_last_error()
+
+
+def test_stage_argument_errors(lib):
+    vp = ctypes.c_void_p
+    assert lib.bf_gc_stack_build(vp(1), 8, 8, 8, 30.0, 28, 0, vp(0), 64 * 8, 64, vp(0), vp(1), None) == 1
+    assert lib.bf_gc_gauss_planes(vp(1), vp(0), 30, 8, 8, 64 * 8, 64, 2.0, 0, vp(1), None) == 1
+    assert lib.bf_gc_combine(vp(1), vp(1), 8, 8, 8, 8 * 8, 4, 30.0, 28, 0, vp(1), vp(0), vp(0), vp(1), None) == 1
