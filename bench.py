@@ -57,6 +57,36 @@ def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch):
     return None
 
 
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in ("paper_1605_02178_amd/csrc/bfgc.hip", "paper_1605_02178_amd/csrc/kernels.hpp"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, stack_tag, profile_name):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
+    copy of known size), or None when that summary is missing or was taken on
+    a different kernel source."""
+    path = os.path.join(ROOT, "profiles", profile_name + "_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256_16") != source_hash():
+        return None
+    base = {"k_hpass_combine": "k_hpass<", "k_hpass": "k_hpass<", "k_vpass": "k_vpass<",
+            "k_stack_build": "k_stack_build<", "k_combine": "k_combine<"}[kernel]
+    for name, v in rec["kernels"].items():
+        if name.startswith(base + stack_tag) and (kernel != "k_hpass_combine" or name.endswith("true>")) \
+                and (kernel != "k_hpass" or name.endswith("false>")):
+            return v["bytes"]
+    return None
+
+
 def profile_read(lib):
     import ctypes
     out = {}
@@ -117,7 +147,9 @@ def main():
     ap.add_argument("--degree", type=int, default=28)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-stack comparison")
-    ap.add_argument("--cpu-rows", type=int, default=4096)
+    ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding is design-only, "
@@ -140,6 +172,14 @@ def main():
     out = torch.empty_like(f)
     ws = torch.empty(bf.workspace_bytes(H, Wd, ss, N, "f32"), dtype=torch.uint8, device="cuda:0")
 
+    if args.copy_mib:
+        a = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log(f"bench: calibration copy of {args.copy_mib} MiB done")
+
     log(f"bench: FP32 stack, {args.warmup} warmup + {args.steps} timed steps")
     ms, prof = time_forward(bf, f, out, ws, ss, sr, N, "f32", args.steps, args.warmup)
     value = H * Wd / 1e6 / (ms / 1e3)
@@ -148,7 +188,8 @@ def main():
     roof = kernel_roofline(dom, H, Wd, W, P, 4, kernels[dom]["avg_ms"])
     roof = {"kernel": dom, **roof}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, "StF32", f"forward_{H}_s{ss:g}_n{N}_f32")
+    roof["traffic_source"] = f"profiles/forward_{H}_s{ss:g}_n{N}_f32.md"
     roof["avg_ms"] = kernels[dom]["avg_ms"]
     log(f"bench: FP32 {ms:.3f} ms/step, {value:.1f} Mpx/s; kernels {kernels}")
 

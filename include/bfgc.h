@@ -101,8 +101,8 @@ bf_status bf_gc_query(double sigma_r, int N, int stack_dtype, double *kernel_err
 /*
  * Workspace bytes needed by bf_gc_forward (for_backward = 0) or
  * bf_gc_backward (for_backward = 1) for one height x width image. Includes
- * the parameter block, the device flag word and N+2 stack planes (twice that
- * with BF_FLAG_STAGED or for the backward). Returns 0 for invalid arguments.
+ * the parameter block, the device flag word, N+2 stack planes and N+2
+ * transposed column-filtered planes. Returns 0 for invalid arguments.
  */
 size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype,
                              int for_backward);
@@ -130,15 +130,18 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
  * Stages of the forward filter, for callers that want the stack itself. These
  * are the kernels bf_gc_forward runs with BF_FLAG_STAGED. The stack is N+2
  * planes of height x width, plane stride `plane_stride` and row stride `lds`
- * elements, element type per stack_dtype; plane n holds 2^k_n H_n (k_n = 0
- * except for FP16, see bf_gc_plane_scales).
+ * elements (both multiples of 16, lds >= width, stack 16-byte aligned),
+ * element type per stack_dtype; plane n holds 2^k_n H_n (k_n = 0 except for
+ * FP16, see bf_gc_plane_scales).
  *
  * bf_gc_stack_build: H_n = exp(-mu s^2/2) s^n, n = 0..N+1 (eq. 6 scaled,
  *   centring eq. 17). Sets the range flag in *devflag (device unsigned, may
  *   be NULL).
  * bf_gc_gauss_planes: Hbar_n = G H_n for every plane (eq. 7, separable,
- *   taps normalised to sum 1), in place; tmp is a second stack of the same
- *   layout used between the row and the column pass.
+ *   taps normalised to sum 1), in place. tmp is device scratch of at least
+ *   bf_gc_gauss_tmp_bytes(planes, height, width, stack_dtype) bytes, 16-byte
+ *   aligned; it holds the column-filtered planes transposed between the two
+ *   passes, and its contents afterwards are unspecified.
  * bf_gc_combine: y = t_c + t_h P/Q from the filtered planes (eqs. 8-10);
  *   P_out and Q_out (device FP32 height x width with row stride ld, may be
  *   NULL) receive the scaled P' = sum b_n s^n Hbar_{n+1} and
@@ -152,7 +155,8 @@ bf_status bf_gc_plane_scales(double sigma_r, int N, int stack_dtype, int *k_out)
 bf_status bf_gc_stack_build(const float *f, int height, int width, int ld, double sigma_r, int N,
                             int stack_dtype, void *stack, long long plane_stride, int lds,
                             unsigned *devflag, void *prm, void *stream);
-bf_status bf_gc_gauss_planes(void *stack, void *tmp, int planes, int height, int width,
+size_t bf_gc_gauss_tmp_bytes(int planes, int height, int width, int stack_dtype);
+bf_status bf_gc_gauss_planes(void *stack, void *tmp, size_t tmp_bytes, int planes, int height, int width,
                              long long plane_stride, int lds, double sigma_s, int stack_dtype,
                              void *prm, void *stream);
 bf_status bf_gc_combine(const float *f, const void *stack, int height, int width, int ld,

@@ -165,15 +165,20 @@ def stack_build(f, sigma_r, N, stack_dtype="f32", stack: StackLayout | None = No
     return stack
 
 
-def gauss_planes(stack: StackLayout, sigma_s, tmp: StackLayout | None = None, prm=None, stream=None):
+def gauss_planes(stack: StackLayout, sigma_s, tmp=None, prm=None, stream=None):
+    """Filters every plane of `stack` in place (eq. 7). `tmp`: optional uint8
+    device scratch of at least bf_gc_gauss_tmp_bytes bytes."""
     import torch
-    tmp = tmp or StackLayout(stack.height, stack.width, stack.N, stack.code, stack.data.device)
+    lib = _lib.load()
+    need = int(lib.bf_gc_gauss_tmp_bytes(stack.planes, stack.height, stack.width, stack.code))
+    if tmp is None:
+        tmp = torch.empty(max(need, 16), dtype=torch.uint8, device=stack.data.device)
     prm = prm if prm is not None else torch.empty(param_bytes(sigma_s, 1) + 8 * 64, dtype=torch.uint8,
                                                   device=stack.data.device)
-    st = _lib.load().bf_gc_gauss_planes(ctypes.c_void_p(stack.data.data_ptr()), ctypes.c_void_p(tmp.data.data_ptr()),
-                                        stack.planes, stack.height, stack.width, stack.plane_stride, stack.lds,
-                                        float(sigma_s), stack.code, ctypes.c_void_p(prm.data_ptr()),
-                                        _stream_ptr(stream))
+    st = lib.bf_gc_gauss_planes(ctypes.c_void_p(stack.data.data_ptr()), ctypes.c_void_p(tmp.data_ptr()),
+                                tmp.numel() * tmp.element_size(), stack.planes, stack.height, stack.width,
+                                stack.plane_stride, stack.lds, float(sigma_s), stack.code,
+                                ctypes.c_void_p(prm.data_ptr()), _stream_ptr(stream))
     _lib.check(st, "bf_gc_gauss_planes")
     stack._tmp, stack._prm2 = tmp, prm
     return stack

@@ -27,8 +27,9 @@ SIGNATURES = {
     "bf_gc_plane_scales": (_c_int, [_c_double, _c_int, _c_int, _ip]),
     "bf_gc_stack_build": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_double, _c_int, _c_int, _vp, _c_ll,
                                    _c_int, _vp, _vp, _vp]),
-    "bf_gc_gauss_planes": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _c_ll, _c_int, _c_double, _c_int,
-                                    _vp, _vp]),
+    "bf_gc_gauss_tmp_bytes": (_c_size_t, [_c_int, _c_int, _c_int, _c_int]),
+    "bf_gc_gauss_planes": (_c_int, [_vp, _vp, _c_size_t, _c_int, _c_int, _c_int, _c_ll, _c_int, _c_double,
+                                    _c_int, _vp, _vp]),
     "bf_gc_combine": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _c_ll, _c_int, _c_double, _c_int, _c_int,
                                _vp, _vp, _vp, _vp, _vp]),
     "bf_gc_read_flags": (_c_int, [_vp, _up, _vp]),

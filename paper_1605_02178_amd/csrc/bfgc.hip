@@ -59,120 +59,185 @@ __global__ __launch_bounds__(256) void k_stack_build(const float *__restrict__ f
     }
 }
 
-// Column pass: lane = column, each wave R consecutive output rows, one plane
-// per blockIdx.z. Each input row j of the window [r0-W, r0+R+W) is read once
-// (coalesced across the wave) and multiplied into the R accumulators it
-// touches; taps outside |k| <= W are zeros of the padded tap array.
+// One line of the separable Gaussian (eq. 7) for R consecutive outputs of a
+// lane. The line has `len` elements; element p sits at base[p * stride], with
+// p taken through the symmetric extension. Output o (o0 <= o < o0+R) is
+// sum_{t=0}^{2W} w[t] x[o - W + t], w[t] the normalised tap of offset t - W.
+// Input-stationary: each input position is loaded once (U loads in flight at a
+// time) and FMA'd in FP64 into every output it reaches; the head and tail of
+// the window touch only the outputs inside the band, so no zero tap is
+// multiplied. `w` points at tap t = 0 inside the zero-padded tap array.
+template <class S, int R, int U>
+__device__ __forceinline__ void conv_line(const typename S::T *__restrict__ plane, int laneoff, long long stride,
+                                          int o0, int len, int W, const double *__restrict__ w, double (&acc)[R]) {
+    // o0, len, W, stride and plane are wave-uniform: the line position p and
+    // the row pointer stay in scalar registers, each load is a uniform base
+    // plus the lane's own offset.
+    const int p0 = o0 - W;
+    const bool interior = p0 >= 0 && o0 + R + W <= len;
+    auto ld = [&](int i) -> double {
+        const int p = interior ? p0 + i : mirror(p0 + i, len);
+        const typename S::T *row = plane + (long long)p * stride;
+        return (double)S::dec(row[laneoff]);
+    };
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    const int T = 2 * W;
+    if (T + 1 >= R) {
+        // head: inputs 0..R-2 reach outputs r <= i
+        double xh[R - 1];
+#pragma unroll
+        for (int i = 0; i < R - 1; ++i) xh[i] = ld(i);
+        // middle: inputs R-1..T reach every output; chunks of U, the next
+        // chunk's loads issued before the current chunk's FMAs
+        const int nM = (T - R + 2 + U - 1) / U;
+        double xa[U], xb[U];
+        auto ldchunk = [&](double (&x)[U], int k) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int i = R - 1 + k * U + u;
+                x[u] = ld(i <= T ? i : T);
+            }
+        };
+        auto fmachunk = [&](const double (&x)[U], int k) {
+            const int i0 = R - 1 + k * U;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (i0 + u <= T) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] = fma(w[i0 + u - r], x[u], acc[r]);
+                }
+        };
+        ldchunk(xa, 0);
+#pragma unroll
+        for (int i = 0; i < R - 1; ++i)
+#pragma unroll
+            for (int r = 0; r <= i; ++r) acc[r] = fma(w[i - r], xh[i], acc[r]);
+        // tail inputs T+1..T+R-1 go into xh once the last middle chunk's
+        // loads are out
+        auto ldtail = [&]() {
+#pragma unroll
+            for (int u = 0; u < R - 1; ++u) xh[u] = ld(T + 1 + u);
+        };
+        if (nM == 1) ldtail();
+        int k = 0;
+        for (; k + 1 < nM; k += 2) {
+            ldchunk(xb, k + 1);
+            if (k + 2 == nM) ldtail();
+            fmachunk(xa, k);
+            if (k + 2 < nM) {
+                ldchunk(xa, k + 2);
+                if (k + 3 == nM) ldtail();
+            }
+            fmachunk(xb, k + 1);
+        }
+        if (k < nM) fmachunk(xa, k);
+#pragma unroll
+        for (int u = 0; u < R - 1; ++u)
+#pragma unroll
+            for (int r = u + 1; r < R; ++r) acc[r] = fma(w[T + 1 + u - r], xh[u], acc[r]);
+    } else {
+        // 2W+1 < R: every input against every output; the padding zeros of
+        // the tap array cover offsets outside the band.
+        for (int i = 0; i < R + T; ++i) {
+            const double x = ld(i);
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = fma(w[i - r], x, acc[r]);
+        }
+    }
+}
+
+// Stores R consecutive elements (dst 16-byte aligned when full).
+template <class S, int R>
+__device__ __forceinline__ void store_run(typename S::T *__restrict__ dst, const double (&v)[R], int count) {
+    typedef typename S::T T;
+    if (count >= R && (R * sizeof(T)) % 16 == 0) {
+        T tmp[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) tmp[q] = S::enc(v[q]);
+#pragma unroll
+        for (int q = 0; q < (int)(R * sizeof(T) / 16); ++q)
+            reinterpret_cast<uint4 *>(dst)[q] = reinterpret_cast<const uint4 *>(tmp)[q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q < count) dst[q] = S::enc(v[q]);
+    }
+}
+
+// Column pass: lane = column, each wave R consecutive rows, one plane per
+// blockIdx.z. Output written transposed, [n][col][row] with row stride ldt,
+// so that the row pass reads it with consecutive lanes on consecutive rows.
 template <class S, int R>
 __global__ __launch_bounds__(256) void k_vpass(const typename S::T *__restrict__ in,
-                                                typename S::T *__restrict__ out, int H, int Wd, long long ps,
-                                                int lds, const double *__restrict__ taps, int W) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                typename S::T *__restrict__ outT, int H, int Wd, long long ps,
+                                                int lds, long long pst, int ldt, const double *__restrict__ taps,
+                                                int W) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int c = blockIdx.x * 64 + lane;
     const int r0 = (blockIdx.y * 4 + wave) * R;
     const long long n = blockIdx.z;
     if (r0 >= H) return;
     const int cl = c < Wd ? c : Wd - 1;
-    const typename S::T *src = in + n * ps + cl;
     double acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    const int span = R + 2 * W;
-    for (int j = 0; j < span; ++j) {
-        const int rr = mirror(r0 - W + j, H);
-        const double x = (double)S::dec(src[(long long)rr * lds]);
-        const double *t = taps + j + (kTapPad - 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fma(t[-r], x, acc[r]);
-    }
-    if (c < Wd) {
-        typename S::T *dst = out + n * ps + c;
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (r0 + r < H) dst[(long long)(r0 + r) * lds] = S::enc(acc[r]);
-    }
+    conv_line<S, R, 8>(in + n * ps, cl, lds, r0, H, W, taps + (kTapPad - 1), acc);
+    if (c < Wd) store_run<S, R>(outT + n * pst + (long long)c * ldt + r0, acc, H - r0);
 }
 
-// Row pass over a tile of 64 rows x 4R columns staged in LDS (lane = row,
-// wave w = columns [4R-block + wR, +R)). The LDS row pitch is odd, so the 64
-// lanes of a wave reading one column each hit distinct banks.
-// COMBINE = false: filtered planes go back to a stack.
-// COMBINE = true : the filtered planes are combined as they come out,
-//   Q += cq_n s^n Hbar_n (n <= N),  P += cp_{n-1} s^{n-1} Hbar_n (n >= 1)
-//   y  = t_c + t_h P / Q                                        (eqs. 8-10)
+// Row pass on the transposed planes: lane = row, each wave R consecutive
+// columns. COMBINE = false writes each filtered plane back as [n][row][col].
+// COMBINE = true visits the planes from n = N+1 down to 0 and folds them in by
+// Horner's rule in s,
+//   P <- P s + cp_{n-1} Hbar_n  (n >= 1),   Q <- Q s + cq_n Hbar_n  (n <= N),
+// which leaves P = sum_n cp_n s^n Hbar_{n+1} and Q = sum_n cq_n s^n Hbar_n
+// (eqs. 8-9); then y = t_c + t_h P/Q (eq. 10, centring undone).
 template <class S, int R, bool COMBINE>
-__global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__ in,
+__global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__ inT,
                                                 typename S::T *__restrict__ out_stack,
                                                 const float *__restrict__ f, float *__restrict__ out,
                                                 float *__restrict__ Pout, float *__restrict__ Qout, int H,
-                                                int Wd, int ld, long long ps, int lds, int P, int N,
-                                                const double *__restrict__ taps, const double *__restrict__ cq,
-                                                const double *__restrict__ cp, int W, int pitch) {
-    extern __shared__ float tile[];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int span = 4 * R + 2 * W;
-    int *colidx = (int *)(tile + 64 * pitch);
-    const int c0 = blockIdx.x * (4 * R);
-    const int rbase = blockIdx.y * 64;
-    const int r = rbase + lane;
-    const int cw = c0 + wave * R;
-    for (int i = threadIdx.x; i < span; i += blockDim.x) colidx[i] = mirror(c0 - W + i, Wd);
-
-    double s[R], sp[R], Qa[R], Pa[R];
+                                                int Wd, int ld, long long ps, int lds, long long pst, int ldt,
+                                                int P, int N, const double *__restrict__ taps,
+                                                const double *__restrict__ cq, const double *__restrict__ cp,
+                                                int W) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = blockIdx.x * 64 + lane;
+    const int c0 = (blockIdx.y * 4 + wave) * R;
+    if (c0 >= Wd) return;
+    const int rl = r < H ? r : H - 1;
+    double s[R], Pa[R], Qa[R];
     if (COMBINE) {
-        const int rl = r < H ? r : H - 1;
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            const int cc = cw + q < Wd ? cw + q : Wd - 1;
+            const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
             s[q] = ((double)f[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
-            sp[q] = 1.0;
-            Qa[q] = 0.0;
             Pa[q] = 0.0;
+            Qa[q] = 0.0;
         }
     }
-    __syncthreads();
-    for (int n = 0; n < P; ++n) {
-        const typename S::T *src = in + (long long)n * ps;
-        for (int row = wave; row < 64; row += 4) {
-            const int gr = rbase + row < H ? rbase + row : H - 1;
-            const typename S::T *srow = src + (long long)gr * lds;
-            for (int i = lane; i < span; i += 64) tile[row * pitch + i] = S::dec(srow[colidx[i]]);
-        }
-        __syncthreads();
+    for (int k = 0; k < P; ++k) {
+        const int n = COMBINE ? P - 1 - k : k;
         double acc[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] = 0.0;
-        const float *trow = tile + lane * pitch + wave * R;
-        const int wspan = R + 2 * W;
-        for (int j = 0; j < wspan; ++j) {
-            const double x = (double)trow[j];
-            const double *t = taps + j + (kTapPad - 1);
-#pragma unroll
-            for (int q = 0; q < R; ++q) acc[q] = fma(t[-q], x, acc[q]);
-        }
-        __syncthreads();
+        conv_line<S, R, 8>(inT + (long long)n * pst, rl, ldt, c0, Wd, W, taps + (kTapPad - 1), acc);
         if (COMBINE) {
-            const double cqn = n <= N ? cq[n] : 0.0;
             const double cpn = n >= 1 ? cp[n - 1] : 0.0;
+            const double cqn = n <= N ? cq[n] : 0.0;
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const double spn = n >= 1 ? sp[q] * s[q] : 1.0;   // s^n; sp holds s^{n-1}
-                Pa[q] = fma(cpn * sp[q], acc[q], Pa[q]);
-                Qa[q] = fma(cqn * spn, acc[q], Qa[q]);
-                sp[q] = spn;
+                if (n >= 1) Pa[q] = fma(Pa[q], s[q], cpn * acc[q]);
+                if (n <= N) Qa[q] = fma(Qa[q], s[q], cqn * acc[q]);
             }
         } else if (r < H) {
-            typename S::T *dst = out_stack + (long long)n * ps + (long long)r * lds;
-#pragma unroll
-            for (int q = 0; q < R; ++q)
-                if (cw + q < Wd) dst[cw + q] = S::enc(acc[q]);
+            store_run<S, R>(out_stack + (long long)n * ps + (long long)r * lds + c0, acc, Wd - c0);
         }
     }
     if (COMBINE && r < H) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            if (cw + q < Wd) {
-                const long long o = (long long)r * ld + cw + q;
+            if (c0 + q < Wd) {
+                const long long o = (long long)r * ld + c0 + q;
                 out[o] = (float)(kTc + kTh * (Pa[q] / Qa[q]));
                 if (Pout) Pout[o] = (float)Pa[q];
                 if (Qout) Qout[o] = (float)Qa[q];
@@ -272,8 +337,9 @@ struct ProfScope {
     }
 };
 
-constexpr int kVR = 16;   // rows per wave in k_vpass
-constexpr int kHR = 8;    // columns per thread in k_hpass
+constexpr int kVR = 16;   // rows per lane in k_vpass
+constexpr int kHR = 16;   // columns per lane in k_hpass (staged)
+constexpr int kHRC = 8;   // columns per lane in k_hpass (fused with the combine)
 constexpr size_t kFlagBytes = 256;
 
 static size_t esize(int dtype) { return dtype == BF_STACK_F32 ? 4 : 2; }
@@ -350,41 +416,43 @@ static bf_status launch_build(const float *f, int H, int Wd, int ld, void *stack
     return check_launch("k_stack_build");
 }
 
+static int ldt_of(int height) { return (height + 63) & ~63; }
+
 template <class S>
-static bf_status launch_gauss(void *stack, void *tmp, int planes, int H, int Wd, long long ps, int lds,
-                              const double *prm, const ParamLayout &L, hipStream_t stream) {
+static bf_status launch_vpass(const void *stack, void *tmpT, int planes, int H, int Wd, long long ps, int lds,
+                              long long pst, int ldt, const double *prm, const ParamLayout &L, hipStream_t stream) {
     dim3 gv((Wd + 63) / 64, (H + 4 * kVR - 1) / (4 * kVR), planes);
-    {
     ProfScope prof_("k_vpass", stream);
     hipLaunchKernelGGL((k_vpass<S, kVR>), gv, dim3(256), 0, stream, (const typename S::T *)stack,
-                       (typename S::T *)tmp, H, Wd, ps, lds, prm + L.off_taps, L.W);
-    }
-    bf_status st = check_launch("k_vpass");
+                       (typename S::T *)tmpT, H, Wd, ps, lds, pst, ldt, prm + L.off_taps, L.W);
+    return check_launch("k_vpass");
+}
+
+template <class S>
+static bf_status launch_gauss(void *stack, void *tmpT, int planes, int H, int Wd, long long ps, int lds,
+                              const double *prm, const ParamLayout &L, hipStream_t stream) {
+    const int ldt = ldt_of(H);
+    const long long pst = (long long)Wd * ldt;
+    bf_status st = launch_vpass<S>(stack, tmpT, planes, H, Wd, ps, lds, pst, ldt, prm, L, stream);
     if (st != BF_OK) return st;
-    const int span = 4 * kHR + 2 * L.W;
-    const int pitch = span | 1;
-    const size_t shm = (size_t)64 * pitch * sizeof(float) + (size_t)span * sizeof(int);
-    dim3 gh((Wd + 4 * kHR - 1) / (4 * kHR), (H + 63) / 64);
+    dim3 gh((H + 63) / 64, (Wd + 4 * kHR - 1) / (4 * kHR));
     ProfScope prof_("k_hpass", stream);
-    hipLaunchKernelGGL((k_hpass<S, kHR, false>), gh, dim3(256), shm, stream, (const typename S::T *)tmp,
+    hipLaunchKernelGGL((k_hpass<S, kHR, false>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
                        (typename S::T *)stack, (const float *)nullptr, (float *)nullptr, (float *)nullptr,
-                       (float *)nullptr, H, Wd, 0, ps, lds, planes, 0, prm + L.off_taps, prm + L.off_cq,
-                       prm + L.off_cp, L.W, pitch);
+                       (float *)nullptr, H, Wd, 0, ps, lds, pst, ldt, planes, 0, prm + L.off_taps,
+                       prm + L.off_cq, prm + L.off_cp, L.W);
     return check_launch("k_hpass");
 }
 
 template <class S>
-static bf_status launch_hpass_combine(const void *tmp, const float *f, float *out, float *Pout, float *Qout, int H,
-                                      int Wd, int ld, long long ps, int lds, const double *prm,
+static bf_status launch_hpass_combine(const void *tmpT, const float *f, float *out, float *Pout, float *Qout, int H,
+                                      int Wd, int ld, long long pst, int ldt, const double *prm,
                                       const ParamLayout &L, hipStream_t stream) {
-    const int span = 4 * kHR + 2 * L.W;
-    const int pitch = span | 1;
-    const size_t shm = (size_t)64 * pitch * sizeof(float) + (size_t)span * sizeof(int);
-    dim3 gh((Wd + 4 * kHR - 1) / (4 * kHR), (H + 63) / 64);
+    dim3 gh((H + 63) / 64, (Wd + 4 * kHRC - 1) / (4 * kHRC));
     ProfScope prof_("k_hpass_combine", stream);
-    hipLaunchKernelGGL((k_hpass<S, kHR, true>), gh, dim3(256), shm, stream, (const typename S::T *)tmp,
-                       (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, ps, lds, L.N + 2, L.N,
-                       prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W, pitch);
+    hipLaunchKernelGGL((k_hpass<S, kHRC, true>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
+                       (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, 0LL, 0, pst, ldt, L.N + 2, L.N,
+                       prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W);
     return check_launch("k_hpass(combine)");
 }
 
@@ -418,14 +486,10 @@ static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, 
         if ((st = launch_gauss<S>(stackA, stackB, P, H, Wd, ps, lds, prm, L, stream)) != BF_OK) return st;
         return launch_combine<S>(f, stackA, H, Wd, ld, ps, lds, prm, L, out, nullptr, nullptr, stream);
     }
-    dim3 gv((Wd + 63) / 64, (H + 4 * kVR - 1) / (4 * kVR), P);
-    {
-        ProfScope prof_("k_vpass", stream);
-        hipLaunchKernelGGL((k_vpass<S, kVR>), gv, dim3(256), 0, stream, (const typename S::T *)stackA,
-                           (typename S::T *)stackB, H, Wd, ps, lds, prm + L.off_taps, L.W);
-    }
-    if ((st = check_launch("k_vpass")) != BF_OK) return st;
-    return launch_hpass_combine<S>(stackB, f, out, nullptr, nullptr, H, Wd, ld, ps, lds, prm, L, stream);
+    const int ldt = ldt_of(H);
+    const long long pst = (long long)Wd * ldt;
+    if ((st = launch_vpass<S>(stackA, stackB, P, H, Wd, ps, lds, pst, ldt, prm, L, stream)) != BF_OK) return st;
+    return launch_hpass_combine<S>(stackB, f, out, nullptr, nullptr, H, Wd, ld, pst, ldt, prm, L, stream);
 }
 
 static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
@@ -469,8 +533,9 @@ size_t bf_gc_param_bytes(double sigma_s, int N) {
 size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype, int for_backward) {
     (void)for_backward;
     if (check_common(height, width, sigma_s, 30.0, N, stack_dtype) != BF_OK) return 0;
-    const size_t planes = (size_t)(N + 2) * height * lds_of(width) * esize(stack_dtype);
-    return kFlagBytes + align256(bf_gc_param_bytes(sigma_s, N)) + 2 * align256(planes);
+    const size_t planesA = (size_t)(N + 2) * height * lds_of(width) * esize(stack_dtype);
+    const size_t planesB = (size_t)(N + 2) * width * ldt_of(height) * esize(stack_dtype);
+    return kFlagBytes + align256(bf_gc_param_bytes(sigma_s, N)) + align256(planesA) + align256(planesB);
 }
 
 bf_status bf_gc_forward(const float *f, float *out, int height, int width, int ld, double sigma_s,
@@ -509,6 +574,8 @@ static bf_status check_stack_args(const void *stack, int height, int width, long
     if (lds < width) return fail(BF_ERR_INVALID_ARG, "lds must be >= width");
     if (plane_stride < (long long)height * lds) return fail(BF_ERR_INVALID_ARG, "plane_stride < height * lds");
     if (planes < 1) return fail(BF_ERR_INVALID_ARG, "planes must be >= 1");
+    if ((lds & 15) || (plane_stride & 15) || ((uintptr_t)stack & 15))
+        return fail(BF_ERR_INVALID_ARG, "stack must be 16-byte aligned with lds and plane_stride multiples of 16");
     return BF_OK;
 }
 
@@ -532,13 +599,20 @@ bf_status bf_gc_stack_build(const float *f, int height, int width, int ld, doubl
     }
 }
 
-bf_status bf_gc_gauss_planes(void *stack, void *tmp, int planes, int height, int width, long long plane_stride,
-                             int lds, double sigma_s, int stack_dtype, void *prm, void *stream) {
+size_t bf_gc_gauss_tmp_bytes(int planes, int height, int width, int stack_dtype) {
+    if (planes < 1 || height < 0 || width < 0 || stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return 0;
+    return (size_t)planes * width * ldt_of(height) * esize(stack_dtype);
+}
+
+bf_status bf_gc_gauss_planes(void *stack, void *tmp, size_t tmp_bytes, int planes, int height, int width,
+                             long long plane_stride, int lds, double sigma_s, int stack_dtype, void *prm,
+                             void *stream) {
     bf_status st = check_common(height, width, sigma_s, 30.0, 1, stack_dtype);
     if (st != BF_OK) return st;
     if (height == 0 || width == 0) return BF_OK;
     if ((st = check_stack_args(stack, height, width, plane_stride, lds, planes, prm)) != BF_OK) return st;
-    if (!tmp) return fail(BF_ERR_INVALID_ARG, "tmp must be non-null");
+    if (!tmp || tmp_bytes < bf_gc_gauss_tmp_bytes(planes, height, width, stack_dtype) || ((uintptr_t)tmp & 15))
+        return fail(BF_ERR_WORKSPACE, "tmp null, not 16-byte aligned or smaller than bf_gc_gauss_tmp_bytes()");
     hipStream_t s = (hipStream_t)stream;
     ParamLayout L;
     if ((st = upload_params((double *)prm, nullptr, sigma_s, 30.0, 1, stack_dtype, s, &L)) != BF_OK) return st;

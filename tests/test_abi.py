@@ -120,5 +120,7 @@ def test_forward_argument_errors_need_no_device(lib):
 def test_stage_argument_errors(lib):
     vp = ctypes.c_void_p
     assert lib.bf_gc_stack_build(vp(1), 8, 8, 8, 30.0, 28, 0, vp(0), 64 * 8, 64, vp(0), vp(1), None) == 1
-    assert lib.bf_gc_gauss_planes(vp(1), vp(0), 30, 8, 8, 64 * 8, 64, 2.0, 0, vp(1), None) == 1
+    assert lib.bf_gc_gauss_planes(vp(1 << 20), vp(0), 1 << 20, 30, 8, 8, 64 * 8, 64, 2.0, 0, vp(1), None) == 4
+    assert lib.bf_gc_gauss_planes(vp(1 << 20), vp(1 << 24), 1 << 20, 30, 8, 8, 64 * 8 + 1, 64, 2.0, 0, vp(1), None) == 1
+    assert lib.bf_gc_gauss_planes(vp(0), vp(1), 1 << 20, 30, 8, 8, 64 * 8, 64, 2.0, 0, vp(1), None) == 1
     assert lib.bf_gc_combine(vp(1), vp(1), 8, 8, 8, 8 * 8, 4, 30.0, 28, 0, vp(1), vp(0), vp(0), vp(1), None) == 1
