@@ -102,7 +102,9 @@ bf_status bf_gc_query(double sigma_r, int N, int stack_dtype, double *kernel_err
  * Workspace bytes needed by bf_gc_forward (for_backward = 0) or
  * bf_gc_backward (for_backward = 1) for one height x width image. Includes
  * the parameter block, the device flag word, N+2 stack planes and N+2
- * transposed column-filtered planes. Returns 0 for invalid arguments.
+ * transposed column-filtered planes (for the backward: both in FP64, plus
+ * four FP64 per-pixel arrays and the reduction partials). Returns 0 for
+ * invalid arguments.
  */
 size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype,
                              int for_backward);
@@ -125,6 +127,23 @@ size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int s
 bf_status bf_gc_forward(const float *f, float *out, int height, int width, int ld,
                         double sigma_s, double sigma_r, int N, int stack_dtype, unsigned flags,
                         void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Backward of bf_gc_forward (not in the paper): for L = sum_i grad_out_i y_i
+ * with y the forward output, writes grad_f = dL/df (device FP32, height x
+ * width, row stride ld) and *grad_sigma_r = dL/dsigma_r (device double;
+ * written, not accumulated). sigma_s and N are constants. The stack is
+ * recomputed in FP64 (nothing is kept from the forward); the adjoint planes
+ * R_m = dL/dHbar_m are filtered with the same Gaussian, which is its own
+ * adjoint under the symmetric extension. Arguments as bf_gc_forward;
+ * stack_dtype must be BF_STACK_F32, the forward's stack type the gradient is
+ * taken for (BF_ERR_UNSUPPORTED otherwise); ws of at
+ * least bf_gc_workspace_bytes(..., 1) bytes. grad_f must not overlap f or
+ * grad_out.
+ */
+bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, double *grad_sigma_r,
+                         int height, int width, int ld, double sigma_s, double sigma_r, int N,
+                         int stack_dtype, unsigned flags, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Stages of the forward filter, for callers that want the stack itself. These

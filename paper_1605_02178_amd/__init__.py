@@ -21,7 +21,8 @@ from ._lib import BFError
 __all__ = [
     "BFError", "STACK_DTYPES", "FLAG_ALLOW_ILL_CONDITIONED", "FLAG_STAGED", "DEVFLAG_RANGE",
     "degree_rule", "coefficients", "query", "plane_scales", "workspace_bytes", "param_bytes",
-    "gc_filter", "stack_build", "gauss_planes", "combine", "read_flags", "radius", "StackLayout",
+    "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
+    "combine", "read_flags", "radius", "StackLayout",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -128,6 +129,94 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
                                    _stream_ptr(stream))
     _lib.check(st, "bf_gc_forward")
     return out
+
+
+def gc_backward(f, grad_out, sigma_s: float, sigma_r: float, degree: int | None = None,
+                allow_ill_conditioned: bool = False, workspace=None, stream=None):
+    """(dL/df, dL/dsigma_r) for L = sum(grad_out * gc_filter(f, ...)) with an
+    FP32 stack. Returns a float32 tensor like f and a 0-d float64 tensor."""
+    import torch
+    _check_image(f)
+    _check_image(grad_out, "grad_out")
+    H, Wd = f.shape
+    N = degree_rule(sigma_r) if degree is None else int(degree)
+    f = f.contiguous()
+    grad_out = grad_out.contiguous()
+    grad_f = torch.empty_like(f)
+    grad_sr = torch.empty((), dtype=torch.float64, device=f.device)
+    ld = f.stride(0) if H > 1 else Wd
+    need = workspace_bytes(H, Wd, sigma_s, N, 0, for_backward=True)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    flags = FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0
+    st = _lib.load().bf_gc_backward(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(grad_out.data_ptr()),
+                                    ctypes.c_void_p(grad_f.data_ptr()), ctypes.c_void_p(grad_sr.data_ptr()), H, Wd,
+                                    max(ld, Wd), float(sigma_s), float(sigma_r), N, 0, flags,
+                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream))
+    _lib.check(st, "bf_gc_backward")
+    return grad_f, grad_sr
+
+
+def _autograd_class():
+    import torch
+
+    class GaussChebyshevBF(torch.autograd.Function):
+        """y = GaussChebyshevBF.apply(f, sigma_r, sigma_s, degree, stack_dtype)
+
+        f: float32 CUDA tensor (H, W) or (..., H, W); sigma_r: 0-d tensor
+        (differentiable); sigma_s, degree: constants. Saves only f and sigma_r;
+        the backward recomputes the stack (bf_gc_backward, FP32 stack)."""
+
+        @staticmethod
+        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype="f32"):
+            sr = float(sigma_r)
+            N = degree_rule(sr) if degree is None else int(degree)
+            shape = f.shape
+            x = f.reshape(-1, shape[-2], shape[-1])
+            y = torch.empty_like(x)
+            ws = torch.empty(max(workspace_bytes(shape[-2], shape[-1], sigma_s, N, stack_dtype), 256),
+                             dtype=torch.uint8, device=f.device)
+            for b in range(x.shape[0]):
+                gc_filter(x[b].contiguous(), sigma_s, sr, N, stack_dtype=stack_dtype, out=y[b], workspace=ws)
+            ctx.save_for_backward(f, sigma_r)
+            ctx.sigma_s, ctx.N = float(sigma_s), N
+            return y.reshape(shape)
+
+        @staticmethod
+        def backward(ctx, grad_y):
+            f, sigma_r = ctx.saved_tensors
+            shape = f.shape
+            x = f.reshape(-1, shape[-2], shape[-1])
+            g = grad_y.reshape(-1, shape[-2], shape[-1]).contiguous()
+            gf = torch.empty_like(x)
+            gsr = torch.zeros((), dtype=torch.float64, device=f.device)
+            ws = torch.empty(max(workspace_bytes(shape[-2], shape[-1], ctx.sigma_s, ctx.N, 0, True), 256),
+                             dtype=torch.uint8, device=f.device)
+            for b in range(x.shape[0]):
+                gfb, gsb = gc_backward(x[b].contiguous(), g[b], ctx.sigma_s, float(sigma_r), ctx.N,
+                                       workspace=ws)
+                gf[b].copy_(gfb)
+                gsr = gsr + gsb
+            return gf.reshape(shape), gsr.to(sigma_r.dtype).reshape(sigma_r.shape), None, None, None
+
+    return GaussChebyshevBF
+
+
+_GCBF = None
+
+
+def __getattr__(name):
+    global _GCBF
+    if name == "GaussChebyshevBF":
+        if _GCBF is None:
+            _GCBF = _autograd_class()
+        return _GCBF
+    raise AttributeError(name)
+
+
+def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32"):
+    """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor."""
+    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype)
 
 
 class StackLayout:

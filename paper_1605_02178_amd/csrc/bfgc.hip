@@ -246,6 +246,166 @@ __global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Backward: gradients of L = sum_i ybar_i y_i with respect to f and sigma_r.
+// The paper has no backward pass; this is the adjoint of the forward above.
+// With P' = sum cp_n s^n Hbar_{n+1}, Q = sum cq_n s^n Hbar_n, y = t_c + t_h P'/Q:
+//   alpha = dL/dP' = ybar t_h / Q,   beta = dL/dQ = -ybar t_h P' / Q^2
+//   R_m   = dL/dHbar_m = alpha cp_{m-1} s^{m-1} [m >= 1] + beta cq_m s^m [m <= N]
+//   dL/dH_m = G R_m (the mirrored, normalised Gaussian is a symmetric matrix)
+//   dL/ds_j = alpha dP'/ds + beta dQ/ds (centre pixel's powers)
+//           + sum_m (G R_m)(j) (m H_{m-1}(j) - mu H_{m+1}(j))   (dH_m/ds)
+//   dL/dmu  = sum_i alpha sum bd_n s^n Hbar_{n+1} + beta sum bd_n s^n Hbar_n
+//           - 1/2 sum_j sum_m (G R_m)(j) H_{m+2}(j)              (dH_m/dmu)
+//   dL/df = dL/ds / t_h,  dL/dsigma_r = dL/dmu (-2 mu / sigma_r).
+// ---------------------------------------------------------------------------
+
+// Row pass of the recomputed forward, folded per pixel into six Horner sums:
+// P', Q, their derivatives in s (Horner value-and-derivative), and the
+// coefficient-derivative sums Pmu, Qmu. Writes alpha, beta, the direct term of
+// dL/ds and the coefficient term of dL/dmu (FP64, row pitch Wd).
+template <class S, int R>
+__global__ __launch_bounds__(256) void k_hpass_adj(const typename S::T *__restrict__ inT,
+                                                    const float *__restrict__ f, const float *__restrict__ ybar,
+                                                    int H, int Wd, int ld, long long pst, int ldt, int N,
+                                                    const double *__restrict__ taps, const double *__restrict__ cq,
+                                                    const double *__restrict__ cp, const double *__restrict__ bd,
+                                                    int W, double *__restrict__ alpha, double *__restrict__ beta,
+                                                    double *__restrict__ gdir, double *__restrict__ gmu) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = blockIdx.x * 64 + lane;
+    const int c0 = (blockIdx.y * 4 + wave) * R;
+    if (c0 >= Wd) return;
+    const int rl = r < H ? r : H - 1;
+    double s[R], Pa[R], Qa[R], dP[R], dQ[R], Pm[R], Qm[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
+        s[q] = ((double)f[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
+        Pa[q] = Qa[q] = dP[q] = dQ[q] = Pm[q] = Qm[q] = 0.0;
+    }
+    const int P = N + 2;
+    for (int k = 0; k < P; ++k) {
+        const int n = P - 1 - k;
+        double acc[R];
+        conv_line<S, R, 8>(inT + (long long)n * pst, rl, ldt, c0, Wd, W, taps + (kTapPad - 1), acc);
+        if (n >= 1) {
+            const double cpn = cp[n - 1], bdn = bd[n - 1];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                dP[q] = fma(dP[q], s[q], Pa[q]);
+                Pa[q] = fma(Pa[q], s[q], cpn * acc[q]);
+                Pm[q] = fma(Pm[q], s[q], bdn * acc[q]);
+            }
+        }
+        if (n <= N) {
+            const double cqn = cq[n], bdn = bd[n];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                dQ[q] = fma(dQ[q], s[q], Qa[q]);
+                Qa[q] = fma(Qa[q], s[q], cqn * acc[q]);
+                Qm[q] = fma(Qm[q], s[q], bdn * acc[q]);
+            }
+        }
+    }
+    if (r < H) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (c0 + q < Wd) {
+                const double yb = (double)ybar[(long long)r * ld + c0 + q];
+                const double a = yb * kTh / Qa[q];
+                const double b = -a * Pa[q] / Qa[q];
+                const long long o = (long long)r * Wd + c0 + q;
+                alpha[o] = a;
+                beta[o] = b;
+                gdir[o] = a * dP[q] + b * dQ[q];
+                gmu[o] = a * Pm[q] + b * Qm[q];
+            }
+        }
+    }
+}
+
+// Adjoint planes R_m(i) = alpha cp_{m-1} s^{m-1} [m >= 1] + beta cq_m s^m [m <= N].
+template <class S>
+__global__ __launch_bounds__(256) void k_adj_build(const float *__restrict__ f, int H, int Wd, int ld,
+                                                    const double *__restrict__ alpha, const double *__restrict__ beta,
+                                                    typename S::T *__restrict__ stack, long long ps, int lds, int N,
+                                                    const double *__restrict__ cq, const double *__restrict__ cp) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= Wd) return;
+    for (int r = blockIdx.y; r < H; r += gridDim.y) {
+        const double s = ((double)f[(long long)r * ld + c] - kTc) * (1.0 / kTh);
+        const long long o = (long long)r * Wd + c;
+        const double a = alpha[o], b = beta[o];
+        typename S::T *dst = stack + (long long)r * lds + c;
+        double pw = 1.0, pm1 = 0.0;                                   // s^m, s^{m-1}
+        for (int m = 0; m <= N + 1; ++m) {
+            double v = 0.0;
+            if (m >= 1) v = a * cp[m - 1] * pm1;
+            if (m <= N) v = fma(b * cq[m], pw, v);
+            dst[m * ps] = S::enc(v);
+            pm1 = pw;
+            pw *= s;
+        }
+    }
+}
+
+// Per pixel j: dL/df_j from the direct term and sum_m (G R_m)(j) dH_m/ds with
+// H_m recomputed in FP64; per-block partial sums of the dL/dmu terms.
+template <class S>
+__global__ __launch_bounds__(256) void k_adj_neighbor(const float *__restrict__ f, int H, int Wd, int ld,
+                                                       const typename S::T *__restrict__ rbar, long long ps, int lds,
+                                                       int N, double mu, const double *__restrict__ gdir,
+                                                       const double *__restrict__ gmu, float *__restrict__ grad_f,
+                                                       double *__restrict__ partial) {
+    __shared__ double red[256];
+    double local = 0.0;
+    const long long npx = (long long)H * Wd;
+    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < npx;
+         o += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(o / Wd), c = (int)(o - (long long)r * Wd);
+        const double s = ((double)f[(long long)r * ld + c] - kTc) * (1.0 / kTh);
+        const double E = exp(-0.5 * mu * s * s);
+        double hm1 = 0.0, h0 = E, h1 = E * s, h2 = E * s * s;        // H_{m-1}, H_m, H_{m+1}, H_{m+2}
+        double gs = 0.0, gm = 0.0;
+        const typename S::T *src = rbar + (long long)r * lds + c;
+        for (int m = 0; m <= N + 1; ++m) {
+            const double rb = (double)S::dec(src[m * ps]);
+            gs = fma(rb, fma((double)m, hm1, -mu * h1), gs);
+            gm = fma(rb, h2, gm);
+            hm1 = h0;
+            h0 = h1;
+            h1 = h2;
+            h2 *= s;
+        }
+        grad_f[(long long)r * ld + c] = (float)((gdir[o] + gs) * (1.0 / kTh));
+        local += gmu[o] - 0.5 * gm;
+    }
+    red[threadIdx.x] = local;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// dL/dsigma_r = (sum of the partials) (-2 mu / sigma_r); fixed summation order.
+__global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ partial, int n, double scale,
+                                                     double *__restrict__ out) {
+    __shared__ double red[256];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0] * scale;
+}
+
 // Staged combine: one thread per pixel, planes read in order (eqs. 8-10).
 template <class S>
 __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ f, const typename S::T *__restrict__ stack,
@@ -492,6 +652,82 @@ static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, 
     return launch_hpass_combine<S>(stackB, f, out, nullptr, nullptr, H, Wd, ld, pst, ldt, prm, L, stream);
 }
 
+constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
+constexpr int kNeighborBlocks = 2048;
+
+struct BwdLayout {
+    size_t params, stackA, stackB, perpx, partial, total;
+};
+
+static BwdLayout bwd_layout(int H, int Wd, double sigma_s, int N) {
+    BwdLayout B;
+    const size_t P = (size_t)N + 2;
+    B.params = align256(sizeof(double) * (size_t)param_layout(radius_of(sigma_s), N).total);
+    B.stackA = align256(P * H * lds_of(Wd) * sizeof(double));
+    B.stackB = align256(P * Wd * ldt_of(H) * sizeof(double));
+    B.perpx = align256((size_t)H * Wd * sizeof(double));
+    B.partial = align256(kNeighborBlocks * sizeof(double));
+    B.total = kFlagBytes + B.params + B.stackA + B.stackB + 4 * B.perpx + B.partial;
+    return B;
+}
+
+static bf_status run_backward(const float *f, const float *ybar, float *grad_f, double *grad_sr, int H, int Wd,
+                              int ld, double sigma_s, double sigma_r, int N, char *ws, hipStream_t stream) {
+    const BwdLayout B = bwd_layout(H, Wd, sigma_s, N);
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    ParamLayout L;
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, BF_STACK_F32, stream, &L);
+    if (st != BF_OK) return st;
+    char *stackA = ws + kFlagBytes + B.params;
+    char *stackB = stackA + B.stackA;
+    double *alpha = (double *)(stackB + B.stackB);
+    double *beta = (double *)((char *)alpha + B.perpx);
+    double *gdir = (double *)((char *)beta + B.perpx);
+    double *gmu = (double *)((char *)gdir + B.perpx);
+    double *partial = (double *)((char *)gmu + B.perpx);
+    const int P = N + 2;
+    const int lds = lds_of(Wd), ldt = ldt_of(H);
+    const long long ps = (long long)H * lds, pst = (long long)Wd * ldt;
+    const double mu = fit(sigma_r, N).mu;
+    // Recompute the forward stack and its column pass in FP64: the derivative
+    // sums below cancel strongly, and FP32 planes cost them three to four
+    // digits (measured against the FP64 gradient oracle).
+    if ((st = launch_build<StF64>(f, H, Wd, ld, stackA, ps, lds, P, prm, L, mu, flag, stream)) != BF_OK) return st;
+    if ((st = launch_vpass<StF64>(stackA, stackB, P, H, Wd, ps, lds, pst, ldt, prm, L, stream)) != BF_OK) return st;
+    {
+        dim3 g((H + 63) / 64, (Wd + 4 * kAdjR - 1) / (4 * kAdjR));
+        ProfScope prof_("k_hpass_adj", stream);
+        hipLaunchKernelGGL((k_hpass_adj<StF64, kAdjR>), g, dim3(256), 0, stream, (const double *)stackB, f, ybar, H,
+                           Wd, ld, pst, ldt, N, prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, prm + L.off_bd,
+                           L.W, alpha, beta, gdir, gmu);
+        if ((st = check_launch("k_hpass_adj")) != BF_OK) return st;
+    }
+    {
+        dim3 g((Wd + 255) / 256, std::min(H, 65535));
+        ProfScope prof_("k_adj_build", stream);
+        hipLaunchKernelGGL(k_adj_build<StF64>, g, dim3(256), 0, stream, f, H, Wd, ld, (const double *)alpha,
+                           (const double *)beta, (double *)stackA, ps, lds, N, prm + L.off_cq, prm + L.off_cp);
+        if ((st = check_launch("k_adj_build")) != BF_OK) return st;
+    }
+    if ((st = launch_gauss<StF64>(stackA, stackB, P, H, Wd, ps, lds, prm, L, stream)) != BF_OK) return st;
+    const long long npx = (long long)H * Wd;
+    const int nb = (int)std::min<long long>(kNeighborBlocks, (npx + 255) / 256);
+    {
+        ProfScope prof_("k_adj_neighbor", stream);
+        hipLaunchKernelGGL(k_adj_neighbor<StF64>, dim3(nb), dim3(256), 0, stream, f, H, Wd, ld,
+                           (const double *)stackA, ps, lds, N, mu, (const double *)gdir, (const double *)gmu,
+                           grad_f, partial);
+        if ((st = check_launch("k_adj_neighbor")) != BF_OK) return st;
+    }
+    {
+        ProfScope prof_("k_reduce_f64", stream);
+        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, stream, (const double *)partial, nb,
+                           -2.0 * mu / sigma_r, grad_sr);
+        return check_launch("k_reduce_f64");
+    }
+}
+
 static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes) {
     const char *pa = (const char *)a, *pb = (const char *)b;
     return pa < pb + bbytes && pb < pa + abytes;
@@ -531,8 +767,8 @@ size_t bf_gc_param_bytes(double sigma_s, int N) {
 }
 
 size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype, int for_backward) {
-    (void)for_backward;
     if (check_common(height, width, sigma_s, 30.0, N, stack_dtype) != BF_OK) return 0;
+    if (for_backward) return bwd_layout(height, width, sigma_s, N).total;
     const size_t planesA = (size_t)(N + 2) * height * lds_of(width) * esize(stack_dtype);
     const size_t planesB = (size_t)(N + 2) * width * ldt_of(height) * esize(stack_dtype);
     return kFlagBytes + align256(bf_gc_param_bytes(sigma_s, N)) + align256(planesA) + align256(planesB);
@@ -557,6 +793,30 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     case BF_STACK_F16: return run_forward<StF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
     default: return run_forward<StBF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
     }
+}
+
+bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, double *grad_sigma_r, int height,
+                         int width, int ld, double sigma_s, double sigma_r, int N, int stack_dtype, unsigned flags,
+                         void *ws, size_t ws_bytes, void *stream) {
+    bf_status st = check_common(height, width, sigma_s, sigma_r, N, stack_dtype);
+    if (st != BF_OK) return st;
+    if (stack_dtype != BF_STACK_F32) return fail(BF_ERR_UNSUPPORTED, "the backward runs with an FP32 stack only");
+    if (!grad_sigma_r) return fail(BF_ERR_INVALID_ARG, "grad_sigma_r must be non-null");
+    if (height == 0 || width == 0) {   // empty image: dL/dsigma_r = 0 (a kernel, so the call can be graph-captured)
+        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, (hipStream_t)stream, (const double *)nullptr, 0, 0.0,
+                           grad_sigma_r);
+        return check_launch("k_reduce_f64");
+    }
+    if (!f || !grad_out || !grad_f) return fail(BF_ERR_INVALID_ARG, "f, grad_out and grad_f must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    const size_t img = ((size_t)(height - 1) * ld + width) * sizeof(float);
+    if (overlaps(f, img, grad_f, img) || overlaps(grad_out, img, grad_f, img))
+        return fail(BF_ERR_INVALID_ARG, "grad_f overlaps f or grad_out");
+    if ((st = check_conditioning(sigma_r, N, stack_dtype, flags)) != BF_OK) return st;
+    const size_t need = bf_gc_workspace_bytes(height, width, sigma_s, N, stack_dtype, 1);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
+    return run_backward(f, grad_out, grad_f, grad_sigma_r, height, width, ld, sigma_s, sigma_r, N, (char *)ws,
+                        (hipStream_t)stream);
 }
 
 bf_status bf_gc_plane_scales(double sigma_r, int N, int stack_dtype, int *k_out) {

@@ -24,6 +24,11 @@ struct StF32 {
     static __device__ __forceinline__ T enc(double v) { return (float)v; }
     static __device__ __forceinline__ float dec(T x) { return x; }
 };
+struct StF64 {
+    typedef double T;
+    static __device__ __forceinline__ T enc(double v) { return v; }
+    static __device__ __forceinline__ double dec(T x) { return x; }
+};
 struct StF16 {
     typedef _Float16 T;
     static __device__ __forceinline__ T enc(double v) { return (_Float16)(float)v; }

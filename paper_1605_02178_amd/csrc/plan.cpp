@@ -53,35 +53,55 @@ static Fit compute_fit(double sigma_r, int N) {
     const qd mu = (qd)kTh * (qd)kTh / ((qd)sigma_r * (qd)sigma_r);
     F.mu = (double)mu;
     const int K = N + 1;
-    std::vector<qd> theta(K), e(K);
+    std::vector<qd> theta(K), e(K), xe(K);
     for (int k = 1; k <= K; ++k) {
         theta[k - 1] = M_PIq * (qd)(2 * k - 1) / (qd)(2 * K);
-        e[k - 1] = expq(mu * cosq(theta[k - 1]));
+        const qd xi = cosq(theta[k - 1]);
+        e[k - 1] = expq(mu * xi);
+        xe[k - 1] = xi * e[k - 1];                 // d/dmu of e^{mu xi_k}
     }
-    std::vector<qd> d(K);
+    std::vector<qd> d(K), dd(K);
     for (int l = 0; l <= N; ++l) {
-        qd s = 0;
-        for (int k = 0; k < K; ++k) s += e[k] * cosq((qd)l * theta[k]);
+        qd s = 0, sd = 0;
+        for (int k = 0; k < K; ++k) {
+            const qd t = cosq((qd)l * theta[k]);
+            s += e[k] * t;
+            sd += xe[k] * t;
+        }
         d[l] = (l == 0 ? (qd)1 : (qd)2) * s / (qd)K;
+        dd[l] = (l == 0 ? (qd)1 : (qd)2) * sd / (qd)K;
     }
     // a[l][n] row by row; three rows are enough to accumulate b_n.
-    std::vector<qd> bq(K, (qd)0), am1(K, (qd)0), a0(K, (qd)0), ap1(K, (qd)0);
+    std::vector<qd> bq(K, (qd)0), bdq(K, (qd)0), am1(K, (qd)0), a0(K, (qd)0), ap1(K, (qd)0);
     a0[0] = 1;                                     // T_0 = 1
-    for (int n = 0; n < K; ++n) bq[n] += d[0] * a0[n];
+    for (int n = 0; n < K; ++n) {
+        bq[n] += d[0] * a0[n];
+        bdq[n] += dd[0] * a0[n];
+    }
     if (N >= 1) {
         am1 = a0;
         std::fill(a0.begin(), a0.end(), (qd)0);
         a0[1] = 1;                                 // T_1 = x
-        for (int n = 0; n < K; ++n) bq[n] += d[1] * a0[n];
+        for (int n = 0; n < K; ++n) {
+            bq[n] += d[1] * a0[n];
+            bdq[n] += dd[1] * a0[n];
+        }
         for (int l = 1; l < N; ++l) {              // T_{l+1} = 2x T_l - T_{l-1}
             for (int n = 0; n < K; ++n) ap1[n] = (n >= 1 ? 2 * a0[n - 1] : (qd)0) - am1[n];
-            for (int n = 0; n < K; ++n) bq[n] += d[l + 1] * ap1[n];
+            for (int n = 0; n < K; ++n) {
+                bq[n] += d[l + 1] * ap1[n];
+                bdq[n] += dd[l + 1] * ap1[n];
+            }
             am1.swap(a0);
             a0.swap(ap1);
         }
     }
     F.b.resize(K);
-    for (int n = 0; n < K; ++n) F.b[n] = (double)bq[n];
+    F.bd.resize(K);
+    for (int n = 0; n < K; ++n) {
+        F.b[n] = (double)bq[n];
+        F.bd[n] = (double)bdq[n];
+    }
 
     // Conditioning of the double coefficients the kernels use, on a grid of y.
     typedef long double ld;
@@ -157,7 +177,8 @@ ParamLayout param_layout(int W, int N) {
     L.off_cq = L.off_taps + ((L.n_taps + 7) & ~7);
     L.off_cp = L.off_cq + ((N + 1 + 7) & ~7);
     L.off_scale = L.off_cp + ((N + 1 + 7) & ~7);
-    L.total = L.off_scale + ((N + 2 + 7) & ~7);
+    L.off_bd = L.off_scale + ((N + 2 + 7) & ~7);
+    L.total = L.off_bd + ((N + 1 + 7) & ~7);
     return L;
 }
 
@@ -173,6 +194,7 @@ void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack
         out[L.off_cp + n] = std::ldexp(F.b[n], -k[n + 1]);
     }
     for (int n = 0; n <= L.N + 1; ++n) out[L.off_scale + n] = std::ldexp(1.0, k[n]);
+    for (int n = 0; n <= L.N; ++n) out[L.off_bd + n] = F.bd[n];
 }
 
 }  // namespace bfgc

@@ -26,6 +26,7 @@ int degree_rule(double sigma_r, int max_degree);
 struct Fit {
     double mu = 0.0;              // t_h^2 / sigma_r^2
     std::vector<double> b;        // b_n = c_n mu^n, n = 0..N
+    std::vector<double> bd;       // db_n/dmu
     double kernel_err = 0.0;      // max_y e^{-mu|y|} |p(mu y) - e^{mu y}|
     double kappa = 0.0;           // max_y e^{-mu|y|} sum |b_n| |y|^n
 };
@@ -50,6 +51,7 @@ struct ParamLayout {
     int off_cq = 0;                 // cq_n = b_n 2^-k_n        (weight of Hbar_n in Q), n = 0..N
     int off_cp = 0;                 // cp_n = b_n 2^-k_{n+1}    (weight of Hbar_{n+1} in P), n = 0..N
     int off_scale = 0;              // 2^k_n, n = 0..N+1
+    int off_bd = 0;                 // db_n/dmu, n = 0..N (gradient with respect to sigma_r)
     int total = 0;                  // doubles
 };
 ParamLayout param_layout(int W, int N);
