@@ -63,6 +63,12 @@ typedef enum {
 /* flags */
 #define BF_FLAG_ALLOW_ILL_CONDITIONED 0x1u  /* compute even where the conditioning check fails */
 #define BF_FLAG_STAGED                0x2u  /* materialise the stack: build | filter | combine (one kernel each) */
+#define BF_FLAG_GRAPH                 0x4u  /* bf_gc_batched: launch through a cached hipGraph */
+/* Tile configuration c in [0, BF_TILE_CONFIGS): output rows per lane in the
+ * column pass and output columns per lane in the row pass + combine,
+ * {16,8}, {8,8}, {16,4}, {8,4}. Without the flag the library uses c = 0. */
+#define BF_TILE_CONFIGS 4
+#define BF_FLAG_TILE(c)               ((((unsigned)(c)) + 1u) << 8)
 
 /* device flag word bits (read with bf_gc_read_flags) */
 #define BF_DEVFLAG_RANGE 0x1u               /* some input pixel was outside [0, 255] or not finite */
@@ -182,8 +188,39 @@ bf_status bf_gc_combine(const float *f, const void *stack, int height, int width
                         long long plane_stride, int lds, double sigma_r, int N, int stack_dtype,
                         float *out, float *P_out, float *Q_out, void *prm, void *stream);
 
-/* Reads the device flag word of a workspace used by bf_gc_forward; waits for
- * `stream` first. flags_out: host unsigned. */
+/*
+ * Batched forward: `count` images of uneven sizes, each with its own sigma_s,
+ * sigma_r and N, in one graph of three persistent kernels (build, column
+ * pass, row pass + combine) after one copy of a small descriptor blob; each
+ * kernel's blocks stride over that phase's tiles of the whole batch.
+ * descs and per_image_status are host arrays, read and written before
+ * return. Each image gets the status its own bf_gc_forward would return from
+ * the host checks; images whose status is not BF_OK are skipped (their out is
+ * untouched) and the call still returns BF_OK. Tiles are the per-image
+ * kernels' blocks, so each output equals the single-image forward's bit for
+ * bit under the same tile configuration. BF_FLAG_GRAPH launches through a
+ * hipGraph cached per (workspace, stream, capacity, tile configuration,
+ * stack type) and replayed with the new descriptors. ws: device, 256-byte
+ * aligned, at least bf_gc_batched_workspace_bytes(descs, count, stack_dtype)
+ * bytes; its flag word (bf_gc_read_flags) collects BF_DEVFLAG_RANGE. Calls
+ * that share a workspace must not overlap.
+ */
+typedef struct {
+    const float *f;            /* device, height x width, row stride ld */
+    float *out;                /* device, same layout, must not overlap f */
+    int height, width, ld;
+    double sigma_s, sigma_r;
+    int N;
+} bf_image_desc;
+
+/* Workspace for a batch: sizes every image with valid dimensions and
+ * parameters (pointers are not read), whatever its conditioning. */
+size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int stack_dtype);
+bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, unsigned flags,
+                        int *per_image_status, void *ws, size_t ws_bytes, void *stream);
+
+/* Reads the device flag word of a workspace used by bf_gc_forward or
+ * bf_gc_batched; waits for `stream` first. flags_out: host unsigned. */
 bf_status bf_gc_read_flags(const void *ws, unsigned *flags_out, void *stream);
 
 /*

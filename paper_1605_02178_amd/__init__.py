@@ -22,13 +22,21 @@ __all__ = [
     "BFError", "STACK_DTYPES", "FLAG_ALLOW_ILL_CONDITIONED", "FLAG_STAGED", "DEVFLAG_RANGE",
     "degree_rule", "coefficients", "query", "plane_scales", "workspace_bytes", "param_bytes",
     "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
-    "combine", "read_flags", "radius", "StackLayout",
+    "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
+    "TILE_CONFIGS", "flag_tile",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 FLAG_ALLOW_ILL_CONDITIONED = 0x1
 FLAG_STAGED = 0x2
+FLAG_GRAPH = 0x4
 DEVFLAG_RANGE = 0x1
+TILE_CONFIGS = ((16, 8), (8, 8), (16, 4), (8, 4))   # (column-pass rows, row-pass columns) per lane
+
+
+def flag_tile(c: int) -> int:
+    """Flag bits selecting tile configuration c (an index into TILE_CONFIGS)."""
+    return (int(c) + 1) << 8
 MAX_DEGREE = 320
 MAX_RADIUS = 96
 
@@ -105,7 +113,7 @@ def _check_image(f, name="f"):
 
 def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
               staged: bool = False, allow_ill_conditioned: bool = False, out=None, workspace=None,
-              stream=None):
+              stream=None, tile_config: int | None = None):
     """Gauss-Chebyshev bilateral filter of a 2-D float32 image in [0, 255]
     (Section III-B). Returns a new tensor (or writes `out`)."""
     import torch
@@ -123,6 +131,8 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
     flags = (FLAG_STAGED if staged else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
+    if tile_config is not None:
+        flags |= flag_tile(tile_config)
     st = _lib.load().bf_gc_forward(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), H, Wd,
                                    max(ld, Wd), float(sigma_s), float(sigma_r), N, code, flags,
                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
@@ -217,6 +227,59 @@ def __getattr__(name):
 def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32"):
     """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor."""
     return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype)
+
+
+def _descs(images, outs, sigmas_s, sigmas_r, degrees):
+    n = len(images)
+    arr = (_lib.ImageDesc * max(n, 1))()
+    for i, (f, o) in enumerate(zip(images, outs)):
+        H, Wd = f.shape
+        arr[i].f = f.data_ptr() if f.numel() else None
+        arr[i].out = o.data_ptr() if o.numel() else None
+        arr[i].height, arr[i].width = H, Wd
+        arr[i].ld = max(f.stride(0) if H > 1 else Wd, Wd)
+        arr[i].sigma_s, arr[i].sigma_r, arr[i].N = float(sigmas_s[i]), float(sigmas_r[i]), int(degrees[i])
+    return arr
+
+
+def batched_workspace_bytes(shapes, sigmas_s, degrees, stack_dtype="f32") -> int:
+    arr = (_lib.ImageDesc * max(len(shapes), 1))()
+    for i, (H, Wd) in enumerate(shapes):
+        arr[i].height, arr[i].width, arr[i].ld = H, Wd, Wd
+        arr[i].sigma_s, arr[i].sigma_r, arr[i].N = float(sigmas_s[i]), 30.0, int(degrees[i])
+    return int(_lib.load().bf_gc_batched_workspace_bytes(arr, len(shapes), _dtype_code(stack_dtype)))
+
+
+def gc_filter_batched(images, sigmas_s, sigmas_r, degrees=None, stack_dtype="f32", graph: bool = True,
+                      tile_config: int | None = None, allow_ill_conditioned: bool = False, outs=None,
+                      workspace=None, stream=None):
+    """Filters a list of 2-D float32 images (uneven sizes, one sigma_s,
+    sigma_r and degree each) in one persistent launch. Returns (outs,
+    statuses): statuses[i] is the bf_status of image i (non-zero: skipped)."""
+    import torch
+    n = len(images)
+    for f in images:
+        _check_image(f)
+    if degrees is None:
+        degrees = [degree_rule(sr) for sr in sigmas_r]
+    images = [f if f.stride(-1) == 1 else f.contiguous() for f in images]
+    if outs is None:
+        outs = [torch.empty_like(f, memory_format=torch.contiguous_format) for f in images]
+    arr = _descs(images, outs, sigmas_s, sigmas_r, degrees)
+    code = _dtype_code(stack_dtype)
+    lib = _lib.load()
+    need = int(lib.bf_gc_batched_workspace_bytes(arr, n, code))
+    if workspace is None or workspace.numel() < need:
+        dev = images[0].device if n else "cuda"
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    status = (ctypes.c_int * max(n, 1))()
+    flags = (FLAG_GRAPH if graph else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
+    if tile_config is not None:
+        flags |= flag_tile(tile_config)
+    st = lib.bf_gc_batched(arr, n, code, flags, status, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                           _stream_ptr(stream))
+    _lib.check(st, "bf_gc_batched")
+    return outs, list(status)[:n]
 
 
 class StackLayout:

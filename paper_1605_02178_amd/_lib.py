@@ -43,6 +43,16 @@ SIGNATURES = {
     "bf_last_error": (ctypes.c_char_p, []),
 }
 
+class ImageDesc(ctypes.Structure):
+    """bf_image_desc of include/bfgc.h."""
+    _fields_ = [("f", _vp), ("out", _vp), ("height", _c_int), ("width", _c_int), ("ld", _c_int),
+                ("sigma_s", _c_double), ("sigma_r", _c_double), ("N", _c_int)]
+
+
+_descp = ctypes.POINTER(ImageDesc)
+SIGNATURES["bf_gc_batched_workspace_bytes"] = (_c_size_t, [_descp, _c_int, _c_int])
+SIGNATURES["bf_gc_batched"] = (_c_int, [_descp, _c_int, _c_int, _c_uint, _ip, _vp, _c_size_t, _vp])
+
 _lib = None
 
 

@@ -19,417 +19,10 @@
 #include <vector>
 
 #include "bfgc.h"
-#include "kernels.hpp"
+#include "device.hpp"
 #include "plan.hpp"
 
 namespace bfgc {
-
-// ---------------------------------------------------------------------------
-// Kernels
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(256) void k_put_params(double *__restrict__ prm, unsigned *__restrict__ flag,
-                                                    ParamChunk chunk) {
-    for (int i = threadIdx.x; i < chunk.count; i += blockDim.x) prm[chunk.offset + i] = chunk.v[i];
-    if (chunk.clear_flag && threadIdx.x == 0 && flag) *flag = 0u;
-}
-
-// One thread per pixel; planes written one after another, coalesced along rows.
-template <class S>
-__global__ __launch_bounds__(256) void k_stack_build(const float *__restrict__ f, int H, int Wd, int ld,
-                                                      typename S::T *__restrict__ stack, long long ps, int lds,
-                                                      int P, const double *__restrict__ scale, double mu,
-                                                      unsigned *__restrict__ flag) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int r = blockIdx.y; r < H; r += gridDim.y) {
-        bool bad = false;
-        if (c < Wd) {
-            const float fv = f[(long long)r * ld + c];
-            bad = !(fv >= 0.0f && fv <= 255.0f);
-            const double s = ((double)fv - kTc) * (1.0 / kTh);           // eq. (17), scaled
-            double v = exp(-0.5 * mu * s * s);                           // H_0 = e^{-mu s^2/2}
-            typename S::T *dst = stack + (long long)r * lds + c;
-            for (int n = 0; n < P; ++n) {
-                dst[n * ps] = S::enc(v * scale[n]);
-                v *= s;                                                  // H_{n+1} = H_n s
-            }
-        }
-        if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1)
-            atomicOr(flag, BF_DEVFLAG_RANGE);
-    }
-}
-
-// One line of the separable Gaussian (eq. 7) for R consecutive outputs of a
-// lane. The line has `len` elements; element p sits at base[p * stride], with
-// p taken through the symmetric extension. Output o (o0 <= o < o0+R) is
-// sum_{t=0}^{2W} w[t] x[o - W + t], w[t] the normalised tap of offset t - W.
-// Input-stationary: each input position is loaded once (U loads in flight at a
-// time) and FMA'd in FP64 into every output it reaches; the head and tail of
-// the window touch only the outputs inside the band, so no zero tap is
-// multiplied. `w` points at tap t = 0 inside the zero-padded tap array.
-template <class S, int R, int U>
-__device__ __forceinline__ void conv_line(const typename S::T *__restrict__ plane, int laneoff, long long stride,
-                                          int o0, int len, int W, const double *__restrict__ w, double (&acc)[R]) {
-    // o0, len, W, stride and plane are wave-uniform: the line position p and
-    // the row pointer stay in scalar registers, each load is a uniform base
-    // plus the lane's own offset.
-    const int p0 = o0 - W;
-    const bool interior = p0 >= 0 && o0 + R + W <= len;
-    auto ld = [&](int i) -> double {
-        const int p = interior ? p0 + i : mirror(p0 + i, len);
-        const typename S::T *row = plane + (long long)p * stride;
-        return (double)S::dec(row[laneoff]);
-    };
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    const int T = 2 * W;
-    if (T + 1 >= R) {
-        // head: inputs 0..R-2 reach outputs r <= i
-        double xh[R - 1];
-#pragma unroll
-        for (int i = 0; i < R - 1; ++i) xh[i] = ld(i);
-        // middle: inputs R-1..T reach every output; chunks of U, the next
-        // chunk's loads issued before the current chunk's FMAs
-        const int nM = (T - R + 2 + U - 1) / U;
-        double xa[U], xb[U];
-        auto ldchunk = [&](double (&x)[U], int k) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = R - 1 + k * U + u;
-                x[u] = ld(i <= T ? i : T);
-            }
-        };
-        auto fmachunk = [&](const double (&x)[U], int k) {
-            const int i0 = R - 1 + k * U;
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (i0 + u <= T) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) acc[r] = fma(w[i0 + u - r], x[u], acc[r]);
-                }
-        };
-        ldchunk(xa, 0);
-#pragma unroll
-        for (int i = 0; i < R - 1; ++i)
-#pragma unroll
-            for (int r = 0; r <= i; ++r) acc[r] = fma(w[i - r], xh[i], acc[r]);
-        // tail inputs T+1..T+R-1 go into xh once the last middle chunk's
-        // loads are out
-        auto ldtail = [&]() {
-#pragma unroll
-            for (int u = 0; u < R - 1; ++u) xh[u] = ld(T + 1 + u);
-        };
-        if (nM == 1) ldtail();
-        int k = 0;
-        for (; k + 1 < nM; k += 2) {
-            ldchunk(xb, k + 1);
-            if (k + 2 == nM) ldtail();
-            fmachunk(xa, k);
-            if (k + 2 < nM) {
-                ldchunk(xa, k + 2);
-                if (k + 3 == nM) ldtail();
-            }
-            fmachunk(xb, k + 1);
-        }
-        if (k < nM) fmachunk(xa, k);
-#pragma unroll
-        for (int u = 0; u < R - 1; ++u)
-#pragma unroll
-            for (int r = u + 1; r < R; ++r) acc[r] = fma(w[T + 1 + u - r], xh[u], acc[r]);
-    } else {
-        // 2W+1 < R: every input against every output; the padding zeros of
-        // the tap array cover offsets outside the band.
-        for (int i = 0; i < R + T; ++i) {
-            const double x = ld(i);
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = fma(w[i - r], x, acc[r]);
-        }
-    }
-}
-
-// Stores R consecutive elements (dst 16-byte aligned when full).
-template <class S, int R>
-__device__ __forceinline__ void store_run(typename S::T *__restrict__ dst, const double (&v)[R], int count) {
-    typedef typename S::T T;
-    if (count >= R && (R * sizeof(T)) % 16 == 0) {
-        T tmp[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) tmp[q] = S::enc(v[q]);
-#pragma unroll
-        for (int q = 0; q < (int)(R * sizeof(T) / 16); ++q)
-            reinterpret_cast<uint4 *>(dst)[q] = reinterpret_cast<const uint4 *>(tmp)[q];
-    } else {
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-            if (q < count) dst[q] = S::enc(v[q]);
-    }
-}
-
-// Column pass: lane = column, each wave R consecutive rows, one plane per
-// blockIdx.z. Output written transposed, [n][col][row] with row stride ldt,
-// so that the row pass reads it with consecutive lanes on consecutive rows.
-template <class S, int R>
-__global__ __launch_bounds__(256) void k_vpass(const typename S::T *__restrict__ in,
-                                                typename S::T *__restrict__ outT, int H, int Wd, long long ps,
-                                                int lds, long long pst, int ldt, const double *__restrict__ taps,
-                                                int W) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c = blockIdx.x * 64 + lane;
-    const int r0 = (blockIdx.y * 4 + wave) * R;
-    const long long n = blockIdx.z;
-    if (r0 >= H) return;
-    const int cl = c < Wd ? c : Wd - 1;
-    double acc[R];
-    conv_line<S, R, 8>(in + n * ps, cl, lds, r0, H, W, taps + (kTapPad - 1), acc);
-    if (c < Wd) store_run<S, R>(outT + n * pst + (long long)c * ldt + r0, acc, H - r0);
-}
-
-// Row pass on the transposed planes: lane = row, each wave R consecutive
-// columns. COMBINE = false writes each filtered plane back as [n][row][col].
-// COMBINE = true visits the planes from n = N+1 down to 0 and folds them in by
-// Horner's rule in s,
-//   P <- P s + cp_{n-1} Hbar_n  (n >= 1),   Q <- Q s + cq_n Hbar_n  (n <= N),
-// which leaves P = sum_n cp_n s^n Hbar_{n+1} and Q = sum_n cq_n s^n Hbar_n
-// (eqs. 8-9); then y = t_c + t_h P/Q (eq. 10, centring undone).
-template <class S, int R, bool COMBINE>
-__global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__ inT,
-                                                typename S::T *__restrict__ out_stack,
-                                                const float *__restrict__ f, float *__restrict__ out,
-                                                float *__restrict__ Pout, float *__restrict__ Qout, int H,
-                                                int Wd, int ld, long long ps, int lds, long long pst, int ldt,
-                                                int P, int N, const double *__restrict__ taps,
-                                                const double *__restrict__ cq, const double *__restrict__ cp,
-                                                int W) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int r = blockIdx.x * 64 + lane;
-    const int c0 = (blockIdx.y * 4 + wave) * R;
-    if (c0 >= Wd) return;
-    const int rl = r < H ? r : H - 1;
-    double s[R], Pa[R], Qa[R];
-    if (COMBINE) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
-            s[q] = ((double)f[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
-            Pa[q] = 0.0;
-            Qa[q] = 0.0;
-        }
-    }
-    for (int k = 0; k < P; ++k) {
-        const int n = COMBINE ? P - 1 - k : k;
-        double acc[R];
-        conv_line<S, R, 8>(inT + (long long)n * pst, rl, ldt, c0, Wd, W, taps + (kTapPad - 1), acc);
-        if (COMBINE) {
-            const double cpn = n >= 1 ? cp[n - 1] : 0.0;
-            const double cqn = n <= N ? cq[n] : 0.0;
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                if (n >= 1) Pa[q] = fma(Pa[q], s[q], cpn * acc[q]);
-                if (n <= N) Qa[q] = fma(Qa[q], s[q], cqn * acc[q]);
-            }
-        } else if (r < H) {
-            store_run<S, R>(out_stack + (long long)n * ps + (long long)r * lds + c0, acc, Wd - c0);
-        }
-    }
-    if (COMBINE && r < H) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            if (c0 + q < Wd) {
-                const long long o = (long long)r * ld + c0 + q;
-                out[o] = (float)(kTc + kTh * (Pa[q] / Qa[q]));
-                if (Pout) Pout[o] = (float)Pa[q];
-                if (Qout) Qout[o] = (float)Qa[q];
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Backward: gradients of L = sum_i ybar_i y_i with respect to f and sigma_r.
-// The paper has no backward pass; this is the adjoint of the forward above.
-// With P' = sum cp_n s^n Hbar_{n+1}, Q = sum cq_n s^n Hbar_n, y = t_c + t_h P'/Q:
-//   alpha = dL/dP' = ybar t_h / Q,   beta = dL/dQ = -ybar t_h P' / Q^2
-//   R_m   = dL/dHbar_m = alpha cp_{m-1} s^{m-1} [m >= 1] + beta cq_m s^m [m <= N]
-//   dL/dH_m = G R_m (the mirrored, normalised Gaussian is a symmetric matrix)
-//   dL/ds_j = alpha dP'/ds + beta dQ/ds (centre pixel's powers)
-//           + sum_m (G R_m)(j) (m H_{m-1}(j) - mu H_{m+1}(j))   (dH_m/ds)
-//   dL/dmu  = sum_i alpha sum bd_n s^n Hbar_{n+1} + beta sum bd_n s^n Hbar_n
-//           - 1/2 sum_j sum_m (G R_m)(j) H_{m+2}(j)              (dH_m/dmu)
-//   dL/df = dL/ds / t_h,  dL/dsigma_r = dL/dmu (-2 mu / sigma_r).
-// ---------------------------------------------------------------------------
-
-// Row pass of the recomputed forward, folded per pixel into six Horner sums:
-// P', Q, their derivatives in s (Horner value-and-derivative), and the
-// coefficient-derivative sums Pmu, Qmu. Writes alpha, beta, the direct term of
-// dL/ds and the coefficient term of dL/dmu (FP64, row pitch Wd).
-template <class S, int R>
-__global__ __launch_bounds__(256) void k_hpass_adj(const typename S::T *__restrict__ inT,
-                                                    const float *__restrict__ f, const float *__restrict__ ybar,
-                                                    int H, int Wd, int ld, long long pst, int ldt, int N,
-                                                    const double *__restrict__ taps, const double *__restrict__ cq,
-                                                    const double *__restrict__ cp, const double *__restrict__ bd,
-                                                    int W, double *__restrict__ alpha, double *__restrict__ beta,
-                                                    double *__restrict__ gdir, double *__restrict__ gmu) {
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int r = blockIdx.x * 64 + lane;
-    const int c0 = (blockIdx.y * 4 + wave) * R;
-    if (c0 >= Wd) return;
-    const int rl = r < H ? r : H - 1;
-    double s[R], Pa[R], Qa[R], dP[R], dQ[R], Pm[R], Qm[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-        const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
-        s[q] = ((double)f[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
-        Pa[q] = Qa[q] = dP[q] = dQ[q] = Pm[q] = Qm[q] = 0.0;
-    }
-    const int P = N + 2;
-    for (int k = 0; k < P; ++k) {
-        const int n = P - 1 - k;
-        double acc[R];
-        conv_line<S, R, 8>(inT + (long long)n * pst, rl, ldt, c0, Wd, W, taps + (kTapPad - 1), acc);
-        if (n >= 1) {
-            const double cpn = cp[n - 1], bdn = bd[n - 1];
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                dP[q] = fma(dP[q], s[q], Pa[q]);
-                Pa[q] = fma(Pa[q], s[q], cpn * acc[q]);
-                Pm[q] = fma(Pm[q], s[q], bdn * acc[q]);
-            }
-        }
-        if (n <= N) {
-            const double cqn = cq[n], bdn = bd[n];
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-                dQ[q] = fma(dQ[q], s[q], Qa[q]);
-                Qa[q] = fma(Qa[q], s[q], cqn * acc[q]);
-                Qm[q] = fma(Qm[q], s[q], bdn * acc[q]);
-            }
-        }
-    }
-    if (r < H) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            if (c0 + q < Wd) {
-                const double yb = (double)ybar[(long long)r * ld + c0 + q];
-                const double a = yb * kTh / Qa[q];
-                const double b = -a * Pa[q] / Qa[q];
-                const long long o = (long long)r * Wd + c0 + q;
-                alpha[o] = a;
-                beta[o] = b;
-                gdir[o] = a * dP[q] + b * dQ[q];
-                gmu[o] = a * Pm[q] + b * Qm[q];
-            }
-        }
-    }
-}
-
-// Adjoint planes R_m(i) = alpha cp_{m-1} s^{m-1} [m >= 1] + beta cq_m s^m [m <= N].
-template <class S>
-__global__ __launch_bounds__(256) void k_adj_build(const float *__restrict__ f, int H, int Wd, int ld,
-                                                    const double *__restrict__ alpha, const double *__restrict__ beta,
-                                                    typename S::T *__restrict__ stack, long long ps, int lds, int N,
-                                                    const double *__restrict__ cq, const double *__restrict__ cp) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= Wd) return;
-    for (int r = blockIdx.y; r < H; r += gridDim.y) {
-        const double s = ((double)f[(long long)r * ld + c] - kTc) * (1.0 / kTh);
-        const long long o = (long long)r * Wd + c;
-        const double a = alpha[o], b = beta[o];
-        typename S::T *dst = stack + (long long)r * lds + c;
-        double pw = 1.0, pm1 = 0.0;                                   // s^m, s^{m-1}
-        for (int m = 0; m <= N + 1; ++m) {
-            double v = 0.0;
-            if (m >= 1) v = a * cp[m - 1] * pm1;
-            if (m <= N) v = fma(b * cq[m], pw, v);
-            dst[m * ps] = S::enc(v);
-            pm1 = pw;
-            pw *= s;
-        }
-    }
-}
-
-// Per pixel j: dL/df_j from the direct term and sum_m (G R_m)(j) dH_m/ds with
-// H_m recomputed in FP64; per-block partial sums of the dL/dmu terms.
-template <class S>
-__global__ __launch_bounds__(256) void k_adj_neighbor(const float *__restrict__ f, int H, int Wd, int ld,
-                                                       const typename S::T *__restrict__ rbar, long long ps, int lds,
-                                                       int N, double mu, const double *__restrict__ gdir,
-                                                       const double *__restrict__ gmu, float *__restrict__ grad_f,
-                                                       double *__restrict__ partial) {
-    __shared__ double red[256];
-    double local = 0.0;
-    const long long npx = (long long)H * Wd;
-    for (long long o = (long long)blockIdx.x * blockDim.x + threadIdx.x; o < npx;
-         o += (long long)gridDim.x * blockDim.x) {
-        const int r = (int)(o / Wd), c = (int)(o - (long long)r * Wd);
-        const double s = ((double)f[(long long)r * ld + c] - kTc) * (1.0 / kTh);
-        const double E = exp(-0.5 * mu * s * s);
-        double hm1 = 0.0, h0 = E, h1 = E * s, h2 = E * s * s;        // H_{m-1}, H_m, H_{m+1}, H_{m+2}
-        double gs = 0.0, gm = 0.0;
-        const typename S::T *src = rbar + (long long)r * lds + c;
-        for (int m = 0; m <= N + 1; ++m) {
-            const double rb = (double)S::dec(src[m * ps]);
-            gs = fma(rb, fma((double)m, hm1, -mu * h1), gs);
-            gm = fma(rb, h2, gm);
-            hm1 = h0;
-            h0 = h1;
-            h1 = h2;
-            h2 *= s;
-        }
-        grad_f[(long long)r * ld + c] = (float)((gdir[o] + gs) * (1.0 / kTh));
-        local += gmu[o] - 0.5 * gm;
-    }
-    red[threadIdx.x] = local;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-// dL/dsigma_r = (sum of the partials) (-2 mu / sigma_r); fixed summation order.
-__global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ partial, int n, double scale,
-                                                     double *__restrict__ out) {
-    __shared__ double red[256];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = red[0] * scale;
-}
-
-// Staged combine: one thread per pixel, planes read in order (eqs. 8-10).
-template <class S>
-__global__ __launch_bounds__(256) void k_combine(const float *__restrict__ f, const typename S::T *__restrict__ stack,
-                                                  int H, int Wd, int ld, long long ps, int lds, int N,
-                                                  const double *__restrict__ cq, const double *__restrict__ cp,
-                                                  float *__restrict__ out, float *__restrict__ Pout,
-                                                  float *__restrict__ Qout) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int r = blockIdx.y; r < H; r += gridDim.y) {
-        if (c >= Wd) continue;
-        const long long o = (long long)r * ld + c;
-        const double s = ((double)f[o] - kTc) * (1.0 / kTh);
-        const typename S::T *src = stack + (long long)r * lds + c;
-        double Q = 0.0, Pn = 0.0, sn = 1.0;                    // sn = s^n
-        for (int n = 0; n <= N; ++n) {
-            Q = fma(cq[n] * sn, (double)S::dec(src[n * ps]), Q);
-            Pn = fma(cp[n] * sn, (double)S::dec(src[(n + 1) * ps]), Pn);
-            sn *= s;
-        }
-        out[o] = (float)(kTc + kTh * (Pn / Q));
-        if (Pout) Pout[o] = (float)Pn;
-        if (Qout) Qout[o] = (float)Q;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Host side
@@ -502,6 +95,13 @@ constexpr int kHR = 16;   // columns per lane in k_hpass (staged)
 constexpr int kHRC = 8;   // columns per lane in k_hpass (fused with the combine)
 constexpr size_t kFlagBytes = 256;
 
+// Tile configuration index from the flags (0 when none is given), -1 if out of range.
+static int tile_config_of(unsigned flags) {
+    const unsigned c = (flags >> 8) & 0xfu;
+    if (c == 0) return 0;
+    return c - 1 < BF_TILE_CONFIGS ? (int)(c - 1) : -1;
+}
+
 static size_t esize(int dtype) { return dtype == BF_STACK_F32 ? 4 : 2; }
 static int lds_of(int width) { return (width + 63) & ~63; }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -569,7 +169,7 @@ template <class S>
 static bf_status launch_build(const float *f, int H, int Wd, int ld, void *stack, long long ps, int lds, int P,
                               const double *prm, const ParamLayout &L, double mu, unsigned *flag,
                               hipStream_t stream) {
-    dim3 grid((Wd + 255) / 256, std::min(H, 65535));
+    dim3 grid((Wd + 255) / 256, (H + kBuildRows - 1) / kBuildRows);
     ProfScope prof_("k_stack_build", stream);
     hipLaunchKernelGGL(k_stack_build<S>, grid, dim3(256), 0, stream, f, H, Wd, ld,
                        (typename S::T *)stack, ps, lds, P, prm + L.off_scale, mu, flag);
@@ -578,12 +178,12 @@ static bf_status launch_build(const float *f, int H, int Wd, int ld, void *stack
 
 static int ldt_of(int height) { return (height + 63) & ~63; }
 
-template <class S>
+template <class S, int RV = kVR>
 static bf_status launch_vpass(const void *stack, void *tmpT, int planes, int H, int Wd, long long ps, int lds,
                               long long pst, int ldt, const double *prm, const ParamLayout &L, hipStream_t stream) {
-    dim3 gv((Wd + 63) / 64, (H + 4 * kVR - 1) / (4 * kVR), planes);
+    dim3 gv((Wd + 63) / 64, (H + 4 * RV - 1) / (4 * RV), planes);
     ProfScope prof_("k_vpass", stream);
-    hipLaunchKernelGGL((k_vpass<S, kVR>), gv, dim3(256), 0, stream, (const typename S::T *)stack,
+    hipLaunchKernelGGL((k_vpass<S, RV>), gv, dim3(256), 0, stream, (const typename S::T *)stack,
                        (typename S::T *)tmpT, H, Wd, ps, lds, pst, ldt, prm + L.off_taps, L.W);
     return check_launch("k_vpass");
 }
@@ -604,13 +204,13 @@ static bf_status launch_gauss(void *stack, void *tmpT, int planes, int H, int Wd
     return check_launch("k_hpass");
 }
 
-template <class S>
+template <class S, int RH = kHRC>
 static bf_status launch_hpass_combine(const void *tmpT, const float *f, float *out, float *Pout, float *Qout, int H,
                                       int Wd, int ld, long long pst, int ldt, const double *prm,
                                       const ParamLayout &L, hipStream_t stream) {
-    dim3 gh((H + 63) / 64, (Wd + 4 * kHRC - 1) / (4 * kHRC));
+    dim3 gh((H + 63) / 64, (Wd + 4 * RH - 1) / (4 * RH));
     ProfScope prof_("k_hpass_combine", stream);
-    hipLaunchKernelGGL((k_hpass<S, kHRC, true>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
+    hipLaunchKernelGGL((k_hpass<S, RH, true>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
                        (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, 0LL, 0, pst, ldt, L.N + 2, L.N,
                        prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W);
     return check_launch("k_hpass(combine)");
@@ -627,7 +227,7 @@ static bf_status launch_combine(const float *f, const void *stack, int H, int Wd
     return check_launch("k_combine");
 }
 
-template <class S>
+template <class S, int RV, int RH>
 static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
                              int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
     unsigned *flag = (unsigned *)ws;
@@ -648,8 +248,8 @@ static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, 
     }
     const int ldt = ldt_of(H);
     const long long pst = (long long)Wd * ldt;
-    if ((st = launch_vpass<S>(stackA, stackB, P, H, Wd, ps, lds, pst, ldt, prm, L, stream)) != BF_OK) return st;
-    return launch_hpass_combine<S>(stackB, f, out, nullptr, nullptr, H, Wd, ld, pst, ldt, prm, L, stream);
+    if ((st = launch_vpass<S, RV>(stackA, stackB, P, H, Wd, ps, lds, pst, ldt, prm, L, stream)) != BF_OK) return st;
+    return launch_hpass_combine<S, RH>(stackB, f, out, nullptr, nullptr, H, Wd, ld, pst, ldt, prm, L, stream);
 }
 
 constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
@@ -733,6 +333,262 @@ static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
     return pa < pb + bbytes && pb < pa + abytes;
 }
 
+// ---------------------------------------------------------------------------
+// Batched host side
+// ---------------------------------------------------------------------------
+
+struct BatchPlan {
+    std::vector<int> status;
+    std::vector<BatchImage> img;        // device descriptors (pointers filled in)
+    std::vector<std::vector<double>> prm;
+    size_t blob_bytes = 0, blob_cap = 0, total = 0;
+    long long items = 0, phase_items[3] = {0, 0, 0};
+};
+
+static size_t batch_blob_cap(size_t bytes) {
+    size_t cap = 64 * 1024;
+    while (cap < bytes) cap *= 2;
+    return cap;
+}
+
+// Plans a batch: per-image status, descriptors, parameter blocks and the
+// workspace layout [blob (capacity blob_cap) | per image: stack A, stack B].
+static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned flags, int RV, int RH,
+                       char *ws, BatchPlan &B, bool sizing = false) {
+    B.status.assign(count, BF_OK);
+    B.img.clear();
+    B.prm.clear();
+    std::vector<int> ok;
+    for (int i = 0; i < count; ++i) {
+        const bf_image_desc &x = d[i];
+        bf_status st = check_common(x.height, x.width, x.sigma_s, x.sigma_r, x.N, dtype);
+        if (st == BF_OK && x.height > 0 && x.width > 0 && !sizing) {
+            if (!x.f || !x.out) st = fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
+            else if (x.ld < x.width) st = fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+            else {
+                const size_t img = ((size_t)(x.height - 1) * x.ld + x.width) * sizeof(float);
+                if (overlaps(x.f, img, x.out, img)) st = fail(BF_ERR_INVALID_ARG, "out overlaps f");
+                else st = check_conditioning(x.sigma_r, x.N, dtype, flags);
+            }
+        }
+        B.status[i] = st;
+        if (st == BF_OK && x.height > 0 && x.width > 0) ok.push_back(i);
+    }
+    const int n = (int)ok.size();
+    size_t prm_bytes = 0;
+    for (int k = 0; k < n; ++k) prm_bytes += align256(sizeof(double) * param_layout(radius_of(d[ok[k]].sigma_s), d[ok[k]].N).total);
+    B.blob_bytes = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n) + prm_bytes;
+    B.blob_cap = batch_blob_cap(B.blob_bytes);
+    size_t off = B.blob_cap;
+    size_t poff = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n);
+    long long start[3] = {0, 0, 0};
+    for (int k = 0; k < n; ++k) {
+        const bf_image_desc &x = d[ok[k]];
+        BatchImage I;
+        std::memset(&I, 0, sizeof I);
+        const ParamLayout L = param_layout(radius_of(x.sigma_s), x.N);
+        std::vector<double> pv;
+        fill_params(L, x.sigma_s, x.sigma_r, dtype, pv);
+        I.f = x.f;
+        I.out = x.out;
+        I.H = x.height;
+        I.Wd = x.width;
+        I.ld = x.ld;
+        I.lds = lds_of(x.width);
+        I.ldt = ldt_of(x.height);
+        I.W = L.W;
+        I.N = x.N;
+        I.P = x.N + 2;
+        I.ps = (long long)I.H * I.lds;
+        I.pst = (long long)I.Wd * I.ldt;
+        I.mu = fit(x.sigma_r, x.N).mu;
+        I.off_taps = L.off_taps;
+        I.off_cq = L.off_cq;
+        I.off_cp = L.off_cp;
+        I.off_scale = L.off_scale;
+        I.prm = (const double *)((uintptr_t)ws + poff);   // ws may be null when only sizing
+        poff += align256(sizeof(double) * L.total);
+        I.stackA = (void *)((uintptr_t)ws + off);
+        off += align256((size_t)I.P * I.ps * esize(dtype));
+        I.stackB = (void *)((uintptr_t)ws + off);
+        off += align256((size_t)I.P * I.pst * esize(dtype));
+        I.gbx = (I.Wd + 255) / 256;
+        I.gvx = (I.Wd + 63) / 64;
+        I.gvy = (I.H + 4 * RV - 1) / (4 * RV);
+        I.ghx = (I.H + 63) / 64;
+        const int ghy = (I.Wd + 4 * RH - 1) / (4 * RH);
+        I.count[0] = I.gbx * ((I.H + kBuildRows - 1) / kBuildRows);
+        I.count[1] = I.gvx * I.gvy * I.P;
+        I.count[2] = I.ghx * ghy;
+        for (int p = 0; p < 3; ++p) {
+            I.start[p] = start[p];
+            start[p] += I.count[p];
+        }
+        B.img.push_back(I);
+        B.prm.push_back(pv);
+    }
+    for (int p = 0; p < 3; ++p) B.phase_items[p] = start[p];
+    B.items = start[0] + start[1] + start[2];
+    B.total = off;
+}
+
+static void pack_blob(const BatchPlan &B, char *host) {
+    std::memset(host, 0, B.blob_bytes);
+    BatchHeader *h = (BatchHeader *)host;
+    h->flags = 0;
+    h->count = (int)B.img.size();
+    for (int p = 0; p < 3; ++p) h->items[p] = B.phase_items[p];
+    std::memcpy(host + sizeof(BatchHeader), B.img.data(), sizeof(BatchImage) * B.img.size());
+    size_t poff = align256(sizeof(BatchHeader) + sizeof(BatchImage) * B.img.size());
+    for (const std::vector<double> &pv : B.prm) {
+        std::memcpy(host + poff, pv.data(), sizeof(double) * pv.size());
+        poff += align256(sizeof(double) * pv.size());
+    }
+}
+
+// Pinned staging for the blob: two slots used in turn, each guarded by an
+// event, so a slot is rewritten only after the copy that read it has run.
+struct StageSlot {
+    char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+struct GraphEntry {
+    void *ws;
+    hipStream_t stream;
+    size_t cap;
+    int cfg, dtype, slot, grid[3];
+    hipGraphExec_t exec;
+    hipGraph_t graph;
+};
+static std::mutex g_batch_mtx;
+static StageSlot g_slots[2];
+static int g_next_slot = 0;
+static std::vector<GraphEntry> g_graphs;
+
+static bf_status stage_slot(size_t cap, int *slot_out) {
+    const int k = g_next_slot;
+    g_next_slot ^= 1;
+    StageSlot &S = g_slots[k];
+    hipError_t e = hipSuccess;
+    if (S.pending) {
+        e = hipEventSynchronize(S.ev);
+        S.pending = false;
+    }
+    if (e == hipSuccess && S.cap < cap) {
+        if (S.host) {
+            e = hipHostFree(S.host);
+            // graphs that copy from the old buffer are stale
+            for (size_t i = 0; i < g_graphs.size();)
+                if (g_graphs[i].slot == k) {
+                    (void)hipGraphExecDestroy(g_graphs[i].exec);
+                    (void)hipGraphDestroy(g_graphs[i].graph);
+                    g_graphs.erase(g_graphs.begin() + i);
+                } else ++i;
+        }
+        S.host = nullptr;
+        S.cap = 0;
+        if (e == hipSuccess) e = hipHostMalloc((void **)&S.host, cap, hipHostMallocDefault);
+        if (e == hipSuccess) S.cap = cap;
+    }
+    if (e == hipSuccess && !S.ev) e = hipEventCreateWithFlags(&S.ev, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("batched staging: ") + hipGetErrorString(e));
+    *slot_out = k;
+    return BF_OK;
+}
+
+// Blocks for a phase kernel: enough to fill every CU at its occupancy, never
+// more than the phase has items.
+static int phase_grid(const void *kernel, long long items) {
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0);
+    const long long full = (long long)std::max(1, cus) * std::max(1, per);
+    return (int)std::max(1LL, std::min(full, items));
+}
+
+template <class S, int RV, int RH>
+static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, unsigned flags, int cfg,
+                             int *status, char *ws, size_t ws_bytes, hipStream_t stream) {
+    BatchPlan B;
+    plan_batch(descs, count, dtype, flags, RV, RH, ws, B);
+    for (int i = 0; i < count; ++i) status[i] = B.status[i];
+    if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
+    if (B.items == 0) return BF_OK;
+    std::lock_guard<std::mutex> lock(g_batch_mtx);
+    int slot = 0;
+    bf_status st = stage_slot(B.blob_cap, &slot);
+    if (st != BF_OK) return st;
+    pack_blob(B, g_slots[slot].host);
+    const void *kern[3] = {(const void *)k_batched<S, RV, RH, 0>, (const void *)k_batched<S, RV, RH, 1>,
+                           (const void *)k_batched<S, RV, RH, 2>};
+    int grid[3];
+    for (int p = 0; p < 3; ++p) grid[p] = phase_grid(kern[p], B.phase_items[p]);
+    hipError_t e = hipSuccess;
+    if (flags & BF_FLAG_GRAPH) {
+        GraphEntry *G = nullptr;
+        for (GraphEntry &g : g_graphs)
+            if (g.ws == ws && g.stream == stream && g.cap == B.blob_cap && g.cfg == cfg && g.dtype == dtype &&
+                g.slot == slot && g.grid[0] == grid[0] && g.grid[1] == grid[1] && g.grid[2] == grid[2])
+                G = &g;
+        if (!G) {
+            GraphEntry g;
+            g.ws = ws;
+            g.stream = stream;
+            g.cap = B.blob_cap;
+            g.cfg = cfg;
+            g.dtype = dtype;
+            g.slot = slot;
+            for (int p = 0; p < 3; ++p) g.grid[p] = grid[p];
+            hipGraphNode_t prev;
+            e = hipGraphCreate(&g.graph, 0);
+            if (e == hipSuccess)
+                e = hipGraphAddMemcpyNode1D(&prev, g.graph, nullptr, 0, ws, g_slots[slot].host, B.blob_cap,
+                                            hipMemcpyHostToDevice);
+            char *blob = ws;
+            void *args[] = {&blob};
+            for (int p = 0; p < 3 && e == hipSuccess; ++p) {
+                hipKernelNodeParams kp;
+                std::memset(&kp, 0, sizeof kp);
+                kp.func = (void *)kern[p];
+                kp.gridDim = dim3(grid[p]);
+                kp.blockDim = dim3(256);
+                kp.sharedMemBytes = 0;
+                kp.kernelParams = args;
+                hipGraphNode_t node;
+                e = hipGraphAddKernelNode(&node, g.graph, &prev, 1, &kp);
+                prev = node;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("batched graph: ") + hipGetErrorString(e));
+            if (g_graphs.size() >= 32) {
+                (void)hipGraphExecDestroy(g_graphs.front().exec);
+                (void)hipGraphDestroy(g_graphs.front().graph);
+                g_graphs.erase(g_graphs.begin());
+            }
+            g_graphs.push_back(g);
+            G = &g_graphs.back();
+        }
+        ProfScope prof_("k_batched(graph)", stream);
+        e = hipGraphLaunch(G->exec, stream);
+    } else {
+        e = hipMemcpyAsync(ws, g_slots[slot].host, B.blob_bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) {
+            ProfScope prof_("k_batched", stream);
+            hipLaunchKernelGGL((k_batched<S, RV, RH, 0>), dim3(grid[0]), dim3(256), 0, stream, ws);
+            hipLaunchKernelGGL((k_batched<S, RV, RH, 1>), dim3(grid[1]), dim3(256), 0, stream, ws);
+            hipLaunchKernelGGL((k_batched<S, RV, RH, 2>), dim3(grid[2]), dim3(256), 0, stream, ws);
+            e = hipGetLastError();
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(g_slots[slot].ev, stream);
+    if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("bf_gc_batched: ") + hipGetErrorString(e));
+    g_slots[slot].pending = true;
+    return BF_OK;
+}
+
 }  // namespace bfgc
 
 using namespace bfgc;
@@ -788,11 +644,23 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     const size_t need = bf_gc_workspace_bytes(height, width, sigma_s, N, stack_dtype, 0);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
     hipStream_t s = (hipStream_t)stream;
-    switch (stack_dtype) {
-    case BF_STACK_F32: return run_forward<StF32>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
-    case BF_STACK_F16: return run_forward<StF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
-    default: return run_forward<StBF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    const int cfg = tile_config_of(flags);
+    if (cfg < 0) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+#define BF_FWD(S, RV, RH) run_forward<S, RV, RH>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s)
+#define BF_FWD_CFG(S)                                   \
+    switch (cfg) {                                      \
+    case 0: return BF_FWD(S, 16, 8);                    \
+    case 1: return BF_FWD(S, 8, 8);                     \
+    case 2: return BF_FWD(S, 16, 4);                    \
+    default: return BF_FWD(S, 8, 4);                    \
     }
+    switch (stack_dtype) {
+    case BF_STACK_F32: BF_FWD_CFG(StF32)
+    case BF_STACK_F16: BF_FWD_CFG(StF16)
+    default: BF_FWD_CFG(StBF16)
+    }
+#undef BF_FWD_CFG
+#undef BF_FWD
 }
 
 bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, double *grad_sigma_r, int height,
@@ -900,6 +768,42 @@ bf_status bf_gc_combine(const float *f, const void *stack, int height, int width
     case BF_STACK_F16: return launch_combine<StF16>(f, stack, height, width, ld, plane_stride, lds, (double *)prm, L, out, P_out, Q_out, s);
     default: return launch_combine<StBF16>(f, stack, height, width, ld, plane_stride, lds, (double *)prm, L, out, P_out, Q_out, s);
     }
+}
+
+size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int stack_dtype) {
+    if (count < 0 || (count > 0 && !descs) || stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return 0;
+    BatchPlan B;
+    // the layout does not depend on the tile configuration or the flags
+    plan_batch(descs, count, stack_dtype, BF_FLAG_ALLOW_ILL_CONDITIONED, 16, 8, nullptr, B, true);
+    return B.total;
+}
+
+bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, unsigned flags,
+                        int *per_image_status, void *ws, size_t ws_bytes, void *stream) {
+    if (count < 0) return fail(BF_ERR_INVALID_ARG, "count must be >= 0");
+    if (count == 0) return BF_OK;
+    if (!descs || !per_image_status) return fail(BF_ERR_INVALID_ARG, "descs and per_image_status must be non-null");
+    if (stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
+    const int cfg = tile_config_of(flags);
+    if (cfg < 0) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    if (!ws || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null or misaligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+#define BF_BAT(S, RV, RH) run_batched<S, RV, RH>(descs, count, stack_dtype, flags, cfg, per_image_status, w, ws_bytes, s)
+#define BF_BAT_CFG(S)                                   \
+    switch (cfg) {                                      \
+    case 0: return BF_BAT(S, 16, 8);                    \
+    case 1: return BF_BAT(S, 8, 8);                     \
+    case 2: return BF_BAT(S, 16, 4);                    \
+    default: return BF_BAT(S, 8, 4);                    \
+    }
+    switch (stack_dtype) {
+    case BF_STACK_F32: BF_BAT_CFG(StF32)
+    case BF_STACK_F16: BF_BAT_CFG(StF16)
+    default: BF_BAT_CFG(StBF16)
+    }
+#undef BF_BAT_CFG
+#undef BF_BAT
 }
 
 bf_status bf_gc_read_flags(const void *ws, unsigned *flags_out, void *stream) {
