@@ -60,7 +60,7 @@ def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch):
 def source_hash():
     import hashlib
     h = hashlib.sha256()
-    for rel in ("paper_1605_02178_amd/csrc/bfgc.hip", "paper_1605_02178_amd/csrc/kernels.hpp"):
+    for rel in ("paper_1605_02178_amd/csrc/bfgc.hip", "paper_1605_02178_amd/csrc/device.hpp"):
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -99,10 +99,10 @@ def profile_read(lib):
     return out
 
 
-def time_forward(bf, f, out, ws, sigma_s, sigma_r, N, stack, steps, warmup, profile=True):
+def time_forward(bf, f, out, ws, sigma_s, sigma_r, N, stack, steps, warmup, profile=True, cfg=None):
     import torch
     for _ in range(warmup):
-        bf.gc_filter(f, sigma_s, sigma_r, N, stack_dtype=stack, out=out, workspace=ws)
+        bf.gc_filter(f, sigma_s, sigma_r, N, stack_dtype=stack, out=out, workspace=ws, tile_config=cfg)
     torch.cuda.synchronize()
     lib = bf._lib.load()
     if profile:
@@ -112,7 +112,7 @@ def time_forward(bf, f, out, ws, sigma_s, sigma_r, N, stack, steps, warmup, prof
     torch.cuda.synchronize()
     e0.record()
     for _ in range(steps):
-        bf.gc_filter(f, sigma_s, sigma_r, N, stack_dtype=stack, out=out, workspace=ws)
+        bf.gc_filter(f, sigma_s, sigma_r, N, stack_dtype=stack, out=out, workspace=ws, tile_config=cfg)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
@@ -121,6 +121,60 @@ def time_forward(bf, f, out, ws, sigma_s, sigma_r, N, stack, steps, warmup, prof
         lib.bf_profile_stop(None)
         prof = profile_read(lib)
     return ms, prof
+
+
+def bench_batched(bf, steps, log):
+    """Uneven batch: 64 edge-rich images, long side uniform over
+    {256, 384, ..., 2048}, square or 2:1, sigma_s ~ U[2,16], sigma_r ~ U[10,60],
+    N from the degree rule; FP32 stack. One graph launch of the batch against
+    a loop of single-image forwards, both with the autotuned tile
+    configuration. Images outside the FP32 domain (sigma_r below about 20) are
+    still filtered (allow flag), for throughput."""
+    import torch
+    from paper_1605_02178_amd import autotune
+    from synth import batch_specs
+    specs = batch_specs()
+    imgs = [torch.tensor(sp.image(), dtype=torch.float32, device="cuda:0") for sp in specs]
+    ss = [sp.sigma_s for sp in specs]
+    sr = [sp.sigma_r for sp in specs]
+    deg = [bf.degree_rule(x) for x in sr]
+    px = sum(x.numel() for x in imgs)
+    ws = torch.empty(bf.batched_workspace_bytes([tuple(x.shape) for x in imgs], ss, deg), dtype=torch.uint8,
+                     device="cuda:0")
+    outs = [torch.empty_like(x) for x in imgs]
+    log(f"bench: batched {len(imgs)} images, {px / 1e6:.1f} Mpx, autotuning")
+    cfg, times = autotune.tune_batched(imgs, ss, sr, deg, repeats=2, allow_ill_conditioned=True, workspace=ws)
+
+    def run_batch():
+        bf.gc_filter_batched(imgs, ss, sr, deg, graph=True, tile_config=cfg, allow_ill_conditioned=True, outs=outs,
+                             workspace=ws)
+    single_ws = torch.empty(max(bf.workspace_bytes(x.shape[0], x.shape[1], s_, d) for x, s_, d in zip(imgs, ss, deg)),
+                            dtype=torch.uint8, device="cuda:0")
+
+    def run_loop():
+        for k, x in enumerate(imgs):
+            bf.gc_filter(x, ss[k], sr[k], deg[k], out=outs[k], workspace=single_ws, tile_config=cfg,
+                         allow_ill_conditioned=True)
+
+    res = {}
+    for name, fn in (("batched_graph", run_batch), ("per_image_loop", run_loop)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        res[name] = {"ms": round(ms, 3), "mpx_s": round(px / 1e6 / (ms / 1e3), 1)}
+        log(f"bench: {name} {ms:.2f} ms")
+    res["speedup"] = round(res["per_image_loop"]["ms"] / res["batched_graph"]["ms"], 3)
+    res.update({"images": len(imgs), "megapixels": round(px / 1e6, 2), "tile_config": cfg,
+                "tile_times_ms": [round(t, 3) for t in times], "steps": steps,
+                "mean_degree_px_weighted": round(sum(d * x.numel() for d, x in zip(deg, imgs)) / px, 1)})
+    return res
 
 
 def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
@@ -148,6 +202,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-stack comparison")
     ap.add_argument("--cpu-rows", type=int, default=1024)
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch comparison")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -180,8 +236,11 @@ def main():
         del a, b
         log(f"bench: calibration copy of {args.copy_mib} MiB done")
 
+    from paper_1605_02178_amd import autotune
+    cfg32, tune32 = autotune.tune_forward(f, ss, sr, N, "f32", out=out, workspace=ws)
+    log(f"bench: tile configuration {cfg32} {bf.TILE_CONFIGS[cfg32]} (ms per config {tune32})")
     log(f"bench: FP32 stack, {args.warmup} warmup + {args.steps} timed steps")
-    ms, prof = time_forward(bf, f, out, ws, ss, sr, N, "f32", args.steps, args.warmup)
+    ms, prof = time_forward(bf, f, out, ws, ss, sr, N, "f32", args.steps, args.warmup, cfg=cfg32)
     value = H * Wd / 1e6 / (ms / 1e3)
     kernels = {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
     dom = max((k for k in kernels if k != "k_put_params"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
@@ -212,7 +271,8 @@ def main():
         "config": {"workload": f"edge-rich {H}x{Wd}, sigma_s={ss:g} (W={W}), sigma_r={sr:g}, N={N} "
                                f"({P} planes), FP32 stack, FP64 accumulation",
                    "image": f"{H}x{Wd}", "sigma_s": ss, "sigma_r": sr, "degree": N, "stack": "f32",
-                   "path": "fused: build | column pass | row pass + combine"},
+                   "path": "fused: build | column pass | row pass + combine",
+                   "tile_config": cfg32, "tile_config_ms": [round(t, 3) for t in tune32]},
         "roofline": roof,
         "kernels": kernels,
         "accuracy": acc32,
@@ -233,7 +293,8 @@ def main():
             if e <= target:
                 break
         N16, e16, o16 = chosen
-        ms16, prof16 = time_forward(bf, f, o16, ws16, ss, sr, N16, "f16", args.steps, args.warmup)
+        cfg16, _ = autotune.tune_forward(f, ss, sr, N16, "f16", out=o16, workspace=ws16)
+        ms16, prof16 = time_forward(bf, f, o16, ws16, ss, sr, N16, "f16", args.steps, args.warmup, cfg=cfg16)
         gc16 = C.gcf(f64, ss, sr, N16, region=reg)
         result["fp16_stack"] = {
             "degree": N16, "value": round(H * Wd / 1e6 / (ms16 / 1e3), 2), "unit": "Mpixel/s",
@@ -243,6 +304,9 @@ def main():
             "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof16.items()},
         }
         log(f"bench: FP16 N={N16} {ms16:.3f} ms/step")
+
+    if not args.no_batched:
+        result["batched"] = bench_batched(bf, args.batch_steps, log)
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

@@ -64,6 +64,10 @@ typedef enum {
 #define BF_FLAG_ALLOW_ILL_CONDITIONED 0x1u  /* compute even where the conditioning check fails */
 #define BF_FLAG_STAGED                0x2u  /* materialise the stack: build | filter | combine (one kernel each) */
 #define BF_FLAG_GRAPH                 0x4u  /* bf_gc_batched: launch through a cached hipGraph */
+/* Gauss-polynomial filter: the cross term exp(x) is replaced by its Taylor
+ * polynomial, c_n = 1/n! (Section II), instead of the Chebyshev interpolant
+ * of eq. 19. Accepted by bf_gc_forward, bf_gc_backward and bf_gc_batched. */
+#define BF_FLAG_TAYLOR                0x8u
 /* Tile configuration c in [0, BF_TILE_CONFIGS): output rows per lane in the
  * column pass and output columns per lane in the row pass + combine,
  * {16,8}, {8,8}, {16,4}, {8,4}. Without the flag the library uses c = 0. */
@@ -75,6 +79,7 @@ typedef enum {
 
 #define BF_MAX_DEGREE 320                   /* largest N accepted */
 #define BF_MAX_RADIUS 96                    /* largest W = ceil(3 sigma_s) accepted */
+#define BF_MAX_BATCH 2048                   /* most images in one bf_gc_batched call */
 
 /*
  * Degree for a given sigma_r when the caller has none. The paper fixes N per
@@ -203,7 +208,9 @@ bf_status bf_gc_combine(const float *f, const void *stack, int height, int width
  * stack type) and replayed with the new descriptors. ws: device, 256-byte
  * aligned, at least bf_gc_batched_workspace_bytes(descs, count, stack_dtype)
  * bytes; its flag word (bf_gc_read_flags) collects BF_DEVFLAG_RANGE. Calls
- * that share a workspace must not overlap.
+ * that share a workspace must not overlap. count <= BF_MAX_BATCH
+ * (BF_ERR_UNSUPPORTED otherwise). Within each phase the images are visited
+ * in decreasing cost per tile, so the blocks' shares stay balanced.
  */
 typedef struct {
     const float *f;            /* device, height x width, row stride ld */

@@ -30,6 +30,7 @@ STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 FLAG_ALLOW_ILL_CONDITIONED = 0x1
 FLAG_STAGED = 0x2
 FLAG_GRAPH = 0x4
+FLAG_TAYLOR = 0x8
 DEVFLAG_RANGE = 0x1
 TILE_CONFIGS = ((16, 8), (8, 8), (16, 4), (8, 4))   # (column-pass rows, row-pass columns) per lane
 
@@ -113,9 +114,11 @@ def _check_image(f, name="f"):
 
 def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
               staged: bool = False, allow_ill_conditioned: bool = False, out=None, workspace=None,
-              stream=None, tile_config: int | None = None):
+              stream=None, tile_config: int | None = None, taylor: bool = False):
     """Gauss-Chebyshev bilateral filter of a 2-D float32 image in [0, 255]
-    (Section III-B). Returns a new tensor (or writes `out`)."""
+    (Section III-B). Returns a new tensor (or writes `out`). taylor=True runs
+    the Gauss-polynomial filter (Taylor coefficients, Section II) instead.
+    tile_config: an index into TILE_CONFIGS, "auto" (autotuned), or None."""
     import torch
     _check_image(f)
     H, Wd = f.shape
@@ -131,6 +134,12 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
     flags = (FLAG_STAGED if staged else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
+    flags |= FLAG_TAYLOR if taylor else 0
+    if tile_config == "auto":
+        from . import autotune
+        tile_config = autotune.lookup(autotune.forward_key(H, Wd, sigma_s, N, code))
+        if tile_config is None:
+            tile_config, _ = autotune.tune_forward(f, sigma_s, sigma_r, N, code, out=out, workspace=workspace)
     if tile_config is not None:
         flags |= flag_tile(tile_config)
     st = _lib.load().bf_gc_forward(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), H, Wd,
@@ -274,6 +283,14 @@ def gc_filter_batched(images, sigmas_s, sigmas_r, degrees=None, stack_dtype="f32
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     status = (ctypes.c_int * max(n, 1))()
     flags = (FLAG_GRAPH if graph else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
+    if tile_config == "auto":
+        from . import autotune
+        tile_config = autotune.lookup(autotune.batched_key([tuple(x.shape) for x in images], sigmas_s, degrees,
+                                                           code))
+        if tile_config is None:
+            tile_config, _ = autotune.tune_batched(images, sigmas_s, sigmas_r, degrees, code, graph=graph,
+                                                   allow_ill_conditioned=allow_ill_conditioned,
+                                                   workspace=workspace)
     if tile_config is not None:
         flags |= flag_tile(tile_config)
     st = lib.bf_gc_batched(arr, n, code, flags, status, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),

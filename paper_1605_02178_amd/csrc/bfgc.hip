@@ -13,6 +13,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -95,6 +96,9 @@ constexpr int kHR = 16;   // columns per lane in k_hpass (staged)
 constexpr int kHRC = 8;   // columns per lane in k_hpass (fused with the combine)
 constexpr size_t kFlagBytes = 256;
 
+// Coefficient kind selected by the flags.
+static int kind_of(unsigned flags) { return (flags & BF_FLAG_TAYLOR) ? kFitTaylor : kFitChebyshev; }
+
 // Tile configuration index from the flags (0 when none is given), -1 if out of range.
 static int tile_config_of(unsigned flags) {
     const unsigned c = (flags >> 8) & 0xfu;
@@ -127,7 +131,7 @@ static double unit_roundoff(int dtype) {
 
 static bf_status check_conditioning(double sigma_r, int N, int dtype, unsigned flags) {
     if (flags & BF_FLAG_ALLOW_ILL_CONDITIONED) return BF_OK;
-    const Fit &F = fit(sigma_r, N);
+    const Fit &F = fit(sigma_r, N, kind_of(flags));
     if (!std::isfinite(F.kappa) || F.kappa * unit_roundoff(dtype) > 1e-2) {
         char buf[200];
         snprintf(buf, sizeof buf, "ill-conditioned: kappa=%.3g times the stack rounding unit exceeds 1e-2 "
@@ -138,11 +142,11 @@ static bf_status check_conditioning(double sigma_r, int N, int dtype, unsigned f
 }
 
 static bf_status upload_params(double *prm, unsigned *flag, double sigma_s, double sigma_r, int N, int dtype,
-                               hipStream_t stream, ParamLayout *Lout) {
+                               hipStream_t stream, ParamLayout *Lout, int kind = kFitChebyshev) {
     const int W = radius_of(sigma_s);
     ParamLayout L = param_layout(W, N);
     std::vector<double> host;
-    fill_params(L, sigma_s, sigma_r, dtype, host);
+    fill_params(L, sigma_s, sigma_r, dtype, host, kind);
     ParamChunk ch;
     int off = 0;
     do {
@@ -233,7 +237,7 @@ static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, 
     unsigned *flag = (unsigned *)ws;
     double *prm = (double *)(ws + kFlagBytes);
     ParamLayout L;
-    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L);
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
     if (st != BF_OK) return st;
     const int lds = lds_of(Wd);
     const long long ps = (long long)H * lds;
@@ -272,12 +276,13 @@ static BwdLayout bwd_layout(int H, int Wd, double sigma_s, int N) {
 }
 
 static bf_status run_backward(const float *f, const float *ybar, float *grad_f, double *grad_sr, int H, int Wd,
-                              int ld, double sigma_s, double sigma_r, int N, char *ws, hipStream_t stream) {
+                              int ld, double sigma_s, double sigma_r, int N, unsigned flags, char *ws,
+                              hipStream_t stream) {
     const BwdLayout B = bwd_layout(H, Wd, sigma_s, N);
     unsigned *flag = (unsigned *)ws;
     double *prm = (double *)(ws + kFlagBytes);
     ParamLayout L;
-    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, BF_STACK_F32, stream, &L);
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, BF_STACK_F32, stream, &L, kind_of(flags));
     if (st != BF_OK) return st;
     char *stackA = ws + kFlagBytes + B.params;
     char *stackB = stackA + B.stackA;
@@ -340,6 +345,8 @@ static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
 struct BatchPlan {
     std::vector<int> status;
     std::vector<BatchImage> img;        // device descriptors (pointers filled in)
+    std::vector<long long> start;       // [3][n] item starts in each phase's visiting order
+    std::vector<int> order;             // [3][n] images in each phase's visiting order
     std::vector<std::vector<double>> prm;
     size_t blob_bytes = 0, blob_cap = 0, total = 0;
     long long items = 0, phase_items[3] = {0, 0, 0};
@@ -377,18 +384,19 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
     const int n = (int)ok.size();
     size_t prm_bytes = 0;
     for (int k = 0; k < n; ++k) prm_bytes += align256(sizeof(double) * param_layout(radius_of(d[ok[k]].sigma_s), d[ok[k]].N).total);
-    B.blob_bytes = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n) + prm_bytes;
+    const size_t head_bytes = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n + (sizeof(long long) + sizeof(int)) * 3 * n);
+    B.blob_bytes = head_bytes + prm_bytes;
     B.blob_cap = batch_blob_cap(B.blob_bytes);
     size_t off = B.blob_cap;
-    size_t poff = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n);
-    long long start[3] = {0, 0, 0};
+    size_t poff = head_bytes;
+    std::vector<long long> cnt[3], cost[3];
     for (int k = 0; k < n; ++k) {
         const bf_image_desc &x = d[ok[k]];
         BatchImage I;
         std::memset(&I, 0, sizeof I);
         const ParamLayout L = param_layout(radius_of(x.sigma_s), x.N);
         std::vector<double> pv;
-        fill_params(L, x.sigma_s, x.sigma_r, dtype, pv);
+        fill_params(L, x.sigma_s, x.sigma_r, dtype, pv, kind_of(flags));
         I.f = x.f;
         I.out = x.out;
         I.H = x.height;
@@ -417,29 +425,47 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
         I.gvy = (I.H + 4 * RV - 1) / (4 * RV);
         I.ghx = (I.H + 63) / 64;
         const int ghy = (I.Wd + 4 * RH - 1) / (4 * RH);
-        I.count[0] = I.gbx * ((I.H + kBuildRows - 1) / kBuildRows);
-        I.count[1] = I.gvx * I.gvy * I.P;
-        I.count[2] = I.ghx * ghy;
-        for (int p = 0; p < 3; ++p) {
-            I.start[p] = start[p];
-            start[p] += I.count[p];
-        }
+        cnt[0].push_back((long long)I.gbx * ((I.H + kBuildRows - 1) / kBuildRows));
+        cnt[1].push_back((long long)I.gvx * I.gvy * I.P);
+        cnt[2].push_back((long long)I.ghx * ghy);
+        cost[0].push_back(I.P);                                   // per item: planes written
+        cost[1].push_back(2LL * L.W + 1);                         // taps per output
+        cost[2].push_back((long long)I.P * (2LL * L.W + 1));      // planes x taps per output
         B.img.push_back(I);
         B.prm.push_back(pv);
     }
-    for (int p = 0; p < 3; ++p) B.phase_items[p] = start[p];
-    B.items = start[0] + start[1] + start[2];
+    B.start.assign(3 * (size_t)n, 0);
+    B.order.assign(3 * (size_t)n, 0);
+    for (int p = 0; p < 3; ++p) {
+        std::vector<int> ord(n);
+        for (int k = 0; k < n; ++k) ord[k] = k;
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[p][a] > cost[p][b]; });
+        long long acc = 0;
+        for (int k = 0; k < n; ++k) {
+            B.order[(size_t)p * n + k] = ord[k];
+            B.start[(size_t)p * n + k] = acc;
+            acc += cnt[p][ord[k]];
+        }
+        B.phase_items[p] = acc;
+    }
+    B.items = B.phase_items[0] + B.phase_items[1] + B.phase_items[2];
     B.total = off;
 }
 
 static void pack_blob(const BatchPlan &B, char *host) {
     std::memset(host, 0, B.blob_bytes);
+    const size_t n = B.img.size();
     BatchHeader *h = (BatchHeader *)host;
     h->flags = 0;
-    h->count = (int)B.img.size();
+    h->count = (int)n;
     for (int p = 0; p < 3; ++p) h->items[p] = B.phase_items[p];
-    std::memcpy(host + sizeof(BatchHeader), B.img.data(), sizeof(BatchImage) * B.img.size());
-    size_t poff = align256(sizeof(BatchHeader) + sizeof(BatchImage) * B.img.size());
+    char *q = host + sizeof(BatchHeader);
+    std::memcpy(q, B.img.data(), sizeof(BatchImage) * n);
+    q += sizeof(BatchImage) * n;
+    std::memcpy(q, B.start.data(), sizeof(long long) * 3 * n);
+    q += sizeof(long long) * 3 * n;
+    std::memcpy(q, B.order.data(), sizeof(int) * 3 * n);
+    size_t poff = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n + (sizeof(long long) + sizeof(int)) * 3 * n);
     for (const std::vector<double> &pv : B.prm) {
         std::memcpy(host + poff, pv.data(), sizeof(double) * pv.size());
         poff += align256(sizeof(double) * pv.size());
@@ -459,6 +485,7 @@ struct GraphEntry {
     hipStream_t stream;
     size_t cap;
     int cfg, dtype, slot, grid[3];
+    size_t lds;
     hipGraphExec_t exec;
     hipGraph_t graph;
 };
@@ -500,12 +527,12 @@ static bf_status stage_slot(size_t cap, int *slot_out) {
 
 // Blocks for a phase kernel: enough to fill every CU at its occupancy, never
 // more than the phase has items.
-static int phase_grid(const void *kernel, long long items) {
+static int phase_grid(const void *kernel, long long items, size_t lds) {
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, 0);
-    const long long full = (long long)std::max(1, cus) * std::max(1, per);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, lds);
+    const long long full = (long long)std::max(1, cus) * std::max(4, per);
     return (int)std::max(1LL, std::min(full, items));
 }
 
@@ -524,14 +551,16 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
     pack_blob(B, g_slots[slot].host);
     const void *kern[3] = {(const void *)k_batched<S, RV, RH, 0>, (const void *)k_batched<S, RV, RH, 1>,
                            (const void *)k_batched<S, RV, RH, 2>};
+    const size_t lds = batch_lds_bytes((int)B.img.size());
     int grid[3];
-    for (int p = 0; p < 3; ++p) grid[p] = phase_grid(kern[p], B.phase_items[p]);
+    for (int p = 0; p < 3; ++p) grid[p] = phase_grid(kern[p], B.phase_items[p], lds);
     hipError_t e = hipSuccess;
     if (flags & BF_FLAG_GRAPH) {
         GraphEntry *G = nullptr;
         for (GraphEntry &g : g_graphs)
             if (g.ws == ws && g.stream == stream && g.cap == B.blob_cap && g.cfg == cfg && g.dtype == dtype &&
-                g.slot == slot && g.grid[0] == grid[0] && g.grid[1] == grid[1] && g.grid[2] == grid[2])
+                g.slot == slot && g.grid[0] == grid[0] && g.grid[1] == grid[1] && g.grid[2] == grid[2] &&
+                g.lds == lds)
                 G = &g;
         if (!G) {
             GraphEntry g;
@@ -542,6 +571,7 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
             g.dtype = dtype;
             g.slot = slot;
             for (int p = 0; p < 3; ++p) g.grid[p] = grid[p];
+            g.lds = lds;
             hipGraphNode_t prev;
             e = hipGraphCreate(&g.graph, 0);
             if (e == hipSuccess)
@@ -555,7 +585,7 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
                 kp.func = (void *)kern[p];
                 kp.gridDim = dim3(grid[p]);
                 kp.blockDim = dim3(256);
-                kp.sharedMemBytes = 0;
+                kp.sharedMemBytes = (unsigned)lds;
                 kp.kernelParams = args;
                 hipGraphNode_t node;
                 e = hipGraphAddKernelNode(&node, g.graph, &prev, 1, &kp);
@@ -577,9 +607,9 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
         e = hipMemcpyAsync(ws, g_slots[slot].host, B.blob_bytes, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) {
             ProfScope prof_("k_batched", stream);
-            hipLaunchKernelGGL((k_batched<S, RV, RH, 0>), dim3(grid[0]), dim3(256), 0, stream, ws);
-            hipLaunchKernelGGL((k_batched<S, RV, RH, 1>), dim3(grid[1]), dim3(256), 0, stream, ws);
-            hipLaunchKernelGGL((k_batched<S, RV, RH, 2>), dim3(grid[2]), dim3(256), 0, stream, ws);
+            hipLaunchKernelGGL((k_batched<S, RV, RH, 0>), dim3(grid[0]), dim3(256), lds, stream, ws);
+            hipLaunchKernelGGL((k_batched<S, RV, RH, 1>), dim3(grid[1]), dim3(256), lds, stream, ws);
+            hipLaunchKernelGGL((k_batched<S, RV, RH, 2>), dim3(grid[2]), dim3(256), lds, stream, ws);
             e = hipGetLastError();
         }
     }
@@ -683,8 +713,8 @@ bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, d
     if ((st = check_conditioning(sigma_r, N, stack_dtype, flags)) != BF_OK) return st;
     const size_t need = bf_gc_workspace_bytes(height, width, sigma_s, N, stack_dtype, 1);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
-    return run_backward(f, grad_out, grad_f, grad_sigma_r, height, width, ld, sigma_s, sigma_r, N, (char *)ws,
-                        (hipStream_t)stream);
+    return run_backward(f, grad_out, grad_f, grad_sigma_r, height, width, ld, sigma_s, sigma_r, N, flags,
+                        (char *)ws, (hipStream_t)stream);
 }
 
 bf_status bf_gc_plane_scales(double sigma_r, int N, int stack_dtype, int *k_out) {
@@ -771,7 +801,9 @@ bf_status bf_gc_combine(const float *f, const void *stack, int height, int width
 }
 
 size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int stack_dtype) {
-    if (count < 0 || (count > 0 && !descs) || stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return 0;
+    if (count < 0 || count > kMaxBatch || (count > 0 && !descs) || stack_dtype < BF_STACK_F32 ||
+        stack_dtype > BF_STACK_BF16)
+        return 0;
     BatchPlan B;
     // the layout does not depend on the tile configuration or the flags
     plan_batch(descs, count, stack_dtype, BF_FLAG_ALLOW_ILL_CONDITIONED, 16, 8, nullptr, B, true);
@@ -782,6 +814,7 @@ bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, 
                         int *per_image_status, void *ws, size_t ws_bytes, void *stream) {
     if (count < 0) return fail(BF_ERR_INVALID_ARG, "count must be >= 0");
     if (count == 0) return BF_OK;
+    if (count > kMaxBatch) return fail(BF_ERR_UNSUPPORTED, "more images than BF_MAX_BATCH");
     if (!descs || !per_image_status) return fail(BF_ERR_INVALID_ARG, "descs and per_image_status must be non-null");
     if (stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
     const int cfg = tile_config_of(flags);

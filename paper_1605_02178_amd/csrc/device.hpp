@@ -330,6 +330,18 @@ __global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__
 // is the only synchronisation, so no block ever waits on another.
 // ---------------------------------------------------------------------------
 
+// Pointers read from the descriptor blob are generic to the compiler, which
+// then emits flat loads with a 64-bit address per lane. Every buffer the
+// batched kernels touch is device (global) memory, so they are cast to the
+// global address space first; the tile code then gets global loads with a
+// scalar base, as in the single-image kernels.
+template <class T>
+__device__ __forceinline__ T *as_global(T *p) {
+    // Through an integer, so that the cast pair is not folded away before the
+    // address-space inference sees the global pointer.
+    return (T *)(__attribute__((address_space(1))) T *)(unsigned long long)p;
+}
+
 struct BatchImage {
     const float *f;
     float *out;
@@ -337,13 +349,10 @@ struct BatchImage {
     void *stackB;
     const double *prm;
     long long ps, pst;
-    long long start[3];        // first item of this image in each phase
     double mu;
     int H, Wd, ld, lds, ldt, W, N, P;
     int off_taps, off_cq, off_cp, off_scale;
-    int count[3];              // items in each phase
     int gbx, gvx, gvy, ghx;    // tile grid widths: build, column pass, row pass
-    int pad_[2];
 };
 
 struct BatchHeader {
@@ -351,42 +360,67 @@ struct BatchHeader {
     int count;                 // images
     long long items[3];        // items in each phase
 };
-// device blob: BatchHeader | BatchImage[count] | parameter blocks
+// device blob: BatchHeader | BatchImage[count] | long long start[3][count] |
+//              int order[3][count] | parameter blocks
+// In phase p the images are visited in order[p][0..count): item t belongs to
+// image order[p][k] for the last k with start[p][k] <= t. The host orders each
+// phase by decreasing cost per item, so the round-robin assignment of items to
+// blocks gives every block a similar mix, heaviest items first.
 
-__device__ __forceinline__ int find_image(const BatchImage *__restrict__ img, int count, int p, long long t) {
-    int lo = 0, hi = count - 1;          // last image whose phase-p start is <= t
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (img[mid].start[p] <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+constexpr int kMaxBatch = 2048;   // images per batched call
+
+// Dynamic LDS for the phase's item table: count starts and count image indices.
+__host__ __device__ constexpr size_t batch_lds_bytes(int count) {
+    return (size_t)count * (sizeof(long long) + sizeof(int));
 }
 
 template <class S, int RV, int RH, int PHASE>
 __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
+    extern __shared__ long long s_start[];
     BatchHeader *hdr = (BatchHeader *)blob;
     const BatchImage *img = (const BatchImage *)(blob + sizeof(BatchHeader));
     const int count = hdr->count;
+    int *s_order = (int *)(s_start + count);
+    const long long *start = (const long long *)(blob + sizeof(BatchHeader) + sizeof(BatchImage) * count);
+    const int *order = (const int *)(start + 3 * count);
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        s_start[k] = start[PHASE * count + k];
+        s_order[k] = order[PHASE * count + k];
+    }
+    __syncthreads();
     const long long items = hdr->items[PHASE];
     for (long long t = blockIdx.x; t < items; t += gridDim.x) {
-        const BatchImage &B = img[find_image(img, count, PHASE, t)];
-        const int l = (int)(t - B.start[PHASE]);
-        const double *prm = B.prm;
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        // The decode reads LDS, so the compiler cannot see that it is the same in
+        // every lane; readfirstlane keeps the image index (and so every field of
+        // its descriptor and everything the tile derives from them) in scalar
+        // registers, as in the single-image kernels.
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
+        const BatchImage &B = img[ii];
+        const int l = (int)(t - s_start[lo]);
+        typedef typename S::T T;
+        const double *prm = as_global(B.prm);
         if (PHASE == 0) {
             const int cb = l % B.gbx, rb = l / B.gbx;
             const int r0 = rb * kBuildRows;
-            build_tile<S>(B.f, B.H, B.Wd, B.ld, (typename S::T *)B.stackA, B.ps, B.lds, B.P, prm + B.off_scale,
-                          B.mu, &hdr->flags, cb, r0, min(B.H, r0 + kBuildRows));
+            build_tile<S>(as_global(B.f), B.H, B.Wd, B.ld, as_global((T *)B.stackA), B.ps, B.lds, B.P,
+                          prm + B.off_scale, B.mu, as_global(&hdr->flags), cb, r0, min(B.H, r0 + kBuildRows));
         } else if (PHASE == 1) {
             const int per_plane = B.gvx * B.gvy;
             const int n = l / per_plane, rem = l - n * per_plane;
-            vpass_tile<S, RV>((const typename S::T *)B.stackA, (typename S::T *)B.stackB, B.H, B.Wd, B.ps, B.lds,
+            vpass_tile<S, RV>(as_global((const T *)B.stackA), as_global((T *)B.stackB), B.H, B.Wd, B.ps, B.lds,
                               B.pst, B.ldt, prm + B.off_taps, B.W, rem % B.gvx, rem / B.gvx, n);
         } else {
-            hpass_tile<S, RH, true>((const typename S::T *)B.stackB, (typename S::T *)nullptr, B.f, B.out, nullptr,
-                                    nullptr, B.H, B.Wd, B.ld, 0LL, 0, B.pst, B.ldt, B.P, B.N, prm + B.off_taps,
-                                    prm + B.off_cq, prm + B.off_cp, B.W, l % B.ghx, l / B.ghx);
+            hpass_tile<S, RH, true>(as_global((const T *)B.stackB), (T *)nullptr, as_global(B.f),
+                                    as_global(B.out), nullptr, nullptr, B.H, B.Wd, B.ld, 0LL, 0, B.pst, B.ldt, B.P,
+                                    B.N, prm + B.off_taps, prm + B.off_cq, prm + B.off_cp, B.W, l % B.ghx,
+                                    l / B.ghx);
         }
     }
 }

@@ -39,6 +39,33 @@ int degree_rule(double sigma_r, int max_degree) {
     return -1;
 }
 
+// Conditioning of the double coefficients the kernels use, on a grid of y:
+// the weighted error of the polynomial against exp(mu y) and kappa.
+static void condition(Fit &F, int N) {
+    typedef long double ld;
+    const int K = N + 1;
+    std::vector<ld> b(K);
+    for (int n = 0; n < K; ++n) b[n] = F.b[n];
+    const ld mul = (ld)F.mu;
+    const int M = 4000;
+    ld kerr = 0.0L, kap = 0.0L;
+    for (int m = 0; m <= M; ++m) {
+        const ld y = -1.0L + 2.0L * m / M;
+        ld p = 0.0L, q = 0.0L;
+        const ld ay = std::fabs(y);
+        for (int n = N; n >= 0; --n) {
+            p = p * y + b[n];
+            q = q * ay + std::fabs(b[n]);
+        }
+        const ld wgt = std::exp(-mul * ay);
+        const ld err = wgt * std::fabs(p - std::exp(mul * y));
+        if (err > kerr) kerr = err;
+        if (wgt * q > kap) kap = wgt * q;
+    }
+    F.kernel_err = (double)kerr;
+    F.kappa = (double)kap;
+}
+
 // The fit of exp(mu y), y in [-1, 1], at the N+1 zeros of T_{N+1}:
 //   xi_k = cos(pi (2k-1) / (2(N+1))),  k = 1..N+1
 //   d_0 = 1/(N+1) sum_k e^{mu xi_k},  d_l = 2/(N+1) sum_k e^{mu xi_k} T_l(xi_k)
@@ -103,40 +130,37 @@ static Fit compute_fit(double sigma_r, int N) {
         F.bd[n] = (double)bdq[n];
     }
 
-    // Conditioning of the double coefficients the kernels use, on a grid of y.
-    typedef long double ld;
-    std::vector<ld> b(K);
-    for (int n = 0; n < K; ++n) b[n] = F.b[n];
-    const ld mul = (ld)F.mu;
-    // Conditioning on a grid of y (with its endpoints and 0).
-    const int M = 4000;
-    ld kerr = 0.0L, kap = 0.0L;
-    for (int m = 0; m <= M; ++m) {
-        const ld y = -1.0L + 2.0L * m / M;
-        ld p = 0.0L, q = 0.0L;
-        const ld ay = std::fabs(y);
-        for (int n = N; n >= 0; --n) {
-            p = p * y + b[n];
-            q = q * ay + std::fabs(b[n]);
-        }
-        const ld wgt = std::exp(-mul * ay);
-        const ld err = wgt * std::fabs(p - std::exp(mul * y));
-        if (err > kerr) kerr = err;
-        if (wgt * q > kap) kap = wgt * q;
-    }
-    F.kernel_err = (double)kerr;
-    F.kappa = (double)kap;
+    condition(F, N);
     return F;
 }
 
-const Fit &fit(double sigma_r, int N) {
+// Taylor coefficients of exp(mu y): b_n = mu^n / n!, db_n/dmu = mu^{n-1}/(n-1)!.
+static Fit compute_taylor(double sigma_r, int N) {
+    typedef __float128 qd;
+    Fit F;
+    const qd mu = (qd)kTh * (qd)kTh / ((qd)sigma_r * (qd)sigma_r);
+    F.mu = (double)mu;
+    F.b.resize(N + 1);
+    F.bd.resize(N + 1);
+    qd t = 1;                                      // mu^n / n!
+    for (int n = 0; n <= N; ++n) {
+        if (n > 0) t = t * mu / (qd)n;
+        F.b[n] = (double)t;
+        F.bd[n] = n == 0 ? 0.0 : (double)(t * (qd)n / mu);
+    }
+    condition(F, N);
+    return F;
+}
+
+const Fit &fit(double sigma_r, int N, int kind) {
     static std::mutex mtx;
-    static std::map<std::pair<double, int>, Fit> cache;
+    static std::map<std::pair<double, int>, Fit> cache[2];
     std::lock_guard<std::mutex> lock(mtx);
+    auto &C = cache[kind == kFitTaylor ? 1 : 0];
     auto key = std::make_pair(sigma_r, N);
-    auto it = cache.find(key);
-    if (it != cache.end()) return it->second;
-    return cache.emplace(key, compute_fit(sigma_r, N)).first->second;
+    auto it = C.find(key);
+    if (it != C.end()) return it->second;
+    return C.emplace(key, kind == kFitTaylor ? compute_taylor(sigma_r, N) : compute_fit(sigma_r, N)).first->second;
 }
 
 std::vector<double> spatial_taps(double sigma_s) {
@@ -183,11 +207,11 @@ ParamLayout param_layout(int W, int N) {
 }
 
 void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack_dtype,
-                 std::vector<double> &out) {
+                 std::vector<double> &out, int kind) {
     out.assign(L.total, 0.0);
     const std::vector<double> w = spatial_taps(sigma_s);
     for (int t = 0; t <= 2 * L.W; ++t) out[L.off_taps + t + (kTapPad - 1)] = w[t];
-    const Fit &F = fit(sigma_r, L.N);
+    const Fit &F = fit(sigma_r, L.N, kind);
     const std::vector<int> k = plane_exponents(F.mu, L.N, stack_dtype);
     for (int n = 0; n <= L.N; ++n) {
         out[L.off_cq + n] = std::ldexp(F.b[n], -k[n]);

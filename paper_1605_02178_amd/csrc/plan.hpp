@@ -31,9 +31,13 @@ struct Fit {
     double kappa = 0.0;           // max_y e^{-mu|y|} sum |b_n| |y|^n
 };
 
-// Chebyshev fit of exp(mu y) at the zeros of T_{N+1} (Section III), in the
-// monomial basis. Cached per (sigma_r, N); thread safe.
-const Fit &fit(double sigma_r, int N);
+// Polynomial for the cross term exp(mu y) of the range kernel, in the
+// monomial basis: kind 0 = the Chebyshev interpolant at the zeros of T_{N+1}
+// (Section III), kind 1 = the Taylor polynomial of the Gauss-polynomial
+// filter, b_n = mu^n / n! (Section II). Cached per (sigma_r, N, kind); thread
+// safe.
+enum { kFitChebyshev = 0, kFitTaylor = 1 };
+const Fit &fit(double sigma_r, int N, int kind = kFitChebyshev);
 
 // Normalised spatial taps exp(-k^2/2 sigma_s^2) / sum, k = -W..W.
 std::vector<double> spatial_taps(double sigma_s);
@@ -58,6 +62,6 @@ ParamLayout param_layout(int W, int N);
 
 // Fills `out` (layout.total doubles).
 void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack_dtype,
-                 std::vector<double> &out);
+                 std::vector<double> &out, int kind = kFitChebyshev);
 
 }  // namespace bfgc

@@ -124,3 +124,28 @@ def test_stage_argument_errors(lib):
     assert lib.bf_gc_gauss_planes(vp(1 << 20), vp(1 << 24), 1 << 20, 30, 8, 8, 64 * 8 + 1, 64, 2.0, 0, vp(1), None) == 1
     assert lib.bf_gc_gauss_planes(vp(0), vp(1), 1 << 20, 30, 8, 8, 64 * 8, 64, 2.0, 0, vp(1), None) == 1
     assert lib.bf_gc_combine(vp(1), vp(1), 8, 8, 8, 8 * 8, 4, 30.0, 28, 0, vp(1), vp(0), vp(0), vp(1), None) == 1
+
+
+def test_autotune_keys_and_cache(tmp_path, monkeypatch):
+    from paper_1605_02178_amd import autotune
+    monkeypatch.setenv("BFGC_AUTOTUNE_CACHE", str(tmp_path / "t.json"))
+    autotune.clear_memory()
+    k1 = autotune.forward_key(4096, 4096, 10.0, 28, 0, arch="gfx950")
+    k2 = autotune.forward_key(4000, 4096, 10.0, 28, 0, arch="gfx950")
+    k3 = autotune.forward_key(4096, 4096, 3.0, 28, 0, arch="gfx950")
+    assert k1 == k2 and k1 != k3
+    assert autotune.lookup(k1) is None
+    autotune._store(k1, 2, [1.0, 0.5, 0.4, 0.9])
+    autotune.clear_memory()
+    assert autotune.lookup(k1) == 2
+    (tmp_path / "t.json").write_text("not json")
+    autotune.clear_memory()
+    assert autotune.lookup(k1) is None
+    autotune.clear_memory()
+
+
+def test_taylor_flag_conditioning(lib):
+    # the Taylor polynomial's kappa is at most 1: accepted in BF16 where the
+    # Chebyshev interpolant at the same degree is refused
+    assert _fwd(lib, sr=30.0, N=28, dt=2) == 3
+    assert _fwd(lib, sr=30.0, N=28, dt=2, flags=0x8, ws=0) == 4
