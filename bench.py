@@ -272,7 +272,7 @@ def main():
                                f"({P} planes), FP32 stack, FP64 accumulation",
                    "image": f"{H}x{Wd}", "sigma_s": ss, "sigma_r": sr, "degree": N, "stack": "f32",
                    "path": "fused: build | column pass | row pass + combine",
-                   "tile_config": cfg32, "tile_config_ms": [round(t, 3) for t in tune32]},
+                   "tile_config": cfg32, "tile_config_ms": [None if t is None else round(t, 3) for t in tune32]},
         "roofline": roof,
         "kernels": kernels,
         "accuracy": acc32,

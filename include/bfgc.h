@@ -68,10 +68,21 @@ typedef enum {
  * polynomial, c_n = 1/n! (Section II), instead of the Chebyshev interpolant
  * of eq. 19. Accepted by bf_gc_forward, bf_gc_backward and bf_gc_batched. */
 #define BF_FLAG_TAYLOR                0x8u
-/* Tile configuration c in [0, BF_TILE_CONFIGS): output rows per lane in the
- * column pass and output columns per lane in the row pass + combine,
- * {16,8}, {8,8}, {16,4}, {8,4}. Without the flag the library uses c = 0. */
-#define BF_TILE_CONFIGS 4
+/* Tile configuration c in [0, BF_TILE_CONFIGS).
+ *   c = 0..3: the three-kernel path (stack in HBM); output rows per lane in
+ *             the column pass and output columns per lane in the row pass +
+ *             combine, {16,8}, {8,8}, {16,4}, {8,4}.
+ *   c = BF_TILE_FUSED: FP16/BF16 stacks with radius ceil(3 sigma_s) <= 48
+ *             only; one kernel per 64-row tile makes each plane in registers,
+ *             runs both passes of eq. 7 on the matrix cores (FP32
+ *             accumulation) and folds eqs. 8-10 in, so the stack never reaches
+ *             HBM. Not combinable with BF_FLAG_STAGED; bf_gc_batched does not
+ *             take it (BF_ERR_UNSUPPORTED).
+ * Without the flag: BF_TILE_FUSED where it applies (FP16/BF16, radius <= 48,
+ * no BF_FLAG_STAGED), else c = 0. */
+#define BF_TILE_CONFIGS 5
+#define BF_TILE_FUSED   4
+#define BF_FUSED_MAX_RADIUS 48
 #define BF_FLAG_TILE(c)               ((((unsigned)(c)) + 1u) << 8)
 
 /* device flag word bits (read with bf_gc_read_flags) */
@@ -134,6 +145,9 @@ size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int s
  *   ws, ws_bytes: device workspace of at least bf_gc_workspace_bytes(..., 0)
  *     bytes, 256-byte aligned; its contents on entry are ignored.
  * The device flag word inside ws is cleared, then set by the kernels.
+ * Path: see BF_TILE_CONFIGS. BF_FLAG_TILE(BF_TILE_FUSED) with an FP32 stack
+ * or a radius above BF_FUSED_MAX_RADIUS is BF_ERR_UNSUPPORTED, with
+ * BF_FLAG_STAGED BF_ERR_INVALID_ARG.
  */
 bf_status bf_gc_forward(const float *f, float *out, int height, int width, int ld,
                         double sigma_s, double sigma_r, int N, int stack_dtype, unsigned flags,

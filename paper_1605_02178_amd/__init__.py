@@ -23,7 +23,7 @@ __all__ = [
     "degree_rule", "coefficients", "query", "plane_scales", "workspace_bytes", "param_bytes",
     "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
-    "TILE_CONFIGS", "flag_tile",
+    "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -32,12 +32,26 @@ FLAG_STAGED = 0x2
 FLAG_GRAPH = 0x4
 FLAG_TAYLOR = 0x8
 DEVFLAG_RANGE = 0x1
-TILE_CONFIGS = ((16, 8), (8, 8), (16, 4), (8, 4))   # (column-pass rows, row-pass columns) per lane
+# Tile configurations: 0-3 are the three-kernel path, (column-pass rows,
+# row-pass columns) per lane; TILE_FUSED is the fused matrix-core kernel for
+# FP16/BF16 stacks with radius <= FUSED_MAX_RADIUS.
+TILE_CONFIGS = ((16, 8), (8, 8), (16, 4), (8, 4), "fused")
+TILE_FUSED = 4
+FUSED_MAX_RADIUS = 48
 
 
 def flag_tile(c: int) -> int:
     """Flag bits selecting tile configuration c (an index into TILE_CONFIGS)."""
     return (int(c) + 1) << 8
+
+
+def tile_configs_for(stack_dtype, sigma_s) -> list:
+    """Tile configurations bf_gc_forward accepts for this stack type and sigma_s."""
+    code = _dtype_code(stack_dtype)
+    cfgs = [0, 1, 2, 3]
+    if code != 0 and radius(sigma_s) <= FUSED_MAX_RADIUS:
+        cfgs.append(TILE_FUSED)
+    return cfgs
 MAX_DEGREE = 320
 MAX_RADIUS = 96
 

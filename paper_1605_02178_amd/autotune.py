@@ -72,7 +72,7 @@ def _load() -> dict:
 def _store(key: str, cfg: int, times_ms: list) -> None:
     with _lock:
         data = _load()
-        data[key] = {"config": int(cfg), "times_ms": [round(t, 5) for t in times_ms]}
+        data[key] = {"config": int(cfg), "times_ms": [None if t is None else round(t, 5) for t in times_ms]}
         path = cache_path()
         try:
             os.makedirs(os.path.dirname(path), exist_ok=True)
@@ -115,19 +115,21 @@ def _time(fn, repeats: int) -> float:
 
 
 def tune_forward(f, sigma_s, sigma_r, degree, stack_dtype="f32", repeats=3, out=None, workspace=None):
-    """Times every tile configuration of bf_gc_forward on (f, sigma_s,
-    sigma_r, degree), caches the fastest and returns (config, times_ms)."""
+    """Times every tile configuration bf_gc_forward accepts for (f, sigma_s,
+    sigma_r, degree, stack_dtype), caches the fastest and returns (config,
+    times_ms), times_ms[c] being None for a configuration that does not
+    apply."""
     import torch
-    from . import TILE_CONFIGS, gc_filter, workspace_bytes
+    from . import TILE_CONFIGS, gc_filter, tile_configs_for, workspace_bytes
     out = torch.empty_like(f) if out is None else out
     if workspace is None:
         workspace = torch.empty(max(256, workspace_bytes(f.shape[0], f.shape[1], sigma_s, degree, stack_dtype)),
                                 dtype=torch.uint8, device=f.device)
-    times = []
-    for c in range(len(TILE_CONFIGS)):
-        times.append(_time(lambda: gc_filter(f, sigma_s, sigma_r, degree, stack_dtype=stack_dtype, out=out,
-                                             workspace=workspace, tile_config=c), repeats))
-    best = min(range(len(times)), key=times.__getitem__)
+    times = [None] * len(TILE_CONFIGS)
+    for c in tile_configs_for(stack_dtype, sigma_s):
+        times[c] = _time(lambda: gc_filter(f, sigma_s, sigma_r, degree, stack_dtype=stack_dtype, out=out,
+                                           workspace=workspace, tile_config=c), repeats)
+    best = min((c for c in range(len(times)) if times[c] is not None), key=times.__getitem__)
     _store(forward_key(f.shape[0], f.shape[1], sigma_s, degree, stack_dtype), best, times)
     return best, times
 
@@ -136,10 +138,10 @@ def tune_batched(images, sigmas_s, sigmas_r, degrees, stack_dtype="f32", repeats
                  allow_ill_conditioned=False, workspace=None):
     """Times every tile configuration of bf_gc_batched on this batch, caches
     the fastest and returns (config, times_ms)."""
-    from . import TILE_CONFIGS, gc_filter_batched
+    from . import TILE_FUSED, gc_filter_batched
     outs = None
     times = []
-    for c in range(len(TILE_CONFIGS)):
+    for c in range(TILE_FUSED):                  # the batched form runs the three-kernel tiles
         def run():
             nonlocal outs
             outs, _ = gc_filter_batched(images, sigmas_s, sigmas_r, degrees, stack_dtype=stack_dtype, graph=graph,

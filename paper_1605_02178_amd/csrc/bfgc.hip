@@ -99,11 +99,16 @@ constexpr size_t kFlagBytes = 256;
 // Coefficient kind selected by the flags.
 static int kind_of(unsigned flags) { return (flags & BF_FLAG_TAYLOR) ? kFitTaylor : kFitChebyshev; }
 
-// Tile configuration index from the flags (0 when none is given), -1 if out of range.
+// Tile configuration index from the flags: -1 when none is given, -2 if out of range.
 static int tile_config_of(unsigned flags) {
     const unsigned c = (flags >> 8) & 0xfu;
-    if (c == 0) return 0;
-    return c - 1 < BF_TILE_CONFIGS ? (int)(c - 1) : -1;
+    if (c == 0) return -1;
+    return c - 1 < BF_TILE_CONFIGS ? (int)(c - 1) : -2;
+}
+
+// The fused matrix-core kernel covers FP16/BF16 stacks up to BF_FUSED_MAX_RADIUS.
+static bool fused_applies(int dtype, double sigma_s) {
+    return dtype != BF_STACK_F32 && radius_of(sigma_s) <= BF_FUSED_MAX_RADIUS;
 }
 
 static size_t esize(int dtype) { return dtype == BF_STACK_F32 ? 4 : 2; }
@@ -229,6 +234,38 @@ static bf_status launch_combine(const float *f, const void *stack, int H, int Wd
     hipLaunchKernelGGL(k_combine<S>, grid, dim3(256), 0, stream, f, (const typename S::T *)stack, H, Wd, ld, ps,
                        lds, L.N, prm + L.off_cq, prm + L.off_cp, out, Pout, Qout);
     return check_launch("k_combine");
+}
+
+template <class M, int Q, int TC, int QA>
+static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const double *prm,
+                                const ParamLayout &L, float mu, unsigned *flag, hipStream_t stream) {
+    dim3 grid((Wd + TC - 1) / TC, (H + kFusedRows - 1) / kFusedRows);
+    ProfScope prof_("k_fused_mfma", stream);
+    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, prm,
+                       L.off_taps, L.off_cq, L.off_cp, L.off_scale, L.W, L.N, mu, flag);
+    return check_launch("k_fused_mfma");
+}
+
+// Fused FP16/BF16 forward: parameters, then one kernel (see k_fused_mfma).
+template <class M>
+static bf_status run_fused(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
+                           int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    ParamLayout L;
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
+    if (st != BF_OK) return st;
+    const float mu = (float)fit(sigma_r, N).mu;
+    const int W = L.W, qa = fused_qa(W);
+    // geometry: TC + 2W <= 128 halo columns, 64 + 2W <= 32Q halo rows
+#define BF_FUSED(Q, TC)                                                                             \
+    return qa == (Q) - 3 ? launch_fused_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, prm, L, mu, flag, stream) \
+                         : launch_fused_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, prm, L, mu, flag, stream)
+    if (W <= 16) BF_FUSED(3, 64);
+    if (W <= 32) BF_FUSED(4, 64);
+    if (W <= 48) BF_FUSED(5, 32);
+#undef BF_FUSED
+    return fail(BF_ERR_UNSUPPORTED, "fused path: radius above BF_FUSED_MAX_RADIUS");
 }
 
 template <class S, int RV, int RH>
@@ -674,8 +711,17 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     const size_t need = bf_gc_workspace_bytes(height, width, sigma_s, N, stack_dtype, 0);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
     hipStream_t s = (hipStream_t)stream;
-    const int cfg = tile_config_of(flags);
-    if (cfg < 0) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    int cfg = tile_config_of(flags);
+    if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    if (cfg == -1) cfg = (fused_applies(stack_dtype, sigma_s) && !(flags & BF_FLAG_STAGED)) ? BF_TILE_FUSED : 0;
+    if (cfg == BF_TILE_FUSED) {
+        if (!fused_applies(stack_dtype, sigma_s))
+            return fail(BF_ERR_UNSUPPORTED, "fused tile: FP16/BF16 stacks with radius <= BF_FUSED_MAX_RADIUS only");
+        if (flags & BF_FLAG_STAGED) return fail(BF_ERR_INVALID_ARG, "fused tile and BF_FLAG_STAGED exclude each other");
+        if (stack_dtype == BF_STACK_F16)
+            return run_fused<MmaF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+        return run_fused<MmaBF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    }
 #define BF_FWD(S, RV, RH) run_forward<S, RV, RH>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s)
 #define BF_FWD_CFG(S)                                   \
     switch (cfg) {                                      \
@@ -817,8 +863,10 @@ bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, 
     if (count > kMaxBatch) return fail(BF_ERR_UNSUPPORTED, "more images than BF_MAX_BATCH");
     if (!descs || !per_image_status) return fail(BF_ERR_INVALID_ARG, "descs and per_image_status must be non-null");
     if (stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
-    const int cfg = tile_config_of(flags);
-    if (cfg < 0) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    int cfg = tile_config_of(flags);
+    if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    if (cfg == BF_TILE_FUSED) return fail(BF_ERR_UNSUPPORTED, "the batched form does not take the fused tile");
+    if (cfg == -1) cfg = 0;
     if (!ws || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null or misaligned");
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;

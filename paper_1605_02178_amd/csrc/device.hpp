@@ -610,4 +610,231 @@ __global__ __launch_bounds__(256) void k_combine(const float *__restrict__ f, co
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Fused reduced-precision path (FP16 / BF16 stack): one kernel per 64-row
+// output tile runs build, both Gaussian passes and the combine for every
+// plane, so the stack never leaves the chip.
+//
+// Each plane H_n (scaled by 2^k_n for FP16, eq. 6 in scaled form) is made in
+// registers by the running product H <- H s and rounded to the stack type; the
+// two passes of eq. 7 are banded Toeplitz products on the matrix cores
+// (v_mfma_f32_16x16x32_{f16,bf16}, FP32 accumulation); the combine of eqs. 8-9
+// adds cq_n s^n Hbar_n to Q and cp_{n-1} s^{n-1} Hbar_n to P in FP32 as the
+// planes go by; eq. 10 gives y.
+//
+// Geometry. Output tile: rows [r0, r0+64), columns [c0, c0+TC). The column
+// pass covers the halo columns c0-W+[0,128) (8 blocks of 16, one per wave)
+// and the halo rows r0-W+[0,32Q) in chunks of 32 (the MFMA K dimension). For
+// output row block j (16 rows) and input chunk q the Toeplitz operand is
+//   B[k][n] = w[32q + k - 16j - n]   (k: row in the chunk, n: row in the block),
+// zero outside [0, 2W]; it depends only on d = 2q - j, so the 2Q fragments
+// d = -1 .. 2Q-2 are made once per tile and serve both passes (the row pass
+// has the same structure along columns). The column pass computes the
+// transposed product (M = halo columns, N = output rows), which leaves each
+// lane four consecutive columns of one row; these go through LDS as the row
+// pass's row-major A operand.
+// ---------------------------------------------------------------------------
+
+typedef _Float16 mf_h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 mf_h4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mf_b8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mf_b4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+
+struct MmaF16 {
+    typedef _Float16 E;
+    typedef mf_h8 V;
+    typedef mf_h4 V4;
+    static __device__ __forceinline__ E cvt(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ mf_f4 mma(V a, V b, mf_f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+struct MmaBF16 {
+    typedef __bf16 E;
+    typedef mf_b8 V;
+    typedef mf_b4 V4;
+    static __device__ __forceinline__ E cvt(float x) { return (__bf16)x; }
+    static __device__ __forceinline__ mf_f4 mma(V a, V b, mf_f4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+constexpr int kFusedRows = 64;               // output rows per tile
+constexpr int kFusedHaloC = 128;             // halo columns of the column pass
+constexpr int kFusedPitch = kFusedHaloC + 8; // LDS row pitch (elements) of the column-pass result
+
+// Chunk ranges. Output block j (16 rows or columns) needs the halo positions
+// [16j, 16j + 15 + 2W], i.e. chunks j/2 .. j/2 + A for even j and
+// j/2 .. j/2 + B for odd j, with A = (2W+15)/32 and B = (2W+31)/32. For each
+// kernel geometry B = Q - 2 and A is Q - 3 or Q - 2 (template parameter QA).
+__host__ __device__ constexpr int fused_qa(int W) { return (2 * W + 15) / 32; }
+
+template <class M, int Q, int TC, int QA>
+__global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
+                                                    int Wd, int ld, const double *__restrict__ prm, int off_taps,
+                                                    int off_cq, int off_cp, int off_scale, int W, int N, float mu,
+                                                    unsigned *__restrict__ flag) {
+    typedef typename M::E E;
+    typedef typename M::V V;
+    constexpr int QB = Q - 2;
+    constexpr int JB = TC / 32;                  // output column blocks per wave in the row pass
+    static_assert((TC == 64 && Q <= 4) || (TC == 32 && Q == 5), "geometry");
+    static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
+    __shared__ __align__(16) E ybuf[2][kFusedRows * kFusedPitch];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int r0 = blockIdx.y * kFusedRows, c0 = blockIdx.x * TC;
+    const int P = N + 2;
+    auto tap = [&](int t) -> float {
+        return (t >= 0 && t <= 2 * W) ? (float)prm[off_taps + kTapPad - 1 + t] : 0.0f;
+    };
+
+    // Toeplitz fragments tf[d+1], d = -1 .. 2Q-2: element jj of lane (li, lg)
+    // is w[16d + 8lg + jj - li].
+    V tf[2 * Q];
+#pragma unroll
+    for (int d = -1; d < 2 * Q - 1; ++d)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = M::cvt(tap(16 * d + 8 * lg + jj - li));
+
+    // Row-pass assignment: row block rb = wave / 2. With 64-column tiles the
+    // wave takes column blocks 2p, 2p+1 (p = wave & 1), which read the halo
+    // chunks shifted by p and use the fragments of blocks 0, 1. With 32-column
+    // tiles it takes block jc = p and builds that block's fragments rf[q].
+    const int rb = wave >> 1;
+    const int p = wave & 1;
+    const int jc0 = p * JB;
+    V rf[TC == 32 ? 4 : 1];
+    if (TC == 32) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) rf[q][jj] = M::cvt(tap(32 * q + 8 * lg + jj - 16 * p - li));
+    }
+
+    // Column-pass A operand state: halo column 16 wave + li, halo rows
+    // 32q + 8lg + jj; s and the running H_n in FP32.
+    const int hc = c0 - W + 16 * wave + li;
+    const int mc = mirror(hc, Wd);
+    const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
+    float sv[Q][8], hv[Q][8];
+    bool bad = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const int hr = r0 - W + 32 * q + 8 * lg + jj;
+            const float x = f[(long long)mirror(hr, H) * ld + mc];
+            if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H) bad |= !(x >= 0.0f && x <= 255.0f);
+            const float s = (x - (float)kTc) * (float)(1.0 / kTh);      // eq. (17)
+            sv[q][jj] = s;
+            hv[q][jj] = expf(-0.5f * mu * s * s);                         // H_0
+        }
+    }
+    if (flag && __any(bad) && lane == __ffsll((unsigned long long)__ballot(bad)) - 1) atomicOr(flag, BF_DEVFLAG_RANGE);
+
+    // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
+    // 16 (jc0 + b) + li.
+    float sc[JB][4], pw[JB][4], pwp[JB][4], Pa[JB][4], Qa[JB][4];
+#pragma unroll
+    for (int b = 0; b < JB; ++b) {
+        const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = min(r0 + 16 * rb + 4 * lg + v, H - 1);
+            sc[b][v] = (f[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
+            pw[b][v] = 1.0f;
+            pwp[b][v] = 0.0f;
+            Pa[b][v] = 0.0f;
+            Qa[b][v] = 0.0f;
+        }
+    }
+
+    // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
+    auto column_pass = [&](int n) {
+        const float scale = (float)prm[off_scale + n];
+        V a[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                a[q][jj] = M::cvt(hv[q][jj] * scale);
+                hv[q][jj] *= sv[q][jj];                                   // H_{n+1} = H_n s
+            }
+        }
+        E *yb = ybuf[n & 1];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
+            mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = j / 2; q <= qlast; ++q) acc = M::mma(a[q], tf[2 * q - j + 1], acc);
+            typename M::V4 o;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
+            *(typename M::V4 *)(yb + (16 * j + li) * kFusedPitch + 16 * wave + 4 * lg) = o;
+        }
+    };
+    // Row pass of plane n from ybuf[n & 1] and its share of eqs. 8-9.
+    auto row_pass = [&](int n) {
+        const E *src = ybuf[n & 1] + (16 * rb + li) * kFusedPitch + 8 * lg;
+        mf_f4 z[JB];
+        if (TC == 64) {
+            V ya[QB + 1];
+#pragma unroll
+            for (int q = 0; q <= QB; ++q) ya[q] = *(const V *)(src + 32 * (q + p));
+            mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
+#pragma unroll
+            for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
+            z[0] = acc0;
+            z[JB - 1] = acc1;
+        } else {
+            mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc = M::mma(*(const V *)(src + 32 * q), rf[q], acc);
+            z[0] = acc;
+        }
+        const float cq = n <= N ? (float)prm[off_cq + n] : 0.0f;
+        const float cp = n >= 1 ? (float)prm[off_cp + n - 1] : 0.0f;
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float zz = z[b][v];
+                Qa[b][v] = fmaf(cq * pw[b][v], zz, Qa[b][v]);
+                Pa[b][v] = fmaf(cp * pwp[b][v], zz, Pa[b][v]);
+                pwp[b][v] = pw[b][v];
+                pw[b][v] *= sc[b][v];
+            }
+        }
+    };
+
+    // Software pipeline: the row pass of plane n-1 and the column pass of
+    // plane n sit between the same two barriers (different LDS buffers).
+    column_pass(0);
+    __syncthreads();
+    for (int n = 1; n < P; ++n) {
+        column_pass(n);
+        row_pass(n - 1);
+        __syncthreads();
+    }
+    row_pass(P - 1);
+
+#pragma unroll
+    for (int b = 0; b < JB; ++b) {
+        const int c = c0 + 16 * (jc0 + b) + li;
+        if (c >= Wd) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = r0 + 16 * rb + 4 * lg + v;
+            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * (Pa[b][v] / Qa[b][v]);   // eq. (10)
+        }
+    }
+}
+
 }  // namespace bfgc

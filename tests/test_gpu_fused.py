@@ -1,0 +1,152 @@
+"""GPU parity of the fused FP16/BF16 kernel (tile configuration TILE_FUSED:
+planes made in registers, both passes of eq. 7 as banded Toeplitz products on
+the matrix cores with FP32 accumulation, eqs. 8-10 folded in) against the FP64
+oracle, element by element, through the C ABI.
+
+Stated bounds (max |gpu - oracle| on the 0-255 scale), the same as for the
+three-kernel reduced-precision path. Storage rounding of the planes
+dominates: FP16 at sigma_r = 30 carries kappa * 2^-11 ~ 7e-3 of kernel error.
+The tap rounding to the stack type and the FP32 sums add little beside it
+(a CPU emulation of exactly this arithmetic gives 0.05-0.2 at sigma_r = 30).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+BOUND = {("f16", 30.0, 28): 2.5, ("f16", 30.0, 30): 2.5, ("f16", 50.0, 11): 0.5, ("bf16", 50.0, 11): 3.0}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda:0")
+
+
+def _np(t):
+    return t.detach().cpu().double().numpy()
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+# (shape, sigma_s): W = 3, 9, 15, 30, 45 covers the three kernel geometries
+# (W <= 16, W <= 32 with 64-column tiles, W <= 48 with 32-column tiles);
+# ragged tails in both directions, single rows and columns, W above a side.
+SHAPES = [
+    ((130, 200), 1.0), ((130, 200), 3.0), ((130, 200), 5.0), ((130, 200), 10.0), ((130, 200), 15.0),
+    ((64, 64), 10.0), ((65, 129), 10.0), ((1, 77), 2.0), ((129, 5), 2.0), ((7, 300), 5.0), ((300, 7), 5.0),
+    ((2, 2), 3.0), ((1, 1), 1.0),
+]
+
+
+@pytest.mark.parametrize("shape,sigma_s", SHAPES)
+def test_fused_f16_parity(torch_cuda, shape, sigma_s):
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    _log(f"fused f16 {shape} ss={sigma_s}")
+    f = edge_rich(*shape, seed=sum(shape) + 7).astype(np.float32).astype(np.float64)
+    y = _np(bf.gc_filter(_gpu(torch_cuda, f), sigma_s, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED))
+    ref = C.gcf(f, sigma_s, 30.0, 28)
+    err = np.abs(y - ref).max()
+    _log(f"fused f16 {shape} ss={sigma_s}: max err {err:.3e}")
+    assert np.isfinite(y).all()
+    assert err <= BOUND[("f16", 30.0, 28)]
+
+
+@pytest.mark.parametrize("dtype,sigma_r,N", [("f16", 50.0, 11), ("bf16", 50.0, 11), ("f16", 30.0, 30)])
+@pytest.mark.parametrize("sigma_s", [3.0, 10.0, 14.0])
+def test_fused_stated_bounds(torch_cuda, dtype, sigma_r, N, sigma_s):
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    f = edge_rich(200, 180, seed=21).astype(np.float32).astype(np.float64)
+    y = _np(bf.gc_filter(_gpu(torch_cuda, f), sigma_s, sigma_r, N, stack_dtype=dtype))
+    err = np.abs(y - C.gcf(f, sigma_s, sigma_r, N)).max()
+    _log(f"fused {dtype} ss={sigma_s} sr={sigma_r} N={N}: max err {err:.3e} (bound {BOUND[(dtype, sigma_r, N)]})")
+    assert err <= BOUND[(dtype, sigma_r, N)]
+
+
+def test_fused_is_default_deterministic_and_strided(torch_cuda):
+    import paper_1605_02178_amd as bf
+    from synth import edge_rich
+    torch = torch_cuda
+    f = _gpu(torch, edge_rich(150, 170, seed=5))
+    a = bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f16")
+    b = bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)
+    assert torch.equal(a, b)
+    assert torch.equal(a, bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f16"))
+    big = torch.full((150, 200), -1.0, device="cuda:0")
+    big[:, :170] = f
+    view = big[:, :170]
+    out = torch.full((150, 200), -5.0, device="cuda:0")
+    bf.gc_filter(view, 4.0, 30.0, 28, stack_dtype="f16", out=out[:, :170])
+    assert torch.equal(out[:, :170], a)
+    assert bool((out[:, 170:] == -5.0).all())
+
+
+def test_fused_argument_errors_and_fallback(torch_cuda):
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    torch = torch_cuda
+    f64 = edge_rich(160, 150, seed=8).astype(np.float32).astype(np.float64)
+    f = _gpu(torch, f64)
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f32", tile_config=bf.TILE_FUSED)
+    assert e.value.status == 2
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_filter(f, 17.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)   # W = 51
+    assert e.value.status == 2
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED, staged=True)
+    assert e.value.status == 1
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_filter_batched([f], [4.0], [30.0], [28], stack_dtype="f16", tile_config=bf.TILE_FUSED)
+    assert e.value.status == 2
+    # W = 51 without a tile flag takes the three-kernel path
+    y = _np(bf.gc_filter(f, 17.0, 30.0, 28, stack_dtype="f16"))
+    assert np.abs(y - C.gcf(f64, 17.0, 30.0, 28)).max() <= BOUND[("f16", 30.0, 28)]
+
+
+def test_fused_range_flag(torch_cuda):
+    import paper_1605_02178_amd as bf
+    from synth import ramp_rectangles
+    torch = torch_cuda
+    f = _gpu(torch, ramp_rectangles(100, 140, seed=2))
+    ws = torch.empty(bf.workspace_bytes(100, 140, 5.0, 28, "f16"), dtype=torch.uint8, device="cuda:0")
+    bf.gc_filter(f, 5.0, 30.0, 28, stack_dtype="f16", workspace=ws)
+    assert bf.read_flags(ws) == 0
+    for r, c in ((99, 139), (0, 0), (70, 3)):
+        g = f.clone()
+        g[r, c] = 256.0
+        bf.gc_filter(g, 5.0, 30.0, 28, stack_dtype="f16", workspace=ws)
+        assert bf.read_flags(ws) & bf.DEVFLAG_RANGE, (r, c)
+    g = f.clone()
+    g[40, 77] = float("nan")
+    bf.gc_filter(g, 5.0, 30.0, 28, stack_dtype="f16", workspace=ws)
+    assert bf.read_flags(ws) & bf.DEVFLAG_RANGE
+
+
+@pytest.mark.parametrize("N", [28, 30])
+def test_fused_headline_size_sampled(torch_cuda, N):
+    """4096^2 edge-rich, sigma_s = 10, sigma_r = 30, FP16 stack, fused tile (the
+    configuration the benchmark times for the FP16 stack): the oracle on a
+    512^2 centre crop and three 96^2 corner crops."""
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    f = edge_rich(4096, 4096, seed=3).astype(np.float32).astype(np.float64)
+    y = _np(bf.gc_filter(_gpu(torch_cuda, f), 10.0, 30.0, N, stack_dtype="f16", tile_config=bf.TILE_FUSED))
+    for reg in ((1792, 2304, 1792, 2304), (0, 96, 0, 96), (4000, 4096, 4000, 4096), (0, 96, 4000, 4096)):
+        ref = C.gcf(f, 10.0, 30.0, N, region=reg)
+        err = np.abs(y[reg[0]:reg[1], reg[2]:reg[3]] - ref).max()
+        _log(f"fused f16 N={N} 4096^2 crop {reg}: {err:.3e}")
+        assert err <= BOUND[("f16", 30.0, N)]
