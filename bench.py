@@ -2,17 +2,22 @@
 
 Workload (the headline configuration): one 4096 x 4096 edge-rich synthetic
 image (0/255 checkerboard with 64-pixel cells, 512 random star polygons,
-N(0, 5^2) noise, clipped), sigma_s = 10 (W = 30), sigma_r = 30, degree N = 28
-(30 stack planes), FP32 stack. A step is one full forward filter
-(bf_gc_forward: parameters, stack build, column pass, row pass + combine) with
-the image already resident in HBM.
+N(0, 5^2) noise, clipped), sigma_s = 10 (W = 30), sigma_r = 30, with the image
+already resident in HBM. A step is one full forward filter.
+
+Two stacks are compared at the same error against the direct filter (eq. 1):
+  FP32 stack at the paper's degree N = 28 (FP64 accumulation, three kernels);
+  FP16 stack at the smallest degree N' >= 28 (steps of 2) whose max-abs error
+  against the direct filter on a 64^2 centre crop is no worse than the FP32
+  stack's (times 1.05), run by the fused matrix-core kernel.
+The headline `value` is the faster of the two; both are reported.
 
 Prints one JSON line. Besides the contract fields it carries
-  roofline      dominant kernel, timed with HIP events on its launch stream
+  roofline      the headline path's dominant kernel, timed with HIP events on
+                its launch stream
   cpu_baseline  the plain-C FP64 oracle on the host cores
-  fp16_stack    the same workload with an FP16 stack, at the smallest degree
-                whose error against the direct filter is no worse than FP32's
-  accuracy      max-abs errors on crops against both FP64 oracles
+  fp32_stack, fp16_stack   per-stack timings, kernels and errors
+  batched       the uneven 64-image batch, one graph launch vs a per-image loop
 """
 from __future__ import annotations
 
@@ -29,17 +34,43 @@ sys.path.insert(0, ROOT)
 METRIC = "Mpixel/s at 4096², σs=10 (FP32 vs FP16 stack, same error); HBM GB/s % peak"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP64_VALU_TFS = 78.6      # 256 CU x 64 lanes x 2 flop x 2.4 GHz, FP64 FMA at full rate
+PEAK_F16_MFMA_TFS = 2500.0     # dense FP16 / BF16 matrix peak
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def fused_mfma_count(H, Wd, W, P):
+    """Matrix-core instructions one launch of the fused kernel issues (16x16x32
+    each): per tile and plane, the column pass runs the chunks each of its 4
+    row blocks needs for each of the 8 halo-column blocks, the row pass the
+    chunks each output column block needs for each of the 4 row blocks."""
+    Q = 3 if W <= 16 else 4 if W <= 32 else 5
+    TC = 64 if W <= 32 else 32
+    QA, QB = (2 * W + 15) // 32, Q - 2
+    col = 8 * sum(min(Q - 1, j // 2 + (QB if j % 2 else QA)) - j // 2 + 1 for j in range(4))
+    if TC == 64:
+        row = 4 * 2 * ((QA + 1) + (QB + 1))
+    else:
+        row = 4 * 2 * 4
+    tiles = math.ceil(H / 64) * math.ceil(Wd / TC)
+    return tiles * P * (col + row)
+
+
 def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch):
     """Algorithmic bytes and flops of one launch of `name` and the bound it
-    sits against (see the design doc for the per-pixel figures)."""
+    sits against. Convolution work: 2 (2W+1) flops per pixel, plane and pass;
+    stack bytes: esize per pixel and plane for each write or read."""
     px = H * Wd
     taps = 2 * W + 1
+    if name == "k_fused_mfma":
+        flops = 2.0 * 2.0 * taps * P * px
+        issued = fused_mfma_count(H, Wd, W, P) * 16 * 16 * 32 * 2.0
+        return {"bound": "mfma", "achieved": flops / ms_per_launch / 1e9, "peak": PEAK_F16_MFMA_TFS,
+                "unit": "TFLOP/s", "flops_per_launch": flops, "bytes_per_launch": px * 8,
+                "mfma_issued_tflops": issued / ms_per_launch / 1e9,
+                "hbm_gbs_algorithmic": px * 8 / ms_per_launch / 1e6}
     if name == "k_stack_build":
         byts = px * (4 + P * esize)
         return {"bound": "hbm", "achieved": byts / ms_per_launch / 1e6, "peak": PEAK_HBM_GBS, "unit": "GB/s",
@@ -79,7 +110,7 @@ def measured_traffic(kernel, stack_tag, profile_name):
     if rec.get("source_sha256_16") != source_hash():
         return None
     base = {"k_hpass_combine": "k_hpass<", "k_hpass": "k_hpass<", "k_vpass": "k_vpass<",
-            "k_stack_build": "k_stack_build<", "k_combine": "k_combine<"}[kernel]
+            "k_stack_build": "k_stack_build<", "k_combine": "k_combine<", "k_fused_mfma": "k_fused_mfma<"}[kernel]
     for name, v in rec["kernels"].items():
         if name.startswith(base + stack_tag) and (kernel != "k_hpass_combine" or name.endswith("true>")) \
                 and (kernel != "k_hpass" or name.endswith("false>")):
@@ -198,9 +229,13 @@ def main():
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--sigma-s", type=float, default=10.0)
     ap.add_argument("--sigma-r", type=float, default=30.0)
-    ap.add_argument("--degree", type=int, default=28)
+    ap.add_argument("--degree", type=int, default=28, help="degree of the FP32 stack")
+    ap.add_argument("--fp16-degree", type=int, default=0,
+                    help="degree of the FP16 stack (0: smallest one matching the FP32 stack's error)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16-stack comparison")
+    ap.add_argument("--no-fp16", action="store_true", help="skip the FP16 stack")
+    ap.add_argument("--no-fp32-timing", action="store_true",
+                    help="run the FP32 stack once for its error only, without timing it")
     ap.add_argument("--cpu-rows", type=int, default=1024)
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--batch-steps", type=int, default=5)
@@ -208,25 +243,24 @@ def main():
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding is design-only, "
-              "see DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
     import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from paper_1605_02178_amd import autotune
     from synth import edge_rich
 
     H = Wd = args.size
     ss, sr, N = args.sigma_s, args.sigma_r, args.degree
     W = bf.radius(ss)
-    P = N + 2
     log(f"bench: generating {H}x{Wd} edge-rich image")
     f64 = edge_rich(H, Wd, seed=3).astype(np.float32).astype(np.float64)
     f = torch.tensor(f64, dtype=torch.float32, device="cuda:0")
-    out = torch.empty_like(f)
-    ws = torch.empty(bf.workspace_bytes(H, Wd, ss, N, "f32"), dtype=torch.uint8, device="cuda:0")
 
     if args.copy_mib:
         a = torch.ones(args.copy_mib * (1 << 18), dtype=torch.float32, device="cuda:0")
@@ -236,81 +270,98 @@ def main():
         del a, b
         log(f"bench: calibration copy of {args.copy_mib} MiB done")
 
-    from paper_1605_02178_amd import autotune
-    cfg32, tune32 = autotune.tune_forward(f, ss, sr, N, "f32", out=out, workspace=ws)
-    log(f"bench: tile configuration {cfg32} {bf.TILE_CONFIGS[cfg32]} (ms per config {tune32})")
-    log(f"bench: FP32 stack, {args.warmup} warmup + {args.steps} timed steps")
-    ms, prof = time_forward(bf, f, out, ws, ss, sr, N, "f32", args.steps, args.warmup, cfg=cfg32)
-    value = H * Wd / 1e6 / (ms / 1e3)
-    kernels = {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
-    dom = max((k for k in kernels if k != "k_put_params"), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-    roof = kernel_roofline(dom, H, Wd, W, P, 4, kernels[dom]["avg_ms"])
-    roof = {"kernel": dom, **roof}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(dom, "StF32", f"forward_{H}_s{ss:g}_n{N}_f32")
-    roof["traffic_source"] = f"profiles/forward_{H}_s{ss:g}_n{N}_f32.md"
-    roof["avg_ms"] = kernels[dom]["avg_ms"]
-    log(f"bench: FP32 {ms:.3f} ms/step, {value:.1f} Mpx/s; kernels {kernels}")
-
-    # accuracy on crops against both oracles
-    from oracle import native as C
-    y = out.cpu().double().numpy()
+    # error references: the GC oracle on a 256^2 centre crop, the direct filter on a 64^2 one
     c0 = H // 2 - 128
     reg = (c0, c0 + 256, c0, c0 + 256)
-    gc_ref = C.gcf(f64, ss, sr, N, region=reg)
     d0 = H // 2 - 32
     dreg = (d0, d0 + 64, d0, d0 + 64)
     direct_ref = C.direct_bf(f64, ss, sr, region=dreg)
-    acc32 = {"max_abs_vs_gc_oracle_256c": float(np.abs(y[c0:c0 + 256, c0:c0 + 256] - gc_ref).max()),
-             "max_abs_vs_direct_64c": float(np.abs(y[d0:d0 + 64, d0:d0 + 64] - direct_ref).max())}
 
-    result = {
-        "metric": METRIC, "value": round(value, 2), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"edge-rich {H}x{Wd}, sigma_s={ss:g} (W={W}), sigma_r={sr:g}, N={N} "
-                               f"({P} planes), FP32 stack, FP64 accumulation",
-                   "image": f"{H}x{Wd}", "sigma_s": ss, "sigma_r": sr, "degree": N, "stack": "f32",
-                   "path": "fused: build | column pass | row pass + combine",
-                   "tile_config": cfg32, "tile_config_ms": [None if t is None else round(t, 3) for t in tune32]},
-        "roofline": roof,
-        "kernels": kernels,
-        "accuracy": acc32,
-    }
+    def errors(y, n):
+        gc_ref = C.gcf(f64, ss, sr, n, region=reg)
+        return {"max_abs_vs_gc_oracle_256c": float(np.abs(y[c0:c0 + 256, c0:c0 + 256] - gc_ref).max()),
+                "max_abs_vs_direct_64c": float(np.abs(y[d0:d0 + 64, d0:d0 + 64] - direct_ref).max())}
 
+    def run_stack(stack, n, time_it):
+        out = torch.empty_like(f)
+        ws = torch.empty(bf.workspace_bytes(H, Wd, ss, n, stack), dtype=torch.uint8, device="cuda:0")
+        bf.gc_filter(f, ss, sr, n, stack_dtype=stack, out=out, workspace=ws)
+        rec = {"degree": n, "planes": n + 2, **errors(out.cpu().double().numpy(), n)}
+        if not time_it:
+            return rec
+        cfg, tune = autotune.tune_forward(f, ss, sr, n, stack, out=out, workspace=ws)
+        log(f"bench: {stack} N={n} tile configuration {cfg} {bf.TILE_CONFIGS[cfg]} (ms per config {tune})")
+        ms, prof = time_forward(bf, f, out, ws, ss, sr, n, stack, args.steps, args.warmup, cfg=cfg)
+        kernels = {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
+        dom = max((k for k in kernels if k != "k_put_params"),
+                  key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+        roof = kernel_roofline(dom, H, Wd, W, n + 2, 4 if stack == "f32" else 2, kernels[dom]["avg_ms"])
+        roof = {"kernel": dom, **roof}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        prof_name = f"forward_{H}_s{ss:g}_n{n}_{stack}"
+        roof["traffic"] = measured_traffic(dom, {"f32": "StF32", "f16": "MmaF16", "bf16": "MmaBF16"}[stack]
+                                           if dom == "k_fused_mfma" else {"f32": "StF32", "f16": "StF16",
+                                                                          "bf16": "StBF16"}[stack], prof_name)
+        roof["traffic_source"] = f"profiles/{prof_name}.md"
+        roof["avg_ms"] = kernels[dom]["avg_ms"]
+        rec.update({"ms_per_step": round(ms, 4), "value": round(H * Wd / 1e6 / (ms / 1e3), 2), "unit": "Mpixel/s",
+                    "tile_config": cfg, "tile_config_ms": [None if t is None else round(t, 3) for t in tune],
+                    "kernels": kernels, "roofline": roof})
+        log(f"bench: {stack} N={n} {ms:.3f} ms/step, {rec['value']:.1f} Mpx/s; kernels {kernels}")
+        return rec
+
+    log("bench: FP32 stack")
+    r32 = run_stack("f32", N, not args.no_fp32_timing)
+    r16 = None
     if not args.no_fp16:
-        # smallest N' >= N whose error against the direct filter (64^2 crop) is
-        # no worse than the FP32 stack's at N
-        target = acc32["max_abs_vs_direct_64c"] * 1.05
-        ws16 = None
-        chosen = None
-        for N16 in range(N, N + 9, 2):
-            ws16 = torch.empty(bf.workspace_bytes(H, Wd, ss, N16, "f16"), dtype=torch.uint8, device="cuda:0")
-            o16 = torch.empty_like(f)
-            bf.gc_filter(f, ss, sr, N16, stack_dtype="f16", out=o16, workspace=ws16)
-            e = float(np.abs(o16.cpu().double().numpy()[d0:d0 + 64, d0:d0 + 64] - direct_ref).max())
-            chosen = (N16, e, o16)
-            if e <= target:
-                break
-        N16, e16, o16 = chosen
-        cfg16, _ = autotune.tune_forward(f, ss, sr, N16, "f16", out=o16, workspace=ws16)
-        ms16, prof16 = time_forward(bf, f, o16, ws16, ss, sr, N16, "f16", args.steps, args.warmup, cfg=cfg16)
-        gc16 = C.gcf(f64, ss, sr, N16, region=reg)
-        result["fp16_stack"] = {
-            "degree": N16, "value": round(H * Wd / 1e6 / (ms16 / 1e3), 2), "unit": "Mpixel/s",
-            "ms_per_step": round(ms16, 4), "max_abs_vs_direct_64c": e16, "fp32_max_abs_vs_direct_64c": target / 1.05,
-            "same_error": e16 <= target,
-            "max_abs_vs_gc_oracle_256c": float(np.abs(o16.cpu().double().numpy()[c0:c0 + 256, c0:c0 + 256] - gc16).max()),
-            "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof16.items()},
-        }
-        log(f"bench: FP16 N={N16} {ms16:.3f} ms/step")
+        target = r32["max_abs_vs_direct_64c"] * 1.05
+        if args.fp16_degree:
+            n16 = args.fp16_degree
+        else:
+            n16 = N
+            while n16 < N + 8:
+                o16 = bf.gc_filter(f, ss, sr, n16, stack_dtype="f16")
+                e = float(np.abs(o16.cpu().double().numpy()[d0:d0 + 64, d0:d0 + 64] - direct_ref).max())
+                log(f"bench: FP16 N={n16}: max abs vs direct {e:.4f} (target {target:.4f})")
+                if e <= target:
+                    break
+                n16 += 2
+        log(f"bench: FP16 stack, N={n16}")
+        r16 = run_stack("f16", n16, True)
+        r16["same_error"] = r16["max_abs_vs_direct_64c"] <= target
+        r16["fp32_max_abs_vs_direct_64c"] = r32["max_abs_vs_direct_64c"]
+
+    cands = [("f32", r32)] if "value" in r32 else []
+    if r16 is not None and (r16["same_error"] or not cands):
+        cands.append(("f16", r16))
+    if not cands:
+        print("bench.py: nothing was timed (--no-fp32-timing together with --no-fp16)", file=sys.stderr)
+        sys.exit(2)
+    head_stack, head = max(cands, key=lambda c: c[1]["value"])
+    path = ("fused matrix-core kernel: planes in registers, both passes as banded Toeplitz MFMA "
+            "(FP16 x FP16, FP32 accumulation), combine folded in" if head["roofline"]["kernel"] == "k_fused_mfma"
+            else "build | column pass | row pass + combine, FP64 accumulation")
+    result = {
+        "metric": METRIC, "value": head["value"], "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f16" if head_stack == "f16" else "f64", "data": "synthetic",
+        "config": {"workload": f"edge-rich {H}x{Wd}, sigma_s={ss:g} (W={W}), sigma_r={sr:g}, "
+                               f"{head_stack.upper()} stack at N={head['degree']} ({head['planes']} planes), "
+                               f"same error against the direct filter as the FP32 stack at N={N}",
+                   "image": f"{H}x{Wd}", "sigma_s": ss, "sigma_r": sr, "degree": head["degree"],
+                   "stack": head_stack, "path": path, "tile_config": head["tile_config"]},
+        "roofline": head["roofline"],
+        "fp32_stack": r32,
+    }
+    if r16 is not None:
+        result["fp16_stack"] = r16
 
     if not args.no_batched:
         result["batched"] = bench_batched(bf, args.batch_steps, log)
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        result["cpu_baseline"] = cpu_baseline(f64, ss, sr, N, min(args.cpu_rows, H))
+        result["cpu_baseline"] = cpu_baseline(f64, ss, sr, head["degree"], min(args.cpu_rows, H))
 
     print(json.dumps(result), flush=True)
 

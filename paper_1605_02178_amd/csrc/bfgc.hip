@@ -17,6 +17,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "bfgc.h"
@@ -240,9 +241,12 @@ template <class M, int Q, int TC, int QA>
 static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const double *prm,
                                 const ParamLayout &L, float mu, unsigned *flag, hipStream_t stream) {
     dim3 grid((Wd + TC - 1) / TC, (H + kFusedRows - 1) / kFusedRows);
+    // FP16: every plane carries 2^14 (plane 0 peaks at 2^14; the smallest plane
+    // maximum e^{-mu/2} 2^14 stays a normal FP16 number while sigma_r >= 21).
+    const float prescale = std::is_same<M, MmaF16>::value ? 16384.0f : 1.0f;
     ProfScope prof_("k_fused_mfma", stream);
     hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, prm,
-                       L.off_taps, L.off_cq, L.off_cp, L.off_scale, L.W, L.N, mu, flag);
+                       L.off_taps, L.off_cq, L.off_scale, L.W, L.N, mu, prescale, flag);
     return check_launch("k_fused_mfma");
 }
 

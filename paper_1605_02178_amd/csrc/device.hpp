@@ -671,26 +671,43 @@ constexpr int kFusedPitch = kFusedHaloC + 8; // LDS row pitch (elements) of the 
 // kernel geometry B = Q - 2 and A is Q - 3 or Q - 2 (template parameter QA).
 __host__ __device__ constexpr int fused_qa(int W) { return (2 * W + 15) / 32; }
 
+// Symmetric extension for |overhang| <= M (one reflection).
+__device__ __forceinline__ int mirror1(int i, int M) { return i < 0 ? -1 - i : (i >= M ? 2 * M - 1 - i : i); }
+
+// Halo index -> image index. Positions at or beyond M + W only feed outputs at
+// or beyond M, which are not stored, so they are clamped to M + W - 1 first;
+// with W < M one reflection then suffices.
+__device__ __forceinline__ int halo_index(int i, int M, int W, bool one_reflection) {
+    return one_reflection ? mirror1(min(i, M + W - 1), M) : mirror(i, M);
+}
+
 template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
                                                     int Wd, int ld, const double *__restrict__ prm, int off_taps,
-                                                    int off_cq, int off_cp, int off_scale, int W, int N, float mu,
-                                                    unsigned *__restrict__ flag) {
+                                                    int off_cq, int off_scale, int W, int N, float mu,
+                                                    float prescale, unsigned *__restrict__ flag) {
     typedef typename M::E E;
     typedef typename M::V V;
     constexpr int QB = Q - 2;
     constexpr int JB = TC / 32;                  // output column blocks per wave in the row pass
+    constexpr int kTabPad = 32;                  // zero taps below t = 0 in the LDS tap table
+    constexpr int kTab = kTabPad + 32 * Q;       // covers t in [-32, 32Q)
     static_assert((TC == 64 && Q <= 4) || (TC == 32 && Q == 5), "geometry");
     static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
     __shared__ __align__(16) E ybuf[2][kFusedRows * kFusedPitch];
+    __shared__ E tab[kTab];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
     const int r0 = blockIdx.y * kFusedRows, c0 = blockIdx.x * TC;
     const int P = N + 2;
-    auto tap = [&](int t) -> float {
-        return (t >= 0 && t <= 2 * W) ? (float)prm[off_taps + kTapPad - 1 + t] : 0.0f;
-    };
+
+    // Tap table in LDS: tab[kTabPad + t] = w[t] for t in [0, 2W], zero elsewhere.
+    for (int i = threadIdx.x; i < kTab; i += blockDim.x) {
+        const int t = i - kTabPad;
+        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? (float)prm[off_taps + kTapPad - 1 + t] : 0.0f);
+    }
+    __syncthreads();
 
     // Toeplitz fragments tf[d+1], d = -1 .. 2Q-2: element jj of lane (li, lg)
     // is w[16d + 8lg + jj - li].
@@ -698,12 +715,12 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
 #pragma unroll
     for (int d = -1; d < 2 * Q - 1; ++d)
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = M::cvt(tap(16 * d + 8 * lg + jj - li));
+        for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = tab[kTabPad + 16 * d + 8 * lg + jj - li];
 
     // Row-pass assignment: row block rb = wave / 2. With 64-column tiles the
     // wave takes column blocks 2p, 2p+1 (p = wave & 1), which read the halo
     // chunks shifted by p and use the fragments of blocks 0, 1. With 32-column
-    // tiles it takes block jc = p and builds that block's fragments rf[q].
+    // tiles it takes block jc = p and uses that block's fragments rf[q].
     const int rb = wave >> 1;
     const int p = wave & 1;
     const int jc0 = p * JB;
@@ -712,33 +729,51 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) rf[q][jj] = M::cvt(tap(32 * q + 8 * lg + jj - 16 * p - li));
+            for (int jj = 0; jj < 8; ++jj) rf[q][jj] = tab[kTabPad + 32 * q + 8 * lg + jj - 16 * p - li];
     }
 
     // Column-pass A operand state: halo column 16 wave + li, halo rows
-    // 32q + 8lg + jj; s and the running H_n in FP32.
+    // 32q + 8lg + jj; s and the running 2^K H_n in FP32 (one scale 2^K for
+    // every plane keeps FP16 planes normal: it cancels in P/Q).
+    const bool one_ref = W < H && W < Wd;
     const int hc = c0 - W + 16 * wave + li;
-    const int mc = mirror(hc, Wd);
+    const int mc = halo_index(hc, Wd, W, one_ref);
     const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
     float sv[Q][8], hv[Q][8];
+    {
+        // rows of the halo inside the image need no extension (most tiles)
+        const bool rows_inside = r0 - W >= 0 && r0 - W + 32 * Q <= H;
+        const float *col = f + mc;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const int hr = r0 - W + 32 * q + 8 * lg + jj;
+                sv[q][jj] = col[(long long)(rows_inside ? hr : halo_index(hr, H, W, one_ref)) * ld];
+            }
+        }
+    }
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
             const int hr = r0 - W + 32 * q + 8 * lg + jj;
-            const float x = f[(long long)mirror(hr, H) * ld + mc];
+            const float x = sv[q][jj];
             if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H) bad |= !(x >= 0.0f && x <= 255.0f);
             const float s = (x - (float)kTc) * (float)(1.0 / kTh);      // eq. (17)
             sv[q][jj] = s;
-            hv[q][jj] = expf(-0.5f * mu * s * s);                         // H_0
+            hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;            // 2^K H_0
         }
     }
     if (flag && __any(bad) && lane == __ffsll((unsigned long long)__ballot(bad)) - 1) atomicOr(flag, BF_DEVFLAG_RANGE);
 
     // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
-    // 16 (jc0 + b) + li.
-    float sc[JB][4], pw[JB][4], pwp[JB][4], Pa[JB][4], Qa[JB][4];
+    // 16 (jc0 + b) + li. With u_n = s^n Hbar_n the sums are accumulated as
+    //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
+    // so one product serves both; P = Ps / s, and at s = 0, where only the
+    // n = 1 term of P survives, P = b_0 Hbar_1 (kept in z1).
+    float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4], z1[JB][4];
 #pragma unroll
     for (int b = 0; b < JB; ++b) {
         const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
@@ -746,22 +781,23 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
         for (int v = 0; v < 4; ++v) {
             const int r = min(r0 + 16 * rb + 4 * lg + v, H - 1);
             sc[b][v] = (f[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
-            pw[b][v] = 1.0f;
-            pwp[b][v] = 0.0f;
-            Pa[b][v] = 0.0f;
+            pw[b][v] = sc[b][v];
+            Ps[b][v] = 0.0f;
             Qa[b][v] = 0.0f;
         }
     }
+    // b_n = cq_n 2^k_n (the parameter block stores the FP16 three-kernel
+    // path's scaled coefficients; the product is exact).
+    auto bcoef = [&](int n) -> float { return (float)(prm[off_cq + n] * prm[off_scale + n]); };
 
     // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
     auto column_pass = [&](int n) {
-        const float scale = (float)prm[off_scale + n];
         V a[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
-                a[q][jj] = M::cvt(hv[q][jj] * scale);
+                a[q][jj] = M::cvt(hv[q][jj]);
                 hv[q][jj] *= sv[q][jj];                                   // H_{n+1} = H_n s
             }
         }
@@ -778,10 +814,9 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
             *(typename M::V4 *)(yb + (16 * j + li) * kFusedPitch + 16 * wave + 4 * lg) = o;
         }
     };
-    // Row pass of plane n from ybuf[n & 1] and its share of eqs. 8-9.
-    auto row_pass = [&](int n) {
+    // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
+    auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
         const E *src = ybuf[n & 1] + (16 * rb + li) * kFusedPitch + 8 * lg;
-        mf_f4 z[JB];
         if (TC == 64) {
             V ya[QB + 1];
 #pragma unroll
@@ -799,16 +834,18 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
             for (int q = 0; q < 4; ++q) acc = M::mma(*(const V *)(src + 32 * q), rf[q], acc);
             z[0] = acc;
         }
-        const float cq = n <= N ? (float)prm[off_cq + n] : 0.0f;
-        const float cp = n >= 1 ? (float)prm[off_cp + n - 1] : 0.0f;
+    };
+    // Eqs. 8-9 for plane n >= 1 (pw = s^n on entry).
+    auto combine = [&](int n, const mf_f4 (&z)[JB]) {
+        const float bp = bcoef(n - 1);
+        const float bq = n <= N ? bcoef(n) : 0.0f;
 #pragma unroll
         for (int b = 0; b < JB; ++b) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float zz = z[b][v];
-                Qa[b][v] = fmaf(cq * pw[b][v], zz, Qa[b][v]);
-                Pa[b][v] = fmaf(cp * pwp[b][v], zz, Pa[b][v]);
-                pwp[b][v] = pw[b][v];
+                const float u = pw[b][v] * z[b][v];
+                Ps[b][v] = fmaf(bp, u, Ps[b][v]);
+                Qa[b][v] = fmaf(bq, u, Qa[b][v]);
                 pw[b][v] *= sc[b][v];
             }
         }
@@ -818,13 +855,42 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
     // plane n sit between the same two barriers (different LDS buffers).
     column_pass(0);
     __syncthreads();
-    for (int n = 1; n < P; ++n) {
+    column_pass(1);
+    {
+        mf_f4 z[JB];
+        row_pass(0, z);
+        const float b0 = bcoef(0);
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Qa[b][v] = b0 * z[b][v];
+    }
+    __syncthreads();
+    column_pass(2);
+    {
+        mf_f4 z[JB];
+        row_pass(1, z);
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z1[b][v] = z[b][v];
+        combine(1, z);
+    }
+    __syncthreads();
+    for (int n = 3; n < P; ++n) {
         column_pass(n);
-        row_pass(n - 1);
+        mf_f4 z[JB];
+        row_pass(n - 1, z);
+        combine(n - 1, z);
         __syncthreads();
     }
-    row_pass(P - 1);
+    {
+        mf_f4 z[JB];
+        row_pass(P - 1, z);
+        combine(P - 1, z);
+    }
 
+    const float b0 = bcoef(0);
 #pragma unroll
     for (int b = 0; b < JB; ++b) {
         const int c = c0 + 16 * (jc0 + b) + li;
@@ -832,7 +898,9 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = r0 + 16 * rb + 4 * lg + v;
-            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * (Pa[b][v] / Qa[b][v]);   // eq. (10)
+            const float s = sc[b][v];
+            const float ratio = s != 0.0f ? Ps[b][v] / (s * Qa[b][v]) : b0 * z1[b][v] / Qa[b][v];
+            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
         }
     }
 }

@@ -150,3 +150,25 @@ def test_fused_headline_size_sampled(torch_cuda, N):
         err = np.abs(y[reg[0]:reg[1], reg[2]:reg[3]] - ref).max()
         _log(f"fused f16 N={N} 4096^2 crop {reg}: {err:.3e}")
         assert err <= BOUND[("f16", 30.0, N)]
+
+
+def test_fused_centre_value_pixels(torch_cuda):
+    """Pixels equal to t_c = 127.5 have s = 0, where the kernel takes P from
+    its n = 1 term instead of dividing the accumulated s P by s: a constant
+    127.5 image stays 127.5, and an image with many such pixels matches the
+    oracle."""
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    torch = torch_cuda
+    for dtype, sr, N in (("f16", 30.0, 28), ("bf16", 50.0, 11)):
+        y = bf.gc_filter(torch.full((70, 90), 127.5, device="cuda:0"), 4.0, sr, N, stack_dtype=dtype)
+        assert float((y - 127.5).abs().max()) <= 1e-3, dtype
+        f = edge_rich(96, 130, seed=31).astype(np.float32)
+        rng = np.random.default_rng(31)
+        f[rng.random(f.shape) < 0.2] = 127.5
+        f64 = f.astype(np.float64)
+        out = _np(bf.gc_filter(_gpu(torch, f64), 4.0, sr, N, stack_dtype=dtype))
+        err = np.abs(out - C.gcf(f64, 4.0, sr, N)).max()
+        _log(f"fused {dtype} with s = 0 pixels: max err {err:.3e}")
+        assert np.isfinite(out).all() and err <= BOUND[(dtype, sr, N)]
