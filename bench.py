@@ -154,13 +154,13 @@ def time_forward(bf, f, out, ws, sigma_s, sigma_r, N, stack, steps, warmup, prof
     return ms, prof
 
 
-def bench_batched(bf, steps, log):
+def bench_batched(bf, steps, log, stack="f32"):
     """Uneven batch: 64 edge-rich images, long side uniform over
     {256, 384, ..., 2048}, square or 2:1, sigma_s ~ U[2,16], sigma_r ~ U[10,60],
-    N from the degree rule; FP32 stack. One graph launch of the batch against
-    a loop of single-image forwards, both with the autotuned tile
-    configuration. Images outside the FP32 domain (sigma_r below about 20) are
-    still filtered (allow flag), for throughput."""
+    N from the degree rule. One graph launch of the batch against a loop of
+    single-image forwards, both with the autotuned tile configuration. Images
+    outside the stack type's domain (sigma_r below about 20 for FP32, about
+    28 for FP16) are still filtered (allow flag), for throughput."""
     import torch
     from paper_1605_02178_amd import autotune
     from synth import batch_specs
@@ -170,22 +170,22 @@ def bench_batched(bf, steps, log):
     sr = [sp.sigma_r for sp in specs]
     deg = [bf.degree_rule(x) for x in sr]
     px = sum(x.numel() for x in imgs)
-    ws = torch.empty(bf.batched_workspace_bytes([tuple(x.shape) for x in imgs], ss, deg), dtype=torch.uint8,
+    ws = torch.empty(bf.batched_workspace_bytes([tuple(x.shape) for x in imgs], ss, deg, stack), dtype=torch.uint8,
                      device="cuda:0")
     outs = [torch.empty_like(x) for x in imgs]
-    log(f"bench: batched {len(imgs)} images, {px / 1e6:.1f} Mpx, autotuning")
-    cfg, times = autotune.tune_batched(imgs, ss, sr, deg, repeats=2, allow_ill_conditioned=True, workspace=ws)
+    log(f"bench: batched {len(imgs)} images, {px / 1e6:.1f} Mpx, {stack} stack, autotuning")
+    cfg, times = autotune.tune_batched(imgs, ss, sr, deg, stack, repeats=2, allow_ill_conditioned=True, workspace=ws)
 
     def run_batch():
-        bf.gc_filter_batched(imgs, ss, sr, deg, graph=True, tile_config=cfg, allow_ill_conditioned=True, outs=outs,
-                             workspace=ws)
-    single_ws = torch.empty(max(bf.workspace_bytes(x.shape[0], x.shape[1], s_, d) for x, s_, d in zip(imgs, ss, deg)),
-                            dtype=torch.uint8, device="cuda:0")
+        bf.gc_filter_batched(imgs, ss, sr, deg, stack_dtype=stack, graph=True, tile_config=cfg,
+                             allow_ill_conditioned=True, outs=outs, workspace=ws)
+    single_ws = torch.empty(max(bf.workspace_bytes(x.shape[0], x.shape[1], s_, d, stack)
+                                for x, s_, d in zip(imgs, ss, deg)), dtype=torch.uint8, device="cuda:0")
 
     def run_loop():
         for k, x in enumerate(imgs):
-            bf.gc_filter(x, ss[k], sr[k], deg[k], out=outs[k], workspace=single_ws, tile_config=cfg,
-                         allow_ill_conditioned=True)
+            bf.gc_filter(x, ss[k], sr[k], deg[k], stack_dtype=stack, out=outs[k], workspace=single_ws,
+                         tile_config=cfg, allow_ill_conditioned=True)
 
     res = {}
     for name, fn in (("batched_graph", run_batch), ("per_image_loop", run_loop)):
@@ -200,10 +200,10 @@ def bench_batched(bf, steps, log):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
         res[name] = {"ms": round(ms, 3), "mpx_s": round(px / 1e6 / (ms / 1e3), 1)}
-        log(f"bench: {name} {ms:.2f} ms")
+        log(f"bench: {stack} {name} {ms:.2f} ms")
     res["speedup"] = round(res["per_image_loop"]["ms"] / res["batched_graph"]["ms"], 3)
-    res.update({"images": len(imgs), "megapixels": round(px / 1e6, 2), "tile_config": cfg,
-                "tile_times_ms": [round(t, 3) for t in times], "steps": steps,
+    res.update({"stack": stack, "images": len(imgs), "megapixels": round(px / 1e6, 2), "tile_config": cfg,
+                "tile_times_ms": [None if t is None else round(t, 3) for t in times], "steps": steps,
                 "mean_degree_px_weighted": round(sum(d * x.numel() for d, x in zip(deg, imgs)) / px, 1)})
     return res
 
@@ -357,7 +357,9 @@ def main():
         result["fp16_stack"] = r16
 
     if not args.no_batched:
-        result["batched"] = bench_batched(bf, args.batch_steps, log)
+        result["batched"] = bench_batched(bf, args.batch_steps, log, "f32")
+        if not args.no_fp16:
+            result["batched_fp16"] = bench_batched(bf, args.batch_steps, log, "f16")
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

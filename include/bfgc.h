@@ -209,9 +209,14 @@ bf_status bf_gc_combine(const float *f, const void *stack, int height, int width
 
 /*
  * Batched forward: `count` images of uneven sizes, each with its own sigma_s,
- * sigma_r and N, in one graph of three persistent kernels (build, column
- * pass, row pass + combine) after one copy of a small descriptor blob; each
- * kernel's blocks stride over that phase's tiles of the whole batch.
+ * sigma_r and N, in one graph after one copy of a small descriptor blob.
+ * Three-kernel form (tile configurations 0-3, and the FP32 stack): three
+ * persistent kernels (build, column pass, row pass + combine), each striding
+ * over that phase's tiles of the whole batch. Fused form (BF_TILE_FUSED, the
+ * default for FP16/BF16 stacks when every image's radius is at most
+ * BF_FUSED_MAX_RADIUS; with the flag given, larger radii get
+ * BF_ERR_UNSUPPORTED): one persistent kernel per geometry class present
+ * (radius ranges with their own tile shape), striding over the class's tiles.
  * descs and per_image_status are host arrays, read and written before
  * return. Each image gets the status its own bf_gc_forward would return from
  * the host checks; images whose status is not BF_OK are skipped (their out is
@@ -235,7 +240,8 @@ typedef struct {
 } bf_image_desc;
 
 /* Workspace for a batch: sizes every image with valid dimensions and
- * parameters (pointers are not read), whatever its conditioning. */
+ * parameters (pointers are not read), whatever its conditioning, for the
+ * three-kernel form (which needs more than the fused form). */
 size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int stack_dtype);
 bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, unsigned flags,
                         int *per_image_status, void *ws, size_t ws_bytes, void *stream);

@@ -138,16 +138,19 @@ def tune_batched(images, sigmas_s, sigmas_r, degrees, stack_dtype="f32", repeats
                  allow_ill_conditioned=False, workspace=None):
     """Times every tile configuration of bf_gc_batched on this batch, caches
     the fastest and returns (config, times_ms)."""
-    from . import TILE_FUSED, gc_filter_batched
+    from . import TILE_CONFIGS, TILE_FUSED, FUSED_MAX_RADIUS, _dtype_code, gc_filter_batched, radius
     outs = None
-    times = []
-    for c in range(TILE_FUSED):                  # the batched form runs the three-kernel tiles
+    times = [None] * len(TILE_CONFIGS)
+    cfgs = list(range(TILE_FUSED))
+    if _dtype_code(stack_dtype) != 0 and all(radius(s) <= FUSED_MAX_RADIUS for s in sigmas_s):
+        cfgs.append(TILE_FUSED)
+    for c in cfgs:
         def run():
             nonlocal outs
             outs, _ = gc_filter_batched(images, sigmas_s, sigmas_r, degrees, stack_dtype=stack_dtype, graph=graph,
                                         tile_config=c, allow_ill_conditioned=allow_ill_conditioned, outs=outs,
                                         workspace=workspace)
-        times.append(_time(run, repeats))
-    best = min(range(len(times)), key=times.__getitem__)
+        times[c] = _time(run, repeats)
+    best = min(cfgs, key=times.__getitem__)
     _store(batched_key([tuple(x.shape) for x in images], sigmas_s, degrees, stack_dtype), best, times)
     return best, times

@@ -241,9 +241,7 @@ template <class M, int Q, int TC, int QA>
 static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const double *prm,
                                 const ParamLayout &L, float mu, unsigned *flag, hipStream_t stream) {
     dim3 grid((Wd + TC - 1) / TC, (H + kFusedRows - 1) / kFusedRows);
-    // FP16: every plane carries 2^14 (plane 0 peaks at 2^14; the smallest plane
-    // maximum e^{-mu/2} 2^14 stays a normal FP16 number while sigma_r >= 21).
-    const float prescale = std::is_same<M, MmaF16>::value ? 16384.0f : 1.0f;
+    const float prescale = M::kPrescale;
     ProfScope prof_("k_fused_mfma", stream);
     hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, prm,
                        L.off_taps, L.off_cq, L.off_scale, L.W, L.N, mu, prescale, flag);
@@ -386,11 +384,11 @@ static bool overlaps(const void *a, size_t abytes, const void *b, size_t bbytes)
 struct BatchPlan {
     std::vector<int> status;
     std::vector<BatchImage> img;        // device descriptors (pointers filled in)
-    std::vector<long long> start;       // [3][n] item starts in each phase's visiting order
-    std::vector<int> order;             // [3][n] images in each phase's visiting order
+    std::vector<long long> start;       // [kBatchPhases][n] item starts in each phase's visiting order
+    std::vector<int> order;             // [kBatchPhases][n] images in each phase's visiting order
     std::vector<std::vector<double>> prm;
     size_t blob_bytes = 0, blob_cap = 0, total = 0;
-    long long items = 0, phase_items[3] = {0, 0, 0};
+    long long items = 0, phase_items[kBatchPhases] = {0, 0, 0, 0, 0, 0};
 };
 
 static size_t batch_blob_cap(size_t bytes) {
@@ -399,9 +397,14 @@ static size_t batch_blob_cap(size_t bytes) {
     return cap;
 }
 
+static size_t batch_head_bytes(size_t n) {
+    return align256(sizeof(BatchHeader) + sizeof(BatchImage) * n + (sizeof(long long) + sizeof(int)) * kBatchPhases * n);
+}
+
 // Plans a batch: per-image status, descriptors, parameter blocks and the
-// workspace layout [blob (capacity blob_cap) | per image: stack A, stack B].
-static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned flags, int RV, int RH,
+// workspace layout [blob (capacity blob_cap) | per image: stack A, stack B]
+// (three-kernel form) or [blob] (fused form, phases = geometry classes).
+static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned flags, int RV, int RH, bool fused,
                        char *ws, BatchPlan &B, bool sizing = false) {
     B.status.assign(count, BF_OK);
     B.img.clear();
@@ -410,6 +413,8 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
     for (int i = 0; i < count; ++i) {
         const bf_image_desc &x = d[i];
         bf_status st = check_common(x.height, x.width, x.sigma_s, x.sigma_r, x.N, dtype);
+        if (st == BF_OK && fused && radius_of(x.sigma_s) > BF_FUSED_MAX_RADIUS)
+            st = fail(BF_ERR_UNSUPPORTED, "fused tile: radius above BF_FUSED_MAX_RADIUS");
         if (st == BF_OK && x.height > 0 && x.width > 0 && !sizing) {
             if (!x.f || !x.out) st = fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
             else if (x.ld < x.width) st = fail(BF_ERR_INVALID_ARG, "ld must be >= width");
@@ -425,12 +430,12 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
     const int n = (int)ok.size();
     size_t prm_bytes = 0;
     for (int k = 0; k < n; ++k) prm_bytes += align256(sizeof(double) * param_layout(radius_of(d[ok[k]].sigma_s), d[ok[k]].N).total);
-    const size_t head_bytes = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n + (sizeof(long long) + sizeof(int)) * 3 * n);
+    const size_t head_bytes = batch_head_bytes(n);
     B.blob_bytes = head_bytes + prm_bytes;
     B.blob_cap = batch_blob_cap(B.blob_bytes);
     size_t off = B.blob_cap;
     size_t poff = head_bytes;
-    std::vector<long long> cnt[3], cost[3];
+    std::vector<long long> cnt[kBatchPhases], cost[kBatchPhases];
     for (int k = 0; k < n; ++k) {
         const bf_image_desc &x = d[ok[k]];
         BatchImage I;
@@ -457,29 +462,44 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
         I.off_scale = L.off_scale;
         I.prm = (const double *)((uintptr_t)ws + poff);   // ws may be null when only sizing
         poff += align256(sizeof(double) * L.total);
-        I.stackA = (void *)((uintptr_t)ws + off);
-        off += align256((size_t)I.P * I.ps * esize(dtype));
-        I.stackB = (void *)((uintptr_t)ws + off);
-        off += align256((size_t)I.P * I.pst * esize(dtype));
-        I.gbx = (I.Wd + 255) / 256;
-        I.gvx = (I.Wd + 63) / 64;
-        I.gvy = (I.H + 4 * RV - 1) / (4 * RV);
-        I.ghx = (I.H + 63) / 64;
-        const int ghy = (I.Wd + 4 * RH - 1) / (4 * RH);
-        cnt[0].push_back((long long)I.gbx * ((I.H + kBuildRows - 1) / kBuildRows));
-        cnt[1].push_back((long long)I.gvx * I.gvy * I.P);
-        cnt[2].push_back((long long)I.ghx * ghy);
-        cost[0].push_back(I.P);                                   // per item: planes written
-        cost[1].push_back(2LL * L.W + 1);                         // taps per output
-        cost[2].push_back((long long)I.P * (2LL * L.W + 1));      // planes x taps per output
+        for (int p = 0; p < kBatchPhases; ++p) {
+            cnt[p].push_back(0);
+            cost[p].push_back(0);
+        }
+        if (fused) {
+            const int TC = L.W <= 32 ? 64 : 32;
+            const int c = fused_class_of_radius(L.W);
+            I.gvx = (I.Wd + TC - 1) / TC;
+            cnt[c].back() = (long long)I.gvx * ((I.H + kFusedRows - 1) / kFusedRows);
+            cost[c].back() = I.P;                                 // per tile: planes
+        } else {
+            I.stackA = (void *)((uintptr_t)ws + off);
+            off += align256((size_t)I.P * I.ps * esize(dtype));
+            I.stackB = (void *)((uintptr_t)ws + off);
+            off += align256((size_t)I.P * I.pst * esize(dtype));
+            I.gbx = (I.Wd + 255) / 256;
+            I.gvx = (I.Wd + 63) / 64;
+            I.gvy = (I.H + 4 * RV - 1) / (4 * RV);
+            I.ghx = (I.H + 63) / 64;
+            const int ghy = (I.Wd + 4 * RH - 1) / (4 * RH);
+            cnt[0].back() = (long long)I.gbx * ((I.H + kBuildRows - 1) / kBuildRows);
+            cnt[1].back() = (long long)I.gvx * I.gvy * I.P;
+            cnt[2].back() = (long long)I.ghx * ghy;
+            cost[0].back() = I.P;                                   // per item: planes written
+            cost[1].back() = 2LL * L.W + 1;                         // taps per output
+            cost[2].back() = (long long)I.P * (2LL * L.W + 1);      // planes x taps per output
+        }
         B.img.push_back(I);
         B.prm.push_back(pv);
     }
-    B.start.assign(3 * (size_t)n, 0);
-    B.order.assign(3 * (size_t)n, 0);
-    for (int p = 0; p < 3; ++p) {
+    B.start.assign((size_t)kBatchPhases * n, 0);
+    B.order.assign((size_t)kBatchPhases * n, 0);
+    B.items = 0;
+    for (int p = 0; p < kBatchPhases; ++p) {
         std::vector<int> ord(n);
         for (int k = 0; k < n; ++k) ord[k] = k;
+        // decreasing cost; images without items in this phase (cost 0) last,
+        // where their start equals the phase's item count
         std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[p][a] > cost[p][b]; });
         long long acc = 0;
         for (int k = 0; k < n; ++k) {
@@ -488,8 +508,8 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
             acc += cnt[p][ord[k]];
         }
         B.phase_items[p] = acc;
+        B.items += acc;
     }
-    B.items = B.phase_items[0] + B.phase_items[1] + B.phase_items[2];
     B.total = off;
 }
 
@@ -499,14 +519,14 @@ static void pack_blob(const BatchPlan &B, char *host) {
     BatchHeader *h = (BatchHeader *)host;
     h->flags = 0;
     h->count = (int)n;
-    for (int p = 0; p < 3; ++p) h->items[p] = B.phase_items[p];
+    for (int p = 0; p < kBatchPhases; ++p) h->items[p] = B.phase_items[p];
     char *q = host + sizeof(BatchHeader);
     std::memcpy(q, B.img.data(), sizeof(BatchImage) * n);
     q += sizeof(BatchImage) * n;
-    std::memcpy(q, B.start.data(), sizeof(long long) * 3 * n);
-    q += sizeof(long long) * 3 * n;
-    std::memcpy(q, B.order.data(), sizeof(int) * 3 * n);
-    size_t poff = align256(sizeof(BatchHeader) + sizeof(BatchImage) * n + (sizeof(long long) + sizeof(int)) * 3 * n);
+    std::memcpy(q, B.start.data(), sizeof(long long) * kBatchPhases * n);
+    q += sizeof(long long) * kBatchPhases * n;
+    std::memcpy(q, B.order.data(), sizeof(int) * kBatchPhases * n);
+    size_t poff = batch_head_bytes(n);
     for (const std::vector<double> &pv : B.prm) {
         std::memcpy(host + poff, pv.data(), sizeof(double) * pv.size());
         poff += align256(sizeof(double) * pv.size());
@@ -521,12 +541,20 @@ struct StageSlot {
     hipEvent_t ev = nullptr;
     bool pending = false;
 };
+// Phase kernels of one batched launch (each takes the device blob).
+struct BatchKernels {
+    int n = 0;
+    const void *func[kBatchPhases];
+    int grid[kBatchPhases];
+    int block = 256;
+    size_t lds = 0;
+};
 struct GraphEntry {
     void *ws;
     hipStream_t stream;
     size_t cap;
-    int cfg, dtype, slot, grid[3];
-    size_t lds;
+    int slot;
+    BatchKernels k;
     hipGraphExec_t exec;
     hipGraph_t graph;
 };
@@ -534,6 +562,13 @@ static std::mutex g_batch_mtx;
 static StageSlot g_slots[2];
 static int g_next_slot = 0;
 static std::vector<GraphEntry> g_graphs;
+
+static bool same_kernels(const BatchKernels &a, const BatchKernels &b) {
+    if (a.n != b.n || a.block != b.block || a.lds != b.lds) return false;
+    for (int i = 0; i < a.n; ++i)
+        if (a.func[i] != b.func[i] || a.grid[i] != b.grid[i]) return false;
+    return true;
+}
 
 static bf_status stage_slot(size_t cap, int *slot_out) {
     const int k = g_next_slot;
@@ -568,51 +603,37 @@ static bf_status stage_slot(size_t cap, int *slot_out) {
 
 // Blocks for a phase kernel: enough to fill every CU at its occupancy, never
 // more than the phase has items.
-static int phase_grid(const void *kernel, long long items, size_t lds) {
+static int phase_grid(const void *kernel, long long items, int block, size_t lds) {
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, lds);
-    const long long full = (long long)std::max(1, cus) * std::max(4, per);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, lds);
+    const long long full = (long long)std::max(1, cus) * std::max(block >= 512 ? 1 : 4, per);
     return (int)std::max(1LL, std::min(full, items));
 }
 
-template <class S, int RV, int RH>
-static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, unsigned flags, int cfg,
-                             int *status, char *ws, size_t ws_bytes, hipStream_t stream) {
-    BatchPlan B;
-    plan_batch(descs, count, dtype, flags, RV, RH, ws, B);
-    for (int i = 0; i < count; ++i) status[i] = B.status[i];
-    if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
-    if (B.items == 0) return BF_OK;
+// Uploads the planned blob and runs the phase kernels, through a cached
+// hipGraph (memcpy node + one kernel node per phase) or as plain launches.
+static bf_status launch_batch(const BatchPlan &B, const BatchKernels &K, unsigned flags, char *ws,
+                              hipStream_t stream) {
     std::lock_guard<std::mutex> lock(g_batch_mtx);
     int slot = 0;
     bf_status st = stage_slot(B.blob_cap, &slot);
     if (st != BF_OK) return st;
     pack_blob(B, g_slots[slot].host);
-    const void *kern[3] = {(const void *)k_batched<S, RV, RH, 0>, (const void *)k_batched<S, RV, RH, 1>,
-                           (const void *)k_batched<S, RV, RH, 2>};
-    const size_t lds = batch_lds_bytes((int)B.img.size());
-    int grid[3];
-    for (int p = 0; p < 3; ++p) grid[p] = phase_grid(kern[p], B.phase_items[p], lds);
     hipError_t e = hipSuccess;
     if (flags & BF_FLAG_GRAPH) {
         GraphEntry *G = nullptr;
         for (GraphEntry &g : g_graphs)
-            if (g.ws == ws && g.stream == stream && g.cap == B.blob_cap && g.cfg == cfg && g.dtype == dtype &&
-                g.slot == slot && g.grid[0] == grid[0] && g.grid[1] == grid[1] && g.grid[2] == grid[2] &&
-                g.lds == lds)
+            if (g.ws == ws && g.stream == stream && g.cap == B.blob_cap && g.slot == slot && same_kernels(g.k, K))
                 G = &g;
         if (!G) {
             GraphEntry g;
             g.ws = ws;
             g.stream = stream;
             g.cap = B.blob_cap;
-            g.cfg = cfg;
-            g.dtype = dtype;
             g.slot = slot;
-            for (int p = 0; p < 3; ++p) g.grid[p] = grid[p];
-            g.lds = lds;
+            g.k = K;
             hipGraphNode_t prev;
             e = hipGraphCreate(&g.graph, 0);
             if (e == hipSuccess)
@@ -620,13 +641,13 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
                                             hipMemcpyHostToDevice);
             char *blob = ws;
             void *args[] = {&blob};
-            for (int p = 0; p < 3 && e == hipSuccess; ++p) {
+            for (int p = 0; p < K.n && e == hipSuccess; ++p) {
                 hipKernelNodeParams kp;
                 std::memset(&kp, 0, sizeof kp);
-                kp.func = (void *)kern[p];
-                kp.gridDim = dim3(grid[p]);
-                kp.blockDim = dim3(256);
-                kp.sharedMemBytes = (unsigned)lds;
+                kp.func = (void *)K.func[p];
+                kp.gridDim = dim3(K.grid[p]);
+                kp.blockDim = dim3(K.block);
+                kp.sharedMemBytes = (unsigned)K.lds;
                 kp.kernelParams = args;
                 hipGraphNode_t node;
                 e = hipGraphAddKernelNode(&node, g.graph, &prev, 1, &kp);
@@ -648,16 +669,61 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
         e = hipMemcpyAsync(ws, g_slots[slot].host, B.blob_bytes, hipMemcpyHostToDevice, stream);
         if (e == hipSuccess) {
             ProfScope prof_("k_batched", stream);
-            hipLaunchKernelGGL((k_batched<S, RV, RH, 0>), dim3(grid[0]), dim3(256), lds, stream, ws);
-            hipLaunchKernelGGL((k_batched<S, RV, RH, 1>), dim3(grid[1]), dim3(256), lds, stream, ws);
-            hipLaunchKernelGGL((k_batched<S, RV, RH, 2>), dim3(grid[2]), dim3(256), lds, stream, ws);
-            e = hipGetLastError();
+            char *blob = ws;
+            void *args[] = {&blob};
+            for (int p = 0; p < K.n && e == hipSuccess; ++p)
+                e = hipLaunchKernel(K.func[p], dim3(K.grid[p]), dim3(K.block), args, K.lds, stream);
+            if (e == hipSuccess) e = hipGetLastError();
         }
     }
     if (e == hipSuccess) e = hipEventRecord(g_slots[slot].ev, stream);
     if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("bf_gc_batched: ") + hipGetErrorString(e));
     g_slots[slot].pending = true;
     return BF_OK;
+}
+
+template <class S, int RV, int RH>
+static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, unsigned flags, int *status,
+                             char *ws, size_t ws_bytes, hipStream_t stream) {
+    BatchPlan B;
+    plan_batch(descs, count, dtype, flags, RV, RH, false, ws, B);
+    for (int i = 0; i < count; ++i) status[i] = B.status[i];
+    if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
+    if (B.items == 0) return BF_OK;
+    BatchKernels K;
+    K.n = 3;
+    K.func[0] = (const void *)k_batched<S, RV, RH, 0>;
+    K.func[1] = (const void *)k_batched<S, RV, RH, 1>;
+    K.func[2] = (const void *)k_batched<S, RV, RH, 2>;
+    K.block = 256;
+    K.lds = batch_lds_bytes((int)B.img.size());
+    for (int p = 0; p < 3; ++p) K.grid[p] = phase_grid(K.func[p], B.phase_items[p], K.block, K.lds);
+    return launch_batch(B, K, flags, ws, stream);
+}
+
+// Fused FP16/BF16 form: one persistent kernel per non-empty geometry class.
+template <class M>
+static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dtype, unsigned flags, int *status,
+                                   char *ws, size_t ws_bytes, hipStream_t stream) {
+    BatchPlan B;
+    plan_batch(descs, count, dtype, flags, 0, 0, true, ws, B);
+    for (int i = 0; i < count; ++i) status[i] = B.status[i];
+    if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
+    if (B.items == 0) return BF_OK;
+    const void *cls[kBatchPhases] = {
+        (const void *)k_fused_batched<M, 3, 64, 0>, (const void *)k_fused_batched<M, 3, 64, 1>,
+        (const void *)k_fused_batched<M, 4, 64, 1>, (const void *)k_fused_batched<M, 4, 64, 2>,
+        (const void *)k_fused_batched<M, 5, 32, 2>, (const void *)k_fused_batched<M, 5, 32, 3>};
+    BatchKernels K;
+    K.block = 512;
+    K.lds = batch_lds_bytes((int)B.img.size());
+    for (int c = 0; c < kBatchPhases; ++c)
+        if (B.phase_items[c] > 0) {
+            K.func[K.n] = cls[c];
+            K.grid[K.n] = phase_grid(cls[c], B.phase_items[c], K.block, K.lds);
+            ++K.n;
+        }
+    return launch_batch(B, K, flags, ws, stream);
 }
 
 }  // namespace bfgc
@@ -855,8 +921,8 @@ size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int 
         stack_dtype > BF_STACK_BF16)
         return 0;
     BatchPlan B;
-    // the layout does not depend on the tile configuration or the flags
-    plan_batch(descs, count, stack_dtype, BF_FLAG_ALLOW_ILL_CONDITIONED, 16, 8, nullptr, B, true);
+    // the three-kernel layout (blob and stacks) covers the fused one (blob only)
+    plan_batch(descs, count, stack_dtype, BF_FLAG_ALLOW_ILL_CONDITIONED, 16, 8, false, nullptr, B, true);
     return B.total;
 }
 
@@ -869,12 +935,26 @@ bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, 
     if (stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
     int cfg = tile_config_of(flags);
     if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
-    if (cfg == BF_TILE_FUSED) return fail(BF_ERR_UNSUPPORTED, "the batched form does not take the fused tile");
-    if (cfg == -1) cfg = 0;
+    if (cfg == -1) {
+        // the fused form where it covers every image the call would filter
+        bool fused = stack_dtype != BF_STACK_F32;
+        for (int i = 0; i < count && fused; ++i) {
+            const bf_image_desc &x = descs[i];
+            if (x.height > 0 && x.width > 0 && finite_pos(x.sigma_s) && radius_of(x.sigma_s) > BF_FUSED_MAX_RADIUS)
+                fused = false;
+        }
+        cfg = fused ? BF_TILE_FUSED : 0;
+    }
     if (!ws || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null or misaligned");
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
-#define BF_BAT(S, RV, RH) run_batched<S, RV, RH>(descs, count, stack_dtype, flags, cfg, per_image_status, w, ws_bytes, s)
+    if (cfg == BF_TILE_FUSED) {
+        if (stack_dtype == BF_STACK_F32) return fail(BF_ERR_UNSUPPORTED, "fused tile: FP16/BF16 stacks only");
+        if (stack_dtype == BF_STACK_F16)
+            return run_batched_fused<MmaF16>(descs, count, stack_dtype, flags, per_image_status, w, ws_bytes, s);
+        return run_batched_fused<MmaBF16>(descs, count, stack_dtype, flags, per_image_status, w, ws_bytes, s);
+    }
+#define BF_BAT(S, RV, RH) run_batched<S, RV, RH>(descs, count, stack_dtype, flags, per_image_status, w, ws_bytes, s)
 #define BF_BAT_CFG(S)                                   \
     switch (cfg) {                                      \
     case 0: return BF_BAT(S, 16, 8);                    \

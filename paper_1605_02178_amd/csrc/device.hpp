@@ -352,20 +352,25 @@ struct BatchImage {
     double mu;
     int H, Wd, ld, lds, ldt, W, N, P;
     int off_taps, off_cq, off_cp, off_scale;
-    int gbx, gvx, gvy, ghx;    // tile grid widths: build, column pass, row pass
+    int gbx, gvx, gvy, ghx;    // tile grid widths: build, column pass, row pass (fused form: gvx = tiles per row)
 };
+
+// Phases of the three-kernel form (build, column pass, row pass + combine) or
+// geometry classes of the fused form; a form uses the first 3 or all 6.
+constexpr int kBatchPhases = 6;
 
 struct BatchHeader {
     unsigned flags;            // BF_DEVFLAG_RANGE from the builds
     int count;                 // images
-    long long items[3];        // items in each phase
+    long long items[kBatchPhases];   // items in each phase
 };
-// device blob: BatchHeader | BatchImage[count] | long long start[3][count] |
-//              int order[3][count] | parameter blocks
+// device blob: BatchHeader | BatchImage[count] | long long start[6][count] |
+//              int order[6][count] | parameter blocks
 // In phase p the images are visited in order[p][0..count): item t belongs to
 // image order[p][k] for the last k with start[p][k] <= t. The host orders each
-// phase by decreasing cost per item, so the round-robin assignment of items to
-// blocks gives every block a similar mix, heaviest items first.
+// phase by decreasing cost per item (images with no items in a phase last), so
+// the round-robin assignment of items to blocks gives every block a similar
+// mix, heaviest items first.
 
 constexpr int kMaxBatch = 2048;   // images per batched call
 
@@ -382,7 +387,7 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
     const int count = hdr->count;
     int *s_order = (int *)(s_start + count);
     const long long *start = (const long long *)(blob + sizeof(BatchHeader) + sizeof(BatchImage) * count);
-    const int *order = (const int *)(start + 3 * count);
+    const int *order = (const int *)(start + kBatchPhases * count);
     for (int k = threadIdx.x; k < count; k += blockDim.x) {
         s_start[k] = start[PHASE * count + k];
         s_order[k] = order[PHASE * count + k];
@@ -643,6 +648,9 @@ typedef __bf16 mf_b4 __attribute__((ext_vector_type(4)));
 typedef float mf_f4 __attribute__((ext_vector_type(4)));
 
 struct MmaF16 {
+    // every FP16 plane carries 2^14: plane 0 peaks there, and the smallest
+    // plane maximum e^{-mu/2} 2^14 stays a normal FP16 number while sigma_r >= 21
+    static constexpr float kPrescale = 16384.0f;
     typedef _Float16 E;
     typedef mf_h8 V;
     typedef mf_h4 V4;
@@ -652,6 +660,7 @@ struct MmaF16 {
     }
 };
 struct MmaBF16 {
+    static constexpr float kPrescale = 1.0f;   // BF16 has the FP32 exponent range
     typedef __bf16 E;
     typedef mf_b8 V;
     typedef mf_b4 V4;
@@ -681,25 +690,31 @@ __device__ __forceinline__ int halo_index(int i, int M, int W, bool one_reflecti
     return one_reflection ? mirror1(min(i, M + W - 1), M) : mirror(i, M);
 }
 
+constexpr int kFusedTabPad = 32;             // zero taps below t = 0 in the LDS tap table
+constexpr int kFusedYElems = kFusedRows * kFusedPitch;
+__host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 32 * Q; }   // t in [-32, 32Q)
+
+// One 64-row output tile (rows r0.., columns c0..) of the fused kernel; all
+// 512 threads of the block call it together. ybuf: two LDS buffers of
+// kFusedYElems elements; tab: fused_tab_len(Q) elements of LDS.
 template <class M, int Q, int TC, int QA>
-__global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
-                                                    int Wd, int ld, const double *__restrict__ prm, int off_taps,
-                                                    int off_cq, int off_scale, int W, int N, float mu,
-                                                    float prescale, unsigned *__restrict__ flag) {
+__device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *__restrict__ out, int H, int Wd,
+                                           int ld, const double *__restrict__ prm, int off_taps, int off_cq,
+                                           int off_scale, int W, int N, float mu, float prescale,
+                                           unsigned *__restrict__ flag, int r0, int c0,
+                                           typename M::E *__restrict__ ybuf_base,
+                                           typename M::E *__restrict__ tab) {
     typedef typename M::E E;
     typedef typename M::V V;
     constexpr int QB = Q - 2;
     constexpr int JB = TC / 32;                  // output column blocks per wave in the row pass
-    constexpr int kTabPad = 32;                  // zero taps below t = 0 in the LDS tap table
-    constexpr int kTab = kTabPad + 32 * Q;       // covers t in [-32, 32Q)
+    constexpr int kTabPad = kFusedTabPad;
+    constexpr int kTab = fused_tab_len(Q);
     static_assert((TC == 64 && Q <= 4) || (TC == 32 && Q == 5), "geometry");
     static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
-    __shared__ __align__(16) E ybuf[2][kFusedRows * kFusedPitch];
-    __shared__ E tab[kTab];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
-    const int r0 = blockIdx.y * kFusedRows, c0 = blockIdx.x * TC;
     const int P = N + 2;
 
     // Tap table in LDS: tab[kTabPad + t] = w[t] for t in [0, 2W], zero elsewhere.
@@ -801,7 +816,7 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
                 hv[q][jj] *= sv[q][jj];                                   // H_{n+1} = H_n s
             }
         }
-        E *yb = ybuf[n & 1];
+        E *yb = ybuf_base + (n & 1) * kFusedYElems;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
@@ -816,7 +831,7 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
     };
     // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
     auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
-        const E *src = ybuf[n & 1] + (16 * rb + li) * kFusedPitch + 8 * lg;
+        const E *src = ybuf_base + (n & 1) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
         if (TC == 64) {
             V ya[QB + 1];
 #pragma unroll
@@ -902,6 +917,69 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
             const float ratio = s != 0.0f ? Ps[b][v] / (s * Qa[b][v]) : b0 * z1[b][v] / Qa[b][v];
             if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
         }
+    }
+}
+
+// Single-image fused kernel: one block per 64 x TC output tile.
+template <class M, int Q, int TC, int QA>
+__global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
+                                                    int Wd, int ld, const double *__restrict__ prm, int off_taps,
+                                                    int off_cq, int off_scale, int W, int N, float mu,
+                                                    float prescale, unsigned *__restrict__ flag) {
+    typedef typename M::E E;
+    __shared__ __align__(16) E ybuf[2 * kFusedYElems];
+    __shared__ E tab[fused_tab_len(Q)];
+    fused_tile<M, Q, TC, QA>(f, out, H, Wd, ld, prm, off_taps, off_cq, off_scale, W, N, mu, prescale, flag,
+                             blockIdx.y * kFusedRows, blockIdx.x * TC, ybuf, tab);
+}
+
+// Geometry classes of the fused kernel, in the order the batched form keeps
+// them: (Q, TC, QA) = (3,64,0) (3,64,1) (4,64,1) (4,64,2) (5,32,2) (5,32,3).
+__host__ __device__ constexpr int fused_class(int Q, int QA) { return 2 * (Q - 3) + (QA - (Q - 3)); }
+__host__ __device__ constexpr int fused_class_of_radius(int W) {
+    return W <= 16 ? fused_class(3, fused_qa(W)) : W <= 32 ? fused_class(4, fused_qa(W)) : fused_class(5, fused_qa(W));
+}
+
+// Batched fused kernel for one geometry class: blocks stride over the class's
+// (image, tile) items, decoded as in k_batched; the tiles are the
+// single-image kernel's, so every image matches its bf_gc_forward result bit
+// for bit.
+template <class M, int Q, int TC, int QA>
+__global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) {
+    typedef typename M::E E;
+    constexpr int C = fused_class(Q, QA);
+    const float prescale = M::kPrescale;
+    extern __shared__ long long s_start[];
+    __shared__ __align__(16) E ybuf[2 * kFusedYElems];
+    __shared__ E tab[fused_tab_len(Q)];
+    BatchHeader *hdr = (BatchHeader *)blob;
+    const BatchImage *img = (const BatchImage *)(blob + sizeof(BatchHeader));
+    const int count = hdr->count;
+    int *s_order = (int *)(s_start + count);
+    const long long *start = (const long long *)(blob + sizeof(BatchHeader) + sizeof(BatchImage) * count);
+    const int *order = (const int *)(start + kBatchPhases * count);
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        s_start[k] = start[C * count + k];
+        s_order[k] = order[C * count + k];
+    }
+    __syncthreads();
+    const long long items = hdr->items[C];
+    for (long long t = blockIdx.x; t < items; t += gridDim.x) {
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_start[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
+        const BatchImage &B = img[ii];
+        const int l = (int)(t - s_start[lo]);
+        const int bx = l % B.gvx, by = l / B.gvx;
+        fused_tile<M, Q, TC, QA>(as_global(B.f), as_global(B.out), B.H, B.Wd, B.ld, as_global(B.prm), B.off_taps,
+                                 B.off_cq, B.off_scale, B.W, B.N, (float)B.mu, prescale, as_global(&hdr->flags),
+                                 by * kFusedRows, bx * TC, ybuf, tab);
+        __syncthreads();          // the next item rewrites the tap table and buffer 0
     }
 }
 

@@ -109,7 +109,7 @@ def test_fused_argument_errors_and_fallback(torch_cuda):
         bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED, staged=True)
     assert e.value.status == 1
     with pytest.raises(bf.BFError) as e:
-        bf.gc_filter_batched([f], [4.0], [30.0], [28], stack_dtype="f16", tile_config=bf.TILE_FUSED)
+        bf.gc_filter_batched([f], [4.0], [30.0], [28], stack_dtype="f32", tile_config=bf.TILE_FUSED)
     assert e.value.status == 2
     # W = 51 without a tile flag takes the three-kernel path
     y = _np(bf.gc_filter(f, 17.0, 30.0, 28, stack_dtype="f16"))
