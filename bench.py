@@ -18,6 +18,8 @@ Prints one JSON line. Besides the contract fields it carries
   cpu_baseline  the plain-C FP64 oracle on the host cores
   fp32_stack, fp16_stack   per-stack timings, kernels and errors
   batched       the uneven 64-image batch, one graph launch vs a per-image loop
+  differentiation   forward + backward of 8 x 1024^2 images through the
+                autograd function
 """
 from __future__ import annotations
 
@@ -208,6 +210,48 @@ def bench_batched(bf, steps, log, stack="f32"):
     return res
 
 
+def bench_differentiation(bf, steps, log):
+    """Differentiation workload: batch 8 x 1 x 1024 x 1024 edge-rich images,
+    sigma_s = 5, sigma_r = 30, N = 28, loss = mean((y - target)^2) with i.i.d.
+    U[0,255] targets; one step = forward + backward through
+    GaussChebyshevBF (gradients with respect to f and sigma_r)."""
+    import numpy as np
+    import torch
+    from synth import diff_batch
+    imgs, tgts = diff_batch(8, 1024, 1024)
+    f = torch.tensor(imgs[:, None].astype(np.float32), device="cuda:0")
+    tgt = torch.tensor(tgts[:, None].astype(np.float32), device="cuda:0")
+    sr = torch.tensor(30.0, dtype=torch.float64, device="cuda:0")
+
+    def step():
+        x = f.detach().requires_grad_(True)
+        s_ = sr.detach().requires_grad_(True)
+        y = bf.gc_filter_autograd(x, s_, 5.0, 28)
+        loss = ((y - tgt) ** 2).mean()
+        loss.backward()
+        return x.grad, s_.grad
+
+    step()
+    torch.cuda.synchronize()
+    lib = bf._lib.load()
+    lib.bf_profile_start()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    lib.bf_profile_stop(None)
+    prof = profile_read(lib)
+    ms = e0.elapsed_time(e1) / steps
+    px = f.numel()
+    log(f"bench: differentiation 8x1024^2 forward+backward {ms:.2f} ms")
+    return {"ms_per_step": round(ms, 3), "mpx_s": round(px / 1e6 / (ms / 1e3), 1), "images": 8,
+            "shape": "8x1x1024x1024", "sigma_s": 5.0, "sigma_r": 30.0, "degree": 28, "steps": steps,
+            "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}}
+
+
 def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
     """Plain-C FP64 oracle (OpenMP over rows) on rows [0, rows) of the image."""
     from oracle import native as C
@@ -239,6 +283,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1024)
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-backward", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -360,6 +405,9 @@ def main():
         result["batched"] = bench_batched(bf, args.batch_steps, log, "f32")
         if not args.no_fp16:
             result["batched_fp16"] = bench_batched(bf, args.batch_steps, log, "f16")
+
+    if not args.no_backward:
+        result["differentiation"] = bench_differentiation(bf, args.batch_steps, log)
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")

@@ -201,3 +201,83 @@ def test_bad_arguments():
         K.gcf_coefficients(30.0, 0)
     with pytest.raises(ValueError):
         K.gcf_coefficients(-1.0, 5)
+
+
+# ---- minimax (Remez) coefficients: pinned by the alternation theorem, a
+# closed form at degree 1, and the de la Vallee Poussin bracket.
+
+def _dense_max_error(mu, coeffs_T, n=6001):
+    import mpmath
+    from oracle import coeffs as K
+    with mpmath.workdps(40):
+        ys = [mpmath.mpf(-1) + 2 * mpmath.mpf(i) / (n - 1) for i in range(n)]
+        return max(abs(mpmath.exp(mu * y) - K._clenshaw(coeffs_T, y)) for y in ys)
+
+
+@pytest.mark.parametrize("mu,N", [(1.0, 5), (6.5025, 11), (18.0625, 16)])
+def test_minimax_equioscillates(mu, N):
+    """Alternation theorem: the error takes the values (-1)^k E at N+2
+    increasing points and nowhere exceeds |E|, which makes the polynomial the
+    unique best uniform approximation of degree N."""
+    import mpmath
+    from oracle import coeffs as K
+    e, E, ref = K.minimax_fit(mu, N)
+    assert len(ref) == N + 2 and all(ref[k] < ref[k + 1] for k in range(N + 1))
+    with mpmath.workdps(40):
+        vals = [mpmath.exp(mu * x) - K._clenshaw(e, x) for x in ref]
+        for k, v in enumerate(vals):
+            assert abs(v - (-1) ** k * E) <= 1e-25 * abs(E) + mpmath.mpf(10) ** -35
+        assert _dense_max_error(mu, e) <= abs(E) * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("mu", [1.0, 2.5])
+def test_minimax_linear_closed_form(mu):
+    """Degree 1, convex exp(mu y): slope = the secant's, intercept halfway
+    between the secant and the tangent of that slope (touching at x* with
+    mu exp(mu x*) = slope)."""
+    import math
+    from oracle import coeffs as K
+    e, E, _ = K.minimax_fit(mu, 1)
+    m = (math.exp(mu) - math.exp(-mu)) / 2
+    xs = math.log(m / mu) / mu
+    c = (math.exp(-mu) + m + math.exp(mu * xs) - m * xs) / 2
+    assert abs(float(e[1]) - m) <= 1e-13 * m
+    assert abs(float(e[0]) - c) <= 1e-13 * abs(c)
+    assert abs(abs(float(E)) - abs(math.exp(-mu) - (c - m))) <= 1e-13
+
+
+@pytest.mark.parametrize("mu,N", [(1.0, 6), (18.0625, 20), (18.0625, 28)])
+def test_minimax_bracketed_by_interpolant(mu, N):
+    """min_k |r(x_k)| over the N+2 Chebyshev extrema, where the interpolant's
+    error r alternates in sign, is a lower bound for the minimax error (de la
+    Vallee Poussin); the interpolant's own maximum error is an upper bound."""
+    import mpmath
+    from oracle import coeffs as K
+    _, E, _ = K.minimax_fit(mu, N)
+    with mpmath.workdps(60):
+        d = K.chebyshev_fit(mpmath.exp, mpmath.mpf(mu), N)     # coefficients of T_l(x / mu)
+        ext = [mpmath.cos(mpmath.pi * k / (N + 1)) for k in range(N + 2)]
+        r = [mpmath.exp(mu * x) - K._clenshaw(d, x) for x in ext]
+        assert all(r[k] * r[k + 1] < 0 for k in range(N + 1))
+        lower = min(abs(v) for v in r)
+        upper = _dense_max_error(mu, d)
+    assert lower <= abs(E) * (1 + 1e-12)
+    assert abs(E) <= upper
+    assert abs(E) < upper          # strictly better than node interpolation
+
+
+def test_minimax_monomial_coefficients_evaluate_the_fit():
+    """The monomial c_n (scaled as in eq. 19) evaluate to the same polynomial
+    as the Chebyshev-basis fit."""
+    import mpmath
+    from oracle import coeffs as K
+    sr, N = 50.0, 11
+    _, mu = K.gcf_params(sr)
+    c = K.minimax_coefficients(sr, N)
+    e, _, _ = K.minimax_fit(mu, N)
+    for y in np.linspace(-1, 1, 41):
+        x = mu * y
+        mono = sum(cn * x ** n for n, cn in enumerate(c))
+        with mpmath.workdps(40):
+            ref = float(K._clenshaw(e, mpmath.mpf(y)))
+        assert abs(mono - ref) <= 1e-12 * math.exp(mu)
