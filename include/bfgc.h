@@ -68,6 +68,15 @@ typedef enum {
  * polynomial, c_n = 1/n! (Section II), instead of the Chebyshev interpolant
  * of eq. 19. Accepted by bf_gc_forward, bf_gc_backward and bf_gc_batched. */
 #define BF_FLAG_TAYLOR                0x8u
+/* Minimax filter: the cross term is replaced by the best uniform polynomial
+ * approximation of exp on [-mu, mu] of degree N (Remez exchange; Section III
+ * names it the ideal choice, of which the Chebyshev interpolant is a near
+ * version). Degrees up to BF_MINIMAX_MAX_DEGREE; where binary128 cannot
+ * resolve the levelled error (the error below 1e-28 of e^mu) the call returns
+ * BF_ERR_UNSUPPORTED. Accepted by bf_gc_forward, bf_gc_backward and
+ * bf_gc_batched; with BF_FLAG_TAYLOR it is BF_ERR_INVALID_ARG. */
+#define BF_FLAG_MINIMAX               0x10u
+#define BF_MINIMAX_MAX_DEGREE         100
 /* Tile configuration c in [0, BF_TILE_CONFIGS).
  *   c = 0..3: the three-kernel path (stack in HBM); output rows per lane in
  *             the column pass and output columns per lane in the row pass +
@@ -109,6 +118,17 @@ int bf_gc_degree_rule(double sigma_r);
  * mu_out: host double (may be NULL).
  */
 bf_status bf_gc_coefficients(double sigma_r, int N, double *b_out, double *mu_out);
+
+/*
+ * The polynomial the flags select (the Chebyshev interpolant of Section III;
+ * BF_FLAG_TAYLOR: Taylor, Section II; BF_FLAG_MINIMAX: minimax), in the same
+ * scaled monomial form: b_out[n] = b_n and db_out[n] = db_n/dmu, n = 0..N
+ * (host arrays of N+1 doubles; db_out may be NULL), mu_out, kernel_err and
+ * kappa as in bf_gc_query (each may be NULL). Errors as the forward's flag
+ * and degree checks.
+ */
+bf_status bf_gc_fit(double sigma_r, int N, unsigned flags, double *b_out, double *db_out, double *mu_out,
+                    double *kernel_err, double *kappa);
 
 /*
  * Conditioning of the approximation for (sigma_r, N): kernel_err = max over

@@ -23,7 +23,7 @@ __all__ = [
     "degree_rule", "coefficients", "query", "plane_scales", "workspace_bytes", "param_bytes",
     "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
-    "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for",
+    "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -31,6 +31,11 @@ FLAG_ALLOW_ILL_CONDITIONED = 0x1
 FLAG_STAGED = 0x2
 FLAG_GRAPH = 0x4
 FLAG_TAYLOR = 0x8
+FLAG_MINIMAX = 0x10
+MINIMAX_MAX_DEGREE = 100
+# coefficient kinds: the Chebyshev interpolant (Section III), the Taylor
+# polynomial (Section II), the minimax polynomial (Remez)
+COEFFS = {"chebyshev": 0, "taylor": FLAG_TAYLOR, "minimax": FLAG_MINIMAX}
 DEVFLAG_RANGE = 0x1
 # Tile configurations: 0-3 are the three-kernel path, (column-pass rows,
 # row-pass columns) per lane; TILE_FUSED is the fused matrix-core kernel for
@@ -86,6 +91,25 @@ def coefficients(sigma_r: float, N: int):
     return list(b), mu.value
 
 
+def _coeff_flags(coeffs, taylor=False) -> int:
+    if taylor:
+        if coeffs not in (None, "taylor"):
+            raise ValueError("taylor=True with coeffs=%r" % (coeffs,))
+        coeffs = "taylor"
+    return COEFFS[coeffs or "chebyshev"]
+
+
+def fit(sigma_r: float, N: int, coeffs="chebyshev"):
+    """The library's polynomial for (sigma_r, N) and the coefficient kind:
+    dict with b (b_n), db (db_n/dmu), mu, kernel_err, kappa."""
+    b = (ctypes.c_double * (N + 1))()
+    db = (ctypes.c_double * (N + 1))()
+    mu, ke, ka = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(_lib.load().bf_gc_fit(float(sigma_r), int(N), _coeff_flags(coeffs), b, db, ctypes.byref(mu),
+                                      ctypes.byref(ke), ctypes.byref(ka)), "bf_gc_fit")
+    return {"b": list(b), "db": list(db), "mu": mu.value, "kernel_err": ke.value, "kappa": ka.value}
+
+
 def query(sigma_r: float, N: int, stack_dtype="f32"):
     """(kernel_err, kappa) for (sigma_r, N)."""
     e, k = ctypes.c_double(), ctypes.c_double()
@@ -128,10 +152,11 @@ def _check_image(f, name="f"):
 
 def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
               staged: bool = False, allow_ill_conditioned: bool = False, out=None, workspace=None,
-              stream=None, tile_config: int | None = None, taylor: bool = False):
+              stream=None, tile_config: int | None = None, taylor: bool = False, coeffs=None):
     """Gauss-Chebyshev bilateral filter of a 2-D float32 image in [0, 255]
-    (Section III-B). Returns a new tensor (or writes `out`). taylor=True runs
-    the Gauss-polynomial filter (Taylor coefficients, Section II) instead.
+    (Section III-B). Returns a new tensor (or writes `out`). coeffs: the
+    polynomial for the cross term, "chebyshev" (default), "taylor" (the
+    Gauss-polynomial filter of Section II; also taylor=True) or "minimax".
     tile_config: an index into TILE_CONFIGS, "auto" (autotuned), or None."""
     import torch
     _check_image(f)
@@ -148,7 +173,7 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
     flags = (FLAG_STAGED if staged else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
-    flags |= FLAG_TAYLOR if taylor else 0
+    flags |= _coeff_flags(coeffs, taylor)
     if tile_config == "auto":
         from . import autotune
         tile_config = autotune.lookup(autotune.forward_key(H, Wd, sigma_s, N, code))
@@ -165,7 +190,7 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
 
 
 def gc_backward(f, grad_out, sigma_s: float, sigma_r: float, degree: int | None = None,
-                allow_ill_conditioned: bool = False, workspace=None, stream=None):
+                allow_ill_conditioned: bool = False, workspace=None, stream=None, coeffs=None):
     """(dL/df, dL/dsigma_r) for L = sum(grad_out * gc_filter(f, ...)) with an
     FP32 stack. Returns a float32 tensor like f and a 0-d float64 tensor."""
     import torch
@@ -181,7 +206,7 @@ def gc_backward(f, grad_out, sigma_s: float, sigma_r: float, degree: int | None 
     need = workspace_bytes(H, Wd, sigma_s, N, 0, for_backward=True)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
-    flags = FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0
+    flags = (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0) | _coeff_flags(coeffs)
     st = _lib.load().bf_gc_backward(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(grad_out.data_ptr()),
                                     ctypes.c_void_p(grad_f.data_ptr()), ctypes.c_void_p(grad_sr.data_ptr()), H, Wd,
                                     max(ld, Wd), float(sigma_s), float(sigma_r), N, 0, flags,
@@ -201,7 +226,7 @@ def _autograd_class():
         the backward recomputes the stack (bf_gc_backward, FP32 stack)."""
 
         @staticmethod
-        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype="f32"):
+        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None):
             sr = float(sigma_r)
             N = degree_rule(sr) if degree is None else int(degree)
             shape = f.shape
@@ -210,9 +235,10 @@ def _autograd_class():
             ws = torch.empty(max(workspace_bytes(shape[-2], shape[-1], sigma_s, N, stack_dtype), 256),
                              dtype=torch.uint8, device=f.device)
             for b in range(x.shape[0]):
-                gc_filter(x[b].contiguous(), sigma_s, sr, N, stack_dtype=stack_dtype, out=y[b], workspace=ws)
+                gc_filter(x[b].contiguous(), sigma_s, sr, N, stack_dtype=stack_dtype, out=y[b], workspace=ws,
+                          coeffs=coeffs)
             ctx.save_for_backward(f, sigma_r)
-            ctx.sigma_s, ctx.N = float(sigma_s), N
+            ctx.sigma_s, ctx.N, ctx.coeffs = float(sigma_s), N, coeffs
             return y.reshape(shape)
 
         @staticmethod
@@ -227,10 +253,10 @@ def _autograd_class():
                              dtype=torch.uint8, device=f.device)
             for b in range(x.shape[0]):
                 gfb, gsb = gc_backward(x[b].contiguous(), g[b], ctx.sigma_s, float(sigma_r), ctx.N,
-                                       workspace=ws)
+                                       workspace=ws, coeffs=ctx.coeffs)
                 gf[b].copy_(gfb)
                 gsr = gsr + gsb
-            return gf.reshape(shape), gsr.to(sigma_r.dtype).reshape(sigma_r.shape), None, None, None
+            return gf.reshape(shape), gsr.to(sigma_r.dtype).reshape(sigma_r.shape), None, None, None, None
 
     return GaussChebyshevBF
 
@@ -247,9 +273,9 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32"):
+def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None):
     """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor."""
-    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype)
+    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs)
 
 
 def _descs(images, outs, sigmas_s, sigmas_r, degrees):
@@ -275,7 +301,7 @@ def batched_workspace_bytes(shapes, sigmas_s, degrees, stack_dtype="f32") -> int
 
 def gc_filter_batched(images, sigmas_s, sigmas_r, degrees=None, stack_dtype="f32", graph: bool = True,
                       tile_config: int | None = None, allow_ill_conditioned: bool = False, outs=None,
-                      workspace=None, stream=None):
+                      workspace=None, stream=None, coeffs=None):
     """Filters a list of 2-D float32 images (uneven sizes, one sigma_s,
     sigma_r and degree each) in one persistent launch. Returns (outs,
     statuses): statuses[i] is the bf_status of image i (non-zero: skipped)."""
@@ -297,6 +323,7 @@ def gc_filter_batched(images, sigmas_s, sigmas_r, degrees=None, stack_dtype="f32
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     status = (ctypes.c_int * max(n, 1))()
     flags = (FLAG_GRAPH if graph else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
+    flags |= _coeff_flags(coeffs)
     if tile_config == "auto":
         from . import autotune
         tile_config = autotune.lookup(autotune.batched_key([tuple(x.shape) for x in images], sigmas_s, degrees,

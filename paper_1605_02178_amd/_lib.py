@@ -20,6 +20,7 @@ SIGNATURES = {
     "bf_gc_degree_rule": (_c_int, [_c_double]),
     "bf_gc_coefficients": (_c_int, [_c_double, _c_int, _dp, _dp]),
     "bf_gc_query": (_c_int, [_c_double, _c_int, _c_int, _dp, _dp]),
+    "bf_gc_fit": (_c_int, [_c_double, _c_int, _c_uint, _dp, _dp, _dp, _dp, _dp]),
     "bf_gc_workspace_bytes": (_c_size_t, [_c_int, _c_int, _c_double, _c_int, _c_int, _c_int]),
     "bf_gc_forward": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _c_double, _c_double, _c_int, _c_int,
                                _c_uint, _vp, _c_size_t, _vp]),

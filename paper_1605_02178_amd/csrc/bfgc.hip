@@ -98,7 +98,22 @@ constexpr int kHRC = 8;   // columns per lane in k_hpass (fused with the combine
 constexpr size_t kFlagBytes = 256;
 
 // Coefficient kind selected by the flags.
-static int kind_of(unsigned flags) { return (flags & BF_FLAG_TAYLOR) ? kFitTaylor : kFitChebyshev; }
+static int kind_of(unsigned flags) {
+    return (flags & BF_FLAG_TAYLOR) ? kFitTaylor : (flags & BF_FLAG_MINIMAX) ? kFitMinimax : kFitChebyshev;
+}
+
+// The coefficient kind the flags select must be available for (sigma_r, N);
+// checked whatever BF_FLAG_ALLOW_ILL_CONDITIONED says.
+static bf_status check_kind(double sigma_r, int N, unsigned flags) {
+    if ((flags & BF_FLAG_TAYLOR) && (flags & BF_FLAG_MINIMAX))
+        return fail(BF_ERR_INVALID_ARG, "BF_FLAG_TAYLOR and BF_FLAG_MINIMAX exclude each other");
+    if (flags & BF_FLAG_MINIMAX) {
+        if (N > BF_MINIMAX_MAX_DEGREE) return fail(BF_ERR_UNSUPPORTED, "minimax fit: N above BF_MINIMAX_MAX_DEGREE");
+        if (fit(sigma_r, N, kFitMinimax).b.empty())
+            return fail(BF_ERR_UNSUPPORTED, "minimax fit: not resolvable in binary128 at this (sigma_r, N)");
+    }
+    return BF_OK;
+}
 
 // Tile configuration index from the flags: -1 when none is given, -2 if out of range.
 static int tile_config_of(unsigned flags) {
@@ -136,7 +151,8 @@ static double unit_roundoff(int dtype) {
 }
 
 static bf_status check_conditioning(double sigma_r, int N, int dtype, unsigned flags) {
-    if (flags & BF_FLAG_ALLOW_ILL_CONDITIONED) return BF_OK;
+    bf_status st = check_kind(sigma_r, N, flags);
+    if (st != BF_OK || (flags & BF_FLAG_ALLOW_ILL_CONDITIONED)) return st;
     const Fit &F = fit(sigma_r, N, kind_of(flags));
     if (!std::isfinite(F.kappa) || F.kappa * unit_roundoff(dtype) > 1e-2) {
         char buf[200];
@@ -741,6 +757,24 @@ bf_status bf_gc_coefficients(double sigma_r, int N, double *b_out, double *mu_ou
     const Fit &F = fit(sigma_r, N);
     for (int n = 0; n <= N; ++n) b_out[n] = F.b[n];
     if (mu_out) *mu_out = F.mu;
+    return BF_OK;
+}
+
+bf_status bf_gc_fit(double sigma_r, int N, unsigned flags, double *b_out, double *db_out, double *mu_out,
+                    double *kernel_err, double *kappa) {
+    if (!finite_pos(sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be positive and finite");
+    if (N < 1 || N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N out of [1, BF_MAX_DEGREE]");
+    if (!b_out) return fail(BF_ERR_INVALID_ARG, "b_out is null");
+    bf_status st = check_kind(sigma_r, N, flags);
+    if (st != BF_OK) return st;
+    const Fit &F = fit(sigma_r, N, kind_of(flags));
+    for (int n = 0; n <= N; ++n) {
+        b_out[n] = F.b[n];
+        if (db_out) db_out[n] = F.bd[n];
+    }
+    if (mu_out) *mu_out = F.mu;
+    if (kernel_err) *kernel_err = F.kernel_err;
+    if (kappa) *kappa = F.kappa;
     return BF_OK;
 }
 

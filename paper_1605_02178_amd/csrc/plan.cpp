@@ -134,6 +134,177 @@ static Fit compute_fit(double sigma_r, int N) {
     return F;
 }
 
+// Monomial coefficients of sum_l c_l T_l(y), from the rows of the T_l table
+// (T_{l+1} = 2y T_l - T_{l-1}, eqs. 12-13), accumulated in binary128.
+static std::vector<__float128> monomial_of(const std::vector<__float128> &c) {
+    typedef __float128 qd;
+    const int K = (int)c.size();
+    std::vector<qd> out(K, (qd)0), am1(K, (qd)0), a0(K, (qd)0), ap1(K, (qd)0);
+    a0[0] = 1;
+    for (int n = 0; n < K; ++n) out[n] += c[0] * a0[n];
+    if (K >= 2) {
+        am1 = a0;
+        std::fill(a0.begin(), a0.end(), (qd)0);
+        a0[1] = 1;
+        for (int n = 0; n < K; ++n) out[n] += c[1] * a0[n];
+        for (int l = 1; l + 1 < K; ++l) {
+            for (int n = 0; n < K; ++n) ap1[n] = (n >= 1 ? 2 * a0[n - 1] : (qd)0) - am1[n];
+            for (int n = 0; n < K; ++n) out[n] += c[l + 1] * ap1[n];
+            am1.swap(a0);
+            a0.swap(ap1);
+        }
+    }
+    return out;
+}
+
+static __float128 clenshaw_q(const std::vector<__float128> &c, __float128 y) {
+    __float128 b1 = 0, b2 = 0;
+    for (int l = (int)c.size() - 1; l >= 1; --l) {
+        const __float128 t = 2 * y * b1 - b2 + c[l];
+        b2 = b1;
+        b1 = t;
+    }
+    return y * b1 - b2 + c[0];
+}
+
+// Solves A x = r in place (Gaussian elimination, partial pivoting). n x n, row-major.
+static bool solve_q(std::vector<__float128> &A, std::vector<__float128> &r, int n) {
+    typedef __float128 qd;
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int i = col + 1; i < n; ++i)
+            if (fabsq(A[(size_t)i * n + col]) > fabsq(A[(size_t)piv * n + col])) piv = i;
+        if (A[(size_t)piv * n + col] == 0) return false;
+        if (piv != col) {
+            for (int j = 0; j < n; ++j) std::swap(A[(size_t)piv * n + j], A[(size_t)col * n + j]);
+            std::swap(r[piv], r[col]);
+        }
+        const qd inv = 1 / A[(size_t)col * n + col];
+        for (int i = col + 1; i < n; ++i) {
+            const qd m = A[(size_t)i * n + col] * inv;
+            if (m == 0) continue;
+            for (int j = col; j < n; ++j) A[(size_t)i * n + j] -= m * A[(size_t)col * n + j];
+            r[i] -= m * r[col];
+        }
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        qd s = r[i];
+        for (int j = i + 1; j < n; ++j) s -= A[(size_t)i * n + j] * r[j];
+        r[i] = s / A[(size_t)i * n + i];
+    }
+    return true;
+}
+
+// Minimax (best uniform) polynomial of degree N for exp(mu y) on [-1, 1]
+// (the ideal choice Section III names), by the Remez exchange algorithm in
+// binary128, Chebyshev basis:
+//   1. reference: the N+2 extrema of T_{N+1};
+//   2. level: sum_l c_l T_l(y_k) + (-1)^k E = e^{mu y_k} on the reference;
+//   3. the error r = e^{mu y} - p alternates over the reference, so it has a
+//      zero in each gap (bisection); between consecutive zeros (and the ends)
+//      its extremum (golden section) gives the next reference;
+//   4. repeat until max |r| exceeds |E| by at most 1e-15 relative, then level
+//      once more on the final reference.
+// db_n/dmu: at the optimum the interior reference points are extrema of r, so
+// to first order only the right-hand side moves: the levelled system with
+// right-hand side y_k e^{mu y_k} gives dc_l/dmu. Returns false where the
+// levelled error falls below 1e-28 of e^mu (binary128 would not resolve it)
+// or the exchange does not converge.
+static bool compute_remez(double sigma_r, int N, Fit &F) {
+    typedef __float128 qd;
+    const qd mu = (qd)kTh * (qd)kTh / ((qd)sigma_r * (qd)sigma_r);
+    F.mu = (double)mu;
+    const int K = N + 1, M = N + 2;
+    std::vector<qd> ref(M), c(K), dc(K);
+    for (int k = 0; k < M; ++k) ref[k] = -cosq(M_PIq * (qd)k / (qd)(N + 1));
+    qd E = 0;
+    auto level = [&](const std::vector<qd> &pts, bool deriv) -> bool {
+        std::vector<qd> A((size_t)M * M), r(M), A2, r2(M);
+        for (int k = 0; k < M; ++k) {
+            const qd y = pts[k];
+            qd tm1 = 1, t0 = y;
+            for (int l = 0; l < K; ++l) {
+                qd t;
+                if (l == 0) t = 1;
+                else if (l == 1) t = y;
+                else {
+                    t = 2 * y * t0 - tm1;
+                    tm1 = t0;
+                    t0 = t;
+                }
+                A[(size_t)k * M + l] = t;
+            }
+            A[(size_t)k * M + K] = (k & 1) ? -1 : 1;
+            r[k] = expq(mu * y);
+            r2[k] = y * r[k];
+        }
+        if (deriv) A2 = A;
+        if (!solve_q(A, r, M)) return false;
+        for (int l = 0; l < K; ++l) c[l] = r[l];
+        E = r[K];
+        if (deriv) {
+            if (!solve_q(A2, r2, M)) return false;
+            for (int l = 0; l < K; ++l) dc[l] = r2[l];
+        }
+        return true;
+    };
+    auto err = [&](qd y) { return expq(mu * y) - clenshaw_q(c, y); };
+    bool converged = false;
+    for (int it = 0; it < 60 && !converged; ++it) {
+        if (!level(ref, false)) return false;
+        std::vector<qd> edges(M + 1);
+        edges[0] = -1;
+        edges[M] = 1;
+        for (int k = 0; k + 1 < M; ++k) {          // zero of r in (ref[k], ref[k+1])
+            qd a = ref[k], b = ref[k + 1];
+            const bool neg_a = err(a) < 0;
+            for (int i = 0; i < 80; ++i) {
+                const qd m = (a + b) / 2;
+                if ((err(m) < 0) == neg_a) a = m;
+                else b = m;
+            }
+            edges[k + 1] = (a + b) / 2;
+        }
+        std::vector<qd> next(M);
+        qd emax = 0;
+        const qd g = (sqrtq((qd)5) - 1) / 2;
+        for (int k = 0; k < M; ++k) {              // extremum of sgn r on [edges[k], edges[k+1]]
+            qd a = edges[k], b = edges[k + 1];
+            const qd sgn = err((a + b) / 2) >= 0 ? 1 : -1;
+            qd x1 = b - g * (b - a), x2 = a + g * (b - a);
+            qd f1 = sgn * err(x1), f2 = sgn * err(x2);
+            for (int i = 0; i < 110; ++i) {
+                if (f1 >= f2) {
+                    b = x2; x2 = x1; f2 = f1;
+                    x1 = b - g * (b - a); f1 = sgn * err(x1);
+                } else {
+                    a = x1; x1 = x2; f1 = f2;
+                    x2 = a + g * (b - a); f2 = sgn * err(x2);
+                }
+            }
+            qd x = (a + b) / 2;
+            if (k == 0 && sgn * err((qd)-1) >= sgn * err(x)) x = -1;
+            if (k == M - 1 && sgn * err((qd)1) >= sgn * err(x)) x = 1;
+            next[k] = x;
+            const qd v = fabsq(err(x));
+            if (v > emax) emax = v;
+        }
+        ref = next;
+        converged = emax - fabsq(E) <= (qd)1e-15 * fabsq(E);
+    }
+    if (!converged || !level(ref, true)) return false;
+    if (!(fabsq(E) > (qd)1e-28 * expq(mu))) return false;
+    const std::vector<qd> bq = monomial_of(c), bdq = monomial_of(dc);
+    F.b.resize(K);
+    F.bd.resize(K);
+    for (int n = 0; n < K; ++n) {
+        F.b[n] = (double)bq[n];
+        F.bd[n] = (double)bdq[n];
+    }
+    condition(F, N);
+    return true;
+}
+
 // Taylor coefficients of exp(mu y): b_n = mu^n / n!, db_n/dmu = mu^{n-1}/(n-1)!.
 static Fit compute_taylor(double sigma_r, int N) {
     typedef __float128 qd;
@@ -154,13 +325,24 @@ static Fit compute_taylor(double sigma_r, int N) {
 
 const Fit &fit(double sigma_r, int N, int kind) {
     static std::mutex mtx;
-    static std::map<std::pair<double, int>, Fit> cache[2];
+    static std::map<std::pair<double, int>, Fit> cache[3];
     std::lock_guard<std::mutex> lock(mtx);
-    auto &C = cache[kind == kFitTaylor ? 1 : 0];
+    const int slot = kind == kFitTaylor ? 1 : kind == kFitMinimax ? 2 : 0;
+    auto &C = cache[slot];
     auto key = std::make_pair(sigma_r, N);
     auto it = C.find(key);
     if (it != C.end()) return it->second;
-    return C.emplace(key, kind == kFitTaylor ? compute_taylor(sigma_r, N) : compute_fit(sigma_r, N)).first->second;
+    Fit F;
+    if (slot == 1) F = compute_taylor(sigma_r, N);
+    else if (slot == 2) {
+        if (!compute_remez(sigma_r, N, F)) {   // marked unusable: the caller reports it
+            F = Fit();
+            F.mu = (double)kTh * kTh / (sigma_r * sigma_r);
+            F.kappa = INFINITY;
+            F.kernel_err = INFINITY;
+        }
+    } else F = compute_fit(sigma_r, N);
+    return C.emplace(key, std::move(F)).first->second;
 }
 
 std::vector<double> spatial_taps(double sigma_s) {

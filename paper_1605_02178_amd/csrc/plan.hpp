@@ -34,9 +34,11 @@ struct Fit {
 // Polynomial for the cross term exp(mu y) of the range kernel, in the
 // monomial basis: kind 0 = the Chebyshev interpolant at the zeros of T_{N+1}
 // (Section III), kind 1 = the Taylor polynomial of the Gauss-polynomial
-// filter, b_n = mu^n / n! (Section II). Cached per (sigma_r, N, kind); thread
-// safe.
-enum { kFitChebyshev = 0, kFitTaylor = 1 };
+// filter, b_n = mu^n / n! (Section II), kind 2 = the minimax polynomial
+// (Remez exchange; Section III names it the ideal choice). Cached per
+// (sigma_r, N, kind); thread safe. A minimax fit that cannot be computed has
+// empty b and infinite kappa.
+enum { kFitChebyshev = 0, kFitTaylor = 1, kFitMinimax = 2 };
 const Fit &fit(double sigma_r, int N, int kind = kFitChebyshev);
 
 // Normalised spatial taps exp(-k^2/2 sigma_s^2) / sum, k = -W..W.

@@ -149,3 +149,47 @@ def test_taylor_flag_conditioning(lib):
     # Chebyshev interpolant at the same degree is refused
     assert _fwd(lib, sr=30.0, N=28, dt=2) == 3
     assert _fwd(lib, sr=30.0, N=28, dt=2, flags=0x8, ws=0) == 4
+
+
+@pytest.mark.parametrize("sigma_r,N", [(30.0, 28), (50.0, 11), (25.0, 40), (60.0, 8)])
+def test_planner_minimax_matches_oracle_at_kernel_level(sigma_r, N):
+    """The binary128 Remez of the planner against the oracle's 60-digit one,
+    compared as polynomials weighted by exp(-mu|y|), as for eq. 19."""
+    import paper_1605_02178_amd as bf
+    F = bf.fit(sigma_r, N, "minimax")
+    c = K.minimax_coefficients(sigma_r, N)
+    mu = F["mu"]
+    with mpmath.workdps(50):
+        worst = 0.0
+        for y in np.linspace(-1, 1, 401):
+            pb = mpmath.fsum(mpmath.mpf(v) * mpmath.mpf(y) ** n for n, v in enumerate(F["b"]))
+            pc = mpmath.fsum(mpmath.mpf(v) * (mu * mpmath.mpf(y)) ** n for n, v in enumerate(c))
+            worst = max(worst, float(abs(pb - pc) * mpmath.exp(-mu * abs(y))))
+    assert worst < 1e-11, worst
+
+
+def test_planner_minimax_derivative_matches_oracle():
+    """db_n/dmu of the planner (implicit form) against the oracle's central
+    difference of dc_n/dsigma_r, as polynomials."""
+    import paper_1605_02178_amd as bf
+    sr, N = 50.0, 11
+    F = bf.fit(sr, N, "minimax")
+    _, dc = K.minimax_coefficients_with_derivative(sr, N)
+    mu = F["mu"]
+    dmu = -2.0 * mu / sr
+    # d/dsigma_r of b_n y^n with b_n = c_n mu^n: (dc_n mu^n + c_n n mu^{n-1} dmu) y^n
+    c = K.minimax_coefficients(sr, N)
+    for y in np.linspace(-1, 1, 81):
+        got = sum(db * dmu * y ** n for n, db in enumerate(F["db"]))
+        want = sum((dc[n] * mu ** n + c[n] * n * mu ** (n - 1) * dmu) * y ** n for n in range(N + 1))
+        assert abs(got - want) <= 1e-9 * math.exp(mu * abs(y)) * mu
+    T = bf.fit(sr, N, "taylor")
+    assert T["b"] == pytest.approx([mu ** n / math.factorial(n) for n in range(N + 1)], rel=1e-14)
+
+
+def test_minimax_flag_errors(lib):
+    assert _fwd(lib, flags=0x8 | 0x10) == 1          # Taylor and minimax together
+    assert _fwd(lib, sr=30.0, N=101, flags=0x10) == 2
+    assert _fwd(lib, sr=30.0, N=28, flags=0x10, ws=0) == 4   # accepted up to the workspace check
+    assert lib.bf_gc_fit(30.0, 28, 0x18, (ctypes.c_double * 29)(), None, None, None, None) == 1
+    assert lib.bf_gc_fit(30.0, 101, 0x10, (ctypes.c_double * 102)(), None, None, None, None) == 2

@@ -80,3 +80,44 @@ def test_autotuner_writes_cache_and_keeps_parity(torch_cuda, tmp_path, monkeypat
     assert np.abs(y.cpu().double().numpy() - C.gcf(f, 4.0, 30.0, 28)).max() <= 1e-3
     _log(f"autotune: config {cfg}, times {times}")
     autotune.clear_memory()
+
+
+@pytest.mark.parametrize("stack,sigma_r,N", [("f32", 30.0, 28), ("f32", 50.0, 11), ("f16", 50.0, 11)])
+def test_minimax_filter_matches_oracle(torch_cuda, stack, sigma_r, N):
+    """The minimax polynomial (Remez) through the same kernels, against the C
+    oracle's polynomial filter with the oracle's minimax coefficients: the
+    FP32 bar for the FP32 stack, the stated FP16 bound for the fused path."""
+    import paper_1605_02178_amd as bf
+    from oracle import coeffs as K
+    from oracle import native as C
+    from synth import edge_rich
+    f = edge_rich(150, 170, seed=91).astype(np.float32).astype(np.float64)
+    y = bf.gc_filter(torch_cuda.tensor(f, dtype=torch_cuda.float32, device="cuda:0"), 4.0, sigma_r, N,
+                     stack_dtype=stack, coeffs="minimax")
+    ref = C.polynomial_filter(f, 4.0, sigma_r, K.minimax_coefficients(sigma_r, N))
+    err = np.abs(y.cpu().double().numpy() - ref).max()
+    kappa = bf.fit(sigma_r, N, "minimax")["kappa"]
+    bound = 1e-3 * max(1.0, kappa / 15.0) if stack == "f32" else 0.5
+    _log(f"minimax {stack} sr={sigma_r} N={N}: {err:.3e} (kappa {kappa:.2f}, bound {bound:.2e})")
+    assert err <= bound
+
+
+def test_minimax_backward_matches_fp64_oracle(torch_cuda):
+    """Gradients with minimax coefficients: dL/dsigma_r includes d b_n / d mu
+    from the planner's implicit derivative; the oracle differentiates its own
+    minimax fit by high-precision central differences."""
+    import paper_1605_02178_amd as bf
+    from oracle import adjoint as A
+    from synth import edge_rich
+    torch = torch_cuda
+    f = edge_rich(40, 46, seed=93).astype(np.float32).astype(np.float64)
+    ybar = np.random.default_rng(93).uniform(-1, 1, size=f.shape).astype(np.float32).astype(np.float64)
+    gf, gs = bf.gc_backward(torch.tensor(f, dtype=torch.float32, device="cuda:0"),
+                            torch.tensor(ybar, dtype=torch.float32, device="cuda:0"), 2.0, 50.0, 11,
+                            coeffs="minimax")
+    rf, rs = A.gcf_grad(f, 2.0, 50.0, 11, ybar, kind="minimax")
+    ef = np.abs(gf.cpu().double().numpy() - rf).max()
+    _log(f"minimax backward: |dL/df| err {ef:.3e} (max {np.abs(rf).max():.3e}); dL/dsr {float(gs.item()):.6e} "
+         f"oracle {rs:.6e}")
+    assert ef <= 1e-6 * np.abs(rf).max()
+    assert abs(float(gs.item()) - rs) <= 1e-6 * abs(rs) + 1e-9 * np.abs(ybar).sum()

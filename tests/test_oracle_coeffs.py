@@ -281,3 +281,32 @@ def test_minimax_monomial_coefficients_evaluate_the_fit():
         with mpmath.workdps(40):
             ref = float(K._clenshaw(e, mpmath.mpf(y)))
         assert abs(mono - ref) <= 1e-12 * math.exp(mu)
+
+
+def test_minimax_coefficient_derivative_matches_implicit_form():
+    """dc/dsigma_r of the minimax fit by central differences (the oracle)
+    against the implicit-function form: with the reference frozen, the
+    levelled system with right-hand side y_k exp(mu y_k) gives de_l/dmu (the
+    interior reference points are extrema of the error, so their motion
+    drops out to first order)."""
+    import mpmath
+    sr, N = 50.0, 7
+    c, dc = K.minimax_coefficients_with_derivative(sr, N)
+    with mpmath.workdps(60):
+        mu = mpmath.mpf(255) ** 2 / (4 * mpmath.mpf(sr) ** 2)
+        e, E, ref = K.minimax_fit(mu, N, tol=1e-40)
+        A = mpmath.matrix(N + 2, N + 2)
+        rhs = mpmath.matrix(N + 2, 1)
+        for k, x in enumerate(ref):
+            for l in range(N + 1):
+                A[k, l] = K.chebyshev_T(l, x)
+            A[k, N + 1] = (-1) ** k
+            rhs[k] = x * mpmath.exp(mu * x)
+        de = mpmath.lu_solve(A, rhs)
+        a = K.chebyshev_monomial_table(N)
+        dmu = -2 * mu / sr
+        for n in range(N + 1):
+            b = mpmath.fsum(e[l] * a[l][n] for l in range(n, N + 1))
+            db = mpmath.fsum(de[l] * a[l][n] for l in range(n, N + 1))
+            want = (db - n * b / mu) / mu ** n * dmu           # c_n = mu^-n b_n
+            assert abs(float(want) - dc[n]) <= 1e-10 * abs(float(want)) + 1e-300
