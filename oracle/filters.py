@@ -31,6 +31,9 @@ __all__ = [
     "gcf",
     "gcf_pairwise",
     "polynomial_filter",
+    "direct_joint_bf",
+    "joint_polynomial_filter",
+    "joint_gcf",
 ]
 
 
@@ -233,3 +236,75 @@ def gcf_pairwise(f: np.ndarray, sigma_s: float, sigma_r: float, N: int,
             num += gs * k * t
             den += gs * k
     return num / den + t_c
+
+
+# ---------------------------------------------------------------------------
+# Joint (cross) bilateral filter: the range kernel is taken on a guide image g
+# while f is averaged (the application the conclusion points to, e.g.
+# aggregation of matching costs). Not a formula of the paper; its fast form is
+# the paper's Section II expansion with the range variable taken from g.
+# ---------------------------------------------------------------------------
+
+def direct_joint_bf(f: np.ndarray, g: np.ndarray, sigma_s: float, sigma_r: float, region=None) -> np.ndarray:
+    """sum_j g_s(j) g_r(g(i-j) - g(i)) f(i-j) / sum_j g_s(j) g_r(g(i-j) - g(i))
+    by brute force over Omega, both images through the symmetric extension."""
+    f = np.asarray(f, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    if f.shape != g.shape:
+        raise ValueError("f and g must have the same shape")
+    r0, r1, c0, c1 = _region(f, region)
+    W = radius(sigma_s)
+    rows = np.arange(r0, r1)
+    cols = np.arange(c0, c1)
+    gc = g[r0:r1, c0:c1]
+    num = np.zeros_like(gc)
+    den = np.zeros_like(gc)
+    for j1 in range(-W, W + 1):
+        for j2 in range(-W, W + 1):
+            gs = math.exp(-(j1 * j1 + j2 * j2) / (2.0 * sigma_s * sigma_s))
+            d = _gather(g, rows - j1, cols - j2) - gc
+            w = gs * np.exp(-d * d / (2.0 * sigma_r * sigma_r))
+            num += w * _gather(f, rows - j1, cols - j2)
+            den += w
+    return num / den
+
+
+def joint_polynomial_filter(f: np.ndarray, g: np.ndarray, sigma_s: float, sigma_r: float, c,
+                            L: float = DEFAULT_L, U: float = DEFAULT_U, region=None):
+    """The Section II expansion with the range variable from the guide:
+      h = g - t_c (eq. 17 on the guide),  G_n = (h / sigma_r)^n,
+      F_n = exp(-h^2 / 2 sigma_r^2) G_n                         (eq. 6 on g)
+      Q = sum_{n=0}^{N} c_n G_n Gauss[F_n]                      (eq. 9)
+      P = sum_{n=0}^{N} c_n G_n Gauss[F_n f]                    (eq. 8, f in place of g)
+      output P / Q                                              (eq. 10)
+    With g = f, F_n f = F_n (h + t_c) = sigma_r F_{n+1} + t_c F_n, which gives
+    back the plain filter."""
+    f = np.asarray(f, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    N = c.size - 1
+    t_c = 0.5 * (L + U)
+    r0, r1, c0, c1 = _region(f, region)
+    W = radius(sigma_s)
+    rows = np.arange(r0 - W, r1 + W)
+    cols = np.arange(c0 - W, c1 + W)
+    h_ext = _gather(g, rows, cols) - t_c
+    f_ext = _gather(f, rows, cols)
+    u_ext = h_ext / sigma_r
+    u_ctr = u_ext[W:W + (r1 - r0), W:W + (c1 - c0)]
+    E_ext = np.exp(-h_ext * h_ext / (2.0 * sigma_r * sigma_r))
+    inner = (W, W + (r1 - r0), W, W + (c1 - c0))
+    P = np.zeros_like(u_ctr)
+    Q = np.zeros_like(u_ctr)
+    for n in range(N + 1):
+        F_n = E_ext * u_ext ** n
+        Q += c[n] * u_ctr ** n * gauss_filter_separable(F_n, sigma_s, region=inner)
+        P += c[n] * u_ctr ** n * gauss_filter_separable(F_n * f_ext, sigma_s, region=inner)
+    return P / Q
+
+
+def joint_gcf(f: np.ndarray, g: np.ndarray, sigma_s: float, sigma_r: float, N: int,
+              L: float = DEFAULT_L, U: float = DEFAULT_U, region=None):
+    """Joint filter with the Gauss-Chebyshev coefficients of eq. (19)."""
+    c, _ = gcf_coefficients(sigma_r, N, L, U)
+    return joint_polynomial_filter(f, g, sigma_s, sigma_r, c, L, U, region)
