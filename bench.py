@@ -20,6 +20,7 @@ Prints one JSON line. Besides the contract fields it carries
   batched       the uneven 64-image batch, one graph launch vs a per-image loop
   differentiation   forward + backward of 8 x 1024^2 images through the
                 autograd function
+  joint         the joint (cross) filter at the headline size
 """
 from __future__ import annotations
 
@@ -252,6 +253,36 @@ def bench_differentiation(bf, steps, log):
             "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}}
 
 
+def bench_joint(bf, f, f64, sigma_s, sigma_r, N, steps, log):
+    """Joint (cross) filter at the headline size: the headline image as guide,
+    a ramp + rectangles image as the averaged values, FP32 stack at N and
+    FP16 stack at N, three-kernel tiles (2(N+1) planes)."""
+    import numpy as np
+    import torch
+    from synth import ramp_rectangles
+    H, Wd = f.shape
+    v = torch.tensor(ramp_rectangles(H, Wd, seed=17).astype(np.float32), device="cuda:0")
+    out = {}
+    for stack in ("f32", "f16"):
+        ws = torch.empty(bf.joint_workspace_bytes(H, Wd, sigma_s, N, stack), dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(v)
+        bf.gc_joint_filter(v, f, sigma_s, sigma_r, N, stack_dtype=stack, out=y, workspace=ws)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            bf.gc_joint_filter(v, f, sigma_s, sigma_r, N, stack_dtype=stack, out=y, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[stack] = {"ms_per_step": round(ms, 3), "mpx_s": round(H * Wd / 1e6 / (ms / 1e3), 1)}
+        log(f"bench: joint {stack} N={N} {ms:.2f} ms")
+    out.update({"image": f"{H}x{Wd}", "sigma_s": sigma_s, "sigma_r": sigma_r, "degree": N, "planes": 2 * (N + 1),
+                "steps": steps})
+    return out
+
+
 def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
     """Plain-C FP64 oracle (OpenMP over rows) on rows [0, rows) of the image."""
     from oracle import native as C
@@ -284,6 +315,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the uneven-batch comparison")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-backward", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-joint", action="store_true", help="skip the joint-filter timing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -405,6 +437,9 @@ def main():
         result["batched"] = bench_batched(bf, args.batch_steps, log, "f32")
         if not args.no_fp16:
             result["batched_fp16"] = bench_batched(bf, args.batch_steps, log, "f16")
+
+    if not args.no_joint:
+        result["joint"] = bench_joint(bf, f, f64, ss, sr, N, args.batch_steps, log)
 
     if not args.no_backward:
         result["differentiation"] = bench_differentiation(bf, args.batch_steps, log)

@@ -174,6 +174,26 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
                         void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Joint (cross) bilateral filter: the range kernel is evaluated on the guide
+ * g and the values of f are averaged (the use the conclusion points to, e.g.
+ * aggregation with an image as guide). Same expansion as bf_gc_forward with
+ * the range variable from g: planes A_n = e^{-mu s^2/2} s^n (s from g) and
+ * B_n = A_n (f - t_c)/t_h, both filtered (eq. 7), Q = sum b_n s_i^n Abar_n,
+ * P = sum b_n s_i^n Bbar_n, y = t_c + t_h P/Q.
+ *   g, f   device, height x width FP32, row stride ld (the same for both),
+ *          read only; values in [0, 255] (others set BF_DEVFLAG_RANGE)
+ *   out    device, same layout; must overlap neither g nor f
+ *   other arguments as bf_gc_forward; 2(N+1) planes per stack. Tile
+ *   configurations 0-3 only (BF_TILE_FUSED: BF_ERR_UNSUPPORTED); no staged
+ *   form (BF_FLAG_STAGED: BF_ERR_INVALID_ARG). ws: at least
+ *   bf_gc_joint_workspace_bytes(...) bytes, 256-byte aligned.
+ */
+size_t bf_gc_joint_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype);
+bf_status bf_gc_joint_forward(const float *g, const float *f, float *out, int height, int width, int ld,
+                              double sigma_s, double sigma_r, int N, int stack_dtype, unsigned flags,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Backward of bf_gc_forward (not in the paper): for L = sum_i grad_out_i y_i
  * with y the forward output, writes grad_f = dL/df (device FP32, height x
  * width, row stride ld) and *grad_sigma_r = dL/dsigma_r (device double;

@@ -24,6 +24,7 @@ __all__ = [
     "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
     "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
+    "gc_joint_filter", "joint_workspace_bytes",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -186,6 +187,44 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    _stream_ptr(stream))
     _lib.check(st, "bf_gc_forward")
+    return out
+
+
+def joint_workspace_bytes(height, width, sigma_s, N, stack_dtype="f32") -> int:
+    return int(_lib.load().bf_gc_joint_workspace_bytes(int(height), int(width), float(sigma_s), int(N),
+                                                       _dtype_code(stack_dtype)))
+
+
+def gc_joint_filter(f, guide, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
+                    allow_ill_conditioned: bool = False, out=None, workspace=None, stream=None,
+                    tile_config: int | None = None, coeffs=None):
+    """Joint (cross) bilateral filter of f with the range kernel on `guide`
+    (both 2-D float32 in [0, 255], same shape and row stride)."""
+    import torch
+    _check_image(f)
+    _check_image(guide, "guide")
+    if tuple(guide.shape) != tuple(f.shape) or (f.shape[0] > 1 and guide.stride(0) != f.stride(0)):
+        raise ValueError("guide must have the shape and row stride of f")
+    H, Wd = f.shape
+    N = degree_rule(sigma_r) if degree is None else int(degree)
+    code = _dtype_code(stack_dtype)
+    if out is None:
+        out = torch.empty_like(f, memory_format=torch.contiguous_format)
+    _check_image(out, "out")
+    if out.stride(0) != f.stride(0) and H > 1:
+        raise ValueError("out must have the row stride of f")
+    ld = f.stride(0) if H > 1 else Wd
+    need = joint_workspace_bytes(H, Wd, sigma_s, N, code)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    flags = (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0) | _coeff_flags(coeffs)
+    if tile_config is not None:
+        flags |= flag_tile(tile_config)
+    st = _lib.load().bf_gc_joint_forward(ctypes.c_void_p(guide.data_ptr()), ctypes.c_void_p(f.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), H, Wd, max(ld, Wd), float(sigma_s),
+                                         float(sigma_r), N, code, flags, ctypes.c_void_p(workspace.data_ptr()),
+                                         workspace.numel(), _stream_ptr(stream))
+    _lib.check(st, "bf_gc_joint_forward")
     return out
 
 

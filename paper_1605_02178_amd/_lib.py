@@ -26,6 +26,9 @@ SIGNATURES = {
                                _c_uint, _vp, _c_size_t, _vp]),
     "bf_gc_backward": (_c_int, [_vp, _vp, _vp, _vp, _c_int, _c_int, _c_int, _c_double, _c_double, _c_int,
                                 _c_int, _c_uint, _vp, _c_size_t, _vp]),
+    "bf_gc_joint_workspace_bytes": (_c_size_t, [_c_int, _c_int, _c_double, _c_int, _c_int]),
+    "bf_gc_joint_forward": (_c_int, [_vp, _vp, _vp, _c_int, _c_int, _c_int, _c_double, _c_double, _c_int, _c_int,
+                                     _c_uint, _vp, _c_size_t, _vp]),
     "bf_gc_param_bytes": (_c_size_t, [_c_double, _c_int]),
     "bf_gc_plane_scales": (_c_int, [_c_double, _c_int, _c_int, _ip]),
     "bf_gc_stack_build": (_c_int, [_vp, _c_int, _c_int, _c_int, _c_double, _c_int, _c_int, _vp, _c_ll,

@@ -311,6 +311,41 @@ static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, 
     return launch_hpass_combine<S, RH>(stackB, f, out, nullptr, nullptr, H, Wd, ld, pst, ldt, prm, L, stream);
 }
 
+// Joint filter: build both plane sets, column pass over all 2(N+1) planes,
+// row pass + combine of A_n and B_n together.
+template <class S, int RV, int RH>
+static bf_status run_joint_forward(const float *g, const float *f, float *out, int H, int Wd, int ld,
+                                   double sigma_s, double sigma_r, int N, int dtype, unsigned flags, char *ws,
+                                   hipStream_t stream) {
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    ParamLayout L;
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
+    if (st != BF_OK) return st;
+    const int lds = lds_of(Wd);
+    const long long ps = (long long)H * lds;
+    const int planes = 2 * (N + 1);
+    char *stackA = ws + kFlagBytes + align256(sizeof(double) * L.total);
+    char *stackB = stackA + align256((size_t)planes * ps * sizeof(typename S::T));
+    const double mu = fit(sigma_r, N).mu;
+    {
+        dim3 grid((Wd + 255) / 256, (H + kBuildRows - 1) / kBuildRows);
+        ProfScope prof_("k_joint_build", stream);
+        hipLaunchKernelGGL((k_joint_build<S>), grid, dim3(256), 0, stream, g, f, H, Wd, ld,
+                           (typename S::T *)stackA, ps, lds, N, prm + L.off_scale, mu, flag);
+        if ((st = check_launch("k_joint_build")) != BF_OK) return st;
+    }
+    const int ldt = ldt_of(H);
+    const long long pst = (long long)Wd * ldt;
+    if ((st = launch_vpass<S, RV>(stackA, stackB, planes, H, Wd, ps, lds, pst, ldt, prm, L, stream)) != BF_OK)
+        return st;
+    dim3 gh((H + 63) / 64, (Wd + 4 * RH - 1) / (4 * RH));
+    ProfScope prof_("k_hpass_joint", stream);
+    hipLaunchKernelGGL((k_hpass_joint<S, RH>), gh, dim3(256), 0, stream, (const typename S::T *)stackB, g, out, H,
+                       Wd, ld, pst, ldt, N, prm + L.off_taps, prm + L.off_cq, L.W);
+    return check_launch("k_hpass_joint");
+}
+
 constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
 constexpr int kNeighborBlocks = 2048;
 
@@ -841,6 +876,51 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     }
 #undef BF_FWD_CFG
 #undef BF_FWD
+}
+
+size_t bf_gc_joint_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype) {
+    if (check_common(height, width, sigma_s, 30.0, N, stack_dtype) != BF_OK) return 0;
+    const size_t planes = 2 * ((size_t)N + 1);
+    const size_t A = planes * height * lds_of(width) * esize(stack_dtype);
+    const size_t B = planes * width * ldt_of(height) * esize(stack_dtype);
+    return kFlagBytes + align256(bf_gc_param_bytes(sigma_s, N)) + align256(A) + align256(B);
+}
+
+bf_status bf_gc_joint_forward(const float *g, const float *f, float *out, int height, int width, int ld,
+                              double sigma_s, double sigma_r, int N, int stack_dtype, unsigned flags, void *ws,
+                              size_t ws_bytes, void *stream) {
+    bf_status st = check_common(height, width, sigma_s, sigma_r, N, stack_dtype);
+    if (st != BF_OK) return st;
+    if (height == 0 || width == 0) return BF_OK;
+    if (!g || !f || !out) return fail(BF_ERR_INVALID_ARG, "g, f and out must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    const size_t img = ((size_t)(height - 1) * ld + width) * sizeof(float);
+    if (overlaps(f, img, out, img) || overlaps(g, img, out, img))
+        return fail(BF_ERR_INVALID_ARG, "out overlaps f or g");
+    if (flags & BF_FLAG_STAGED) return fail(BF_ERR_INVALID_ARG, "the joint filter has no staged form");
+    if ((st = check_conditioning(sigma_r, N, stack_dtype, flags)) != BF_OK) return st;
+    const size_t need = bf_gc_joint_workspace_bytes(height, width, sigma_s, N, stack_dtype);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
+    int cfg = tile_config_of(flags);
+    if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    if (cfg == BF_TILE_FUSED) return fail(BF_ERR_UNSUPPORTED, "the joint filter runs the three-kernel tiles");
+    if (cfg == -1) cfg = 0;
+    hipStream_t s = (hipStream_t)stream;
+#define BF_JNT(S, RV, RH) run_joint_forward<S, RV, RH>(g, f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s)
+#define BF_JNT_CFG(S)                                   \
+    switch (cfg) {                                      \
+    case 0: return BF_JNT(S, 16, 8);                    \
+    case 1: return BF_JNT(S, 8, 8);                     \
+    case 2: return BF_JNT(S, 16, 4);                    \
+    default: return BF_JNT(S, 8, 4);                    \
+    }
+    switch (stack_dtype) {
+    case BF_STACK_F32: BF_JNT_CFG(StF32)
+    case BF_STACK_F16: BF_JNT_CFG(StF16)
+    default: BF_JNT_CFG(StBF16)
+    }
+#undef BF_JNT_CFG
+#undef BF_JNT
 }
 
 bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, double *grad_sigma_r, int height,

@@ -431,6 +431,84 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
 }
 
 // ---------------------------------------------------------------------------
+// Joint (cross) filter: the range variable comes from a guide g, the averaged
+// values from f. Planes 0..N hold A_n = e^{-mu s^2/2} s^n with s from g (eq. 6
+// on the guide), planes N+1..2N+1 hold B_n = A_n ft with ft = (f - t_c)/t_h;
+// both carry the plane scale 2^k_n. Q = sum cq_n s^n Abar_n and
+// Pt = sum cq_n s^n Bbar_n (eqs. 8-9 with f in place of the image), and
+// y = t_c + t_h Pt/Q (eq. 10).
+// ---------------------------------------------------------------------------
+
+template <class S>
+__global__ __launch_bounds__(256) void k_joint_build(const float *__restrict__ g, const float *__restrict__ f,
+                                                      int H, int Wd, int ld, typename S::T *__restrict__ stack,
+                                                      long long ps, int lds, int N,
+                                                      const double *__restrict__ scale, double mu,
+                                                      unsigned *__restrict__ flag) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int r0 = blockIdx.y * kBuildRows, r1 = min(H, r0 + kBuildRows);
+    for (int r = r0; r < r1; ++r) {
+        bool bad = false;
+        if (c < Wd) {
+            const float gv = g[(long long)r * ld + c], fv = f[(long long)r * ld + c];
+            bad = !(gv >= 0.0f && gv <= 255.0f) || !(fv >= 0.0f && fv <= 255.0f);
+            const double s = ((double)gv - kTc) * (1.0 / kTh);          // eq. (17) on the guide
+            const double ft = ((double)fv - kTc) * (1.0 / kTh);
+            double v = exp(-0.5 * mu * s * s);
+            typename S::T *dst = stack + (long long)r * lds + c;
+            for (int n = 0; n <= N; ++n) {
+                dst[n * ps] = S::enc(v * scale[n]);
+                dst[(N + 1 + n) * ps] = S::enc(v * ft * scale[n]);
+                v *= s;
+            }
+        }
+        if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1)
+            atomicOr(flag, BF_DEVFLAG_RANGE);
+    }
+}
+
+// Row pass of the joint filter on the transposed planes (lane = row, R
+// columns per wave), A_n and B_n together, folded by Horner's rule over
+// descending n.
+template <class S, int R>
+__global__ __launch_bounds__(256) void k_hpass_joint(const typename S::T *__restrict__ inT,
+                                                      const float *__restrict__ g, float *__restrict__ out,
+                                                      int H, int Wd, int ld, long long pst, int ldt, int N,
+                                                      const double *__restrict__ taps,
+                                                      const double *__restrict__ cq, int W) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r = blockIdx.x * 64 + lane;
+    const int c0 = (blockIdx.y * 4 + wave) * R;
+    if (c0 >= Wd) return;
+    const int rl = r < H ? r : H - 1;
+    double s[R], Pa[R], Qa[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
+        s[q] = ((double)g[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
+        Pa[q] = 0.0;
+        Qa[q] = 0.0;
+    }
+    for (int n = N; n >= 0; --n) {
+        double a[R], b[R];
+        conv_line<S, R, 8>(inT + (long long)n * pst, rl, ldt, c0, Wd, W, taps + (kTapPad - 1), a);
+        conv_line<S, R, 8>(inT + (long long)(N + 1 + n) * pst, rl, ldt, c0, Wd, W, taps + (kTapPad - 1), b);
+        const double c = cq[n];
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            Qa[q] = fma(Qa[q], s[q], c * a[q]);
+            Pa[q] = fma(Pa[q], s[q], c * b[q]);
+        }
+    }
+    if (r < H) {
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (c0 + q < Wd) out[(long long)r * ld + c0 + q] = (float)(kTc + kTh * (Pa[q] / Qa[q]));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Backward: gradients of L = sum_i ybar_i y_i with respect to f and sigma_r.
 // The paper has no backward pass; this is the adjoint of the forward above.
 // With P' = sum cp_n s^n Hbar_{n+1}, Q = sum cq_n s^n Hbar_n, y = t_c + t_h P'/Q:
