@@ -31,6 +31,8 @@ __all__ = [
     "gcf",
     "gcf_pairwise",
     "polynomial_filter",
+    "pivot_plan",
+    "pivot_gcf",
     "direct_joint_bf",
     "joint_polynomial_filter",
     "joint_gcf",
@@ -145,7 +147,7 @@ def gauss_filter_separable(F: np.ndarray, sigma_s: float, region=None) -> np.nda
 
 def polynomial_filter(f: np.ndarray, sigma_s: float, sigma_r: float, c,
                       L: float = DEFAULT_L, U: float = DEFAULT_U, region=None,
-                      separable: bool = True, return_parts: bool = False):
+                      separable: bool = True, return_parts: bool = False, t_c: float | None = None):
     """The fast algorithm of Section II for a given polynomial
     exp(x) ~ sum_n c_n x^n (eq. 3), applied to the centred image (eq. 17),
     with the centring undone at the end (Section III-B).
@@ -159,11 +161,12 @@ def polynomial_filter(f: np.ndarray, sigma_s: float, sigma_r: float, c,
       B_hat[f] = B_hat[g] + t_c
 
     With return_parts, also returns a dict holding P, Q and the stacks F
-    (n = 0..N+1, on the output region) and F_bar."""
+    (n = 0..N+1, on the output region) and F_bar. t_c overrides the centre
+    (L + U)/2 (the pivoted form below)."""
     f = np.asarray(f, dtype=np.float64)
     c = np.asarray(c, dtype=np.float64)
     N = c.size - 1
-    t_c = 0.5 * (L + U)
+    t_c = 0.5 * (L + U) if t_c is None else float(t_c)
     r0, r1, c0, c1 = _region(f, region)
     W = radius(sigma_s)
     H, Wd = f.shape
@@ -308,3 +311,51 @@ def joint_gcf(f: np.ndarray, g: np.ndarray, sigma_s: float, sigma_r: float, N: i
     """Joint filter with the Gauss-Chebyshev coefficients of eq. (19)."""
     c, _ = gcf_coefficients(sigma_r, N, L, U)
     return joint_polynomial_filter(f, g, sigma_s, sigma_r, c, L, U, region)
+
+
+# ---------------------------------------------------------------------------
+# Pivoted form for small sigma_r (not in the paper). The single expansion of
+# Section III-B centres every pixel at t_c = (L+U)/2, so the cross term
+# exp(g_i g_j / sigma_r^2) spans [-mu, mu], mu = (U-L)^2 / (4 sigma_r^2), which
+# grows as 1/sigma_r^2 and makes the monomial sums ill-conditioned. Splitting
+# [L, U] into K equal sub-ranges and centring each at its midpoint t_k bounds
+# the centre pixel's offset by h = (U-L)/(2K), so the cross term spans
+# [-mu_k, mu_k] with mu_k = h R_k / sigma_r^2, R_k = max(t_k - L, U - t_k) the
+# largest neighbour offset. A pixel takes the output of the sub-range its own
+# value lies in (the last sub-range includes U).
+# ---------------------------------------------------------------------------
+
+def pivot_plan(sigma_r: float, K: int, N=None, L: float = DEFAULT_L, U: float = DEFAULT_U):
+    """Per sub-range k: (lo_k, hi_k, t_k, h, R_k, mu_k, N_k); N_k from the
+    degree rule at mu_k when N is None."""
+    from .coeffs import degree_rule_mu
+    out = []
+    h = (U - L) / (2.0 * K)
+    for k in range(K):
+        lo = L + (U - L) * k / K
+        hi = L + (U - L) * (k + 1) / K
+        t = 0.5 * (lo + hi)
+        R = max(t - L, U - t)
+        mu = h * R / (sigma_r * sigma_r)
+        out.append((lo, hi, t, h, R, mu, degree_rule_mu(mu, L, U) if N is None else int(N)))
+    return out
+
+
+def pivot_gcf(f: np.ndarray, sigma_s: float, sigma_r: float, K: int, N=None,
+              L: float = DEFAULT_L, U: float = DEFAULT_U, region=None):
+    """Pivoted Gauss-Chebyshev filter: for each sub-range, the fast algorithm
+    of Section II centred at t_k with the eq. 19 coefficients of exp on
+    [-mu_k, mu_k]; each output pixel from the sub-range of its own value."""
+    from .coeffs import chebyshev_coefficients_mu
+    f = np.asarray(f, dtype=np.float64)
+    r0, r1, c0, c1 = _region(f, region)
+    ctr = f[r0:r1, c0:c1]
+    out = np.full(ctr.shape, np.nan)
+    for k, (lo, hi, t, h, R, mu, Nk) in enumerate(pivot_plan(sigma_r, K, N, L, U)):
+        mask = (ctr >= lo) & ((ctr < hi) if k < K - 1 else (ctr <= hi))
+        if not mask.any():
+            continue
+        c = chebyshev_coefficients_mu(mu, Nk)
+        y = polynomial_filter(f, sigma_s, sigma_r, c, L, U, region=(r0, r1, c0, c1), t_c=t)
+        out[mask] = y[mask]
+    return out
