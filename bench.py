@@ -21,6 +21,7 @@ Prints one JSON line. Besides the contract fields it carries
   differentiation   forward + backward of 8 x 1024^2 images through the
                 autograd function
   joint         the joint (cross) filter at the headline size
+  small_sigma_r the pivoted form at sigma_r = 10 (sub-ranges of [0, 255])
 """
 from __future__ import annotations
 
@@ -283,6 +284,39 @@ def bench_joint(bf, f, f64, sigma_s, sigma_r, N, steps, log):
     return out
 
 
+def bench_small_sigma_r(bf, f, f64, sigma_s, steps, log, sigma_r=10.0):
+    """Small sigma_r at the headline size (sigma_r = 10, where the single
+    expansion is refused): the pivoted form with the smallest well-conditioned
+    sub-range count for the FP32 stack, rule degrees; time and max-abs error
+    against the direct filter on a 64^2 centre crop."""
+    import numpy as np
+    import torch
+    from oracle import native as C
+    H, Wd = f.shape
+    K = bf.pivot_count(sigma_r, "f32")
+    ws = torch.empty(bf.pivots_workspace_bytes(H, Wd, sigma_s, sigma_r, K), dtype=torch.uint8, device="cuda:0")
+    y = torch.empty_like(f)
+    bf.gc_filter_pivots(f, sigma_s, sigma_r, K, out=y, workspace=ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        bf.gc_filter_pivots(f, sigma_s, sigma_r, K, out=y, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    d0 = H // 2 - 32
+    direct = C.direct_bf(f64, sigma_s, sigma_r, region=(d0, d0 + 64, d0, d0 + 64))
+    err = float(np.abs(y.cpu().double().numpy()[d0:d0 + 64, d0:d0 + 64] - direct).max())
+    plan = bf.pivot_plan(sigma_r, K)
+    log(f"bench: sigma_r={sigma_r} pivoted K={K} {ms:.2f} ms, max abs vs direct {err:.4f}")
+    return {"sigma_r": sigma_r, "sigma_s": sigma_s, "sub_ranges": K, "degrees": [p[0] for p in plan],
+            "planes": sum(p[0] + 2 for p in plan), "ms_per_step": round(ms, 3),
+            "mpx_s": round(H * Wd / 1e6 / (ms / 1e3), 1), "max_abs_vs_direct_64c": err, "stack": "f32",
+            "steps": steps}
+
+
 def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
     """Plain-C FP64 oracle (OpenMP over rows) on rows [0, rows) of the image."""
     from oracle import native as C
@@ -316,6 +350,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-backward", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-filter timing")
+    ap.add_argument("--no-small-sigma-r", action="store_true", help="skip the pivoted small-sigma_r timing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -437,6 +472,9 @@ def main():
         result["batched"] = bench_batched(bf, args.batch_steps, log, "f32")
         if not args.no_fp16:
             result["batched_fp16"] = bench_batched(bf, args.batch_steps, log, "f16")
+
+    if not args.no_small_sigma_r:
+        result["small_sigma_r"] = bench_small_sigma_r(bf, f, f64, ss, args.batch_steps, log)
 
     if not args.no_joint:
         result["joint"] = bench_joint(bf, f, f64, ss, sr, N, args.batch_steps, log)

@@ -174,6 +174,38 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
                         void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Pivoted forward for small sigma_r (not in the paper). The single expansion
+ * centres every pixel at t_c = 127.5, so the cross term spans [-mu, mu] with
+ * mu = t_h^2/sigma_r^2, which grows as 1/sigma_r^2 and makes the monomial sums
+ * ill-conditioned (FP32 fails below sigma_r ~ 20). Here [0, 255] is split
+ * into K equal sub-ranges; for a pixel whose value lies in sub-range k the
+ * expansion is centred at its midpoint t_k (eq. 17 with t_k), so the centre
+ * offset is at most h = 127.5/K and the cross term spans [-mu_k, mu_k],
+ * mu_k = h R_k / sigma_r^2 (R_k = max(t_k, 255 - t_k)). Each sub-range runs
+ * the three-kernel forward over the whole image and keeps the outputs whose
+ * centre value lies in it ([lo, hi); values below 0 go to the first, values
+ * from 255 up and NaN to the last).
+ *   K: sub-ranges, 1..BF_MAX_PIVOTS (K = 1 is the plain expansion)
+ *   N: the degree of every sub-range, or <= 0 for the degree rule at mu_k
+ *   other arguments as bf_gc_forward (Chebyshev coefficients only:
+ *   BF_FLAG_TAYLOR, BF_FLAG_MINIMAX, BF_FLAG_STAGED are BF_ERR_INVALID_ARG;
+ *   BF_TILE_FUSED is BF_ERR_UNSUPPORTED). The conditioning check applies to
+ *   every sub-range. ws: at least bf_gc_pivots_workspace_bytes(...) bytes.
+ * bf_gc_pivot_count: the smallest K in {1, 2, 4, ..., BF_MAX_PIVOTS} whose
+ * sub-ranges pass the conditioning check for the stack type at the rule's
+ * degrees, or -1. bf_gc_pivot_plan: per sub-range (host arrays of K, each may
+ * be NULL) its degree (-1 where the rule finds none), mu_k and kappa.
+ */
+#define BF_MAX_PIVOTS 64
+int bf_gc_pivot_count(double sigma_r, int stack_dtype);
+bf_status bf_gc_pivot_plan(double sigma_r, int K, int N, int *N_out, double *mu_out, double *kappa_out);
+size_t bf_gc_pivots_workspace_bytes(int height, int width, double sigma_s, double sigma_r, int K, int N,
+                                    int stack_dtype);
+bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width, int ld, double sigma_s,
+                               double sigma_r, int K, int N, int stack_dtype, unsigned flags, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/*
  * Joint (cross) bilateral filter: the range kernel is evaluated on the guide
  * g and the values of f are averaged (the use the conclusion points to, e.g.
  * aggregation with an image as guide). Same expansion as bf_gc_forward with

@@ -24,7 +24,8 @@ __all__ = [
     "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
     "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
-    "gc_joint_filter", "joint_workspace_bytes",
+    "gc_joint_filter", "joint_workspace_bytes", "gc_filter_pivots", "pivot_count", "pivot_plan",
+    "pivots_workspace_bytes",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -187,6 +188,62 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    _stream_ptr(stream))
     _lib.check(st, "bf_gc_forward")
+    return out
+
+
+def pivot_count(sigma_r: float, stack_dtype="f32") -> int:
+    """Smallest number of sub-ranges (a power of two) whose pivoted expansions
+    pass the conditioning check for the stack type; -1 if none up to 64."""
+    return int(_lib.load().bf_gc_pivot_count(float(sigma_r), _dtype_code(stack_dtype)))
+
+
+def pivot_plan(sigma_r: float, K: int, degree: int | None = None):
+    """[(N_k, mu_k, kappa_k)] of the pivoted form."""
+    n = (ctypes.c_int * K)()
+    mu = (ctypes.c_double * K)()
+    ka = (ctypes.c_double * K)()
+    _lib.check(_lib.load().bf_gc_pivot_plan(float(sigma_r), int(K), int(degree or 0), n, mu, ka),
+               "bf_gc_pivot_plan")
+    return [(n[k], mu[k], ka[k]) for k in range(K)]
+
+
+def pivots_workspace_bytes(height, width, sigma_s, sigma_r, K, degree=None, stack_dtype="f32") -> int:
+    return int(_lib.load().bf_gc_pivots_workspace_bytes(int(height), int(width), float(sigma_s), float(sigma_r),
+                                                        int(K), int(degree or 0), _dtype_code(stack_dtype)))
+
+
+def gc_filter_pivots(f, sigma_s: float, sigma_r: float, K: int | None = None, degree: int | None = None,
+                     stack_dtype="f32", allow_ill_conditioned: bool = False, out=None, workspace=None,
+                     stream=None, tile_config: int | None = None):
+    """Pivoted Gauss-Chebyshev filter for small sigma_r: K sub-ranges of
+    [0, 255], each expanded around its midpoint (K=None: the smallest count
+    that is well conditioned for the stack type); degree None: the rule per
+    sub-range."""
+    import torch
+    _check_image(f)
+    H, Wd = f.shape
+    code = _dtype_code(stack_dtype)
+    if K is None:
+        K = pivot_count(sigma_r, code)
+        if K < 1:
+            raise ValueError(f"no sub-range count up to 64 is well conditioned at sigma_r={sigma_r}")
+    if out is None:
+        out = torch.empty_like(f, memory_format=torch.contiguous_format)
+    _check_image(out, "out")
+    if out.stride(0) != f.stride(0) and H > 1:
+        raise ValueError("out must have the row stride of f")
+    ld = f.stride(0) if H > 1 else Wd
+    need = pivots_workspace_bytes(H, Wd, sigma_s, sigma_r, K, degree, code)
+    if workspace is None:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    flags = FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0
+    if tile_config is not None:
+        flags |= flag_tile(tile_config)
+    st = _lib.load().bf_gc_forward_pivots(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), H, Wd,
+                                          max(ld, Wd), float(sigma_s), float(sigma_r), int(K), int(degree or 0),
+                                          code, flags, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                          _stream_ptr(stream))
+    _lib.check(st, "bf_gc_forward_pivots")
     return out
 
 

@@ -194,11 +194,11 @@ struct Plan {
 template <class S>
 static bf_status launch_build(const float *f, int H, int Wd, int ld, void *stack, long long ps, int lds, int P,
                               const double *prm, const ParamLayout &L, double mu, unsigned *flag,
-                              hipStream_t stream) {
+                              hipStream_t stream, const Centring &C = plain_centring()) {
     dim3 grid((Wd + 255) / 256, (H + kBuildRows - 1) / kBuildRows);
     ProfScope prof_("k_stack_build", stream);
     hipLaunchKernelGGL(k_stack_build<S>, grid, dim3(256), 0, stream, f, H, Wd, ld,
-                       (typename S::T *)stack, ps, lds, P, prm + L.off_scale, mu, flag);
+                       (typename S::T *)stack, ps, lds, P, prm + L.off_scale, mu, flag, C);
     return check_launch("k_stack_build");
 }
 
@@ -226,19 +226,20 @@ static bf_status launch_gauss(void *stack, void *tmpT, int planes, int H, int Wd
     hipLaunchKernelGGL((k_hpass<S, kHR, false>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
                        (typename S::T *)stack, (const float *)nullptr, (float *)nullptr, (float *)nullptr,
                        (float *)nullptr, H, Wd, 0, ps, lds, pst, ldt, planes, 0, prm + L.off_taps,
-                       prm + L.off_cq, prm + L.off_cp, L.W);
+                       prm + L.off_cq, prm + L.off_cp, L.W, plain_centring());
     return check_launch("k_hpass");
 }
 
 template <class S, int RH = kHRC>
 static bf_status launch_hpass_combine(const void *tmpT, const float *f, float *out, float *Pout, float *Qout, int H,
                                       int Wd, int ld, long long pst, int ldt, const double *prm,
-                                      const ParamLayout &L, hipStream_t stream) {
+                                      const ParamLayout &L, hipStream_t stream,
+                                      const Centring &C = plain_centring()) {
     dim3 gh((H + 63) / 64, (Wd + 4 * RH - 1) / (4 * RH));
     ProfScope prof_("k_hpass_combine", stream);
     hipLaunchKernelGGL((k_hpass<S, RH, true>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
                        (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, 0LL, 0, pst, ldt, L.N + 2, L.N,
-                       prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W);
+                       prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W, C);
     return check_launch("k_hpass(combine)");
 }
 
@@ -344,6 +345,74 @@ static bf_status run_joint_forward(const float *g, const float *f, float *out, i
     hipLaunchKernelGGL((k_hpass_joint<S, RH>), gh, dim3(256), 0, stream, (const typename S::T *)stackB, g, out, H,
                        Wd, ld, pst, ldt, N, prm + L.off_taps, prm + L.off_cq, L.W);
     return check_launch("k_hpass_joint");
+}
+
+// Uploads a filled parameter vector (k_put_params chunks); clears the device
+// flag only when asked.
+static bf_status upload_vector(double *prm, unsigned *flag, const std::vector<double> &host, bool clear_flag,
+                               hipStream_t stream) {
+    ParamChunk ch;
+    int off = 0;
+    const int total = (int)host.size();
+    do {
+        std::memset(&ch, 0, sizeof ch);
+        ch.offset = off;
+        ch.count = std::min(400, total - off);
+        ch.clear_flag = (off == 0 && clear_flag) ? 1 : 0;
+        for (int i = 0; i < ch.count; ++i) ch.v[i] = host[off + i];
+        ProfScope prof_("k_put_params", stream);
+        hipLaunchKernelGGL(k_put_params, dim3(1), dim3(256), 0, stream, prm, flag, ch);
+        off += 400;
+    } while (off < total);
+    return check_launch("k_put_params");
+}
+
+static int pivot_nmax(const std::vector<Pivot> &plan) {
+    int n = 0;
+    for (const Pivot &p : plan) n = std::max(n, p.N);
+    return n;
+}
+
+static size_t pivots_ws_bytes(int H, int Wd, int W, int Nmax, int dtype) {
+    const size_t P = (size_t)Nmax + 2;
+    return kFlagBytes + align256(sizeof(double) * (size_t)param_layout(W, Nmax).total) +
+           align256(P * H * lds_of(Wd) * esize(dtype)) + align256(P * Wd * ldt_of(H) * esize(dtype));
+}
+
+// Pivoted forward: per sub-range, the three-kernel forward centred at its
+// midpoint, writing only the outputs whose centre value lies in it.
+template <class S, int RV, int RH>
+static bf_status run_pivots(const float *f, float *out, int H, int Wd, int ld, double sigma_s,
+                            const std::vector<Pivot> &plan, int dtype, char *ws, hipStream_t stream) {
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    const int W = radius_of(sigma_s);
+    const int Nmax = pivot_nmax(plan);
+    const int lds = lds_of(Wd);
+    const long long ps = (long long)H * lds;
+    const int ldt = ldt_of(H);
+    const long long pst = (long long)Wd * ldt;
+    char *stackA = ws + kFlagBytes + align256(sizeof(double) * (size_t)param_layout(W, Nmax).total);
+    char *stackB = stackA + align256((size_t)(Nmax + 2) * ps * sizeof(typename S::T));
+    const int K = (int)plan.size();
+    for (int k = 0; k < K; ++k) {
+        const Pivot &p = plan[k];
+        const ParamLayout L = param_layout(W, p.N);
+        std::vector<double> host;
+        fill_params_pivot(L, sigma_s, p.mu, p.nu, dtype, host);
+        bf_status st = upload_vector(prm, flag, host, k == 0, stream);
+        if (st != BF_OK) return st;
+        const int mask = K == 1 ? 0 : k == 0 ? 2 : k == K - 1 ? 3 : 1;
+        const Centring C{p.t, 1.0 / p.R, 1.0 / p.h, p.R, (float)p.lo, (float)p.hi, mask};
+        if ((st = launch_build<S>(f, H, Wd, ld, stackA, ps, lds, p.N + 2, prm, L, p.nu, flag, stream, C)) != BF_OK)
+            return st;
+        if ((st = launch_vpass<S, RV>(stackA, stackB, p.N + 2, H, Wd, ps, lds, pst, ldt, prm, L, stream)) != BF_OK)
+            return st;
+        if ((st = launch_hpass_combine<S, RH>(stackB, f, out, nullptr, nullptr, H, Wd, ld, pst, ldt, prm, L, stream,
+                                              C)) != BF_OK)
+            return st;
+    }
+    return BF_OK;
 }
 
 constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
@@ -876,6 +945,94 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     }
 #undef BF_FWD_CFG
 #undef BF_FWD
+}
+
+int bf_gc_pivot_count(double sigma_r, int stack_dtype) {
+    if (!finite_pos(sigma_r) || stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return -1;
+    for (int K = 1; K <= BF_MAX_PIVOTS; K *= 2) {
+        bool ok = true;
+        for (const Pivot &p : pivot_plan(sigma_r, K, 0, BF_MAX_DEGREE)) {
+            if (p.N < 1) { ok = false; break; }
+            const double kappa = fit_mu(p.mu, p.N).kappa;
+            if (!std::isfinite(kappa) || kappa * unit_roundoff(stack_dtype) > 1e-2) { ok = false; break; }
+        }
+        if (ok) return K;
+    }
+    return -1;
+}
+
+bf_status bf_gc_pivot_plan(double sigma_r, int K, int N, int *N_out, double *mu_out, double *kappa_out) {
+    if (!finite_pos(sigma_r)) return fail(BF_ERR_INVALID_ARG, "sigma_r must be positive and finite");
+    if (K < 1 || K > BF_MAX_PIVOTS) return fail(BF_ERR_INVALID_ARG, "K out of [1, BF_MAX_PIVOTS]");
+    if (N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N above BF_MAX_DEGREE");
+    const std::vector<Pivot> plan = pivot_plan(sigma_r, K, N, BF_MAX_DEGREE);
+    for (int k = 0; k < K; ++k) {
+        if (N_out) N_out[k] = plan[k].N;
+        if (mu_out) mu_out[k] = plan[k].mu;
+        if (kappa_out) kappa_out[k] = plan[k].N >= 1 ? fit_mu(plan[k].mu, plan[k].N).kappa : INFINITY;
+    }
+    return BF_OK;
+}
+
+size_t bf_gc_pivots_workspace_bytes(int height, int width, double sigma_s, double sigma_r, int K, int N,
+                                    int stack_dtype) {
+    if (check_common(height, width, sigma_s, sigma_r, 1, stack_dtype) != BF_OK) return 0;
+    if (K < 1 || K > BF_MAX_PIVOTS || N > BF_MAX_DEGREE) return 0;
+    const std::vector<Pivot> plan = pivot_plan(sigma_r, K, N, BF_MAX_DEGREE);
+    for (const Pivot &p : plan)
+        if (p.N < 1) return 0;
+    return pivots_ws_bytes(height, width, radius_of(sigma_s), pivot_nmax(plan), stack_dtype);
+}
+
+bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width, int ld, double sigma_s,
+                               double sigma_r, int K, int N, int stack_dtype, unsigned flags, void *ws,
+                               size_t ws_bytes, void *stream) {
+    bf_status st = check_common(height, width, sigma_s, sigma_r, 1, stack_dtype);
+    if (st != BF_OK) return st;
+    if (K < 1 || K > BF_MAX_PIVOTS) return fail(BF_ERR_INVALID_ARG, "K out of [1, BF_MAX_PIVOTS]");
+    if (N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N above BF_MAX_DEGREE");
+    if (flags & (BF_FLAG_TAYLOR | BF_FLAG_MINIMAX | BF_FLAG_STAGED))
+        return fail(BF_ERR_INVALID_ARG, "the pivoted form takes the Chebyshev coefficients, three-kernel tiles only");
+    int cfg = tile_config_of(flags);
+    if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    if (cfg == BF_TILE_FUSED) return fail(BF_ERR_UNSUPPORTED, "the pivoted form runs the three-kernel tiles");
+    if (cfg == -1) cfg = 0;
+    if (height == 0 || width == 0) return BF_OK;
+    if (!f || !out) return fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    const size_t img = ((size_t)(height - 1) * ld + width) * sizeof(float);
+    if (overlaps(f, img, out, img)) return fail(BF_ERR_INVALID_ARG, "out overlaps f");
+    const std::vector<Pivot> plan = pivot_plan(sigma_r, K, N, BF_MAX_DEGREE);
+    for (const Pivot &p : plan) {
+        if (p.N < 1) return fail(BF_ERR_UNSUPPORTED, "no degree <= BF_MAX_DEGREE meets the rule for a sub-range");
+        if (!(flags & BF_FLAG_ALLOW_ILL_CONDITIONED)) {
+            const double kappa = fit_mu(p.mu, p.N).kappa;
+            if (!std::isfinite(kappa) || kappa * unit_roundoff(stack_dtype) > 1e-2) {
+                char buf[200];
+                snprintf(buf, sizeof buf, "ill-conditioned sub-range: kappa=%.3g at mu=%g, N=%d (more sub-ranges "
+                                          "lower mu)", kappa, p.mu, p.N);
+                return fail(BF_ERR_ILL_CONDITIONED, buf);
+            }
+        }
+    }
+    const size_t need = pivots_ws_bytes(height, width, radius_of(sigma_s), pivot_nmax(plan), stack_dtype);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
+    hipStream_t s = (hipStream_t)stream;
+#define BF_PIV(S, RV, RH) run_pivots<S, RV, RH>(f, out, height, width, ld, sigma_s, plan, stack_dtype, (char *)ws, s)
+#define BF_PIV_CFG(S)                                   \
+    switch (cfg) {                                      \
+    case 0: return BF_PIV(S, 16, 8);                    \
+    case 1: return BF_PIV(S, 8, 8);                     \
+    case 2: return BF_PIV(S, 16, 4);                    \
+    default: return BF_PIV(S, 8, 4);                    \
+    }
+    switch (stack_dtype) {
+    case BF_STACK_F32: BF_PIV_CFG(StF32)
+    case BF_STACK_F16: BF_PIV_CFG(StF16)
+    default: BF_PIV_CFG(StBF16)
+    }
+#undef BF_PIV_CFG
+#undef BF_PIV
 }
 
 size_t bf_gc_joint_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype) {

@@ -78,6 +78,27 @@ __global__ __launch_bounds__(256) void k_put_params(double *__restrict__ prm, un
     if (chunk.clear_flag && threadIdx.x == 0 && flag) *flag = 0u;
 }
 
+// Centring of the expansion (eq. 17) and the output mask. The plain filter
+// centres every pixel at t_c = (L+U)/2 with half range t_h; the pivoted form
+// (small sigma_r) runs once per sub-range k with its midpoint t_k, scales the
+// neighbour offsets by 1/R_k and the centre offsets by 1/h, and keeps the
+// output only where the centre value lies in the sub-range.
+struct Centring {
+    double tc;         // centre t
+    double inv_s;      // build: s_j = (f_j - tc) inv_s
+    double inv_c;      // combine: s_i = (f_i - tc) inv_c
+    double out_scale;  // y = tc + out_scale P / Q
+    float lo, hi;      // sub-range of the centre value
+    int mask;          // 0: store every output; 1: lo <= f_i < hi; 2: f_i < hi; 3: !(f_i < lo)
+};
+__host__ __device__ inline Centring plain_centring() {
+    return Centring{kTc, 1.0 / kTh, 1.0 / kTh, kTh, 0.0f, 0.0f, 0};
+}
+__device__ __forceinline__ bool centring_keeps(const Centring &C, float fi) {
+    return C.mask == 0 || (C.mask == 1 && fi >= C.lo && fi < C.hi) || (C.mask == 2 && fi < C.hi) ||
+           (C.mask == 3 && !(fi < C.lo));
+}
+
 constexpr int kBuildRows = 8;   // rows per block in the stack build
 
 // Stack build for rows [r0, r1) of the 256-column block cb: one thread per
@@ -86,14 +107,14 @@ template <class S>
 __device__ __forceinline__ void build_tile(const float *__restrict__ f, int H, int Wd, int ld,
                                            typename S::T *__restrict__ stack, long long ps, int lds, int P,
                                            const double *__restrict__ scale, double mu, unsigned *__restrict__ flag,
-                                           int cb, int r0, int r1) {
+                                           int cb, int r0, int r1, const Centring &C) {
     const int c = cb * 256 + threadIdx.x;
     for (int r = r0; r < r1; ++r) {
         bool bad = false;
         if (c < Wd) {
             const float fv = f[(long long)r * ld + c];
             bad = !(fv >= 0.0f && fv <= 255.0f);
-            const double s = ((double)fv - kTc) * (1.0 / kTh);           // eq. (17), scaled
+            const double s = ((double)fv - C.tc) * C.inv_s;               // eq. (17), scaled
             double v = exp(-0.5 * mu * s * s);                           // H_0 = e^{-mu s^2/2}
             typename S::T *dst = stack + (long long)r * lds + c;
             for (int n = 0; n < P; ++n) {
@@ -110,9 +131,9 @@ template <class S>
 __global__ __launch_bounds__(256) void k_stack_build(const float *__restrict__ f, int H, int Wd, int ld,
                                                       typename S::T *__restrict__ stack, long long ps, int lds,
                                                       int P, const double *__restrict__ scale, double mu,
-                                                      unsigned *__restrict__ flag) {
+                                                      unsigned *__restrict__ flag, Centring C) {
     const int r0 = blockIdx.y * kBuildRows;
-    build_tile<S>(f, H, Wd, ld, stack, ps, lds, P, scale, mu, flag, blockIdx.x, r0, min(H, r0 + kBuildRows));
+    build_tile<S>(f, H, Wd, ld, stack, ps, lds, P, scale, mu, flag, blockIdx.x, r0, min(H, r0 + kBuildRows), C);
 }
 
 // One line of the separable Gaussian (eq. 7) for R consecutive outputs of a
@@ -262,7 +283,7 @@ __device__ __forceinline__ void hpass_tile(const typename S::T *__restrict__ inT
                                            float *__restrict__ Qout, int H, int Wd, int ld, long long ps, int lds,
                                            long long pst, int ldt, int P, int N, const double *__restrict__ taps,
                                            const double *__restrict__ cq, const double *__restrict__ cp, int W,
-                                           int bx, int by) {
+                                           int bx, int by, const Centring &C) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int r = bx * 64 + lane;
@@ -274,7 +295,7 @@ __device__ __forceinline__ void hpass_tile(const typename S::T *__restrict__ inT
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
-            s[q] = ((double)f[(long long)rl * ld + cc] - kTc) * (1.0 / kTh);
+            s[q] = ((double)f[(long long)rl * ld + cc] - C.tc) * C.inv_c;
             Pa[q] = 0.0;
             Qa[q] = 0.0;
         }
@@ -300,7 +321,8 @@ __device__ __forceinline__ void hpass_tile(const typename S::T *__restrict__ inT
         for (int q = 0; q < R; ++q) {
             if (c0 + q < Wd) {
                 const long long o = (long long)r * ld + c0 + q;
-                out[o] = (float)(kTc + kTh * (Pa[q] / Qa[q]));
+                if (C.mask != 0 && !centring_keeps(C, f[o])) continue;
+                out[o] = (float)(C.tc + C.out_scale * (Pa[q] / Qa[q]));
                 if (Pout) Pout[o] = (float)Pa[q];
                 if (Qout) Qout[o] = (float)Qa[q];
             }
@@ -316,9 +338,9 @@ __global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__
                                                 int Wd, int ld, long long ps, int lds, long long pst, int ldt,
                                                 int P, int N, const double *__restrict__ taps,
                                                 const double *__restrict__ cq, const double *__restrict__ cp,
-                                                int W) {
+                                                int W, Centring C) {
     hpass_tile<S, R, COMBINE>(inT, out_stack, f, out, Pout, Qout, H, Wd, ld, ps, lds, pst, ldt, P, N, taps, cq, cp,
-                              W, blockIdx.x, blockIdx.y);
+                              W, blockIdx.x, blockIdx.y, C);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,7 +437,8 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
             const int cb = l % B.gbx, rb = l / B.gbx;
             const int r0 = rb * kBuildRows;
             build_tile<S>(as_global(B.f), B.H, B.Wd, B.ld, as_global((T *)B.stackA), B.ps, B.lds, B.P,
-                          prm + B.off_scale, B.mu, as_global(&hdr->flags), cb, r0, min(B.H, r0 + kBuildRows));
+                          prm + B.off_scale, B.mu, as_global(&hdr->flags), cb, r0, min(B.H, r0 + kBuildRows),
+                          plain_centring());
         } else if (PHASE == 1) {
             const int per_plane = B.gvx * B.gvy;
             const int n = l / per_plane, rem = l - n * per_plane;
@@ -425,7 +448,7 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
             hpass_tile<S, RH, true>(as_global((const T *)B.stackB), (T *)nullptr, as_global(B.f),
                                     as_global(B.out), nullptr, nullptr, B.H, B.Wd, B.ld, 0LL, 0, B.pst, B.ldt, B.P,
                                     B.N, prm + B.off_taps, prm + B.off_cq, prm + B.off_cp, B.W, l % B.ghx,
-                                    l / B.ghx);
+                                    l / B.ghx, plain_centring());
         }
     }
 }

@@ -74,10 +74,9 @@ static void condition(Fit &F, int N) {
 // b_n = sum_{l >= n} d_l a_{l,n} (eq. 19 with mu^n folded into y = x/mu).
 // The last sum cancels heavily (its terms reach I_0(mu) 2^{N-1} while b_n can
 // be tiny), so the fit runs in binary128 and is rounded to double at the end.
-static Fit compute_fit(double sigma_r, int N) {
+static Fit compute_fit_q(__float128 mu, int N) {
     typedef __float128 qd;
     Fit F;
-    const qd mu = (qd)kTh * (qd)kTh / ((qd)sigma_r * (qd)sigma_r);
     F.mu = (double)mu;
     const int K = N + 1;
     std::vector<qd> theta(K), e(K), xe(K);
@@ -305,6 +304,11 @@ static bool compute_remez(double sigma_r, int N, Fit &F) {
     return true;
 }
 
+static Fit compute_fit(double sigma_r, int N) {
+    typedef __float128 qd;
+    return compute_fit_q((qd)kTh * (qd)kTh / ((qd)sigma_r * (qd)sigma_r), N);
+}
+
 // Taylor coefficients of exp(mu y): b_n = mu^n / n!, db_n/dmu = mu^{n-1}/(n-1)!.
 static Fit compute_taylor(double sigma_r, int N) {
     typedef __float128 qd;
@@ -343,6 +347,59 @@ const Fit &fit(double sigma_r, int N, int kind) {
         }
     } else F = compute_fit(sigma_r, N);
     return C.emplace(key, std::move(F)).first->second;
+}
+
+const Fit &fit_mu(double mu, int N) {
+    static std::mutex mtx;
+    static std::map<std::pair<double, int>, Fit> cache;
+    std::lock_guard<std::mutex> lock(mtx);
+    auto key = std::make_pair(mu, N);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    return cache.emplace(key, compute_fit_q((__float128)mu, N)).first->second;
+}
+
+int degree_rule_mu(double mu, int max_degree) {
+    if (!(mu > 0.0) || !std::isfinite(mu)) return -1;
+    const long double mu30 = (long double)kTh * kTh / (30.0L * 30.0L);
+    const long double eps0 = std::sqrt(2.0L * bessel_i(28, mu30) * 2.0L * bessel_i(29, mu30));
+    for (int N = 1; N <= max_degree; ++N)
+        if (2.0L * bessel_i(N + 1, (long double)mu) <= eps0) return N;
+    return -1;
+}
+
+std::vector<Pivot> pivot_plan(double sigma_r, int K, int N, int max_degree) {
+    std::vector<Pivot> out;
+    const double L0 = kTc - kTh, U0 = kTc + kTh;
+    const double h = (U0 - L0) / (2.0 * K);
+    for (int k = 0; k < K; ++k) {
+        Pivot p;
+        p.lo = L0 + (U0 - L0) * k / K;
+        p.hi = L0 + (U0 - L0) * (k + 1) / K;
+        p.t = 0.5 * (p.lo + p.hi);
+        p.h = h;
+        p.R = std::max(p.t - L0, U0 - p.t);
+        p.mu = h * p.R / (sigma_r * sigma_r);
+        p.nu = p.R * p.R / (sigma_r * sigma_r);
+        p.N = N > 0 ? N : degree_rule_mu(p.mu, max_degree);
+        out.push_back(p);
+    }
+    return out;
+}
+
+void fill_params_pivot(const ParamLayout &L, double sigma_s, double mu, double nu, int stack_dtype,
+                       std::vector<double> &out) {
+    out.assign(L.total, 0.0);
+    const std::vector<double> w = spatial_taps(sigma_s);
+    for (int t = 0; t <= 2 * L.W; ++t) out[L.off_taps + t + (kTapPad - 1)] = w[t];
+    const Fit &F = fit_mu(mu, L.N);
+    const std::vector<int> k = plane_exponents(nu, L.N, stack_dtype);
+    for (int n = 0; n <= L.N; ++n) {
+        out[L.off_cq + n] = std::ldexp(F.b[n], -k[n]);
+        out[L.off_cp + n] = std::ldexp(F.b[n], -k[n + 1]);
+    }
+    for (int n = 0; n <= L.N + 1; ++n) out[L.off_scale + n] = std::ldexp(1.0, k[n]);
+    for (int n = 0; n <= L.N; ++n) out[L.off_bd + n] = F.bd[n];
 }
 
 std::vector<double> spatial_taps(double sigma_s) {

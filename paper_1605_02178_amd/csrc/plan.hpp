@@ -41,6 +41,25 @@ struct Fit {
 enum { kFitChebyshev = 0, kFitTaylor = 1, kFitMinimax = 2 };
 const Fit &fit(double sigma_r, int N, int kind = kFitChebyshev);
 
+// The Chebyshev fit of exp(mu y) on [-1, 1] for a given mu (the pivoted form
+// below); cached per (mu, N).
+const Fit &fit_mu(double mu, int N);
+
+// The degree rule for a given mu. -1 if none <= max_degree.
+int degree_rule_mu(double mu, int max_degree);
+
+// Pivoted form for small sigma_r: [L, U] = [0, 255] split into K equal
+// sub-ranges [lo, hi) with midpoint t and half-width h; neighbour offsets from
+// t reach R = max(t - L, U - t). The cross term exp(mu y), y = s_i s_j with
+// s_i = (f_i - t)/h and s_j = (f_j - t)/R, has mu = h R / sigma_r^2; the
+// planes carry e^{-nu s_j^2/2} s_j^n with nu = R^2 / sigma_r^2. N: the given
+// degree, or the rule at mu when N <= 0 (-1 where none <= max_degree).
+struct Pivot {
+    double lo, hi, t, h, R, mu, nu;
+    int N;
+};
+std::vector<Pivot> pivot_plan(double sigma_r, int K, int N, int max_degree);
+
 // Normalised spatial taps exp(-k^2/2 sigma_s^2) / sum, k = -W..W.
 std::vector<double> spatial_taps(double sigma_s);
 
@@ -65,5 +84,10 @@ ParamLayout param_layout(int W, int N);
 // Fills `out` (layout.total doubles).
 void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack_dtype,
                  std::vector<double> &out, int kind = kFitChebyshev);
+
+// Parameter block of one pivot (Chebyshev coefficients at mu, plane scales
+// from nu).
+void fill_params_pivot(const ParamLayout &L, double sigma_s, double mu, double nu, int stack_dtype,
+                       std::vector<double> &out);
 
 }  // namespace bfgc
