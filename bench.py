@@ -22,6 +22,7 @@ Prints one JSON line. Besides the contract fields it carries
                 autograd function
   joint         the joint (cross) filter at the headline size
   small_sigma_r the pivoted form at sigma_r = 10 (sub-ranges of [0, 255])
+  recursive     the recursive (IIR) Gaussian variant against the truncated one
 """
 from __future__ import annotations
 
@@ -317,6 +318,41 @@ def bench_small_sigma_r(bf, f, f64, sigma_s, steps, log, sigma_r=10.0):
             "steps": steps}
 
 
+def bench_recursive(bf, f, sigma_r, N, steps, log):
+    """The recursive variant of eq. 7 (FP32 stack) against the truncated
+    convolution (FP32 stack, three kernels) at the headline size, for
+    sigma_s = 10 and 20: time per step and the largest difference between the
+    two filters (they approximate different Gaussians)."""
+    import numpy as np
+    import torch
+    H, Wd = f.shape
+    out = {}
+    for ss in (10.0, 20.0):
+        ws = torch.empty(bf.workspace_bytes(H, Wd, ss, N, "f32"), dtype=torch.uint8, device="cuda:0")
+        res = {}
+        ys = {}
+        for name, kw in (("recursive", {"recursive": True}), ("truncated", {"tile_config": 0})):
+            y = torch.empty_like(f)
+            bf.gc_filter(f, ss, sigma_r, N, out=y, workspace=ws, **kw)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                bf.gc_filter(f, ss, sigma_r, N, out=y, workspace=ws, **kw)
+            e1.record()
+            torch.cuda.synchronize()
+            res[name] = round(e0.elapsed_time(e1) / steps, 3)
+            ys[name] = y
+        d = float((ys["recursive"] - ys["truncated"]).abs().max())
+        log(f"bench: sigma_s={ss:g} recursive {res['recursive']:.2f} ms, truncated {res['truncated']:.2f} ms, "
+            f"max difference {d:.3f}")
+        out[f"sigma_s_{ss:g}"] = {"recursive_ms": res["recursive"], "truncated_ms": res["truncated"],
+                                  "max_abs_difference": d}
+    out.update({"stack": "f32", "sigma_r": sigma_r, "degree": N, "steps": steps})
+    return out
+
+
 def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
     """Plain-C FP64 oracle (OpenMP over rows) on rows [0, rows) of the image."""
     from oracle import native as C
@@ -351,6 +387,7 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-filter timing")
     ap.add_argument("--no-small-sigma-r", action="store_true", help="skip the pivoted small-sigma_r timing")
+    ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-variant timing")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -472,6 +509,9 @@ def main():
         result["batched"] = bench_batched(bf, args.batch_steps, log, "f32")
         if not args.no_fp16:
             result["batched_fp16"] = bench_batched(bf, args.batch_steps, log, "f16")
+
+    if not args.no_recursive:
+        result["recursive"] = bench_recursive(bf, f, sr, N, args.batch_steps, log)
 
     if not args.no_small_sigma_r:
         result["small_sigma_r"] = bench_small_sigma_r(bf, f, f64, ss, args.batch_steps, log)

@@ -76,6 +76,15 @@ typedef enum {
  * BF_ERR_UNSUPPORTED. Accepted by bf_gc_forward, bf_gc_backward and
  * bf_gc_batched; with BF_FLAG_TAYLOR it is BF_ERR_INVALID_ARG. */
 #define BF_FLAG_MINIMAX               0x10u
+/* Recursive variant of eq. 7 (Section I: recursion as the O(1) way to apply
+ * the Gaussian): Deriche's recursive Gaussian along columns and rows (causal
+ * + anticausal 4th-order recursions in FP64, each line extended by 14 sigma_s
+ * through the symmetric extension), then the combine. It approximates the
+ * untruncated Gaussian (within 5e-4 of the peak), so it is a different filter
+ * from the truncated convolution of the other paths. bf_gc_forward only, FP32
+ * stack (others: BF_ERR_UNSUPPORTED), without tile or staged flags
+ * (BF_ERR_INVALID_ARG). */
+#define BF_FLAG_RECURSIVE             0x20u
 #define BF_MINIMAX_MAX_DEGREE         100
 /* Tile configuration c in [0, BF_TILE_CONFIGS).
  *   c = 0..3: the three-kernel path (stack in HBM); output rows per lane in

@@ -34,6 +34,7 @@ FLAG_STAGED = 0x2
 FLAG_GRAPH = 0x4
 FLAG_TAYLOR = 0x8
 FLAG_MINIMAX = 0x10
+FLAG_RECURSIVE = 0x20
 MINIMAX_MAX_DEGREE = 100
 # coefficient kinds: the Chebyshev interpolant (Section III), the Taylor
 # polynomial (Section II), the minimax polynomial (Remez)
@@ -154,12 +155,15 @@ def _check_image(f, name="f"):
 
 def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
               staged: bool = False, allow_ill_conditioned: bool = False, out=None, workspace=None,
-              stream=None, tile_config: int | None = None, taylor: bool = False, coeffs=None):
+              stream=None, tile_config: int | None = None, taylor: bool = False, coeffs=None,
+              recursive: bool = False):
     """Gauss-Chebyshev bilateral filter of a 2-D float32 image in [0, 255]
     (Section III-B). Returns a new tensor (or writes `out`). coeffs: the
     polynomial for the cross term, "chebyshev" (default), "taylor" (the
     Gauss-polynomial filter of Section II; also taylor=True) or "minimax".
-    tile_config: an index into TILE_CONFIGS, "auto" (autotuned), or None."""
+    tile_config: an index into TILE_CONFIGS, "auto" (autotuned), or None.
+    recursive=True applies the Gaussian of eq. 7 by Deriche's recursion
+    instead of the truncated convolution (FP32 stack)."""
     import torch
     _check_image(f)
     H, Wd = f.shape
@@ -176,6 +180,7 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
     flags = (FLAG_STAGED if staged else 0) | (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0)
     flags |= _coeff_flags(coeffs, taylor)
+    flags |= FLAG_RECURSIVE if recursive else 0
     if tile_config == "auto":
         from . import autotune
         tile_config = autotune.lookup(autotune.forward_key(H, Wd, sigma_s, N, code))

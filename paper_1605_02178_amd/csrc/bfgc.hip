@@ -415,6 +415,41 @@ static bf_status run_pivots(const float *f, float *out, int H, int Wd, int ld, d
     return BF_OK;
 }
 
+// Recursive variant: build, recursive Gaussian along columns (stack A -> B)
+// and rows (B -> A), then the combine of the staged path.
+template <class S>
+static bf_status run_recursive(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
+                               int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    ParamLayout L;
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
+    if (st != BF_OK) return st;
+    const int lds = lds_of(Wd);
+    const long long ps = (long long)H * lds;
+    const int P = N + 2;
+    char *stackA = ws + kFlagBytes + align256(sizeof(double) * L.total);
+    char *stackB = stackA + align256((size_t)P * ps * sizeof(typename S::T));
+    const double mu = fit(sigma_r, N).mu;
+    if ((st = launch_build<S>(f, H, Wd, ld, stackA, ps, lds, P, prm, L, mu, flag, stream)) != BF_OK) return st;
+    const Recursive R = recursive_coefficients(sigma_s);
+    const IirCoef c{R.num[0], R.num[1], R.num[2], R.num[3], R.anum[0], R.anum[1], R.anum[2], R.anum[3],
+                    R.den[0], R.den[1], R.den[2], R.den[3], R.k, R.P};
+    {
+        ProfScope prof_("k_iir_col", stream);
+        hipLaunchKernelGGL((k_iir_col<S>), dim3((Wd + 255) / 256, P), dim3(256), 0, stream,
+                           (const typename S::T *)stackA, (typename S::T *)stackB, H, Wd, ps, lds, c);
+        if ((st = check_launch("k_iir_col")) != BF_OK) return st;
+    }
+    {
+        ProfScope prof_("k_iir_row", stream);
+        hipLaunchKernelGGL((k_iir_row<S>), dim3((H + 63) / 64, P), dim3(64), 0, stream,
+                           (const typename S::T *)stackB, (typename S::T *)stackA, H, Wd, ps, lds, c);
+        if ((st = check_launch("k_iir_row")) != BF_OK) return st;
+    }
+    return launch_combine<S>(f, stackA, H, Wd, ld, ps, lds, prm, L, out, nullptr, nullptr, stream);
+}
+
 constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
 constexpr int kNeighborBlocks = 2048;
 
@@ -901,7 +936,10 @@ size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int s
     if (check_common(height, width, sigma_s, 30.0, N, stack_dtype) != BF_OK) return 0;
     if (for_backward) return bwd_layout(height, width, sigma_s, N).total;
     const size_t planesA = (size_t)(N + 2) * height * lds_of(width) * esize(stack_dtype);
-    const size_t planesB = (size_t)(N + 2) * width * ldt_of(height) * esize(stack_dtype);
+    // stack B holds the transposed column-filtered planes, or (recursive
+    // variant) the planes in stack A's layout
+    const size_t planesB = (size_t)(N + 2) * std::max((size_t)width * ldt_of(height),
+                                                      (size_t)height * lds_of(width)) * esize(stack_dtype);
     return kFlagBytes + align256(bf_gc_param_bytes(sigma_s, N)) + align256(planesA) + align256(planesB);
 }
 
@@ -921,6 +959,12 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     hipStream_t s = (hipStream_t)stream;
     int cfg = tile_config_of(flags);
     if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
+    if (flags & BF_FLAG_RECURSIVE) {
+        if (stack_dtype != BF_STACK_F32) return fail(BF_ERR_UNSUPPORTED, "the recursive variant takes the FP32 stack");
+        if (cfg != -1 || (flags & BF_FLAG_STAGED))
+            return fail(BF_ERR_INVALID_ARG, "the recursive variant has its own kernels (no tile or staged flag)");
+        return run_recursive<StF32>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    }
     if (cfg == -1) cfg = (fused_applies(stack_dtype, sigma_s) && !(flags & BF_FLAG_STAGED)) ? BF_TILE_FUSED : 0;
     if (cfg == BF_TILE_FUSED) {
         if (!fused_applies(stack_dtype, sigma_s))

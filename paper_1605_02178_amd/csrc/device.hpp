@@ -454,6 +454,110 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
 }
 
 // ---------------------------------------------------------------------------
+// Recursive variant of eq. 7 (Section I names recursion as the O(1) way to
+// apply the Gaussian): Deriche's recursive Gaussian, a causal 4th-order
+// recursion plus an anticausal one, per line, in FP64. Each line is extended
+// by P samples per side through the symmetric extension and both recursions
+// start from zero at the far ends; y = k (y+ + y-) on the line itself. This
+// approximates the untruncated Gaussian, so it is a different filter from the
+// truncated convolution (its own reference). FP32 stack; y+ is parked in the
+// output plane (one extra FP32 rounding).
+// ---------------------------------------------------------------------------
+
+struct IirCoef {
+    double n0, n1, n2, n3;   // causal numerator
+    double m1, m2, m3, m4;   // anticausal numerator
+    double d1, d2, d3, d4;   // common denominator 1 + sum d_i z^-i
+    double k;                // unit DC gain
+    int P;                   // extension per side
+};
+
+// Columns: one thread per column (coalesced along rows), plane blockIdx.y.
+template <class S>
+__global__ __launch_bounds__(256) void k_iir_col(const typename S::T *__restrict__ in, typename S::T *__restrict__ out,
+                                                  int H, int Wd, long long ps, int lds, IirCoef c) {
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    if (col >= Wd) return;
+    const typename S::T *src = in + (long long)blockIdx.y * ps + col;
+    typename S::T *dst = out + (long long)blockIdx.y * ps + col;
+    double x1 = 0, x2 = 0, x3 = 0, x4 = 0, y1 = 0, y2 = 0, y3 = 0, y4 = 0;
+    for (int i = -c.P; i < H; ++i) {                        // causal
+        const double x = S::dec(src[(long long)mirror(i, H) * lds]);
+        const double y = c.n0 * x + c.n1 * x1 + c.n2 * x2 + c.n3 * x3 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
+        x3 = x2; x2 = x1; x1 = x;
+        y4 = y3; y3 = y2; y2 = y1; y1 = y;
+        if (i >= 0) dst[(long long)i * lds] = S::enc(y);
+    }
+    x1 = x2 = x3 = x4 = y1 = y2 = y3 = y4 = 0;
+    for (int i = H + c.P - 1; i >= 0; --i) {                // anticausal
+        const double y = c.m1 * x1 + c.m2 * x2 + c.m3 * x3 + c.m4 * x4 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
+        const double x = S::dec(src[(long long)mirror(i, H) * lds]);
+        x4 = x3; x3 = x2; x2 = x1; x1 = x;
+        y4 = y3; y3 = y2; y2 = y1; y1 = y;
+        if (i < H) dst[(long long)i * lds] = S::enc(c.k * ((double)S::dec(dst[(long long)i * lds]) + y));
+    }
+}
+
+// Rows: one wave per block owns 64 rows; 64 x 32 tiles of the line are staged
+// through LDS (coalesced loads and stores, row pitch 33 so a lane walking its
+// row hits its own bank), and each lane runs the recursion along its row.
+constexpr int kIirChunk = 32;
+template <class S>
+__global__ __launch_bounds__(64) void k_iir_row(const typename S::T *__restrict__ in, typename S::T *__restrict__ out,
+                                                 int H, int Wd, long long ps, int lds, IirCoef c) {
+    __shared__ float X[64][kIirChunk + 1];
+    __shared__ float Y[64][kIirChunk + 1];
+    const int lane = threadIdx.x;
+    const int r0 = blockIdx.x * 64;                         // < H by the grid
+    const typename S::T *src = in + (long long)blockIdx.y * ps;
+    typename S::T *dst = out + (long long)blockIdx.y * ps;
+    const int half = lane >> 5, cc = lane & 31;            // two rows of 32 columns per access
+    auto load_x = [&](int j0) {
+        const int jm = mirror(j0 + cc, Wd);
+        for (int rr = half; rr < 64; rr += 2) X[rr][cc] = S::dec(src[(long long)min(r0 + rr, H - 1) * lds + jm]);
+    };
+    auto store_y = [&](int j0) {
+        if (j0 + cc >= 0 && j0 + cc < Wd)
+            for (int rr = half; rr < 64; rr += 2)
+                if (r0 + rr < H) dst[(long long)(r0 + rr) * lds + j0 + cc] = S::enc(Y[rr][cc]);
+    };
+    const int jlo = -((c.P + kIirChunk - 1) / kIirChunk) * kIirChunk;
+    double x1 = 0, x2 = 0, x3 = 0, x4 = 0, y1 = 0, y2 = 0, y3 = 0, y4 = 0;
+    for (int j0 = jlo; j0 < Wd; j0 += kIirChunk) {         // causal, left to right
+        load_x(j0);
+        __syncthreads();
+        for (int k = 0; k < kIirChunk; ++k) {
+            const double x = X[lane][k];
+            const double y = c.n0 * x + c.n1 * x1 + c.n2 * x2 + c.n3 * x3 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
+            x3 = x2; x2 = x1; x1 = x;
+            y4 = y3; y3 = y2; y2 = y1; y1 = y;
+            Y[lane][k] = (float)S::dec(S::enc(y));
+        }
+        __syncthreads();
+        store_y(j0);
+        __syncthreads();
+    }
+    const int jhi = ((Wd + c.P + kIirChunk - 1) / kIirChunk) * kIirChunk;
+    x1 = x2 = x3 = x4 = y1 = y2 = y3 = y4 = 0;
+    for (int j0 = jhi - kIirChunk; j0 >= 0; j0 -= kIirChunk) {   // anticausal, right to left
+        load_x(j0);
+        if (j0 + cc < Wd)
+            for (int rr = half; rr < 64; rr += 2) Y[rr][cc] = S::dec(dst[(long long)min(r0 + rr, H - 1) * lds + j0 + cc]);
+        __syncthreads();
+        for (int k = kIirChunk - 1; k >= 0; --k) {
+            const double y = c.m1 * x1 + c.m2 * x2 + c.m3 * x3 + c.m4 * x4 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
+            const double x = X[lane][k];
+            x4 = x3; x3 = x2; x2 = x1; x1 = x;
+            y4 = y3; y3 = y2; y2 = y1; y1 = y;
+            Y[lane][k] = (float)(c.k * ((double)Y[lane][k] + y));
+        }
+        __syncthreads();
+        store_y(j0);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Joint (cross) filter: the range variable comes from a guide g, the averaged
 // values from f. Planes 0..N hold A_n = e^{-mu s^2/2} s^n with s from g (eq. 6
 // on the guide), planes N+1..2N+1 hold B_n = A_n ft with ft = (f - t_c)/t_h;

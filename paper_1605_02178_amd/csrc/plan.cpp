@@ -402,6 +402,46 @@ void fill_params_pivot(const ParamLayout &L, double sigma_s, double mu, double n
     for (int n = 0; n <= L.N; ++n) out[L.off_bd + n] = F.bd[n];
 }
 
+// Each damped-cosine section r^n (A cos(t n) + B sin(t n)), n >= 0, has the
+// z-transform (A + r (B sin t - A cos t) z^-1) / (1 - 2 r cos t z^-1 + r^2 z^-2)
+// with r = e^{-b/s}, t = w/s; the causal filter is the sum of the two sections
+// over the product of their denominators. The anticausal part is h(n) for
+// n <= -1, i.e. the causal transform in z minus its n = 0 term. k makes the
+// full response sum to 1.
+Recursive recursive_coefficients(double sigma) {
+    const double A[2] = {1.680, -0.6803}, B[2] = {3.735, -0.2598};
+    const double b[2] = {1.783, 1.723}, w[2] = {0.6318, 1.997};
+    double num[2][2], den[2][3];
+    for (int i = 0; i < 2; ++i) {
+        const double r = std::exp(-b[i] / sigma), t = w[i] / sigma;
+        num[i][0] = A[i];
+        num[i][1] = r * (B[i] * std::sin(t) - A[i] * std::cos(t));
+        den[i][0] = 1.0;
+        den[i][1] = -2.0 * r * std::cos(t);
+        den[i][2] = r * r;
+    }
+    double D[5] = {0, 0, 0, 0, 0}, Nm[4] = {0, 0, 0, 0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) D[i + j] += den[0][i] * den[1][j];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 3; ++j) Nm[i + j] += num[0][i] * den[1][j] + num[1][i] * den[0][j];
+    Recursive R;
+    for (int j = 0; j < 4; ++j) {
+        R.num[j] = Nm[j];
+        R.den[j] = D[j + 1];
+    }
+    R.anum[0] = Nm[1] - Nm[0] * D[1];
+    R.anum[1] = Nm[2] - Nm[0] * D[2];
+    R.anum[2] = Nm[3] - Nm[0] * D[3];
+    R.anum[3] = -Nm[0] * D[4];
+    double sn = 0, sd = 0;
+    for (int j = 0; j < 4; ++j) sn += Nm[j];
+    for (int j = 0; j < 5; ++j) sd += D[j];
+    R.k = sd / (2.0 * sn - Nm[0] * sd);
+    R.P = (int)std::ceil(14.0 * sigma);
+    return R;
+}
+
 std::vector<double> spatial_taps(double sigma_s) {
     const int W = radius_of(sigma_s);
     std::vector<long double> w(2 * W + 1);

@@ -60,6 +60,18 @@ struct Pivot {
 };
 std::vector<Pivot> pivot_plan(double sigma_r, int K, int N, int max_degree);
 
+// Recursive Gaussian (the recursion Section I cites, Deriche's): impulse
+// response [a0 cos(w0 n/s) + a1 sin(w0 n/s)] e^{-b0|n|/s}
+// + [c0 cos(w1 n/s) + c1 sin(w1 n/s)] e^{-b1|n|/s}, as a causal recursion
+// y+[i] = sum_{j<4} num[j] x[i-j] - sum_{j<4} den[j] y+[i-1-j] and an
+// anticausal one y-[i] = sum_{j<4} anum[j] x[i+1+j] - sum_{j<4} den[j] y-[i+1+j];
+// y = k (y+ + y-). P: samples of symmetric extension per side (14 sigma).
+struct Recursive {
+    double num[4], anum[4], den[4], k;
+    int P;
+};
+Recursive recursive_coefficients(double sigma);
+
 // Normalised spatial taps exp(-k^2/2 sigma_s^2) / sum, k = -W..W.
 std::vector<double> spatial_taps(double sigma_s);
 
