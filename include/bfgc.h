@@ -108,6 +108,9 @@ typedef enum {
 
 #define BF_MAX_DEGREE 320                   /* largest N accepted */
 #define BF_MAX_RADIUS 96                    /* largest W = ceil(3 sigma_s) accepted */
+/* Largest image side: the launch grids put up to side/32 blocks in a 16-bit
+ * grid dimension. Larger sides: BF_ERR_UNSUPPORTED. */
+#define BF_MAX_SIDE 2097152
 #define BF_MAX_BATCH 2048                   /* most images in one bf_gc_batched call */
 
 /*

@@ -140,6 +140,7 @@ static bf_status check_common(int height, int width, double sigma_s, double sigm
     if (N < 1 || N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N out of [1, BF_MAX_DEGREE]");
     if (dtype < BF_STACK_F32 || dtype > BF_STACK_BF16) return fail(BF_ERR_INVALID_ARG, "unknown stack dtype");
     if (radius_of(sigma_s) > BF_MAX_RADIUS) return fail(BF_ERR_UNSUPPORTED, "radius ceil(3 sigma_s) above BF_MAX_RADIUS");
+    if (height > BF_MAX_SIDE || width > BF_MAX_SIDE) return fail(BF_ERR_UNSUPPORTED, "image side above BF_MAX_SIDE");
     if ((long long)height * lds_of(width) > (1LL << 40)) return fail(BF_ERR_UNSUPPORTED, "image too large");
     return BF_OK;
 }

@@ -106,6 +106,7 @@ def test_forward_argument_errors_need_no_device(lib):
     assert _fwd(lib, dt=7) == 1
     assert _fwd(lib, f=big, out=big + 16) == 1      # out overlaps f
     assert _fwd(lib, ss=40.0) == 2                   # W = 120 > BF_MAX_RADIUS
+    assert _fwd(lib, H=3000000, ld=16) == 2          # side above BF_MAX_SIDE
     assert _fwd(lib, sr=12.0, N=170) == 3            # ill-conditioned in FP32
     assert _fwd(lib, sr=30.0, N=28, dt=2) == 3       # BF16 at sigma_r = 30
     assert _fwd(lib, ws=0) == 4
