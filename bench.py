@@ -257,8 +257,9 @@ def bench_differentiation(bf, steps, log):
 
 def bench_joint(bf, f, f64, sigma_s, sigma_r, N, steps, log):
     """Joint (cross) filter at the headline size: the headline image as guide,
-    a ramp + rectangles image as the averaged values, FP32 stack at N and
-    FP16 stack at N, three-kernel tiles (2(N+1) planes)."""
+    a ramp + rectangles image as the averaged values; FP32 stack at N (three
+    kernels, 2(N+1) planes) and FP16 stack at N (the fused matrix-core kernel
+    with two operand sets per plane)."""
     import numpy as np
     import torch
     from synth import ramp_rectangles

@@ -227,9 +227,10 @@ bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width
  *   g, f   device, height x width FP32, row stride ld (the same for both),
  *          read only; values in [0, 255] (others set BF_DEVFLAG_RANGE)
  *   out    device, same layout; must overlap neither g nor f
- *   other arguments as bf_gc_forward; 2(N+1) planes per stack. Tile
- *   configurations 0-3 only (BF_TILE_FUSED: BF_ERR_UNSUPPORTED); no staged
- *   form (BF_FLAG_STAGED: BF_ERR_INVALID_ARG). ws: at least
+ *   other arguments as bf_gc_forward; 2(N+1) planes per stack. FP16/BF16
+ *   stacks with radius <= 32 default to the fused matrix-core kernel (two
+ *   operand sets per plane); BF_TILE_FUSED elsewhere is BF_ERR_UNSUPPORTED.
+ *   No staged form (BF_FLAG_STAGED: BF_ERR_INVALID_ARG). ws: at least
  *   bf_gc_joint_workspace_bytes(...) bytes, 256-byte aligned.
  */
 size_t bf_gc_joint_workspace_bytes(int height, int width, double sigma_s, int N, int stack_dtype);

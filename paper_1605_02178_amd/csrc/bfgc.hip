@@ -122,6 +122,8 @@ static int tile_config_of(unsigned flags) {
     return c - 1 < BF_TILE_CONFIGS ? (int)(c - 1) : -2;
 }
 
+constexpr int kJointFusedMaxRadius = 32;   // the joint fused tile keeps two operand sets in registers
+
 // The fused matrix-core kernel covers FP16/BF16 stacks up to BF_FUSED_MAX_RADIUS.
 static bool fused_applies(int dtype, double sigma_s) {
     return dtype != BF_STACK_F32 && radius_of(sigma_s) <= BF_FUSED_MAX_RADIUS;
@@ -449,6 +451,39 @@ static bf_status run_recursive(const float *f, float *out, int H, int Wd, int ld
         if ((st = check_launch("k_iir_row")) != BF_OK) return st;
     }
     return launch_combine<S>(f, stackA, H, Wd, ld, ps, lds, prm, L, out, nullptr, nullptr, stream);
+}
+
+// Joint filter on the fused kernel (FP16/BF16, radius <= 32).
+template <class M>
+static bf_status run_joint_fused(const float *g, const float *v, float *out, int H, int Wd, int ld, double sigma_s,
+                                 double sigma_r, int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)(ws + kFlagBytes);
+    ParamLayout L;
+    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
+    if (st != BF_OK) return st;
+    const float mu = (float)fit(sigma_r, N).mu;
+    const int W = L.W, qa = fused_qa(W);
+    dim3 grid((Wd + 63) / 64, (H + kFusedRows - 1) / kFusedRows);
+    ProfScope prof_("k_fused_joint", stream);
+    if (W <= 16) {
+        if (qa == 0)
+            hipLaunchKernelGGL((k_fused_joint<M, 3, 0>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
+                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+        else
+            hipLaunchKernelGGL((k_fused_joint<M, 3, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
+                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+    } else if (W <= 32) {
+        if (qa == 1)
+            hipLaunchKernelGGL((k_fused_joint<M, 4, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
+                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+        else
+            hipLaunchKernelGGL((k_fused_joint<M, 4, 2>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
+                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+    } else {
+        return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above 32");
+    }
+    return check_launch("k_fused_joint");
 }
 
 constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
@@ -1105,9 +1140,17 @@ bf_status bf_gc_joint_forward(const float *g, const float *f, float *out, int he
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
     int cfg = tile_config_of(flags);
     if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
-    if (cfg == BF_TILE_FUSED) return fail(BF_ERR_UNSUPPORTED, "the joint filter runs the three-kernel tiles");
-    if (cfg == -1) cfg = 0;
+    const bool fusable = stack_dtype != BF_STACK_F32 && radius_of(sigma_s) <= kJointFusedMaxRadius;
+    if (cfg == -1) cfg = fusable ? BF_TILE_FUSED : 0;
     hipStream_t s = (hipStream_t)stream;
+    if (cfg == BF_TILE_FUSED) {
+        if (!fusable) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: FP16/BF16 stacks with radius <= 32 only");
+        if (stack_dtype == BF_STACK_F16)
+            return run_joint_fused<MmaF16>(g, f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags,
+                                           (char *)ws, s);
+        return run_joint_fused<MmaBF16>(g, f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags,
+                                        (char *)ws, s);
+    }
 #define BF_JNT(S, RV, RH) run_joint_forward<S, RV, RH>(g, f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s)
 #define BF_JNT_CFG(S)                                   \
     switch (cfg) {                                      \

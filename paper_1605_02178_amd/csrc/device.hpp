@@ -1138,6 +1138,180 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
                              blockIdx.y * kFusedRows, blockIdx.x * TC, ybuf, tab);
 }
 
+// Joint filter on the matrix cores: the plain tile's schedule with two operand
+// sets per plane, A_n = 2^K e^{-mu s^2/2} s^n (s from the guide g) and
+// B_n = A_n ft (ft = (v - t_c)/t_h from the averaged image v), both filtered
+// (two MFMA chains per block, two LDS buffers per plane), then
+// Q = sum b_n s_i^n Abar_n, P = sum b_n s_i^n Bbar_n, y = t_c + t_h P/Q.
+// Planes n = 0..N. 64-column tiles only (radius <= 32).
+template <class M, int Q, int QA>
+__device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, const float *__restrict__ v,
+                                                 float *__restrict__ out, int H, int Wd, int ld,
+                                                 const double *__restrict__ prm, int off_taps, int off_cq,
+                                                 int off_scale, int W, int N, float mu, float prescale,
+                                                 unsigned *__restrict__ flag, int r0, int c0,
+                                                 typename M::E *__restrict__ ybuf_base,
+                                                 typename M::E *__restrict__ tab) {
+    typedef typename M::E E;
+    typedef typename M::V V;
+    constexpr int QB = Q - 2;
+    constexpr int TC = 64;
+    constexpr int kTabPad = kFusedTabPad;
+    constexpr int kTab = fused_tab_len(Q);
+    static_assert(Q <= 4, "joint geometry: 64-column tiles");
+    static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    for (int i = threadIdx.x; i < kTab; i += blockDim.x) {
+        const int t = i - kTabPad;
+        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? (float)prm[off_taps + kTapPad - 1 + t] : 0.0f);
+    }
+    __syncthreads();
+    V tf[2 * Q];
+#pragma unroll
+    for (int d = -1; d < 2 * Q - 1; ++d)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = tab[kTabPad + 16 * d + 8 * lg + jj - li];
+    const int rb = wave >> 1;
+    const int p = wave & 1;
+    const int jc0 = 2 * p;
+
+    const bool one_ref = W < H && W < Wd;
+    const int hc = c0 - W + 16 * wave + li;
+    const int mc = halo_index(hc, Wd, W, one_ref);
+    const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
+    float sv[Q][8], hv[Q][8], fv[Q][8];
+    bool bad = false;
+    {
+        const bool rows_inside = r0 - W >= 0 && r0 - W + 32 * Q <= H;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const int hr = r0 - W + 32 * q + 8 * lg + jj;
+                const long long o = (long long)(rows_inside ? hr : halo_index(hr, H, W, one_ref)) * ld + mc;
+                const float x = g[o], y = v[o];
+                if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H)
+                    bad |= !(x >= 0.0f && x <= 255.0f) || !(y >= 0.0f && y <= 255.0f);
+                const float s = (x - (float)kTc) * (float)(1.0 / kTh);          // eq. (17) on the guide
+                sv[q][jj] = s;
+                hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;
+                fv[q][jj] = (y - (float)kTc) * (float)(1.0 / kTh);
+            }
+        }
+    }
+    if (flag && __any(bad) && lane == __ffsll((unsigned long long)__ballot(bad)) - 1) atomicOr(flag, BF_DEVFLAG_RANGE);
+
+    float sc[2][4], pw[2][4], Pa[2][4], Qa[2][4];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+            const int r = min(r0 + 16 * rb + 4 * lg + vv, H - 1);
+            sc[b][vv] = (g[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
+            pw[b][vv] = 1.0f;
+            Pa[b][vv] = 0.0f;
+            Qa[b][vv] = 0.0f;
+        }
+    }
+    auto bcoef = [&](int n) -> float { return (float)(prm[off_cq + n] * prm[off_scale + n]); };
+    // buffers: plane n's A result in buffer 2 (n & 1), its B result in 2 (n & 1) + 1
+    auto column_pass = [&](int n) {
+        V a[Q], bo[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                a[q][jj] = M::cvt(hv[q][jj]);
+                bo[q][jj] = M::cvt(hv[q][jj] * fv[q][jj]);
+                hv[q][jj] *= sv[q][jj];
+            }
+        }
+        E *ya = ybuf_base + (2 * (n & 1)) * kFusedYElems;
+        E *yb = ya + kFusedYElems;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
+            mf_f4 acc = {0.f, 0.f, 0.f, 0.f}, accb = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = j / 2; q <= qlast; ++q) {
+                acc = M::mma(a[q], tf[2 * q - j + 1], acc);
+                accb = M::mma(bo[q], tf[2 * q - j + 1], accb);
+            }
+            typename M::V4 o, ob;
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                o[vv] = M::cvt(acc[vv]);
+                ob[vv] = M::cvt(accb[vv]);
+            }
+            const int off = (16 * j + li) * kFusedPitch + 16 * wave + 4 * lg;
+            *(typename M::V4 *)(ya + off) = o;
+            *(typename M::V4 *)(yb + off) = ob;
+        }
+    };
+    auto row_pass = [&](int n) {
+        const E *base = ybuf_base + (2 * (n & 1)) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
+        mf_f4 z[2][2];
+#pragma unroll
+        for (int set = 0; set < 2; ++set) {
+            const E *src = base + set * kFusedYElems;
+            V ya[QB + 1];
+#pragma unroll
+            for (int q = 0; q <= QB; ++q) ya[q] = *(const V *)(src + 32 * (q + p));
+            mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
+#pragma unroll
+            for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
+            z[set][0] = acc0;
+            z[set][1] = acc1;
+        }
+        const float bn = bcoef(n);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                Qa[b][vv] = fmaf(bn, pw[b][vv] * z[0][b][vv], Qa[b][vv]);
+                Pa[b][vv] = fmaf(bn, pw[b][vv] * z[1][b][vv], Pa[b][vv]);
+                pw[b][vv] *= sc[b][vv];
+            }
+        }
+    };
+    column_pass(0);
+    __syncthreads();
+    for (int n = 1; n <= N; ++n) {
+        column_pass(n);
+        row_pass(n - 1);
+        __syncthreads();
+    }
+    row_pass(N);
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int c = c0 + 16 * (jc0 + b) + li;
+        if (c >= Wd) continue;
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv) {
+            const int r = r0 + 16 * rb + 4 * lg + vv;
+            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * (Pa[b][vv] / Qa[b][vv]);   // eq. (10)
+        }
+    }
+}
+
+template <class M, int Q, int QA>
+__global__ __launch_bounds__(512) void k_fused_joint(const float *__restrict__ g, const float *__restrict__ v,
+                                                     float *__restrict__ out, int H, int Wd, int ld,
+                                                     const double *__restrict__ prm, int off_taps, int off_cq,
+                                                     int off_scale, int W, int N, float mu,
+                                                     unsigned *__restrict__ flag) {
+    typedef typename M::E E;
+    __shared__ __align__(16) E ybuf[4 * kFusedYElems];
+    __shared__ E tab[fused_tab_len(Q)];
+    fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, prm, off_taps, off_cq, off_scale, W, N, mu, M::kPrescale, flag,
+                               blockIdx.y * kFusedRows, blockIdx.x * 64, ybuf, tab);
+}
+
 // Geometry classes of the fused kernel, in the order the batched form keeps
 // them: (Q, TC, QA) = (3,64,0) (3,64,1) (4,64,1) (4,64,2) (5,32,2) (5,32,3).
 __host__ __device__ constexpr int fused_class(int Q, int QA) { return 2 * (Q - 3) + (QA - (Q - 3)); }

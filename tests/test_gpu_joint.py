@@ -115,7 +115,10 @@ def test_joint_flags_and_errors(torch_cuda):
         bf.gc_joint_filter(ft, gt, 2.0, 30.0, 28, out=gt)
     assert e.value.status == 1
     with pytest.raises(bf.BFError) as e:
-        bf.gc_joint_filter(ft, gt, 2.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)
+        bf.gc_joint_filter(ft, gt, 11.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)   # W = 33
+    assert e.value.status == 2
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_joint_filter(ft, gt, 2.0, 30.0, 28, stack_dtype="f32", tile_config=bf.TILE_FUSED)
     assert e.value.status == 2
     with pytest.raises(ValueError):
         bf.gc_joint_filter(ft, gt[:, :60], 2.0, 30.0, 28)
@@ -134,3 +137,33 @@ def test_joint_1024_crops(torch_cuda):
         err = np.abs(y[reg[0]:reg[1], reg[2]:reg[3]] - F.joint_gcf(f, g, 5.0, 30.0, 28, region=reg)).max()
         _log(f"joint 1024^2 crop {reg}: {err:.3e}")
         assert err <= 1e-3
+
+
+@pytest.mark.parametrize("shape,sigma_s", [((150, 170), 2.0), ((150, 170), 5.0), ((65, 129), 10.0), ((1, 77), 2.0),
+                                           ((129, 5), 2.0), ((300, 7), 3.0)])
+@pytest.mark.parametrize("dtype,sigma_r,N,bound", [("f16", 30.0, 28, 2.5), ("bf16", 50.0, 11, 3.0)])
+def test_joint_fused_parity(torch_cuda, shape, sigma_s, dtype, sigma_r, N, bound):
+    """The fused matrix-core joint kernel (both radius classes, ragged tiles)
+    against the oracle's joint filter at the stated bounds."""
+    import paper_1605_02178_amd as bf
+    from oracle import filters as F
+    f, g = _pair(shape, sum(shape) + 3)
+    y = _np(bf.gc_joint_filter(_gpu(torch_cuda, f), _gpu(torch_cuda, g), sigma_s, sigma_r, N, stack_dtype=dtype,
+                               tile_config=bf.TILE_FUSED))
+    err = np.abs(y - F.joint_gcf(f, g, sigma_s, sigma_r, N)).max()
+    _log(f"joint fused {dtype} {shape} ss={sigma_s}: {err:.3e}")
+    assert np.isfinite(y).all() and err <= bound
+
+
+def test_joint_fused_guide_f_matches_plain_fused(torch_cuda):
+    """With g = f the joint expansion is the plain one (B_n = A_{n+1}); the
+    fused joint kernel and the plain fused kernel round differently but stay
+    within the FP16 bound of each other."""
+    import paper_1605_02178_amd as bf
+    torch = torch_cuda
+    f, _ = _pair((128, 160), 17)
+    ft = _gpu(torch, f)
+    a = _np(bf.gc_joint_filter(ft, ft.clone(), 4.0, 30.0, 28, stack_dtype="f16"))
+    b = _np(bf.gc_filter(ft, 4.0, 30.0, 28, stack_dtype="f16"))
+    assert np.abs(a - b).max() <= 2.5
+    assert np.array_equal(a, _np(bf.gc_joint_filter(ft, ft.clone(), 4.0, 30.0, 28, stack_dtype="f16")))
