@@ -264,7 +264,7 @@ static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int l
     const float prescale = M::kPrescale;
     ProfScope prof_("k_fused_mfma", stream);
     hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, prm,
-                       L.off_taps, L.off_cq, L.off_scale, L.W, L.N, mu, prescale, flag);
+                       L.off_taps, L.off_bf, L.W, L.N, mu, prescale, flag);
     return check_launch("k_fused_mfma");
 }
 
@@ -469,17 +469,17 @@ static bf_status run_joint_fused(const float *g, const float *v, float *out, int
     if (W <= 16) {
         if (qa == 0)
             hipLaunchKernelGGL((k_fused_joint<M, 3, 0>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+                               L.off_taps, L.off_bf, W, N, mu, flag);
         else
             hipLaunchKernelGGL((k_fused_joint<M, 3, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+                               L.off_taps, L.off_bf, W, N, mu, flag);
     } else if (W <= 32) {
         if (qa == 1)
             hipLaunchKernelGGL((k_fused_joint<M, 4, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+                               L.off_taps, L.off_bf, W, N, mu, flag);
         else
             hipLaunchKernelGGL((k_fused_joint<M, 4, 2>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_cq, L.off_scale, W, N, mu, flag);
+                               L.off_taps, L.off_bf, W, N, mu, flag);
     } else {
         return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above 32");
     }
@@ -651,6 +651,7 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
         I.off_cq = L.off_cq;
         I.off_cp = L.off_cp;
         I.off_scale = L.off_scale;
+        I.off_bf = L.off_bf;
         I.prm = (const double *)((uintptr_t)ws + poff);   // ws may be null when only sizing
         poff += align256(sizeof(double) * L.total);
         for (int p = 0; p < kBatchPhases; ++p) {

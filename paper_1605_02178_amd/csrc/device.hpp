@@ -364,6 +364,22 @@ __device__ __forceinline__ T *as_global(T *p) {
     return (T *)(__attribute__((address_space(1))) T *)(unsigned long long)p;
 }
 
+// Wave-uniform copies of descriptor fields: the descriptors sit in a blob the
+// kernels also write (flags), so the compiler loads them per lane; reading
+// the first lane puts them in scalar registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ unsigned long long uniform(unsigned long long v) {
+    return ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+           (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ double uniform(double v) {
+    return __builtin_bit_cast(double, uniform(__builtin_bit_cast(unsigned long long, v)));
+}
+template <class T>
+__device__ __forceinline__ T *uniform(T *p) {
+    return (T *)uniform((unsigned long long)p);
+}
+
 struct BatchImage {
     const float *f;
     float *out;
@@ -373,7 +389,7 @@ struct BatchImage {
     long long ps, pst;
     double mu;
     int H, Wd, ld, lds, ldt, W, N, P;
-    int off_taps, off_cq, off_cp, off_scale;
+    int off_taps, off_cq, off_cp, off_scale, off_bf;
     int gbx, gvx, gvy, ghx;    // tile grid widths: build, column pass, row pass (fused form: gvx = tiles per row)
 };
 
@@ -904,8 +920,8 @@ __host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 3
 // kFusedYElems elements; tab: fused_tab_len(Q) elements of LDS.
 template <class M, int Q, int TC, int QA>
 __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *__restrict__ out, int H, int Wd,
-                                           int ld, const double *__restrict__ prm, int off_taps, int off_cq,
-                                           int off_scale, int W, int N, float mu, float prescale,
+                                           int ld, const double *__restrict__ prm, int off_taps, int off_bf,
+                                           int W, int N, float mu, float prescale,
                                            unsigned *__restrict__ flag, int r0, int c0,
                                            typename M::E *__restrict__ ybuf_base,
                                            typename M::E *__restrict__ tab) {
@@ -991,24 +1007,27 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
     // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
     // 16 (jc0 + b) + li. With u_n = s^n Hbar_n the sums are accumulated as
     //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
-    // so one product serves both; P = Ps / s, and at s = 0, where only the
-    // n = 1 term of P survives, P = b_0 Hbar_1 (kept in z1).
-    float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4], z1[JB][4];
+    // so one product serves both, and P = Ps / s. Where s = 0 the sums take
+    // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
+    // up to terms 2^-64 smaller, and Q moves by as little. (Where b_0 2^-64
+    // Hbar_1 underflows, P/Q lies far below FP32 resolution: the pixel's own
+    // term keeps Q >= w_0 b_0 2^K.)
+    float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4];
 #pragma unroll
     for (int b = 0; b < JB; ++b) {
         const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = min(r0 + 16 * rb + 4 * lg + v, H - 1);
-            sc[b][v] = (f[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
+            const float s = (f[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
+            sc[b][v] = s != 0.0f ? s : 0x1p-64f;
             pw[b][v] = sc[b][v];
             Ps[b][v] = 0.0f;
             Qa[b][v] = 0.0f;
         }
     }
-    // b_n = cq_n 2^k_n (the parameter block stores the FP16 three-kernel
-    // path's scaled coefficients; the product is exact).
-    auto bcoef = [&](int n) -> float { return (float)(prm[off_cq + n] * prm[off_scale + n]); };
+    // b_n as floats, n = 0..N+1 (b_{N+1} = 0), read as scalars
+    const float *__restrict__ bt = (const float *)(prm + off_bf);
 
     // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
     auto column_pass = [&](int n) {
@@ -1057,8 +1076,8 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
     };
     // Eqs. 8-9 for plane n >= 1 (pw = s^n on entry).
     auto combine = [&](int n, const mf_f4 (&z)[JB]) {
-        const float bp = bcoef(n - 1);
-        const float bq = n <= N ? bcoef(n) : 0.0f;
+        const float bp = bt[n - 1];
+        const float bq = bt[n];
 #pragma unroll
         for (int b = 0; b < JB; ++b) {
 #pragma unroll
@@ -1079,25 +1098,14 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
     {
         mf_f4 z[JB];
         row_pass(0, z);
-        const float b0 = bcoef(0);
+        const float b0 = bt[0];
 #pragma unroll
         for (int b = 0; b < JB; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) Qa[b][v] = b0 * z[b][v];
     }
     __syncthreads();
-    column_pass(2);
-    {
-        mf_f4 z[JB];
-        row_pass(1, z);
-#pragma unroll
-        for (int b = 0; b < JB; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) z1[b][v] = z[b][v];
-        combine(1, z);
-    }
-    __syncthreads();
-    for (int n = 3; n < P; ++n) {
+    for (int n = 2; n < P; ++n) {
         column_pass(n);
         mf_f4 z[JB];
         row_pass(n - 1, z);
@@ -1110,7 +1118,6 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
         combine(P - 1, z);
     }
 
-    const float b0 = bcoef(0);
 #pragma unroll
     for (int b = 0; b < JB; ++b) {
         const int c = c0 + 16 * (jc0 + b) + li;
@@ -1118,8 +1125,7 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int r = r0 + 16 * rb + 4 * lg + v;
-            const float s = sc[b][v];
-            const float ratio = s != 0.0f ? Ps[b][v] / (s * Qa[b][v]) : b0 * z1[b][v] / Qa[b][v];
+            const float ratio = Ps[b][v] / (sc[b][v] * Qa[b][v]);
             if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
         }
     }
@@ -1129,12 +1135,12 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
 template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
                                                     int Wd, int ld, const double *__restrict__ prm, int off_taps,
-                                                    int off_cq, int off_scale, int W, int N, float mu,
+                                                    int off_bf, int W, int N, float mu,
                                                     float prescale, unsigned *__restrict__ flag) {
     typedef typename M::E E;
     __shared__ __align__(16) E ybuf[2 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    fused_tile<M, Q, TC, QA>(f, out, H, Wd, ld, prm, off_taps, off_cq, off_scale, W, N, mu, prescale, flag,
+    fused_tile<M, Q, TC, QA>(f, out, H, Wd, ld, prm, off_taps, off_bf, W, N, mu, prescale, flag,
                              blockIdx.y * kFusedRows, blockIdx.x * TC, ybuf, tab);
 }
 
@@ -1147,8 +1153,8 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
 template <class M, int Q, int QA>
 __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, const float *__restrict__ v,
                                                  float *__restrict__ out, int H, int Wd, int ld,
-                                                 const double *__restrict__ prm, int off_taps, int off_cq,
-                                                 int off_scale, int W, int N, float mu, float prescale,
+                                                 const double *__restrict__ prm, int off_taps, int off_bf,
+                                                 int W, int N, float mu, float prescale,
                                                  unsigned *__restrict__ flag, int r0, int c0,
                                                  typename M::E *__restrict__ ybuf_base,
                                                  typename M::E *__restrict__ tab) {
@@ -1216,7 +1222,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
             Qa[b][vv] = 0.0f;
         }
     }
-    auto bcoef = [&](int n) -> float { return (float)(prm[off_cq + n] * prm[off_scale + n]); };
+    const float *__restrict__ bt = (const float *)(prm + off_bf);   // b_n as floats
     // buffers: plane n's A result in buffer 2 (n & 1), its B result in 2 (n & 1) + 1
     auto column_pass = [&](int n) {
         V a[Q], bo[Q];
@@ -1268,7 +1274,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
             z[set][0] = acc0;
             z[set][1] = acc1;
         }
-        const float bn = bcoef(n);
+        const float bn = bt[n];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
 #pragma unroll
@@ -1302,13 +1308,12 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
 template <class M, int Q, int QA>
 __global__ __launch_bounds__(512) void k_fused_joint(const float *__restrict__ g, const float *__restrict__ v,
                                                      float *__restrict__ out, int H, int Wd, int ld,
-                                                     const double *__restrict__ prm, int off_taps, int off_cq,
-                                                     int off_scale, int W, int N, float mu,
-                                                     unsigned *__restrict__ flag) {
+                                                     const double *__restrict__ prm, int off_taps, int off_bf,
+                                                     int W, int N, float mu, unsigned *__restrict__ flag) {
     typedef typename M::E E;
     __shared__ __align__(16) E ybuf[4 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, prm, off_taps, off_cq, off_scale, W, N, mu, M::kPrescale, flag,
+    fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, prm, off_taps, off_bf, W, N, mu, M::kPrescale, flag,
                                blockIdx.y * kFusedRows, blockIdx.x * 64, ybuf, tab);
 }
 
@@ -1355,9 +1360,10 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
         const BatchImage &B = img[ii];
         const int l = (int)(t - s_start[lo]);
         const int bx = l % B.gvx, by = l / B.gvx;
-        fused_tile<M, Q, TC, QA>(as_global(B.f), as_global(B.out), B.H, B.Wd, B.ld, as_global(B.prm), B.off_taps,
-                                 B.off_cq, B.off_scale, B.W, B.N, (float)B.mu, prescale, as_global(&hdr->flags),
-                                 by * kFusedRows, bx * TC, ybuf, tab);
+        fused_tile<M, Q, TC, QA>(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd),
+                                 uniform(B.ld), as_global(uniform(B.prm)), uniform(B.off_taps), uniform(B.off_bf),
+                                 uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale,
+                                 as_global(&hdr->flags), by * kFusedRows, bx * TC, ybuf, tab);
         __syncthreads();          // the next item rewrites the tap table and buffer 0
     }
 }
