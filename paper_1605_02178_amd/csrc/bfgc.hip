@@ -18,6 +18,7 @@
 #include <mutex>
 #include <string>
 #include <type_traits>
+#include <unordered_map>
 #include <vector>
 
 #include "bfgc.h"
@@ -166,8 +167,22 @@ static bf_status check_conditioning(double sigma_r, int N, int dtype, unsigned f
     return BF_OK;
 }
 
+// Where the range flags of a workspace's last call sit: the flag word at its
+// start (cleared by the parameter upload, or by the batched blob), or, after a
+// single-image fused launch, one word per block right after the flag area
+// (every block writes its word, so nothing is cleared first). The map holds
+// the workspaces of the second kind with their word counts.
+static std::mutex g_range_mtx;
+static std::unordered_map<const void *, long long> g_range_words;
+static void note_range_words(const void *ws, long long words) {
+    std::lock_guard<std::mutex> lock(g_range_mtx);
+    if (words > 0) g_range_words[ws] = words;
+    else g_range_words.erase(ws);
+}
+
 static bf_status upload_params(double *prm, unsigned *flag, double sigma_s, double sigma_r, int N, int dtype,
                                hipStream_t stream, ParamLayout *Lout, int kind = kFitChebyshev) {
+    if (flag) note_range_words(flag, 0);
     const int W = radius_of(sigma_s);
     ParamLayout L = param_layout(W, N);
     std::vector<double> host;
@@ -257,32 +272,43 @@ static bf_status launch_combine(const float *f, const void *stack, int H, int Wd
     return check_launch("k_combine");
 }
 
+// Constants of a fused launch: taps and b_n rounded to float, b_{N+1} = 0.
+static FusedConsts fused_consts(double sigma_s, double sigma_r, int N, int kind) {
+    FusedConsts C;
+    std::memset(&C, 0, sizeof C);
+    const std::vector<double> w = spatial_taps(sigma_s);
+    for (size_t t = 0; t < w.size(); ++t) C.taps[t] = (float)w[t];
+    const Fit &F = fit(sigma_r, N, kind);
+    for (int n = 0; n <= N; ++n) C.b[n] = (float)F.b[n];
+    return C;
+}
+
 template <class M, int Q, int TC, int QA>
-static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const double *prm,
-                                const ParamLayout &L, float mu, unsigned *flag, hipStream_t stream) {
+static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const FusedConsts &C, int W,
+                                int N, float mu, char *ws, hipStream_t stream) {
     dim3 grid((Wd + TC - 1) / TC, (H + kFusedRows - 1) / kFusedRows);
     const float prescale = M::kPrescale;
+    note_range_words(ws, (long long)grid.x * grid.y);
     ProfScope prof_("k_fused_mfma", stream);
-    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, prm,
-                       L.off_taps, L.off_bf, L.W, L.N, mu, prescale, flag);
+    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, C, W, N, mu,
+                       prescale, (unsigned *)(ws + kFlagBytes));
     return check_launch("k_fused_mfma");
 }
 
-// Fused FP16/BF16 forward: parameters, then one kernel (see k_fused_mfma).
+// Fused FP16/BF16 forward: one kernel (see k_fused_mfma), its constants
+// passed by value. The workspace holds only the blocks' range words (4 bytes
+// per 64 x TC tile, far below bf_gc_workspace_bytes).
 template <class M>
 static bf_status run_fused(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
                            int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
-    unsigned *flag = (unsigned *)ws;
-    double *prm = (double *)(ws + kFlagBytes);
-    ParamLayout L;
-    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
-    if (st != BF_OK) return st;
+    (void)dtype;
+    const FusedConsts C = fused_consts(sigma_s, sigma_r, N, kind_of(flags));
     const float mu = (float)fit(sigma_r, N).mu;
-    const int W = L.W, qa = fused_qa(W);
+    const int W = radius_of(sigma_s), qa = fused_qa(W);
     // geometry: TC + 2W <= 128 halo columns, 64 + 2W <= 32Q halo rows
 #define BF_FUSED(Q, TC)                                                                             \
-    return qa == (Q) - 3 ? launch_fused_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, prm, L, mu, flag, stream) \
-                         : launch_fused_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, prm, L, mu, flag, stream)
+    return qa == (Q) - 3 ? launch_fused_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, C, W, N, mu, ws, stream) \
+                         : launch_fused_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, C, W, N, mu, ws, stream)
     if (W <= 16) BF_FUSED(3, 64);
     if (W <= 32) BF_FUSED(4, 64);
     if (W <= 48) BF_FUSED(5, 32);
@@ -354,6 +380,7 @@ static bf_status run_joint_forward(const float *g, const float *f, float *out, i
 // flag only when asked.
 static bf_status upload_vector(double *prm, unsigned *flag, const std::vector<double> &host, bool clear_flag,
                                hipStream_t stream) {
+    if (flag && clear_flag) note_range_words(flag, 0);
     ParamChunk ch;
     int off = 0;
     const int total = (int)host.size();
@@ -457,31 +484,29 @@ static bf_status run_recursive(const float *f, float *out, int H, int Wd, int ld
 template <class M>
 static bf_status run_joint_fused(const float *g, const float *v, float *out, int H, int Wd, int ld, double sigma_s,
                                  double sigma_r, int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
-    unsigned *flag = (unsigned *)ws;
-    double *prm = (double *)(ws + kFlagBytes);
-    ParamLayout L;
-    bf_status st = upload_params(prm, flag, sigma_s, sigma_r, N, dtype, stream, &L, kind_of(flags));
-    if (st != BF_OK) return st;
+    (void)dtype;
+    const FusedConsts C = fused_consts(sigma_s, sigma_r, N, kind_of(flags));
     const float mu = (float)fit(sigma_r, N).mu;
-    const int W = L.W, qa = fused_qa(W);
+    const int W = radius_of(sigma_s), qa = fused_qa(W);
     dim3 grid((Wd + 63) / 64, (H + kFusedRows - 1) / kFusedRows);
+    unsigned *slots = (unsigned *)(ws + kFlagBytes);
+    if (W > 32) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above 32");
+    note_range_words(ws, (long long)grid.x * grid.y);
     ProfScope prof_("k_fused_joint", stream);
     if (W <= 16) {
         if (qa == 0)
-            hipLaunchKernelGGL((k_fused_joint<M, 3, 0>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_bf, W, N, mu, flag);
+            hipLaunchKernelGGL((k_fused_joint<M, 3, 0>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
+                               N, mu, slots);
         else
-            hipLaunchKernelGGL((k_fused_joint<M, 3, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_bf, W, N, mu, flag);
-    } else if (W <= 32) {
-        if (qa == 1)
-            hipLaunchKernelGGL((k_fused_joint<M, 4, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_bf, W, N, mu, flag);
-        else
-            hipLaunchKernelGGL((k_fused_joint<M, 4, 2>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, prm,
-                               L.off_taps, L.off_bf, W, N, mu, flag);
+            hipLaunchKernelGGL((k_fused_joint<M, 3, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
+                               N, mu, slots);
     } else {
-        return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above 32");
+        if (qa == 1)
+            hipLaunchKernelGGL((k_fused_joint<M, 4, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
+                               N, mu, slots);
+        else
+            hipLaunchKernelGGL((k_fused_joint<M, 4, 2>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
+                               N, mu, slots);
     }
     return check_launch("k_fused_joint");
 }
@@ -652,6 +677,7 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
         I.off_cp = L.off_cp;
         I.off_scale = L.off_scale;
         I.off_bf = L.off_bf;
+        I.off_tf = L.off_tf;
         I.prm = (const double *)((uintptr_t)ws + poff);   // ws may be null when only sizing
         poff += align256(sizeof(double) * L.total);
         for (int p = 0; p < kBatchPhases; ++p) {
@@ -808,6 +834,7 @@ static int phase_grid(const void *kernel, long long items, int block, size_t lds
 // hipGraph (memcpy node + one kernel node per phase) or as plain launches.
 static bf_status launch_batch(const BatchPlan &B, const BatchKernels &K, unsigned flags, char *ws,
                               hipStream_t stream) {
+    note_range_words(ws, 0);
     std::lock_guard<std::mutex> lock(g_batch_mtx);
     int slot = 0;
     bf_status st = stage_slot(B.blob_cap, &slot);
@@ -1333,8 +1360,22 @@ bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, 
 
 bf_status bf_gc_read_flags(const void *ws, unsigned *flags_out, void *stream) {
     if (!ws || !flags_out) return fail(BF_ERR_INVALID_ARG, "ws and flags_out must be non-null");
+    long long words = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_range_mtx);
+        auto it = g_range_words.find(ws);
+        if (it != g_range_words.end()) words = it->second;
+    }
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e == hipSuccess) e = hipMemcpy(flags_out, ws, sizeof(unsigned), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && words > 0) {
+        std::vector<unsigned> w((size_t)words);
+        e = hipMemcpy(w.data(), (const char *)ws + kFlagBytes, sizeof(unsigned) * w.size(), hipMemcpyDeviceToHost);
+        unsigned acc = 0;
+        for (unsigned x : w) acc |= x;
+        *flags_out = acc;
+    } else if (e == hipSuccess) {
+        e = hipMemcpy(flags_out, ws, sizeof(unsigned), hipMemcpyDeviceToHost);
+    }
     if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("bf_gc_read_flags: ") + hipGetErrorString(e));
     return BF_OK;
 }

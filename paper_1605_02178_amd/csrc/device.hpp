@@ -389,7 +389,7 @@ struct BatchImage {
     long long ps, pst;
     double mu;
     int H, Wd, ld, lds, ldt, W, N, P;
-    int off_taps, off_cq, off_cp, off_scale, off_bf;
+    int off_taps, off_cq, off_cp, off_scale, off_bf, off_tf;
     int gbx, gvx, gvy, ghx;    // tile grid widths: build, column pass, row pass (fused form: gvx = tiles per row)
 };
 
@@ -912,6 +912,25 @@ __device__ __forceinline__ int halo_index(int i, int M, int W, bool one_reflecti
 }
 
 constexpr int kFusedTabPad = 32;             // zero taps below t = 0 in the LDS tap table
+
+// Constants of one fused launch, passed by value (kernel arguments): taps
+// w[t], t = 0..2W (tap t - W), and b_n, n = 0..N+1 with b_{N+1} = 0.
+struct FusedConsts {
+    float taps[2 * BF_FUSED_MAX_RADIUS + 1];
+    float b[BF_MAX_DEGREE + 2];
+};
+
+// Range flag of a block: with a slot (single-image launches) every block
+// writes its own word, 0 or BF_DEVFLAG_RANGE, so no word needs clearing
+// first; without (batched) the flag word is or-ed.
+__device__ __forceinline__ void report_range(bool bad, unsigned *flag, unsigned *slot) {
+    if (slot) {
+        const int any = __syncthreads_or(bad);
+        if (threadIdx.x == 0) *slot = any ? BF_DEVFLAG_RANGE : 0u;
+    } else if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1) {
+        atomicOr(flag, BF_DEVFLAG_RANGE);
+    }
+}
 constexpr int kFusedYElems = kFusedRows * kFusedPitch;
 __host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 32 * Q; }   // t in [-32, 32Q)
 
@@ -920,9 +939,9 @@ __host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 3
 // kFusedYElems elements; tab: fused_tab_len(Q) elements of LDS.
 template <class M, int Q, int TC, int QA>
 __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *__restrict__ out, int H, int Wd,
-                                           int ld, const double *__restrict__ prm, int off_taps, int off_bf,
+                                           int ld, const float *__restrict__ taps, const float *__restrict__ bt,
                                            int W, int N, float mu, float prescale,
-                                           unsigned *__restrict__ flag, int r0, int c0,
+                                           unsigned *__restrict__ flag, unsigned *__restrict__ slot, int r0, int c0,
                                            typename M::E *__restrict__ ybuf_base,
                                            typename M::E *__restrict__ tab) {
     typedef typename M::E E;
@@ -941,7 +960,7 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
     // Tap table in LDS: tab[kTabPad + t] = w[t] for t in [0, 2W], zero elsewhere.
     for (int i = threadIdx.x; i < kTab; i += blockDim.x) {
         const int t = i - kTabPad;
-        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? (float)prm[off_taps + kTapPad - 1 + t] : 0.0f);
+        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? taps[t] : 0.0f);
     }
     __syncthreads();
 
@@ -1002,7 +1021,7 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
             hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;            // 2^K H_0
         }
     }
-    if (flag && __any(bad) && lane == __ffsll((unsigned long long)__ballot(bad)) - 1) atomicOr(flag, BF_DEVFLAG_RANGE);
+    report_range(bad, flag, slot);
 
     // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
     // 16 (jc0 + b) + li. With u_n = s^n Hbar_n the sums are accumulated as
@@ -1026,8 +1045,6 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
             Qa[b][v] = 0.0f;
         }
     }
-    // b_n as floats, n = 0..N+1 (b_{N+1} = 0), read as scalars
-    const float *__restrict__ bt = (const float *)(prm + off_bf);
 
     // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
     auto column_pass = [&](int n) {
@@ -1134,14 +1151,14 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
 // Single-image fused kernel: one block per 64 x TC output tile.
 template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
-                                                    int Wd, int ld, const double *__restrict__ prm, int off_taps,
-                                                    int off_bf, int W, int N, float mu,
-                                                    float prescale, unsigned *__restrict__ flag) {
+                                                    int Wd, int ld, FusedConsts C, int W, int N, float mu,
+                                                    float prescale, unsigned *__restrict__ slots) {
     typedef typename M::E E;
     __shared__ __align__(16) E ybuf[2 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    fused_tile<M, Q, TC, QA>(f, out, H, Wd, ld, prm, off_taps, off_bf, W, N, mu, prescale, flag,
-                             blockIdx.y * kFusedRows, blockIdx.x * TC, ybuf, tab);
+    fused_tile<M, Q, TC, QA>(f, out, H, Wd, ld, C.taps, C.b, W, N, mu, prescale, nullptr,
+                             slots + blockIdx.y * gridDim.x + blockIdx.x, blockIdx.y * kFusedRows, blockIdx.x * TC,
+                             ybuf, tab);
 }
 
 // Joint filter on the matrix cores: the plain tile's schedule with two operand
@@ -1153,9 +1170,9 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
 template <class M, int Q, int QA>
 __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, const float *__restrict__ v,
                                                  float *__restrict__ out, int H, int Wd, int ld,
-                                                 const double *__restrict__ prm, int off_taps, int off_bf,
+                                                 const float *__restrict__ taps, const float *__restrict__ bt,
                                                  int W, int N, float mu, float prescale,
-                                                 unsigned *__restrict__ flag, int r0, int c0,
+                                                 unsigned *__restrict__ slot, int r0, int c0,
                                                  typename M::E *__restrict__ ybuf_base,
                                                  typename M::E *__restrict__ tab) {
     typedef typename M::E E;
@@ -1171,7 +1188,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     const int li = lane & 15, lg = lane >> 4;
     for (int i = threadIdx.x; i < kTab; i += blockDim.x) {
         const int t = i - kTabPad;
-        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? (float)prm[off_taps + kTapPad - 1 + t] : 0.0f);
+        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? taps[t] : 0.0f);
     }
     __syncthreads();
     V tf[2 * Q];
@@ -1207,7 +1224,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
             }
         }
     }
-    if (flag && __any(bad) && lane == __ffsll((unsigned long long)__ballot(bad)) - 1) atomicOr(flag, BF_DEVFLAG_RANGE);
+    report_range(bad, nullptr, slot);
 
     float sc[2][4], pw[2][4], Pa[2][4], Qa[2][4];
 #pragma unroll
@@ -1222,7 +1239,6 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
             Qa[b][vv] = 0.0f;
         }
     }
-    const float *__restrict__ bt = (const float *)(prm + off_bf);   // b_n as floats
     // buffers: plane n's A result in buffer 2 (n & 1), its B result in 2 (n & 1) + 1
     auto column_pass = [&](int n) {
         V a[Q], bo[Q];
@@ -1308,13 +1324,14 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
 template <class M, int Q, int QA>
 __global__ __launch_bounds__(512) void k_fused_joint(const float *__restrict__ g, const float *__restrict__ v,
                                                      float *__restrict__ out, int H, int Wd, int ld,
-                                                     const double *__restrict__ prm, int off_taps, int off_bf,
-                                                     int W, int N, float mu, unsigned *__restrict__ flag) {
+                                                     FusedConsts C, int W, int N, float mu,
+                                                     unsigned *__restrict__ slots) {
     typedef typename M::E E;
     __shared__ __align__(16) E ybuf[4 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, prm, off_taps, off_bf, W, N, mu, M::kPrescale, flag,
-                               blockIdx.y * kFusedRows, blockIdx.x * 64, ybuf, tab);
+    fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, C.taps, C.b, W, N, mu, M::kPrescale,
+                               slots + blockIdx.y * gridDim.x + blockIdx.x, blockIdx.y * kFusedRows,
+                               blockIdx.x * 64, ybuf, tab);
 }
 
 // Geometry classes of the fused kernel, in the order the batched form keeps
@@ -1360,10 +1377,12 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
         const BatchImage &B = img[ii];
         const int l = (int)(t - s_start[lo]);
         const int bx = l % B.gvx, by = l / B.gvx;
+        const double *prm = as_global(uniform(B.prm));
         fused_tile<M, Q, TC, QA>(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd),
-                                 uniform(B.ld), as_global(uniform(B.prm)), uniform(B.off_taps), uniform(B.off_bf),
-                                 uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale,
-                                 as_global(&hdr->flags), by * kFusedRows, bx * TC, ybuf, tab);
+                                 uniform(B.ld), (const float *)(prm + uniform(B.off_tf)),
+                                 (const float *)(prm + uniform(B.off_bf)), uniform(B.W), uniform(B.N),
+                                 (float)uniform(B.mu), prescale, as_global(&hdr->flags), nullptr, by * kFusedRows,
+                                 bx * TC, ybuf, tab);
         __syncthreads();          // the next item rewrites the tap table and buffer 0
     }
 }

@@ -388,11 +388,15 @@ std::vector<Pivot> pivot_plan(double sigma_r, int K, int N, int max_degree) {
     return out;
 }
 
-// b_n rounded to float for the fused kernels, which read them as scalars.
-static void store_float_coefficients(const ParamLayout &L, const std::vector<double> &b, std::vector<double> &out) {
+// b_n and the taps rounded to float for the fused kernels.
+static void store_float_coefficients(const ParamLayout &L, const std::vector<double> &b, const std::vector<double> &w,
+                                     std::vector<double> &out) {
     std::vector<float> bf((size_t)2 * (((L.N + 3) / 2 + 7) & ~7), 0.0f);
     for (int n = 0; n <= L.N; ++n) bf[n] = (float)b[n];
     std::memcpy(out.data() + L.off_bf, bf.data(), bf.size() * sizeof(float));
+    std::vector<float> tf((size_t)2 * (((2 * L.W + 2) / 2 + 7) & ~7), 0.0f);
+    for (int t = 0; t <= 2 * L.W; ++t) tf[t] = (float)w[t];
+    std::memcpy(out.data() + L.off_tf, tf.data(), tf.size() * sizeof(float));
 }
 
 void fill_params_pivot(const ParamLayout &L, double sigma_s, double mu, double nu, int stack_dtype,
@@ -408,7 +412,7 @@ void fill_params_pivot(const ParamLayout &L, double sigma_s, double mu, double n
     }
     for (int n = 0; n <= L.N + 1; ++n) out[L.off_scale + n] = std::ldexp(1.0, k[n]);
     for (int n = 0; n <= L.N; ++n) out[L.off_bd + n] = F.bd[n];
-    store_float_coefficients(L, F.b, out);
+    store_float_coefficients(L, F.b, w, out);
 }
 
 // Each damped-cosine section r^n (A cos(t n) + B sin(t n)), n >= 0, has the
@@ -491,7 +495,8 @@ ParamLayout param_layout(int W, int N) {
     L.off_scale = L.off_cp + ((N + 1 + 7) & ~7);
     L.off_bd = L.off_scale + ((N + 2 + 7) & ~7);
     L.off_bf = L.off_bd + ((N + 1 + 7) & ~7);
-    L.total = L.off_bf + (((N + 3) / 2 + 7) & ~7);
+    L.off_tf = L.off_bf + (((N + 3) / 2 + 7) & ~7);
+    L.total = L.off_tf + (((2 * W + 2) / 2 + 7) & ~7);
     return L;
 }
 
@@ -508,7 +513,7 @@ void fill_params(const ParamLayout &L, double sigma_s, double sigma_r, int stack
     }
     for (int n = 0; n <= L.N + 1; ++n) out[L.off_scale + n] = std::ldexp(1.0, k[n]);
     for (int n = 0; n <= L.N; ++n) out[L.off_bd + n] = F.bd[n];
-    store_float_coefficients(L, F.b, out);
+    store_float_coefficients(L, F.b, w, out);
 }
 
 }  // namespace bfgc

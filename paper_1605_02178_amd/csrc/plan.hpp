@@ -90,6 +90,7 @@ struct ParamLayout {
     int off_scale = 0;              // 2^k_n, n = 0..N+1
     int off_bd = 0;                 // db_n/dmu, n = 0..N (gradient with respect to sigma_r)
     int off_bf = 0;                 // b_n as floats, n = 0..N+1 with b_{N+1} = 0, two per double slot
+    int off_tf = 0;                 // taps as floats, t = 0..2W (tap t - W), two per double slot
     int total = 0;                  // doubles
 };
 ParamLayout param_layout(int W, int N);

@@ -135,6 +135,26 @@ def test_fused_range_flag(torch_cuda):
     assert bf.read_flags(ws) & bf.DEVFLAG_RANGE
 
 
+def test_fused_range_flag_follows_the_last_call(torch_cuda):
+    """The fused kernel reports the range per block (nothing to clear first);
+    the flag read always describes the workspace's last call, whichever path
+    or image size it took."""
+    import paper_1605_02178_amd as bf
+    from synth import ramp_rectangles
+    torch = torch_cuda
+    f = _gpu(torch, ramp_rectangles(200, 260, seed=3))
+    bad = f.clone()
+    bad[150, 250] = -1.0
+    small = f[:70, :90].contiguous()
+    ws = torch.empty(bf.workspace_bytes(200, 260, 5.0, 28, "f16"), dtype=torch.uint8, device="cuda:0")
+    steps = [(bad, bf.TILE_FUSED, True), (f, bf.TILE_FUSED, False), (bad, 0, True), (f, bf.TILE_FUSED, False),
+             (bad, bf.TILE_FUSED, True), (f, 0, False), (bad, bf.TILE_FUSED, True), (small, bf.TILE_FUSED, False)]
+    for k, (img, cfg, flagged) in enumerate(steps):
+        bf.gc_filter(img, 5.0, 30.0, 28, stack_dtype="f16", workspace=ws, tile_config=cfg)
+        got = bf.read_flags(ws) & bf.DEVFLAG_RANGE
+        assert bool(got) == flagged, (k, cfg, flagged)
+
+
 @pytest.mark.parametrize("N", [28, 30])
 def test_fused_headline_size_sampled(torch_cuda, N):
     """4096^2 edge-rich, sigma_s = 10, sigma_r = 30, FP16 stack, fused tile (the
