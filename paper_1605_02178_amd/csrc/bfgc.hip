@@ -11,6 +11,7 @@
 // stack) followed by k_combine, one kernel per stage.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
@@ -283,15 +284,33 @@ static FusedConsts fused_consts(double sigma_s, double sigma_r, int N, int kind)
     return C;
 }
 
+// Blocks that fit on the device at once for a 512-thread kernel (CUs times
+// its occupancy), looked up once per kernel.
+static int resident_blocks(const void *kernel, int *cache) {
+    if (*cache > 0) return *cache;
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 512, 0);
+    *cache = std::max(1, cus) * std::max(1, per);
+    return *cache;
+}
+
 template <class M, int Q, int TC, int QA>
 static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const FusedConsts &C, int W,
                                 int N, float mu, char *ws, hipStream_t stream) {
-    dim3 grid((Wd + TC - 1) / TC, (H + kFusedRows - 1) / kFusedRows);
+    static int resident = 0;
+    const void *kernel = (const void *)k_fused_mfma<M, Q, TC, QA>;
+    const int tiles_x = (Wd + TC - 1) / TC;
+    const long long tiles = (long long)tiles_x * ((H + kFusedRows - 1) / kFusedRows);
+    if (tiles > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused path: too many tiles");
+    const int grid = fused_persistent(Q) ? (int)std::min<long long>(tiles, resident_blocks(kernel, &resident))
+                                         : (int)tiles;
     const float prescale = M::kPrescale;
-    note_range_words(ws, (long long)grid.x * grid.y);
+    note_range_words(ws, tiles);
     ProfScope prof_("k_fused_mfma", stream);
-    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), grid, dim3(512), 0, stream, f, out, H, Wd, ld, C, W, N, mu,
-                       prescale, (unsigned *)(ws + kFlagBytes));
+    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), dim3(grid), dim3(512), 0, stream, f, out, H, Wd, ld, C, W, N,
+                       mu, prescale, (unsigned *)(ws + kFlagBytes), tiles_x, (int)tiles);
     return check_launch("k_fused_mfma");
 }
 

@@ -934,68 +934,83 @@ __device__ __forceinline__ void report_range(bool bad, unsigned *flag, unsigned 
 constexpr int kFusedYElems = kFusedRows * kFusedPitch;
 __host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 32 * Q; }   // t in [-32, 32Q)
 
-// One 64-row output tile (rows r0.., columns c0..) of the fused kernel; all
-// 512 threads of the block call it together. ybuf: two LDS buffers of
-// kFusedYElems elements; tab: fused_tab_len(Q) elements of LDS.
+// Fused tile machinery; all 512 threads of the block use it together.
+// setup() makes the Toeplitz fragments of one image (through the LDS tap
+// table tab, fused_tab_len(Q) elements); load() issues the global loads of
+// one 64 x TC output tile's inputs (halo column values and the lane's own
+// output pixels) into registers; run() filters that tile through ybuf (two
+// LDS buffers of kFusedYElems elements) and stores it.
 template <class M, int Q, int TC, int QA>
-__device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *__restrict__ out, int H, int Wd,
-                                           int ld, const float *__restrict__ taps, const float *__restrict__ bt,
-                                           int W, int N, float mu, float prescale,
-                                           unsigned *__restrict__ flag, unsigned *__restrict__ slot, int r0, int c0,
-                                           typename M::E *__restrict__ ybuf_base,
-                                           typename M::E *__restrict__ tab) {
+struct FusedTile {
     typedef typename M::E E;
     typedef typename M::V V;
-    constexpr int QB = Q - 2;
-    constexpr int JB = TC / 32;                  // output column blocks per wave in the row pass
-    constexpr int kTabPad = kFusedTabPad;
-    constexpr int kTab = fused_tab_len(Q);
+    static constexpr int QB = Q - 2;
+    static constexpr int JB = TC / 32;          // output column blocks per wave in the row pass
     static_assert((TC == 64 && Q <= 4) || (TC == 32 && Q == 5), "geometry");
     static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int li = lane & 15, lg = lane >> 4;
-    const int P = N + 2;
 
-    // Tap table in LDS: tab[kTabPad + t] = w[t] for t in [0, 2W], zero elsewhere.
-    for (int i = threadIdx.x; i < kTab; i += blockDim.x) {
-        const int t = i - kTabPad;
-        tab[i] = M::cvt(t >= 0 && t <= 2 * W ? taps[t] : 0.0f);
-    }
-    __syncthreads();
+    // Inputs of one tile: h[q][jj] = f at halo column 16 wave + li, halo row
+    // 32q + 8lg + jj; c[b][v] = f at output row 16 rb + 4 lg + v, column
+    // 16 (jc0 + b) + li (clamped into the image).
+    struct Raw {
+        float h[Q][8];
+        float c[JB][4];
+    };
 
-    // Toeplitz fragments tf[d+1], d = -1 .. 2Q-2: element jj of lane (li, lg)
-    // is w[16d + 8lg + jj - li].
+    const float *__restrict__ f;
+    float *__restrict__ out;
+    const float *__restrict__ bt;                // b_n as floats, n = 0..N+1 (b_{N+1} = 0)
+    E *__restrict__ ybuf;
+    int H, Wd, ld, W, N;
+    float mu, prescale;
+    int lane, wave, li, lg, rb, p, jc0;
+    bool one_ref;
     V tf[2 * Q];
-#pragma unroll
-    for (int d = -1; d < 2 * Q - 1; ++d)
-#pragma unroll
-        for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = tab[kTabPad + 16 * d + 8 * lg + jj - li];
-
-    // Row-pass assignment: row block rb = wave / 2. With 64-column tiles the
-    // wave takes column blocks 2p, 2p+1 (p = wave & 1), which read the halo
-    // chunks shifted by p and use the fragments of blocks 0, 1. With 32-column
-    // tiles it takes block jc = p and uses that block's fragments rf[q].
-    const int rb = wave >> 1;
-    const int p = wave & 1;
-    const int jc0 = p * JB;
     V rf[TC == 32 ? 4 : 1];
-    if (TC == 32) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) rf[q][jj] = tab[kTabPad + 32 * q + 8 * lg + jj - 16 * p - li];
+
+    __device__ __forceinline__ FusedTile(const float *f_, float *out_, int H_, int Wd_, int ld_, int W_, int N_,
+                                         float mu_, float prescale_, const float *bt_, E *ybuf_)
+        : f(f_), out(out_), bt(bt_), ybuf(ybuf_), H(H_), Wd(Wd_), ld(ld_), W(W_), N(N_), mu(mu_),
+          prescale(prescale_) {
+        lane = threadIdx.x & 63;
+        wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        li = lane & 15;
+        lg = lane >> 4;
+        // Row-pass assignment: row block rb = wave / 2. With 64-column tiles
+        // the wave takes column blocks 2p, 2p+1 (p = wave & 1), which read the
+        // halo chunks shifted by p and use the fragments of blocks 0, 1. With
+        // 32-column tiles it takes block jc = p and uses that block's
+        // fragments rf[q].
+        rb = wave >> 1;
+        p = wave & 1;
+        jc0 = p * JB;
+        one_ref = W < H && W < Wd;
     }
 
-    // Column-pass A operand state: halo column 16 wave + li, halo rows
-    // 32q + 8lg + jj; s and the running 2^K H_n in FP32 (one scale 2^K for
-    // every plane keeps FP16 planes normal: it cancels in P/Q).
-    const bool one_ref = W < H && W < Wd;
-    const int hc = c0 - W + 16 * wave + li;
-    const int mc = halo_index(hc, Wd, W, one_ref);
-    const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
-    float sv[Q][8], hv[Q][8];
-    {
+    // Tap table in LDS, tab[kFusedTabPad + t] = w[t] for t in [0, 2W] and zero
+    // elsewhere, then the Toeplitz fragments tf[d+1], d = -1 .. 2Q-2: element
+    // jj of lane (li, lg) is w[16d + 8lg + jj - li].
+    __device__ __forceinline__ void setup(const float *__restrict__ taps, E *__restrict__ tab) {
+        constexpr int kTabPad = kFusedTabPad;
+        for (int i = threadIdx.x; i < fused_tab_len(Q); i += blockDim.x) {
+            const int t = i - kTabPad;
+            tab[i] = M::cvt(t >= 0 && t <= 2 * W ? taps[t] : 0.0f);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int d = -1; d < 2 * Q - 1; ++d)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = tab[kTabPad + 16 * d + 8 * lg + jj - li];
+        if (TC == 32) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int jj = 0; jj < 8; ++jj) rf[q][jj] = tab[kTabPad + 32 * q + 8 * lg + jj - 16 * p - li];
+        }
+    }
+
+    __device__ __forceinline__ void load(int r0, int c0, Raw &R) const {
+        const int mc = halo_index(c0 - W + 16 * wave + li, Wd, W, one_ref);
         // rows of the halo inside the image need no extension (most tiles)
         const bool rows_inside = r0 - W >= 0 && r0 - W + 32 * Q <= H;
         const float *col = f + mc;
@@ -1004,161 +1019,204 @@ __device__ __forceinline__ void fused_tile(const float *__restrict__ f, float *_
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
                 const int hr = r0 - W + 32 * q + 8 * lg + jj;
-                sv[q][jj] = col[(long long)(rows_inside ? hr : halo_index(hr, H, W, one_ref)) * ld];
+                R.h[q][jj] = col[(long long)(rows_inside ? hr : halo_index(hr, H, W, one_ref)) * ld];
             }
         }
-    }
-    bool bad = false;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
+        for (int b = 0; b < JB; ++b) {
+            const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
 #pragma unroll
-        for (int jj = 0; jj < 8; ++jj) {
-            const int hr = r0 - W + 32 * q + 8 * lg + jj;
-            const float x = sv[q][jj];
-            if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H) bad |= !(x >= 0.0f && x <= 255.0f);
-            const float s = (x - (float)kTc) * (float)(1.0 / kTh);      // eq. (17)
-            sv[q][jj] = s;
-            hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;            // 2^K H_0
-        }
-    }
-    report_range(bad, flag, slot);
-
-    // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
-    // 16 (jc0 + b) + li. With u_n = s^n Hbar_n the sums are accumulated as
-    //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
-    // so one product serves both, and P = Ps / s. Where s = 0 the sums take
-    // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
-    // up to terms 2^-64 smaller, and Q moves by as little. (Where b_0 2^-64
-    // Hbar_1 underflows, P/Q lies far below FP32 resolution: the pixel's own
-    // term keeps Q >= w_0 b_0 2^K.)
-    float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4];
-#pragma unroll
-    for (int b = 0; b < JB; ++b) {
-        const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = min(r0 + 16 * rb + 4 * lg + v, H - 1);
-            const float s = (f[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
-            sc[b][v] = s != 0.0f ? s : 0x1p-64f;
-            pw[b][v] = sc[b][v];
-            Ps[b][v] = 0.0f;
-            Qa[b][v] = 0.0f;
+            for (int v = 0; v < 4; ++v) R.c[b][v] = f[(long long)min(r0 + 16 * rb + 4 * lg + v, H - 1) * ld + c];
         }
     }
 
-    // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
-    auto column_pass = [&](int n) {
-        V a[Q];
+    __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
+                                        unsigned *__restrict__ slot) {
+        const int P = N + 2;
+        // Column-pass A operand state: s and the running 2^K H_n in FP32 (one
+        // scale 2^K for every plane keeps FP16 planes normal: it cancels in P/Q).
+        const int hc = c0 - W + 16 * wave + li;
+        const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
+        float sv[Q][8], hv[Q][8];
+        bool bad = false;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
-                a[q][jj] = M::cvt(hv[q][jj]);
-                hv[q][jj] *= sv[q][jj];                                   // H_{n+1} = H_n s
+                const int hr = r0 - W + 32 * q + 8 * lg + jj;
+                const float x = R.h[q][jj];
+                if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H) bad |= !(x >= 0.0f && x <= 255.0f);
+                const float s = (x - (float)kTc) * (float)(1.0 / kTh);      // eq. (17)
+                sv[q][jj] = s;
+                hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;            // 2^K H_0
             }
         }
-        E *yb = ybuf_base + (n & 1) * kFusedYElems;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
-            mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = j / 2; q <= qlast; ++q) acc = M::mma(a[q], tf[2 * q - j + 1], acc);
-            typename M::V4 o;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
-            *(typename M::V4 *)(yb + (16 * j + li) * kFusedPitch + 16 * wave + 4 * lg) = o;
-        }
-    };
-    // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
-    auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
-        const E *src = ybuf_base + (n & 1) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
-        if (TC == 64) {
-            V ya[QB + 1];
-#pragma unroll
-            for (int q = 0; q <= QB; ++q) ya[q] = *(const V *)(src + 32 * (q + p));
-            mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
-#pragma unroll
-            for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
-            z[0] = acc0;
-            z[JB - 1] = acc1;
-        } else {
-            mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc = M::mma(*(const V *)(src + 32 * q), rf[q], acc);
-            z[0] = acc;
-        }
-    };
-    // Eqs. 8-9 for plane n >= 1 (pw = s^n on entry).
-    auto combine = [&](int n, const mf_f4 (&z)[JB]) {
-        const float bp = bt[n - 1];
-        const float bq = bt[n];
+        report_range(bad, flag, slot);
+
+        // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
+        // 16 (jc0 + b) + li. With u_n = s^n Hbar_n the sums are accumulated as
+        //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
+        // so one product serves both, and P = Ps / s. Where s = 0 the sums take
+        // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
+        // up to terms 2^-64 smaller, and Q moves by as little. (Where b_0 2^-64
+        // Hbar_1 underflows, P/Q lies far below FP32 resolution: the pixel's own
+        // term keeps Q >= w_0 b_0 2^K.)
+        float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4];
 #pragma unroll
         for (int b = 0; b < JB; ++b) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float u = pw[b][v] * z[b][v];
-                Ps[b][v] = fmaf(bp, u, Ps[b][v]);
-                Qa[b][v] = fmaf(bq, u, Qa[b][v]);
-                pw[b][v] *= sc[b][v];
+                const float s = (R.c[b][v] - (float)kTc) * (float)(1.0 / kTh);
+                sc[b][v] = s != 0.0f ? s : 0x1p-64f;
+                pw[b][v] = sc[b][v];
+                Ps[b][v] = 0.0f;
+                Qa[b][v] = 0.0f;
             }
         }
-    };
 
-    // Software pipeline: the row pass of plane n-1 and the column pass of
-    // plane n sit between the same two barriers (different LDS buffers).
-    column_pass(0);
-    __syncthreads();
-    column_pass(1);
-    {
-        mf_f4 z[JB];
-        row_pass(0, z);
-        const float b0 = bt[0];
+        // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
+        auto column_pass = [&](int n) {
+            V a[Q];
 #pragma unroll
-        for (int b = 0; b < JB; ++b)
+            for (int q = 0; q < Q; ++q) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Qa[b][v] = b0 * z[b][v];
-    }
-    __syncthreads();
-    for (int n = 2; n < P; ++n) {
-        column_pass(n);
-        mf_f4 z[JB];
-        row_pass(n - 1, z);
-        combine(n - 1, z);
+                for (int jj = 0; jj < 8; ++jj) {
+                    a[q][jj] = M::cvt(hv[q][jj]);
+                    hv[q][jj] *= sv[q][jj];                               // H_{n+1} = H_n s
+                }
+            }
+            E *yb = ybuf + (n & 1) * kFusedYElems;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
+                mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = j / 2; q <= qlast; ++q) acc = M::mma(a[q], tf[2 * q - j + 1], acc);
+                typename M::V4 o;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
+                *(typename M::V4 *)(yb + (16 * j + li) * kFusedPitch + 16 * wave + 4 * lg) = o;
+            }
+        };
+        // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
+        auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
+            const E *src = ybuf + (n & 1) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
+            if (TC == 64) {
+                V ya[QB + 1];
+#pragma unroll
+                for (int q = 0; q <= QB; ++q) ya[q] = *(const V *)(src + 32 * (q + p));
+                mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
+#pragma unroll
+                for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
+                z[0] = acc0;
+                z[JB - 1] = acc1;
+            } else {
+                mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc = M::mma(*(const V *)(src + 32 * q), rf[q], acc);
+                z[0] = acc;
+            }
+        };
+        // Eqs. 8-9 for plane n >= 1 (pw = s^n on entry).
+        auto combine = [&](int n, const mf_f4 (&z)[JB]) {
+            const float bp = bt[n - 1];
+            const float bq = bt[n];
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float u = pw[b][v] * z[b][v];
+                    Ps[b][v] = fmaf(bp, u, Ps[b][v]);
+                    Qa[b][v] = fmaf(bq, u, Qa[b][v]);
+                    pw[b][v] *= sc[b][v];
+                }
+            }
+        };
+
+        // Software pipeline: the row pass of plane n-1 and the column pass of
+        // plane n sit between the same two barriers (different LDS buffers).
+        column_pass(0);
         __syncthreads();
-    }
-    {
-        mf_f4 z[JB];
-        row_pass(P - 1, z);
-        combine(P - 1, z);
-    }
+        column_pass(1);
+        {
+            mf_f4 z[JB];
+            row_pass(0, z);
+            const float b0 = bt[0];
+#pragma unroll
+            for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Qa[b][v] = b0 * z[b][v];
+        }
+        __syncthreads();
+        for (int n = 2; n < P; ++n) {
+            column_pass(n);
+            mf_f4 z[JB];
+            row_pass(n - 1, z);
+            combine(n - 1, z);
+            __syncthreads();
+        }
+        {
+            mf_f4 z[JB];
+            row_pass(P - 1, z);
+            combine(P - 1, z);
+        }
 
 #pragma unroll
-    for (int b = 0; b < JB; ++b) {
-        const int c = c0 + 16 * (jc0 + b) + li;
-        if (c >= Wd) continue;
+        for (int b = 0; b < JB; ++b) {
+            const int c = c0 + 16 * (jc0 + b) + li;
+            if (c >= Wd) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = r0 + 16 * rb + 4 * lg + v;
-            const float ratio = Ps[b][v] / (sc[b][v] * Qa[b][v]);
-            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 16 * rb + 4 * lg + v;
+                const float ratio = Ps[b][v] / (sc[b][v] * Qa[b][v]);
+                if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
+            }
         }
     }
-}
+};
 
-// Single-image fused kernel: one block per 64 x TC output tile.
+// Whether the single-image fused kernel of a geometry is persistent with
+// prefetch (see k_fused_mfma).
+__host__ __device__ constexpr bool fused_persistent(int Q) { return Q >= 4; }
+
+// Single-image fused kernel over the tiles_x-wide grid of 64 x TC tiles.
+// For Q >= 4 (one block per CU) it is persistent: block b takes tiles b,
+// b + grid, ..., makes the fragments once, and loads the inputs of its next
+// tile while the current one runs, so that no block waits for its halo at the
+// start of a tile. For Q = 3 the registers of that would cost the second
+// block per CU, which hides those loads instead: one block per tile.
 template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
                                                     int Wd, int ld, FusedConsts C, int W, int N, float mu,
-                                                    float prescale, unsigned *__restrict__ slots) {
+                                                    float prescale, unsigned *__restrict__ slots, int tiles_x,
+                                                    int tiles) {
     typedef typename M::E E;
+    typedef FusedTile<M, Q, TC, QA> T;
     __shared__ __align__(16) E ybuf[2 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    fused_tile<M, Q, TC, QA>(f, out, H, Wd, ld, C.taps, C.b, W, N, mu, prescale, nullptr,
-                             slots + blockIdx.y * gridDim.x + blockIdx.x, blockIdx.y * kFusedRows, blockIdx.x * TC,
-                             ybuf, tab);
+    T tile(f, out, H, Wd, ld, W, N, mu, prescale, C.b, ybuf);
+    tile.setup(C.taps, tab);
+    if constexpr (!fused_persistent(Q)) {
+        const int t = blockIdx.x;
+        const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
+        typename T::Raw cur;
+        tile.load(r0, c0, cur);
+        tile.run(r0, c0, cur, nullptr, slots + t);
+    } else {
+        typename T::Raw next;
+        int t = blockIdx.x;
+        if (t < tiles) tile.load((t / tiles_x) * kFusedRows, (t % tiles_x) * TC, next);
+        for (; t < tiles; t += gridDim.x) {
+            const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
+            const typename T::Raw cur = next;
+            const int tn = t + gridDim.x;
+            if (tn < tiles) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, next);
+            tile.run(r0, c0, cur, nullptr, slots + t);
+            __syncthreads();          // the next tile's first column pass rewrites buffer 0
+        }
+    }
 }
 
 // Joint filter on the matrix cores: the plain tile's schedule with two operand
@@ -1378,11 +1436,13 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
         const int l = (int)(t - s_start[lo]);
         const int bx = l % B.gvx, by = l / B.gvx;
         const double *prm = as_global(uniform(B.prm));
-        fused_tile<M, Q, TC, QA>(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd),
-                                 uniform(B.ld), (const float *)(prm + uniform(B.off_tf)),
-                                 (const float *)(prm + uniform(B.off_bf)), uniform(B.W), uniform(B.N),
-                                 (float)uniform(B.mu), prescale, as_global(&hdr->flags), nullptr, by * kFusedRows,
-                                 bx * TC, ybuf, tab);
+        FusedTile<M, Q, TC, QA> tile(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd),
+                                     uniform(B.ld), uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale,
+                                     (const float *)(prm + uniform(B.off_bf)), ybuf);
+        tile.setup((const float *)(prm + uniform(B.off_tf)), tab);
+        typename FusedTile<M, Q, TC, QA>::Raw raw;
+        tile.load(by * kFusedRows, bx * TC, raw);
+        tile.run(by * kFusedRows, bx * TC, raw, as_global(&hdr->flags), nullptr);
         __syncthreads();          // the next item rewrites the tap table and buffer 0
     }
 }
