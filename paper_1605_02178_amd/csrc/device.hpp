@@ -1011,22 +1011,38 @@ struct FusedTile {
 
     __device__ __forceinline__ void load(int r0, int c0, Raw &R) const {
         const int mc = halo_index(c0 - W + 16 * wave + li, Wd, W, one_ref);
-        // rows of the halo inside the image need no extension (most tiles)
-        const bool rows_inside = r0 - W >= 0 && r0 - W + 32 * Q <= H;
-        const float *col = f + mc;
+        const int cr = r0 + 16 * rb + 4 * lg;                    // first output row of the lane
+        if (r0 - W >= 0 && r0 - W + 32 * Q <= H && r0 + kFusedRows <= H && (long long)H * ld < (1LL << 29)) {
+            // Most tiles: every halo row and output row inside the image, and
+            // byte offsets within 32 bits, so each load is one add from the
+            // lane's first offset (the row steps are uniform).
+            const char *base = (const char *)f;
+            const unsigned o = 4u * (unsigned)((r0 - W + 8 * lg) * ld + mc);
+            const unsigned ld4 = 4u * (unsigned)ld;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+            for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                const int hr = r0 - W + 32 * q + 8 * lg + jj;
-                R.h[q][jj] = col[(long long)(rows_inside ? hr : halo_index(hr, H, W, one_ref)) * ld];
+                for (int jj = 0; jj < 8; ++jj) R.h[q][jj] = *(const float *)(base + o + (unsigned)(32 * q + jj) * ld4);
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+                const unsigned oc = 4u * (unsigned)(cr * ld + min(c0 + 16 * (jc0 + b) + li, Wd - 1));
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R.c[b][v] = *(const float *)(base + oc + (unsigned)v * ld4);
             }
-        }
+        } else {
+            // symmetric extension of the halo rows; output rows clamped
+            const float *col = f + mc;
 #pragma unroll
-        for (int b = 0; b < JB; ++b) {
-            const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
+            for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) R.c[b][v] = f[(long long)min(r0 + 16 * rb + 4 * lg + v, H - 1) * ld + c];
+                for (int jj = 0; jj < 8; ++jj)
+                    R.h[q][jj] = col[(long long)halo_index(r0 - W + 32 * q + 8 * lg + jj, H, W, one_ref) * ld];
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+                const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) R.c[b][v] = f[(long long)min(cr + v, H - 1) * ld + c];
+            }
         }
     }
 
@@ -1034,23 +1050,26 @@ struct FusedTile {
                                         unsigned *__restrict__ slot) {
         const int P = N + 2;
         // Column-pass A operand state: s and the running 2^K H_n in FP32 (one
-        // scale 2^K for every plane keeps FP16 planes normal: it cancels in P/Q).
-        const int hc = c0 - W + 16 * wave + li;
-        const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
+        // scale 2^K for every plane keeps FP16 planes normal: it cancels in
+        // P/Q), with 2^K e^{-mu s^2/2} = 2^{K - mu log2(e) s^2 / 2}.
+        const float e2 = -0.5f * mu * 1.4426950408889634f, k2 = __log2f(prescale);
         float sv[Q][8], hv[Q][8];
-        bool bad = false;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
-                const int hr = r0 - W + 32 * q + 8 * lg + jj;
-                const float x = R.h[q][jj];
-                if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H) bad |= !(x >= 0.0f && x <= 255.0f);
-                const float s = (x - (float)kTc) * (float)(1.0 / kTh);      // eq. (17)
+                const float s = fmaf(R.h[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));   // eq. (17)
                 sv[q][jj] = s;
-                hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;            // 2^K H_0
+                hv[q][jj] = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));                     // 2^K H_0
             }
         }
+        // Range check on the lane's own output pixels: every pixel of the
+        // image is the output of exactly one lane of one tile.
+        bool bad = false;
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) bad |= !(R.c[b][v] >= 0.0f && R.c[b][v] <= 255.0f);
         report_range(bad, flag, slot);
 
         // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
@@ -1066,7 +1085,7 @@ struct FusedTile {
         for (int b = 0; b < JB; ++b) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float s = (R.c[b][v] - (float)kTc) * (float)(1.0 / kTh);
+                const float s = fmaf(R.c[b][v], (float)(1.0 / kTh), (float)(-kTc / kTh));
                 sc[b][v] = s != 0.0f ? s : 0x1p-64f;
                 pw[b][v] = sc[b][v];
                 Ps[b][v] = 0.0f;
@@ -1170,7 +1189,8 @@ struct FusedTile {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = r0 + 16 * rb + 4 * lg + v;
-                const float ratio = Ps[b][v] / (sc[b][v] * Qa[b][v]);
+                // a reduced-precision stack: the reciprocal's ulp is far below its error
+                const float ratio = Ps[b][v] * __frcp_rn(sc[b][v] * Qa[b][v]);
                 if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
             }
         }
