@@ -179,7 +179,7 @@ size_t bf_gc_workspace_bytes(int height, int width, double sigma_s, int N, int s
  * The range flags in ws describe this call only (bf_gc_read_flags): the
  * three-kernel paths clear the flag word before their kernels set it; the
  * fused path (one kernel, taps and coefficients passed as kernel arguments)
- * has every block write its own flag word after the first 256 bytes.
+ * has every wave write its own flag word after the first 256 bytes.
  * Path: see BF_TILE_CONFIGS. BF_FLAG_TILE(BF_TILE_FUSED) with an FP32 stack
  * or a radius above BF_FUSED_MAX_RADIUS is BF_ERR_UNSUPPORTED, with
  * BF_FLAG_STAGED BF_ERR_INVALID_ARG.
@@ -336,7 +336,7 @@ bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, 
 
 /* Reads the range flags of the last call that used workspace ws
  * (bf_gc_forward, bf_gc_joint_forward, bf_gc_forward_pivots, bf_gc_backward
- * or bf_gc_batched): the flag word, or the or of the per-block words a fused
+ * or bf_gc_batched): the flag word, or the or of the per-wave words a fused
  * launch wrote (the library remembers, per workspace address, which applies).
  * Waits for `stream` first. flags_out: host unsigned. */
 bf_status bf_gc_read_flags(const void *ws, unsigned *flags_out, void *stream);

@@ -170,9 +170,9 @@ static bf_status check_conditioning(double sigma_r, int N, int dtype, unsigned f
 
 // Where the range flags of a workspace's last call sit: the flag word at its
 // start (cleared by the parameter upload, or by the batched blob), or, after a
-// single-image fused launch, one word per block right after the flag area
-// (every block writes its word, so nothing is cleared first). The map holds
-// the workspaces of the second kind with their word counts.
+// single-image fused launch, one word per wave of each tile right after the
+// flag area (every wave writes its word, so nothing is cleared first). The
+// map holds the workspaces of the second kind with their word counts.
 static std::mutex g_range_mtx;
 static std::unordered_map<const void *, long long> g_range_words;
 static void note_range_words(const void *ws, long long words) {
@@ -307,7 +307,7 @@ static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int l
     const int grid = fused_persistent(Q) ? (int)std::min<long long>(tiles, resident_blocks(kernel, &resident))
                                          : (int)tiles;
     const float prescale = M::kPrescale;
-    note_range_words(ws, tiles);
+    note_range_words(ws, kFusedSlots * tiles);
     ProfScope prof_("k_fused_mfma", stream);
     hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), dim3(grid), dim3(512), 0, stream, f, out, H, Wd, ld, C, W, N,
                        mu, prescale, (unsigned *)(ws + kFlagBytes), tiles_x, (int)tiles);
@@ -315,7 +315,7 @@ static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int l
 }
 
 // Fused FP16/BF16 forward: one kernel (see k_fused_mfma), its constants
-// passed by value. The workspace holds only the blocks' range words (4 bytes
+// passed by value. The workspace holds only the waves' range words (32 bytes
 // per 64 x TC tile, far below bf_gc_workspace_bytes).
 template <class M>
 static bf_status run_fused(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
@@ -510,7 +510,7 @@ static bf_status run_joint_fused(const float *g, const float *v, float *out, int
     dim3 grid((Wd + 63) / 64, (H + kFusedRows - 1) / kFusedRows);
     unsigned *slots = (unsigned *)(ws + kFlagBytes);
     if (W > 32) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above 32");
-    note_range_words(ws, (long long)grid.x * grid.y);
+    note_range_words(ws, (long long)kFusedSlots * grid.x * grid.y);
     ProfScope prof_("k_fused_joint", stream);
     if (W <= 16) {
         if (qa == 0)

@@ -920,17 +920,18 @@ struct FusedConsts {
     float b[BF_MAX_DEGREE + 2];
 };
 
-// Range flag of a block: with a slot (single-image launches) every block
-// writes its own word, 0 or BF_DEVFLAG_RANGE, so no word needs clearing
-// first; without (batched) the flag word is or-ed.
+// Range flag of a wave: with slots (single-image launches) every wave
+// writes its own word slot[wave], 0 or BF_DEVFLAG_RANGE, so no word needs
+// clearing first; without (batched) the flag word is or-ed.
 __device__ __forceinline__ void report_range(bool bad, unsigned *flag, unsigned *slot) {
     if (slot) {
-        const int any = __syncthreads_or(bad);
-        if (threadIdx.x == 0) *slot = any ? BF_DEVFLAG_RANGE : 0u;
+        const bool any = __any(bad);
+        if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = any ? BF_DEVFLAG_RANGE : 0u;
     } else if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1) {
         atomicOr(flag, BF_DEVFLAG_RANGE);
     }
 }
+constexpr int kFusedSlots = 8;    // range words per tile of a single-image fused launch (one per wave)
 constexpr int kFusedYElems = kFusedRows * kFusedPitch;
 __host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 32 * Q; }   // t in [-32, 32Q)
 
@@ -1046,8 +1047,12 @@ struct FusedTile {
         }
     }
 
+    // base: parity of the buffer the tile's plane 0 goes to. A block that
+    // runs tiles back to back continues the alternation (base = planes run
+    // before), so that the next tile's first column pass writes the buffer
+    // the last row pass did not read and needs no barrier before it.
     __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
-                                        unsigned *__restrict__ slot) {
+                                        unsigned *__restrict__ slot, int base = 0) {
         const int P = N + 2;
         // Column-pass A operand state: s and the running 2^K H_n in FP32 (one
         // scale 2^K for every plane keeps FP16 planes normal: it cancels in
@@ -1104,7 +1109,7 @@ struct FusedTile {
                     hv[q][jj] *= sv[q][jj];                               // H_{n+1} = H_n s
                 }
             }
-            E *yb = ybuf + (n & 1) * kFusedYElems;
+            E *yb = ybuf + ((n + base) & 1) * kFusedYElems;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
@@ -1119,7 +1124,7 @@ struct FusedTile {
         };
         // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
         auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
-            const E *src = ybuf + (n & 1) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
+            const E *src = ybuf + ((n + base) & 1) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
             if (TC == 64) {
                 V ya[QB + 1];
 #pragma unroll
@@ -1223,18 +1228,19 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
         const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
         typename T::Raw cur;
         tile.load(r0, c0, cur);
-        tile.run(r0, c0, cur, nullptr, slots + t);
+        tile.run(r0, c0, cur, nullptr, slots + kFusedSlots * t);
     } else {
         typename T::Raw next;
         int t = blockIdx.x;
+        int base = 0;
         if (t < tiles) tile.load((t / tiles_x) * kFusedRows, (t % tiles_x) * TC, next);
         for (; t < tiles; t += gridDim.x) {
             const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
             const typename T::Raw cur = next;
             const int tn = t + gridDim.x;
             if (tn < tiles) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, next);
-            tile.run(r0, c0, cur, nullptr, slots + t);
-            __syncthreads();          // the next tile's first column pass rewrites buffer 0
+            tile.run(r0, c0, cur, nullptr, slots + kFusedSlots * t, base);
+            base += N + 2;
         }
     }
 }
@@ -1408,7 +1414,7 @@ __global__ __launch_bounds__(512) void k_fused_joint(const float *__restrict__ g
     __shared__ __align__(16) E ybuf[4 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
     fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, C.taps, C.b, W, N, mu, M::kPrescale,
-                               slots + blockIdx.y * gridDim.x + blockIdx.x, blockIdx.y * kFusedRows,
+                               slots + kFusedSlots * (blockIdx.y * gridDim.x + blockIdx.x), blockIdx.y * kFusedRows,
                                blockIdx.x * 64, ybuf, tab);
 }
 
