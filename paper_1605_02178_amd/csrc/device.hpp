@@ -891,9 +891,22 @@ struct MmaBF16 {
     }
 };
 
+// An MFMA operand (8 elements) from the column-pass tile in LDS, as two
+// 8-byte reads: the row pitch below is a multiple of 8 bytes but not of 16.
+template <class M>
+__device__ __forceinline__ typename M::V ld_frag(const typename M::E *p) {
+    const typename M::V4 lo = *(const typename M::V4 *)p, hi = *(const typename M::V4 *)(p + 4);
+    return __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+
 constexpr int kFusedRows = 64;               // output rows per tile
 constexpr int kFusedHaloC = 128;             // halo columns of the column pass
-constexpr int kFusedPitch = kFusedHaloC + 8; // LDS row pitch (elements) of the column-pass result
+// LDS row pitch (elements) of the column-pass result: 70 words, 6 mod 32.
+// The column pass writes 8 bytes per lane to rows li = 0..15 and the row
+// pass reads 8 bytes per lane from rows li = 0..15; with this pitch both
+// spread over all 32 banks (SQ_LDS_BANK_CONFLICT reads 0; a 16-byte aligned
+// pitch of 136 leaves the writes two-way conflicted).
+constexpr int kFusedPitch = kFusedHaloC + 12;
 
 // Chunk ranges. Output block j (16 rows or columns) needs the halo positions
 // [16j, 16j + 15 + 2W], i.e. chunks j/2 .. j/2 + A for even j and
@@ -1128,7 +1141,7 @@ struct FusedTile {
             if (TC == 64) {
                 V ya[QB + 1];
 #pragma unroll
-                for (int q = 0; q <= QB; ++q) ya[q] = *(const V *)(src + 32 * (q + p));
+                for (int q = 0; q <= QB; ++q) ya[q] = ld_frag<M>(src + 32 * (q + p));
                 mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
@@ -1139,7 +1152,7 @@ struct FusedTile {
             } else {
                 mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc = M::mma(*(const V *)(src + 32 * q), rf[q], acc);
+                for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), rf[q], acc);
                 z[0] = acc;
             }
         };
@@ -1365,7 +1378,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
             const E *src = base + set * kFusedYElems;
             V ya[QB + 1];
 #pragma unroll
-            for (int q = 0; q <= QB; ++q) ya[q] = *(const V *)(src + 32 * (q + p));
+            for (int q = 0; q <= QB; ++q) ya[q] = ld_frag<M>(src + 32 * (q + p));
             mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
