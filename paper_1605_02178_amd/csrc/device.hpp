@@ -1298,39 +1298,78 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     const int jc0 = 2 * p;
 
     const bool one_ref = W < H && W < Wd;
-    const int hc = c0 - W + 16 * wave + li;
-    const int mc = halo_index(hc, Wd, W, one_ref);
-    const bool col_in_tile = hc >= c0 && hc < c0 + TC && hc < Wd;
-    float sv[Q][8], hv[Q][8], fv[Q][8];
-    bool bad = false;
-    {
-        const bool rows_inside = r0 - W >= 0 && r0 - W + 32 * Q <= H;
+    const int mc = halo_index(c0 - W + 16 * wave + li, Wd, W, one_ref);
+    const int cr = r0 + 16 * rb + 4 * lg;                        // first output row of the lane
+    // Inputs: halo column values of g and v, and the lane's own output pixels
+    // (as in FusedTile::load: one add per load where everything lies inside
+    // the image and byte offsets fit 32 bits).
+    float gx[Q][8], vx[Q][8], gc[2][4], vc[2][4];
+    if (r0 - W >= 0 && r0 - W + 32 * Q <= H && r0 + kFusedRows <= H && (long long)H * ld < (1LL << 29)) {
+        const unsigned o = 4u * (unsigned)((r0 - W + 8 * lg) * ld + mc), ld4 = 4u * (unsigned)ld;
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
+        for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) {
-                const int hr = r0 - W + 32 * q + 8 * lg + jj;
-                const long long o = (long long)(rows_inside ? hr : halo_index(hr, H, W, one_ref)) * ld + mc;
-                const float x = g[o], y = v[o];
-                if (col_in_tile && hr >= r0 && hr < r0 + kFusedRows && hr < H)
-                    bad |= !(x >= 0.0f && x <= 255.0f) || !(y >= 0.0f && y <= 255.0f);
-                const float s = (x - (float)kTc) * (float)(1.0 / kTh);          // eq. (17) on the guide
-                sv[q][jj] = s;
-                hv[q][jj] = __expf(-0.5f * mu * s * s) * prescale;
-                fv[q][jj] = (y - (float)kTc) * (float)(1.0 / kTh);
+                const unsigned oo = o + (unsigned)(32 * q + jj) * ld4;
+                gx[q][jj] = *(const float *)((const char *)g + oo);
+                vx[q][jj] = *(const float *)((const char *)v + oo);
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const unsigned oc = 4u * (unsigned)(cr * ld + min(c0 + 16 * (jc0 + b) + li, Wd - 1));
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                gc[b][vv] = *(const float *)((const char *)g + oc + (unsigned)vv * ld4);
+                vc[b][vv] = *(const float *)((const char *)v + oc + (unsigned)vv * ld4);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const long long o = (long long)halo_index(r0 - W + 32 * q + 8 * lg + jj, H, W, one_ref) * ld + mc;
+                gx[q][jj] = g[o];
+                vx[q][jj] = v[o];
+            }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
+#pragma unroll
+            for (int vv = 0; vv < 4; ++vv) {
+                const long long o = (long long)min(cr + vv, H - 1) * ld + c;
+                gc[b][vv] = g[o];
+                vc[b][vv] = v[o];
             }
         }
     }
+    // s (eq. 17 on the guide) by one fma, 2^K e^{-mu s^2/2} by one exp2
+    const float e2 = -0.5f * mu * 1.4426950408889634f, k2 = __log2f(prescale);
+    float sv[Q][8], hv[Q][8], fv[Q][8];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int jj = 0; jj < 8; ++jj) {
+            const float s = fmaf(gx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
+            sv[q][jj] = s;
+            hv[q][jj] = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));
+            fv[q][jj] = fmaf(vx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
+        }
+    // range check on the lane's own output pixels (each image pixel is one)
+    bool bad = false;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int vv = 0; vv < 4; ++vv)
+            bad |= !(gc[b][vv] >= 0.0f && gc[b][vv] <= 255.0f) || !(vc[b][vv] >= 0.0f && vc[b][vv] <= 255.0f);
     report_range(bad, nullptr, slot);
 
     float sc[2][4], pw[2][4], Pa[2][4], Qa[2][4];
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-        const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
-            const int r = min(r0 + 16 * rb + 4 * lg + vv, H - 1);
-            sc[b][vv] = (g[(long long)r * ld + c] - (float)kTc) * (float)(1.0 / kTh);
+            sc[b][vv] = fmaf(gc[b][vv], (float)(1.0 / kTh), (float)(-kTc / kTh));
             pw[b][vv] = 1.0f;
             Pa[b][vv] = 0.0f;
             Qa[b][vv] = 0.0f;
@@ -1413,7 +1452,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
             const int r = r0 + 16 * rb + 4 * lg + vv;
-            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * (Pa[b][vv] / Qa[b][vv]);   // eq. (10)
+            if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * (Pa[b][vv] * __frcp_rn(Qa[b][vv]));   // eq. (10)
         }
     }
 }
