@@ -464,7 +464,7 @@ def main():
     r32 = run_stack("f32", N, not args.no_fp32_timing)
     r16 = None
     if not args.no_fp16:
-        target = r32["max_abs_vs_direct_64c"] * 1.05
+        target = r32["max_abs_vs_direct_64c"]
         if args.fp16_degree:
             n16 = args.fp16_degree
         else:
@@ -475,7 +475,7 @@ def main():
                 log(f"bench: FP16 N={n16}: max abs vs direct {e:.4f} (target {target:.4f})")
                 if e <= target:
                     break
-                n16 += 2
+                n16 += 1
         log(f"bench: FP16 stack, N={n16}")
         r16 = run_stack("f16", n16, True)
         r16["same_error"] = r16["max_abs_vs_direct_64c"] <= target
