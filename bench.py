@@ -7,9 +7,9 @@ already resident in HBM. A step is one full forward filter.
 
 Two stacks are compared at the same error against the direct filter (eq. 1):
   FP32 stack at the paper's degree N = 28 (FP64 accumulation, three kernels);
-  FP16 stack at the smallest degree N' >= 28 (steps of 2) whose max-abs error
-  against the direct filter on a 64^2 centre crop is no worse than the FP32
-  stack's (times 1.05), run by the fused matrix-core kernel.
+  FP16 stack at the smallest degree N' >= 28 whose max-abs error against the
+  direct filter on a 64^2 centre crop is no worse than the FP32 stack's, run
+  by the fused matrix-core kernel.
 The headline `value` is the faster of the two; both are reported.
 
 Prints one JSON line. Besides the contract fields it carries
