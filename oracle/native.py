@@ -57,9 +57,10 @@ def direct_bf(f, sigma_s, sigma_r, region=None):
 
 
 def polynomial_filter(f, sigma_s, sigma_r, c, L=DEFAULT_L, U=DEFAULT_U, region=None,
-                      return_pq=False):
+                      return_pq=False, t_c=None):
     """Section II fast algorithm in C; same contract as
-    oracle.filters.polynomial_filter (without the plane stacks)."""
+    oracle.filters.polynomial_filter (without the plane stacks). t_c overrides
+    the centre (L + U)/2."""
     f, H, Wd, r0, r1, c0, c1 = _prep(f, region)
     c = np.ascontiguousarray(c, dtype=np.float64)
     out = np.empty((r1 - r0, c1 - c0))
@@ -67,7 +68,8 @@ def polynomial_filter(f, sigma_s, sigma_r, c, L=DEFAULT_L, U=DEFAULT_U, region=N
     Q = np.empty_like(out)
     rc = _load().oracle_polynomial_filter(
         _ptr(f), H, Wd, Wd, float(sigma_s), float(sigma_r), c.size - 1, _ptr(c),
-        0.5 * (L + U), r0, r1, c0, c1, _ptr(out), max(1, c1 - c0), _ptr(P), _ptr(Q))
+        0.5 * (L + U) if t_c is None else float(t_c), r0, r1, c0, c1, _ptr(out), max(1, c1 - c0), _ptr(P),
+        _ptr(Q))
     if rc != 0:
         raise ValueError(f"oracle_polynomial_filter failed ({rc})")
     return (out, P, Q) if return_pq else out
@@ -77,3 +79,23 @@ def gcf(f, sigma_s, sigma_r, N, L=DEFAULT_L, U=DEFAULT_U, region=None, return_pq
     """Gauss-Chebyshev filter in C with the coefficients of eq. (19)."""
     c, _ = gcf_coefficients(sigma_r, N, L, U)
     return polynomial_filter(f, sigma_s, sigma_r, c, L, U, region, return_pq)
+
+
+def pivot_gcf(f, sigma_s, sigma_r, K, N=None, L=DEFAULT_L, U=DEFAULT_U, region=None):
+    """Pivoted Gauss-Chebyshev filter with the C polynomial filter; same
+    contract and steps as oracle.filters.pivot_gcf (per sub-range, the fast
+    algorithm centred at t_k with the coefficients of exp on [-mu_k, mu_k];
+    each output pixel from the sub-range of its own value)."""
+    from .coeffs import chebyshev_coefficients_mu
+    from .filters import pivot_plan
+    f, H, Wd, r0, r1, c0, c1 = _prep(f, region)
+    ctr = f[r0:r1, c0:c1]
+    out = np.full(ctr.shape, np.nan)
+    for k, (lo, hi, t, h, R, mu, Nk) in enumerate(pivot_plan(sigma_r, K, N, L, U)):
+        mask = (ctr >= lo) & ((ctr < hi) if k < K - 1 else (ctr <= hi))
+        if not mask.any():
+            continue
+        c = chebyshev_coefficients_mu(mu, Nk)
+        y = polynomial_filter(f, sigma_s, sigma_r, c, L, U, region=(r0, r1, c0, c1), t_c=t)
+        out[mask] = y[mask]
+    return out

@@ -95,3 +95,14 @@ def test_pivot_error_falls_with_degree():
     errs = [np.abs(F.pivot_gcf(f, 1.0, 10.0, 8, N) - direct).max() for N in (40, 50, 60, 70)]
     assert all(a > b for a, b in zip(errs, errs[1:])), errs
     assert errs[-1] < 1e-6
+
+
+@pytest.mark.parametrize("sigma_r,KK,region", [(10.0, 8, None), (12.0, 32, (5, 30, 3, 40)), (15.0, 4, (0, 1, 0, 44))])
+def test_native_pivots_equal_the_numpy_pivots(sigma_r, KK, region):
+    """The C binding of the pivoted filter (used for large crops) takes the
+    same steps as the numpy one: the same values to rounding."""
+    f = edge_rich(34, 44, seed=26).astype(np.float64)
+    a = C.pivot_gcf(f, 2.0, sigma_r, KK, region=region)
+    b = F.pivot_gcf(f, 2.0, sigma_r, KK, region=region)
+    assert np.isfinite(a).all()
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-9)
