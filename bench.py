@@ -21,7 +21,8 @@ Prints one JSON line. Besides the contract fields it carries
   differentiation   forward + backward of 8 x 1024^2 images through the
                 autograd function
   joint         the joint (cross) filter at the headline size
-  small_sigma_r the pivoted form at sigma_r = 10 (sub-ranges of [0, 255])
+  small_sigma_r the pivoted form at sigma_r = 10 (sub-ranges of [0, 255]):
+                FP32 and FP16 on the three-kernel tiles, FP16 on the fused tile
   recursive     the recursive (IIR) Gaussian variant against the truncated one
 """
 from __future__ import annotations
@@ -289,34 +290,74 @@ def bench_joint(bf, f, f64, sigma_s, sigma_r, N, steps, log):
 def bench_small_sigma_r(bf, f, f64, sigma_s, steps, log, sigma_r=10.0):
     """Small sigma_r at the headline size (sigma_r = 10, where the single
     expansion is refused): the pivoted form with the smallest well-conditioned
-    sub-range count for the FP32 stack, rule degrees; time and max-abs error
-    against the direct filter on a 64^2 centre crop."""
+    sub-range count of each stack, rule degrees. FP32 on the three-kernel
+    tiles; FP16 on the three-kernel tiles and on the fused tile, which runs
+    per 64 x 64 tile only the sub-ranges its own pixels fall in. Per form:
+    time, kernel averages and max-abs error against the direct filter on a
+    64^2 centre crop; for the fused tile also the sub-ranges and planes per
+    tile and the matrix-core rate of the convolutions it runs."""
     import numpy as np
     import torch
     from oracle import native as C
     H, Wd = f.shape
-    K = bf.pivot_count(sigma_r, "f32")
-    ws = torch.empty(bf.pivots_workspace_bytes(H, Wd, sigma_s, sigma_r, K), dtype=torch.uint8, device="cuda:0")
-    y = torch.empty_like(f)
-    bf.gc_filter_pivots(f, sigma_s, sigma_r, K, out=y, workspace=ws)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        bf.gc_filter_pivots(f, sigma_s, sigma_r, K, out=y, workspace=ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    lib = bf._lib.load()
     d0 = H // 2 - 32
     direct = C.direct_bf(f64, sigma_s, sigma_r, region=(d0, d0 + 64, d0, d0 + 64))
-    err = float(np.abs(y.cpu().double().numpy()[d0:d0 + 64, d0:d0 + 64] - direct).max())
-    plan = bf.pivot_plan(sigma_r, K)
-    log(f"bench: sigma_r={sigma_r} pivoted K={K} {ms:.2f} ms, max abs vs direct {err:.4f}")
-    return {"sigma_r": sigma_r, "sigma_s": sigma_s, "sub_ranges": K, "degrees": [p[0] for p in plan],
-            "planes": sum(p[0] + 2 for p in plan), "ms_per_step": round(ms, 3),
-            "mpx_s": round(H * Wd / 1e6 / (ms / 1e3), 1), "max_abs_vs_direct_64c": err, "stack": "f32",
-            "steps": steps}
+    res = {"sigma_r": sigma_r, "sigma_s": sigma_s, "steps": steps}
+
+    def run(stack, cfg):
+        K = bf.pivot_count(sigma_r, stack)
+        ws = torch.empty(bf.pivots_workspace_bytes(H, Wd, sigma_s, sigma_r, K, None, stack), dtype=torch.uint8,
+                         device="cuda:0")
+        y = torch.empty_like(f)
+        bf.gc_filter_pivots(f, sigma_s, sigma_r, K, stack_dtype=stack, out=y, workspace=ws, tile_config=cfg)
+        torch.cuda.synchronize()
+        lib.bf_profile_start()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            bf.gc_filter_pivots(f, sigma_s, sigma_r, K, stack_dtype=stack, out=y, workspace=ws, tile_config=cfg)
+        e1.record()
+        torch.cuda.synchronize()
+        lib.bf_profile_stop(None)
+        prof = profile_read(lib)
+        ms = e0.elapsed_time(e1) / steps
+        err = float(np.abs(y.cpu().double().numpy()[d0:d0 + 64, d0:d0 + 64] - direct).max())
+        plan = bf.pivot_plan(sigma_r, K)
+        del ws
+        return K, plan, ms, err, prof
+
+    for key, stack, cfg in (("f32", "f32", 0), ("f16_three_kernel", "f16", 0), ("f16_fused", "f16", bf.TILE_FUSED)):
+        K, plan, ms, err, prof = run(stack, cfg)
+        ent = {"stack": stack, "tiles": "fused" if cfg == bf.TILE_FUSED else "three-kernel", "sub_ranges": K,
+               "degrees": [p[0] for p in plan], "planes": sum(p[0] + 2 for p in plan),
+               "ms_per_step": round(ms, 3), "mpx_s": round(H * Wd / 1e6 / (ms / 1e3), 1),
+               "max_abs_vs_direct_64c": err,
+               "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}}
+        if cfg == bf.TILE_FUSED:
+            # sub-ranges present per 64 x 64 tile (equal-width partition of [0, 255])
+            W = bf.radius(sigma_s)
+            TC = 64 if W <= 32 else 32
+            kb = np.clip(np.floor(f64 * K / 255.0), 0, K - 1).astype(np.int64)
+            P = np.array([p[0] + 2 for p in plan])
+            present, planes = [], []
+            for r0 in range(0, H, 64):
+                for c0 in range(0, Wd, TC):
+                    u = np.unique(kb[r0:r0 + 64, c0:c0 + TC])
+                    present.append(len(u))
+                    planes.append(int(P[u].sum()))
+            kms = prof["k_fused_pivots"][1] / prof["k_fused_pivots"][0]
+            flops = 2.0 * 2.0 * (2 * W + 1) * 64 * TC * float(sum(planes))
+            ent.update({"subranges_per_tile_mean": round(float(np.mean(present)), 2),
+                        "subranges_per_tile_max": int(np.max(present)),
+                        "planes_per_tile_mean": round(float(np.mean(planes)), 1),
+                        "mfma_tflops_algorithmic": round(flops / kms / 1e9, 1)})
+        log(f"bench: sigma_r={sigma_r} pivoted {key} K={K} {ms:.2f} ms, max abs vs direct {err:.4f}")
+        res[key] = ent
+    best = min((res[k] for k in ("f32", "f16_three_kernel", "f16_fused")), key=lambda e: e["ms_per_step"])
+    res["ms_per_step"], res["mpx_s"] = best["ms_per_step"], best["mpx_s"]
+    return res
 
 
 def bench_recursive(bf, f, sigma_r, N, steps, log):

@@ -199,13 +199,18 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
  * mu_k = h R_k / sigma_r^2 (R_k = max(t_k, 255 - t_k)). Each sub-range runs
  * the three-kernel forward over the whole image and keeps the outputs whose
  * centre value lies in it ([lo, hi); values below 0 go to the first, values
- * from 255 up and NaN to the last).
+ * from 255 up and NaN to the last). With BF_TILE_FUSED (the default for
+ * FP16/BF16 stacks with radius <= BF_FUSED_MAX_RADIUS; otherwise
+ * BF_ERR_UNSUPPORTED) the sub-ranges run on the fused matrix-core tile
+ * instead, each 64-row tile only those its own output pixels fall in, with
+ * the same partition; the workspace then holds the range words and the
+ * sub-range table.
  *   K: sub-ranges, 1..BF_MAX_PIVOTS (K = 1 is the plain expansion)
  *   N: the degree of every sub-range, or <= 0 for the degree rule at mu_k
  *   other arguments as bf_gc_forward (Chebyshev coefficients only:
- *   BF_FLAG_TAYLOR, BF_FLAG_MINIMAX, BF_FLAG_STAGED are BF_ERR_INVALID_ARG;
- *   BF_TILE_FUSED is BF_ERR_UNSUPPORTED). The conditioning check applies to
- *   every sub-range. ws: at least bf_gc_pivots_workspace_bytes(...) bytes.
+ *   BF_FLAG_TAYLOR, BF_FLAG_MINIMAX, BF_FLAG_STAGED are BF_ERR_INVALID_ARG).
+ *   The conditioning check applies to every sub-range. ws: at least
+ *   bf_gc_pivots_workspace_bytes(...) bytes (enough for either tile form).
  * bf_gc_pivot_count: the smallest K in {1, 2, 4, ..., BF_MAX_PIVOTS} whose
  * sub-ranges pass the conditioning check for the stack type at the rule's
  * degrees, or -1. bf_gc_pivot_plan: per sub-range (host arrays of K, each may

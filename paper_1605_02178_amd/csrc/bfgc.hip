@@ -422,10 +422,24 @@ static int pivot_nmax(const std::vector<Pivot> &plan) {
     return n;
 }
 
-static size_t pivots_ws_bytes(int H, int Wd, int W, int Nmax, int dtype) {
+// Fused pivoted form: the range words of the tiles, then the sub-range table
+// (K FusedPivot entries, the taps, the coefficients of every sub-range).
+static long long fused_pivot_tiles(int H, int Wd, int W) {
+    const int TC = W <= 32 ? 64 : 32;
+    return (long long)((Wd + TC - 1) / TC) * ((H + kFusedRows - 1) / kFusedRows);
+}
+static size_t fused_pivot_table_bytes(int K, int W, int Nmax) {
+    return sizeof(FusedPivot) * K + sizeof(float) * (size_t)(((2 * W + 1) + 3) & ~3) +
+           sizeof(float) * (size_t)K * (Nmax + 2);
+}
+
+static size_t pivots_ws_bytes(int H, int Wd, int W, int K, int Nmax, int dtype) {
     const size_t P = (size_t)Nmax + 2;
-    return kFlagBytes + align256(sizeof(double) * (size_t)param_layout(W, Nmax).total) +
-           align256(P * H * lds_of(Wd) * esize(dtype)) + align256(P * Wd * ldt_of(H) * esize(dtype));
+    const size_t staged = kFlagBytes + align256(sizeof(double) * (size_t)param_layout(W, Nmax).total) +
+                          align256(P * H * lds_of(Wd) * esize(dtype)) + align256(P * Wd * ldt_of(H) * esize(dtype));
+    const size_t fused = kFlagBytes + align256(sizeof(unsigned) * kFusedSlots * (size_t)fused_pivot_tiles(H, Wd, W)) +
+                         align256(fused_pivot_table_bytes(K, W, Nmax));
+    return std::max(staged, fused);
 }
 
 // Pivoted forward: per sub-range, the three-kernel forward centred at its
@@ -462,6 +476,83 @@ static bf_status run_pivots(const float *f, float *out, int H, int Wd, int ld, d
             return st;
     }
     return BF_OK;
+}
+
+// Pivoted form on the fused tile. Per sub-range the planes are built from
+// c s_j with one geometric scale c = g(N+1)^{-1/(N+1)}, g(n) = max over |s| <= 1
+// of e^{-nu s^2/2} |s|^n (= (n/(e nu))^{n/2} for n <= nu, else e^{-nu/2}): since
+// log g is convex in n, every plane's peak c^n g(n) then lies in (0, 1], the
+// top and bottom planes at 1, and the 16-bit planes stay normal without a
+// scale per plane. c^{-n} goes into the coefficients (b_n c^{-n}, so the
+// combine's Ps comes out c times too large) and 1/c into the output scale.
+template <class M, int Q, int TC, int QA>
+static bf_status launch_fused_pivots_q(const float *f, float *out, int H, int Wd, int ld, const char *table, int K,
+                                       int W, char *ws, hipStream_t stream) {
+    const int tiles_x = (Wd + TC - 1) / TC;
+    const long long tiles = (long long)tiles_x * ((H + kFusedRows - 1) / kFusedRows);
+    if (tiles > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused path: too many tiles");
+    const FusedPivot *piv = (const FusedPivot *)table;
+    const float *taps = (const float *)(table + sizeof(FusedPivot) * K);
+    const float *coef = taps + (((2 * W + 1) + 3) & ~3);
+    note_range_words(ws, kFusedSlots * tiles);
+    ProfScope prof_("k_fused_pivots", stream);
+    hipLaunchKernelGGL((k_fused_pivots<M, Q, TC, QA>), dim3((unsigned)tiles), dim3(512), 0, stream, f, out, H, Wd, ld,
+                       piv, coef, taps, K, (float)(K / (kTc + kTh)), W, (unsigned *)(ws + kFlagBytes), tiles_x);
+    return check_launch("k_fused_pivots");
+}
+
+template <class M>
+static bf_status run_fused_pivots(const float *f, float *out, int H, int Wd, int ld, double sigma_s,
+                                  const std::vector<Pivot> &plan, char *ws, hipStream_t stream) {
+    const int W = radius_of(sigma_s), qa = fused_qa(W);
+    const int K = (int)plan.size();
+    const long long tiles = fused_pivot_tiles(H, Wd, W);
+    char *table = ws + kFlagBytes + align256(sizeof(unsigned) * kFusedSlots * (size_t)tiles);
+    // host image of the table
+    std::vector<FusedPivot> piv(K);
+    const std::vector<double> w = spatial_taps(sigma_s);
+    const int ntap = ((2 * W + 1) + 3) & ~3;
+    std::vector<float> coef;
+    const double k2 = std::log2((double)M::kPrescale);
+    for (int k = 0; k < K; ++k) {
+        const Pivot &p = plan[k];
+        const int n1 = p.N + 1;
+        const double lg = n1 <= p.nu ? 0.5 * n1 * std::log(n1 / (std::exp(1.0) * p.nu)) : -0.5 * p.nu;
+        const double c = std::exp(-lg / n1);
+        FusedCentre &C = piv[k].c;
+        C.sb = (float)(c / p.R);
+        C.ob = (float)(-c * p.t / p.R);
+        C.e2 = (float)(-0.5 * p.nu / (c * c) / std::log(2.0));
+        C.k2 = (float)k2;
+        C.sc = (float)(1.0 / p.h);
+        C.oc = (float)(-p.t / p.h);
+        C.ys = (float)(p.R / c);
+        C.yo = (float)p.t;
+        piv[k].lo = (float)p.lo;
+        piv[k].N = p.N;
+        piv[k].boff = (int)coef.size();
+        piv[k].pad = 0;
+        const Fit &F = fit_mu(p.mu, p.N);
+        for (int n = 0; n <= p.N; ++n) coef.push_back((float)(F.b[n] * std::pow(c, -n)));
+        coef.push_back(0.0f);
+    }
+    std::vector<char> bytes(sizeof(FusedPivot) * K + sizeof(float) * (ntap + coef.size()), 0);
+    std::memcpy(bytes.data(), piv.data(), sizeof(FusedPivot) * K);
+    float *tp = (float *)(bytes.data() + sizeof(FusedPivot) * K);
+    for (int t = 0; t <= 2 * W; ++t) tp[t] = (float)w[t];
+    std::memcpy(tp + ntap, coef.data(), sizeof(float) * coef.size());
+    std::vector<double> host((bytes.size() + 7) / 8, 0.0);
+    std::memcpy(host.data(), bytes.data(), bytes.size());
+    bf_status st = upload_vector((double *)table, nullptr, host, false, stream);
+    if (st != BF_OK) return st;
+#define BF_FPIV(Q, TC)                                                                                       \
+    return qa == (Q) - 3 ? launch_fused_pivots_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, table, K, W, ws, stream) \
+                         : launch_fused_pivots_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, table, K, W, ws, stream)
+    if (W <= 16) BF_FPIV(3, 64);
+    if (W <= 32) BF_FPIV(4, 64);
+    if (W <= 48) BF_FPIV(5, 32);
+#undef BF_FPIV
+    return fail(BF_ERR_UNSUPPORTED, "fused path: radius above BF_FUSED_MAX_RADIUS");
 }
 
 // Recursive variant: build, recursive Gaussian along columns (stack A -> B)
@@ -1108,7 +1199,7 @@ size_t bf_gc_pivots_workspace_bytes(int height, int width, double sigma_s, doubl
     const std::vector<Pivot> plan = pivot_plan(sigma_r, K, N, BF_MAX_DEGREE);
     for (const Pivot &p : plan)
         if (p.N < 1) return 0;
-    return pivots_ws_bytes(height, width, radius_of(sigma_s), pivot_nmax(plan), stack_dtype);
+    return pivots_ws_bytes(height, width, radius_of(sigma_s), K, pivot_nmax(plan), stack_dtype);
 }
 
 bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width, int ld, double sigma_s,
@@ -1119,11 +1210,12 @@ bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width
     if (K < 1 || K > BF_MAX_PIVOTS) return fail(BF_ERR_INVALID_ARG, "K out of [1, BF_MAX_PIVOTS]");
     if (N > BF_MAX_DEGREE) return fail(BF_ERR_INVALID_ARG, "degree N above BF_MAX_DEGREE");
     if (flags & (BF_FLAG_TAYLOR | BF_FLAG_MINIMAX | BF_FLAG_STAGED))
-        return fail(BF_ERR_INVALID_ARG, "the pivoted form takes the Chebyshev coefficients, three-kernel tiles only");
+        return fail(BF_ERR_INVALID_ARG, "the pivoted form takes the Chebyshev coefficients and no staged flag");
     int cfg = tile_config_of(flags);
     if (cfg == -2) return fail(BF_ERR_INVALID_ARG, "tile configuration out of range");
-    if (cfg == BF_TILE_FUSED) return fail(BF_ERR_UNSUPPORTED, "the pivoted form runs the three-kernel tiles");
-    if (cfg == -1) cfg = 0;
+    if (cfg == -1) cfg = fused_applies(stack_dtype, sigma_s) ? BF_TILE_FUSED : 0;
+    if (cfg == BF_TILE_FUSED && !fused_applies(stack_dtype, sigma_s))
+        return fail(BF_ERR_UNSUPPORTED, "fused tile: FP16/BF16 stacks with radius <= BF_FUSED_MAX_RADIUS only");
     if (height == 0 || width == 0) return BF_OK;
     if (!f || !out) return fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
     if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
@@ -1142,9 +1234,14 @@ bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width
             }
         }
     }
-    const size_t need = pivots_ws_bytes(height, width, radius_of(sigma_s), pivot_nmax(plan), stack_dtype);
+    const size_t need = pivots_ws_bytes(height, width, radius_of(sigma_s), K, pivot_nmax(plan), stack_dtype);
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
     hipStream_t s = (hipStream_t)stream;
+    if (cfg == BF_TILE_FUSED) {
+        if (stack_dtype == BF_STACK_F16)
+            return run_fused_pivots<MmaF16>(f, out, height, width, ld, sigma_s, plan, (char *)ws, s);
+        return run_fused_pivots<MmaBF16>(f, out, height, width, ld, sigma_s, plan, (char *)ws, s);
+    }
 #define BF_PIV(S, RV, RH) run_pivots<S, RV, RH>(f, out, height, width, ld, sigma_s, plan, stack_dtype, (char *)ws, s)
 #define BF_PIV_CFG(S)                                   \
     switch (cfg) {                                      \

@@ -948,6 +948,23 @@ constexpr int kFusedSlots = 8;    // range words per tile of a single-image fuse
 constexpr int kFusedYElems = kFusedRows * kFusedPitch;
 __host__ __device__ constexpr int fused_tab_len(int Q) { return kFusedTabPad + 32 * Q; }   // t in [-32, 32Q)
 
+// Centring of one expansion in the fused tile (eq. 17 with a centre t and
+// scales): the planes are built from s_j = f_j sb + ob, with 2^K e^{-nu s^2/2}
+// computed as 2^{e2 s_j^2 + k2}; the combine takes s_i = f_i sc + oc and
+// gives y = yo + ys Ps / (s_i Q).
+struct FusedCentre {
+    float sb, ob, e2, k2, sc, oc, ys, yo;
+};
+
+// One sub-range of the pivoted form for the fused tile (device memory):
+// its centring, the lower end lo of [lo, hi) as the selection compares it,
+// the degree N and the offset (floats) of its coefficients, n = 0..N+1.
+struct FusedPivot {
+    FusedCentre c;
+    float lo;
+    int N, boff, pad;
+};
+
 // Fused tile machinery; all 512 threads of the block use it together.
 // setup() makes the Toeplitz fragments of one image (through the LDS tap
 // table tab, fused_tab_len(Q) elements); load() issues the global loads of
@@ -1060,38 +1077,43 @@ struct FusedTile {
         }
     }
 
-    // base: parity of the buffer the tile's plane 0 goes to. A block that
-    // runs tiles back to back continues the alternation (base = planes run
-    // before), so that the next tile's first column pass writes the buffer
-    // the last row pass did not read and needs no barrier before it.
-    __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
-                                        unsigned *__restrict__ slot, int base = 0) {
-        const int P = N + 2;
-        // Column-pass A operand state: s and the running 2^K H_n in FP32 (one
-        // scale 2^K for every plane keeps FP16 planes normal: it cancels in
-        // P/Q), with 2^K e^{-mu s^2/2} = 2^{K - mu log2(e) s^2 / 2}.
-        const float e2 = -0.5f * mu * 1.4426950408889634f, k2 = __log2f(prescale);
-        float sv[Q][8], hv[Q][8];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                const float s = fmaf(R.h[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));   // eq. (17)
-                sv[q][jj] = s;
-                hv[q][jj] = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));                     // 2^K H_0
-            }
-        }
-        // Range check on the lane's own output pixels: every pixel of the
-        // image is the output of exactly one lane of one tile.
+    // Range check on the lane's own output pixels: every pixel of the image
+    // is the output of exactly one lane of one tile.
+    __device__ __forceinline__ void check_range(const Raw &R, unsigned *__restrict__ flag,
+                                                unsigned *__restrict__ slot) const {
         bool bad = false;
 #pragma unroll
         for (int b = 0; b < JB; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) bad |= !(R.c[b][v] >= 0.0f && R.c[b][v] <= 255.0f);
         report_range(bad, flag, slot);
+    }
 
-        // Row-pass outputs of this lane: rows 16 rb + 4 lg + v, columns
-        // 16 (jc0 + b) + li. With u_n = s^n Hbar_n the sums are accumulated as
+    // Filters the N+2 planes of one centring (coefficients bt[n], n = 0..N+1,
+    // with bt[N+1] = 0) and leaves the lane's outputs (rows 16 rb + 4 lg + v,
+    // columns 16 (jc0 + b) + li) in y.
+    // base: parity of the buffer the tile's plane 0 goes to. A block that
+    // runs tiles (or centrings) back to back continues the alternation (base
+    // = planes run before), so that the next first column pass writes the
+    // buffer the last row pass did not read and needs no barrier before it.
+    __device__ __forceinline__ void filter(const Raw &R, const FusedCentre &C, const float *__restrict__ bt, int N,
+                                           int base, float (&y)[JB][4]) {
+        const int P = N + 2;
+        // Column-pass A operand state: s and the running 2^K H_n in FP32 (one
+        // scale 2^K for every plane keeps FP16 planes normal: it cancels in
+        // P/Q), with 2^K e^{-nu s^2/2} = 2^{e2 s^2 + k2}.
+        float sv[Q][8], hv[Q][8];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                const float s = fmaf(R.h[q][jj], C.sb, C.ob);                     // eq. (17)
+                sv[q][jj] = s;
+                hv[q][jj] = __builtin_amdgcn_exp2f(fmaf(C.e2 * s, s, C.k2));      // 2^K H_0
+            }
+        }
+
+        // With u_n = s^n Hbar_n the sums are accumulated as
         //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
         // so one product serves both, and P = Ps / s. Where s = 0 the sums take
         // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
@@ -1103,7 +1125,7 @@ struct FusedTile {
         for (int b = 0; b < JB; ++b) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const float s = fmaf(R.c[b][v], (float)(1.0 / kTh), (float)(-kTc / kTh));
+                const float s = fmaf(R.c[b][v], C.sc, C.oc);
                 sc[b][v] = s != 0.0f ? s : 0x1p-64f;
                 pw[b][v] = sc[b][v];
                 Ps[b][v] = 0.0f;
@@ -1202,16 +1224,96 @@ struct FusedTile {
 
 #pragma unroll
         for (int b = 0; b < JB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // a reduced-precision stack: the reciprocal's ulp is far below its error
+                const float ratio = Ps[b][v] * __frcp_rn(sc[b][v] * Qa[b][v]);
+                y[b][v] = C.yo + C.ys * ratio;                                   // eq. (10)
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(int r0, int c0, const float (&y)[JB][4]) const {
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
             const int c = c0 + 16 * (jc0 + b) + li;
             if (c >= Wd) continue;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int r = r0 + 16 * rb + 4 * lg + v;
-                // a reduced-precision stack: the reciprocal's ulp is far below its error
-                const float ratio = Ps[b][v] * __frcp_rn(sc[b][v] * Qa[b][v]);
-                if (r < H) out[(long long)r * ld + c] = (float)kTc + (float)kTh * ratio;   // eq. (10)
+                if (r < H) out[(long long)r * ld + c] = y[b][v];
             }
         }
+    }
+
+    // The filter of eqs. (6)-(10) centred at t_c with half range t_h.
+    __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
+                                        unsigned *__restrict__ slot, int base = 0) {
+        FusedCentre C;
+        C.sb = C.sc = (float)(1.0 / kTh);
+        C.ob = C.oc = (float)(-kTc / kTh);
+        C.e2 = -0.5f * mu * 1.4426950408889634f;
+        C.k2 = __log2f(prescale);
+        C.ys = (float)kTh;
+        C.yo = (float)kTc;
+        check_range(R, flag, slot);
+        float y[JB][4];
+        filter(R, C, bt, N, base, y);
+        store(r0, c0, y);
+    }
+
+    // Pivoted form: the sub-range of each of the lane's output pixels (the
+    // partition of bf_gc_forward_pivots: k = number of k' >= 1 with
+    // !(f < lo_k'), so NaN goes to the last), the set of sub-ranges present in
+    // the tile (mask, two LDS words cleared before the call and a barrier
+    // later), then the planes of each present sub-range, every pixel keeping
+    // the outputs of its own. lo: the sub-ranges' lower ends in LDS.
+    __device__ __forceinline__ void run_pivots(int r0, int c0, const Raw &R, const FusedPivot *__restrict__ piv,
+                                               const float *__restrict__ coef, int K, float kscale,
+                                               const float *lo, unsigned *mask, unsigned *__restrict__ slot) {
+        check_range(R, nullptr, slot);
+        int kb[JB][4];
+        unsigned long long m = 0;
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float x = R.c[b][v];
+                // first guess from the equal widths, then one step each way
+                // against the exact lower ends
+                int g = x == x ? (int)fminf(fmaxf(x * kscale, 0.0f), (float)(K - 1)) : K - 1;
+                if (g > 0 && x < lo[g]) --g;
+                else if (g < K - 1 && !(x < lo[g + 1])) ++g;
+                kb[b][v] = g;
+                m |= 1ull << g;
+            }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
+        if (lane == 0) {
+            if ((unsigned)m) atomicOr(&mask[0], (unsigned)m);
+            if ((unsigned)(m >> 32)) atomicOr(&mask[1], (unsigned)(m >> 32));
+        }
+        __syncthreads();
+        unsigned long long todo = ((unsigned long long)__builtin_amdgcn_readfirstlane(mask[1]) << 32) |
+                                  (unsigned)__builtin_amdgcn_readfirstlane(mask[0]);
+        float y[JB][4] = {};
+        int base = 0;
+        while (todo) {
+            const int k = __builtin_amdgcn_readfirstlane(__ffsll(todo) - 1);
+            todo &= todo - 1;
+            const FusedPivot &Pk = piv[k];
+            const int Nk = Pk.N;
+            float yk[JB][4];
+            filter(R, Pk.c, coef + Pk.boff, Nk, base, yk);
+            base += Nk + 2;
+#pragma unroll
+            for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (kb[b][v] == k) y[b][v] = yk[b][v];
+        }
+        store(r0, c0, y);
     }
 };
 
@@ -1256,6 +1358,32 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
             base += N + 2;
         }
     }
+}
+
+// Pivoted form on the fused tile: one block per 64 x TC tile. piv: K
+// sub-ranges; coef: their coefficients; taps: w[t], t = 0..2W (all in device
+// memory). kscale = K / 255 gives the first guess of a pixel's sub-range.
+template <class M, int Q, int TC, int QA>
+__global__ __launch_bounds__(512) void k_fused_pivots(const float *__restrict__ f, float *__restrict__ out, int H,
+                                                      int Wd, int ld, const FusedPivot *__restrict__ piv,
+                                                      const float *__restrict__ coef, const float *__restrict__ taps,
+                                                      int K, float kscale, int W, unsigned *__restrict__ slots,
+                                                      int tiles_x) {
+    typedef typename M::E E;
+    typedef FusedTile<M, Q, TC, QA> T;
+    __shared__ __align__(16) E ybuf[2 * kFusedYElems];
+    __shared__ E tab[fused_tab_len(Q)];
+    __shared__ float s_lo[BF_MAX_PIVOTS];
+    __shared__ unsigned s_mask[2];
+    T tile(f, out, H, Wd, ld, W, 0, 0.0f, M::kPrescale, nullptr, ybuf);
+    for (int i = threadIdx.x; i < K; i += blockDim.x) s_lo[i] = piv[i].lo;
+    if (threadIdx.x < 2) s_mask[threadIdx.x] = 0u;
+    tile.setup(taps, tab);                     // its barrier also publishes s_lo and s_mask
+    const int t = blockIdx.x;
+    const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
+    typename T::Raw raw;
+    tile.load(r0, c0, raw);
+    tile.run_pivots(r0, c0, raw, piv, coef, K, kscale, s_lo, s_mask, slots + kFusedSlots * t);
 }
 
 // Joint filter on the matrix cores: the plain tile's schedule with two operand
