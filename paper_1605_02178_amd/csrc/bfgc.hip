@@ -423,7 +423,8 @@ static int pivot_nmax(const std::vector<Pivot> &plan) {
 }
 
 // Fused pivoted form: the range words of the tiles, then the sub-range table
-// (K FusedPivot entries, the taps, the coefficients of every sub-range).
+// (K FusedPivot entries, the taps, the coefficients of every sub-range), the
+// tiles' sub-range masks, their order and the queue counter.
 static long long fused_pivot_tiles(int H, int Wd, int W) {
     const int TC = W <= 32 ? 64 : 32;
     return (long long)((Wd + TC - 1) / TC) * ((H + kFusedRows - 1) / kFusedRows);
@@ -437,8 +438,10 @@ static size_t pivots_ws_bytes(int H, int Wd, int W, int K, int Nmax, int dtype) 
     const size_t P = (size_t)Nmax + 2;
     const size_t staged = kFlagBytes + align256(sizeof(double) * (size_t)param_layout(W, Nmax).total) +
                           align256(P * H * lds_of(Wd) * esize(dtype)) + align256(P * Wd * ldt_of(H) * esize(dtype));
-    const size_t fused = kFlagBytes + align256(sizeof(unsigned) * kFusedSlots * (size_t)fused_pivot_tiles(H, Wd, W)) +
-                         align256(fused_pivot_table_bytes(K, W, Nmax));
+    const size_t tiles = (size_t)fused_pivot_tiles(H, Wd, W);
+    const size_t fused = kFlagBytes + align256(sizeof(unsigned) * kFusedSlots * tiles) +
+                         align256(fused_pivot_table_bytes(K, W, Nmax)) + align256(sizeof(unsigned long long) * tiles) +
+                         align256(sizeof(int) * tiles) + 256;
     return std::max(staged, fused);
 }
 
@@ -486,18 +489,37 @@ static bf_status run_pivots(const float *f, float *out, int H, int Wd, int ld, d
 // scale per plane. c^{-n} goes into the coefficients (b_n c^{-n}, so the
 // combine's Ps comes out c times too large) and 1/c into the output scale.
 template <class M, int Q, int TC, int QA>
-static bf_status launch_fused_pivots_q(const float *f, float *out, int H, int Wd, int ld, const char *table, int K,
-                                       int W, char *ws, hipStream_t stream) {
+static bf_status launch_fused_pivots_q(const float *f, float *out, int H, int Wd, int ld, char *table,
+                                       size_t table_bytes, int K, int W, char *ws, hipStream_t stream) {
+    static int resident = 0;
+    const void *kernel = (const void *)k_fused_pivots<M, Q, TC, QA>;
     const int tiles_x = (Wd + TC - 1) / TC;
     const long long tiles = (long long)tiles_x * ((H + kFusedRows - 1) / kFusedRows);
     if (tiles > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused path: too many tiles");
     const FusedPivot *piv = (const FusedPivot *)table;
     const float *taps = (const float *)(table + sizeof(FusedPivot) * K);
     const float *coef = taps + (((2 * W + 1) + 3) & ~3);
+    unsigned long long *masks = (unsigned long long *)(table + align256(table_bytes));
+    int *order = (int *)((char *)masks + align256(sizeof(unsigned long long) * tiles));
+    int *counter = (int *)((char *)order + align256(sizeof(int) * tiles));
+    const float kscale = (float)(K / (kTc + kTh));
     note_range_words(ws, kFusedSlots * tiles);
+    {
+        ProfScope prof_("k_pivot_masks", stream);
+        hipLaunchKernelGGL((k_pivot_masks<TC>), dim3((unsigned)tiles), dim3(256), 0, stream, f, H, Wd, ld, piv, K,
+                           kscale, tiles_x, masks);
+    }
+    bf_status st = check_launch("k_pivot_masks");
+    if (st != BF_OK) return st;
+    {
+        ProfScope prof_("k_pivot_order", stream);
+        hipLaunchKernelGGL(k_pivot_order, dim3(1), dim3(1024), 0, stream, masks, (int)tiles, order, counter);
+    }
+    if ((st = check_launch("k_pivot_order")) != BF_OK) return st;
+    const int grid = (int)std::min<long long>(tiles, resident_blocks(kernel, &resident));
     ProfScope prof_("k_fused_pivots", stream);
-    hipLaunchKernelGGL((k_fused_pivots<M, Q, TC, QA>), dim3((unsigned)tiles), dim3(512), 0, stream, f, out, H, Wd, ld,
-                       piv, coef, taps, K, (float)(K / (kTc + kTh)), W, (unsigned *)(ws + kFlagBytes), tiles_x);
+    hipLaunchKernelGGL((k_fused_pivots<M, Q, TC, QA>), dim3(grid), dim3(512), 0, stream, f, out, H, Wd, ld, piv, coef,
+                       taps, K, kscale, W, (unsigned *)(ws + kFlagBytes), tiles_x, (int)tiles, masks, order, counter);
     return check_launch("k_fused_pivots");
 }
 
@@ -545,9 +567,10 @@ static bf_status run_fused_pivots(const float *f, float *out, int H, int Wd, int
     std::memcpy(host.data(), bytes.data(), bytes.size());
     bf_status st = upload_vector((double *)table, nullptr, host, false, stream);
     if (st != BF_OK) return st;
-#define BF_FPIV(Q, TC)                                                                                       \
-    return qa == (Q) - 3 ? launch_fused_pivots_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, table, K, W, ws, stream) \
-                         : launch_fused_pivots_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, table, K, W, ws, stream)
+    const size_t tb = bytes.size();
+#define BF_FPIV(Q, TC)                                                                                           \
+    return qa == (Q) - 3 ? launch_fused_pivots_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, table, tb, K, W, ws, stream) \
+                         : launch_fused_pivots_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, table, tb, K, W, ws, stream)
     if (W <= 16) BF_FPIV(3, 64);
     if (W <= 32) BF_FPIV(4, 64);
     if (W <= 48) BF_FPIV(5, 32);

@@ -965,6 +965,17 @@ struct FusedPivot {
     int N, boff, pad;
 };
 
+// Sub-range of a centre value x among K equal sub-ranges with lower ends
+// lo[k] (the partition of the pivoted form: the number of k >= 1 with
+// !(x < lo[k]), so NaN goes to the last): a first guess from the equal widths
+// (kscale = K / 255), then one step each way against the exact ends.
+__device__ __forceinline__ int pivot_of(float x, const float *lo, int K, float kscale) {
+    int g = x == x ? (int)fminf(fmaxf(x * kscale, 0.0f), (float)(K - 1)) : K - 1;
+    if (g > 0 && x < lo[g]) --g;
+    else if (g < K - 1 && !(x < lo[g + 1])) ++g;
+    return g;
+}
+
 // Fused tile machinery; all 512 threads of the block use it together.
 // setup() makes the Toeplitz fragments of one image (through the LDS tap
 // table tab, fused_tab_len(Q) elements); load() issues the global loads of
@@ -1262,43 +1273,22 @@ struct FusedTile {
         store(r0, c0, y);
     }
 
-    // Pivoted form: the sub-range of each of the lane's output pixels (the
-    // partition of bf_gc_forward_pivots: k = number of k' >= 1 with
-    // !(f < lo_k'), so NaN goes to the last), the set of sub-ranges present in
-    // the tile (mask, two LDS words cleared before the call and a barrier
-    // later), then the planes of each present sub-range, every pixel keeping
-    // the outputs of its own. lo: the sub-ranges' lower ends in LDS.
+    // Pivoted form: the sub-range of each of the lane's output pixels
+    // (pivot_of), then the planes of each sub-range in the tile's mask (every
+    // sub-range some output pixel of the tile falls in, uniform), every pixel
+    // keeping the outputs of its own. lo: the sub-ranges' lower ends in LDS;
+    // base: buffer parity, continued from tile to tile.
     __device__ __forceinline__ void run_pivots(int r0, int c0, const Raw &R, const FusedPivot *__restrict__ piv,
                                                const float *__restrict__ coef, int K, float kscale,
-                                               const float *lo, unsigned *mask, unsigned *__restrict__ slot) {
+                                               const float *lo, unsigned long long todo,
+                                               unsigned *__restrict__ slot, int &base) {
         check_range(R, nullptr, slot);
         int kb[JB][4];
-        unsigned long long m = 0;
 #pragma unroll
-        for (int b = 0; b < JB; ++b) {
+        for (int b = 0; b < JB; ++b)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float x = R.c[b][v];
-                // first guess from the equal widths, then one step each way
-                // against the exact lower ends
-                int g = x == x ? (int)fminf(fmaxf(x * kscale, 0.0f), (float)(K - 1)) : K - 1;
-                if (g > 0 && x < lo[g]) --g;
-                else if (g < K - 1 && !(x < lo[g + 1])) ++g;
-                kb[b][v] = g;
-                m |= 1ull << g;
-            }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
-        if (lane == 0) {
-            if ((unsigned)m) atomicOr(&mask[0], (unsigned)m);
-            if ((unsigned)(m >> 32)) atomicOr(&mask[1], (unsigned)(m >> 32));
-        }
-        __syncthreads();
-        unsigned long long todo = ((unsigned long long)__builtin_amdgcn_readfirstlane(mask[1]) << 32) |
-                                  (unsigned)__builtin_amdgcn_readfirstlane(mask[0]);
+            for (int v = 0; v < 4; ++v) kb[b][v] = pivot_of(R.c[b][v], lo, K, kscale);
         float y[JB][4] = {};
-        int base = 0;
         while (todo) {
             const int k = __builtin_amdgcn_readfirstlane(__ffsll(todo) - 1);
             todo &= todo - 1;
@@ -1360,30 +1350,114 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
     }
 }
 
-// Pivoted form on the fused tile: one block per 64 x TC tile. piv: K
-// sub-ranges; coef: their coefficients; taps: w[t], t = 0..2W (all in device
-// memory). kscale = K / 255 gives the first guess of a pixel's sub-range.
+// Pivoted form on the fused tile, in three launches.
+// k_pivot_masks: the mask of the sub-ranges present among each tile's output
+// pixels (one block of 256 threads per tile).
+template <int TC>
+__global__ __launch_bounds__(256) void k_pivot_masks(const float *__restrict__ f, int H, int Wd, int ld,
+                                                     const FusedPivot *__restrict__ piv, int K, float kscale,
+                                                     int tiles_x, unsigned long long *__restrict__ masks) {
+    __shared__ float s_lo[BF_MAX_PIVOTS];
+    __shared__ unsigned s_mask[2];
+    for (int i = threadIdx.x; i < K; i += blockDim.x) s_lo[i] = piv[i].lo;
+    if (threadIdx.x < 2) s_mask[threadIdx.x] = 0u;
+    __syncthreads();
+    const int t = blockIdx.x;
+    const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
+    const int rows = min(kFusedRows, H - r0), cols = min(TC, Wd - c0);
+    unsigned long long m = 0;
+    for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) {
+        const int r = r0 + i / cols, c = c0 + i % cols;
+        m |= 1ull << pivot_of(f[(long long)r * ld + c], s_lo, K, kscale);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
+    if ((threadIdx.x & 63) == 0) {
+        if ((unsigned)m) atomicOr(&s_mask[0], (unsigned)m);
+        if ((unsigned)(m >> 32)) atomicOr(&s_mask[1], (unsigned)(m >> 32));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) masks[t] = ((unsigned long long)s_mask[1] << 32) | s_mask[0];
+}
+
+// k_pivot_order (one block of 1024 threads): the tiles ordered by the number
+// of sub-ranges they run, most first (a counting sort; order within a count
+// is arbitrary and does not change any output), and the queue counter reset.
+__global__ __launch_bounds__(1024) void k_pivot_order(const unsigned long long *__restrict__ masks, int tiles,
+                                                      int *__restrict__ order, int *__restrict__ counter) {
+    __shared__ int s_cnt[BF_MAX_PIVOTS + 1];
+    for (int i = threadIdx.x; i <= BF_MAX_PIVOTS; i += blockDim.x) s_cnt[i] = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x) atomicAdd(&s_cnt[__popcll(masks[t])], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int at = 0;
+        for (int c = BF_MAX_PIVOTS; c >= 0; --c) {
+            const int n = s_cnt[c];
+            s_cnt[c] = at;
+            at += n;
+        }
+        *counter = 0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < tiles; t += blockDim.x) order[atomicAdd(&s_cnt[__popcll(masks[t])], 1)] = t;
+}
+
+// k_fused_pivots: persistent blocks take tiles from the queue (order,
+// counter) and run each one's sub-ranges (FusedTile::run_pivots). Where the
+// registers allow (Q <= 4) a block loads the next tile's inputs while the
+// current one runs. piv: K sub-ranges; coef: their coefficients; taps: w[t],
+// t = 0..2W (all in device memory).
 template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_pivots(const float *__restrict__ f, float *__restrict__ out, int H,
                                                       int Wd, int ld, const FusedPivot *__restrict__ piv,
                                                       const float *__restrict__ coef, const float *__restrict__ taps,
                                                       int K, float kscale, int W, unsigned *__restrict__ slots,
-                                                      int tiles_x) {
+                                                      int tiles_x, int tiles,
+                                                      const unsigned long long *__restrict__ masks,
+                                                      const int *__restrict__ order, int *__restrict__ counter) {
     typedef typename M::E E;
     typedef FusedTile<M, Q, TC, QA> T;
+    constexpr bool kPrefetch = Q <= 4;
     __shared__ __align__(16) E ybuf[2 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
     __shared__ float s_lo[BF_MAX_PIVOTS];
-    __shared__ unsigned s_mask[2];
+    __shared__ int s_ticket[2];
     T tile(f, out, H, Wd, ld, W, 0, 0.0f, M::kPrescale, nullptr, ybuf);
     for (int i = threadIdx.x; i < K; i += blockDim.x) s_lo[i] = piv[i].lo;
-    if (threadIdx.x < 2) s_mask[threadIdx.x] = 0u;
-    tile.setup(taps, tab);                     // its barrier also publishes s_lo and s_mask
-    const int t = blockIdx.x;
-    const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
-    typename T::Raw raw;
-    tile.load(r0, c0, raw);
-    tile.run_pivots(r0, c0, raw, piv, coef, K, kscale, s_lo, s_mask, slots + kFusedSlots * t);
+    // Ticket slot j & 1 is written at the top of step j and read after the
+    // barrier that follows; the tile's own barriers separate those reads
+    // from the write of step j + 2.
+    if (threadIdx.x == 0) s_ticket[0] = atomicAdd(counter, 1);
+    tile.setup(taps, tab);                     // its barrier also publishes s_lo and s_ticket[0]
+    int ticket = __builtin_amdgcn_readfirstlane(s_ticket[0]);
+    if (ticket >= tiles) return;
+    int t = __builtin_amdgcn_readfirstlane(order[ticket]);
+    typename T::Raw cur;
+    tile.load((t / tiles_x) * kFusedRows, (t % tiles_x) * TC, cur);
+    int base = 0;
+    for (int step = 1;; ++step) {
+        if (threadIdx.x == 0) s_ticket[step & 1] = atomicAdd(counter, 1);
+        __syncthreads();
+        ticket = __builtin_amdgcn_readfirstlane(s_ticket[step & 1]);
+        const int tn = ticket < tiles ? __builtin_amdgcn_readfirstlane(order[ticket]) : -1;
+        const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
+        const unsigned long long m = masks[t];
+        const unsigned long long todo =
+            ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(m >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((unsigned)m);
+        if constexpr (kPrefetch) {
+            typename T::Raw next;
+            if (tn >= 0) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, next);
+            tile.run_pivots(r0, c0, cur, piv, coef, K, kscale, s_lo, todo, slots + kFusedSlots * t, base);
+            cur = next;
+        } else {
+            tile.run_pivots(r0, c0, cur, piv, coef, K, kscale, s_lo, todo, slots + kFusedSlots * t, base);
+            if (tn >= 0) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, cur);
+        }
+        if (tn < 0) break;
+        t = tn;
+    }
 }
 
 // Joint filter on the matrix cores: the plain tile's schedule with two operand
