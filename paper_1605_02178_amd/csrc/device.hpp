@@ -1364,12 +1364,16 @@ __global__ __launch_bounds__(256) void k_pivot_masks(const float *__restrict__ f
     __syncthreads();
     const int t = blockIdx.x;
     const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
-    const int rows = min(kFusedRows, H - r0), cols = min(TC, Wd - c0);
+    // thread i takes column i % TC of rows i / TC + (256 / TC) j; all loads
+    // first, then the classification
+    constexpr int kRowsPer = 256 / TC, kSteps = kFusedRows / kRowsPer;
+    const int c = min(c0 + (int)threadIdx.x % TC, Wd - 1), rr = threadIdx.x / TC;
+    float x[kSteps];
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) x[j] = f[(long long)min(r0 + rr + kRowsPer * j, H - 1) * ld + c];
     unsigned long long m = 0;
-    for (int i = threadIdx.x; i < rows * cols; i += blockDim.x) {
-        const int r = r0 + i / cols, c = c0 + i % cols;
-        m |= 1ull << pivot_of(f[(long long)r * ld + c], s_lo, K, kscale);
-    }
+#pragma unroll
+    for (int j = 0; j < kSteps; ++j) m |= 1ull << pivot_of(x[j], s_lo, K, kscale);
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
     if ((threadIdx.x & 63) == 0) {
