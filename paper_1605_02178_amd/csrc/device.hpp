@@ -401,6 +401,7 @@ struct BatchHeader {
     unsigned flags;            // BF_DEVFLAG_RANGE from the builds
     int count;                 // images
     long long items[kBatchPhases];   // items in each phase
+    long long queue[kBatchPhases];   // fused form: next item of each class (zero in every upload)
 };
 // device blob: BatchHeader | BatchImage[count] | long long start[6][count] |
 //              int order[6][count] | parameter blocks
@@ -1683,18 +1684,23 @@ __host__ __device__ constexpr int fused_class_of_radius(int W) {
     return W <= 16 ? fused_class(3, fused_qa(W)) : W <= 32 ? fused_class(4, fused_qa(W)) : fused_class(5, fused_qa(W));
 }
 
-// Batched fused kernel for one geometry class: blocks stride over the class's
-// (image, tile) items, decoded as in k_batched; the tiles are the
-// single-image kernel's, so every image matches its bf_gc_forward result bit
-// for bit.
+// Batched fused kernel for one geometry class: persistent blocks take the
+// class's (image, tile) items from a queue (the header's counter, in the
+// order of the item numbering: images by decreasing cost), load the next
+// item's inputs while the current one runs, and rebuild the tap fragments
+// only when the image changes. Items are decoded as in k_batched; the tiles
+// are the single-image kernel's, so every image matches its bf_gc_forward
+// result bit for bit.
 template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) {
     typedef typename M::E E;
+    typedef FusedTile<M, Q, TC, QA> T;
     constexpr int C = fused_class(Q, QA);
     const float prescale = M::kPrescale;
     extern __shared__ long long s_start[];
     __shared__ __align__(16) E ybuf[2 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
+    __shared__ long long s_ticket[2];
     BatchHeader *hdr = (BatchHeader *)blob;
     const BatchImage *img = (const BatchImage *)(blob + sizeof(BatchHeader));
     const int count = hdr->count;
@@ -1705,9 +1711,21 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
         s_start[k] = start[C * count + k];
         s_order[k] = order[C * count + k];
     }
-    __syncthreads();
     const long long items = hdr->items[C];
-    for (long long t = blockIdx.x; t < items; t += gridDim.x) {
+    long long *queue = &hdr->queue[C];
+    unsigned *flags = as_global(&hdr->flags);
+    // Ticket slot j & 1 is written at the top of step j and read after the
+    // barrier that follows; the item's own barriers separate those reads
+    // from the write of step j + 2.
+    if (threadIdx.x == 0) s_ticket[0] = (long long)atomicAdd((unsigned long long *)queue, 1ull);
+    __syncthreads();
+    auto ticket_of = [&](int slot) {
+        const long long v = s_ticket[slot];
+        return ((long long)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+               (unsigned)__builtin_amdgcn_readfirstlane((int)v);
+    };
+    // item t -> image (uniform) and its tile
+    auto decode = [&](long long t, int &ii, int &r0, int &c0) {
         int lo = 0, hi = count - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -1715,19 +1733,53 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
             else hi = mid - 1;
         }
         lo = __builtin_amdgcn_readfirstlane(lo);
-        const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
-        const BatchImage &B = img[ii];
+        ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
         const int l = (int)(t - s_start[lo]);
-        const int bx = l % B.gvx, by = l / B.gvx;
+        const int gvx = uniform(img[ii].gvx);
+        r0 = (l / gvx) * kFusedRows;
+        c0 = (l % gvx) * TC;
+    };
+    auto make = [&](int ii) {
+        const BatchImage &B = img[ii];
         const double *prm = as_global(uniform(B.prm));
-        FusedTile<M, Q, TC, QA> tile(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd),
-                                     uniform(B.ld), uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale,
-                                     (const float *)(prm + uniform(B.off_bf)), ybuf);
-        tile.setup((const float *)(prm + uniform(B.off_tf)), tab);
-        typename FusedTile<M, Q, TC, QA>::Raw raw;
-        tile.load(by * kFusedRows, bx * TC, raw);
-        tile.run(by * kFusedRows, bx * TC, raw, as_global(&hdr->flags), nullptr);
-        __syncthreads();          // the next item rewrites the tap table and buffer 0
+        return T(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd), uniform(B.ld),
+                 uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale, (const float *)(prm + uniform(B.off_bf)),
+                 ybuf);
+    };
+    auto taps_of = [&](int ii) {
+        const double *prm = as_global(uniform(img[ii].prm));
+        return (const float *)(prm + uniform(img[ii].off_tf));
+    };
+    long long t = ticket_of(0);
+    if (t >= items) return;
+    int ii, r0, c0;
+    decode(t, ii, r0, c0);
+    T tile = make(ii);
+    tile.setup(taps_of(ii), tab);
+    typename T::Raw cur;
+    tile.load(r0, c0, cur);
+    int base = 0;
+    for (int step = 1;; ++step) {
+        if (threadIdx.x == 0) s_ticket[step & 1] = (long long)atomicAdd((unsigned long long *)queue, 1ull);
+        __syncthreads();
+        const long long tn = ticket_of(step & 1);
+        int ni = -1, nr0 = 0, nc0 = 0;
+        typename T::Raw next;
+        if (tn < items) {
+            decode(tn, ni, nr0, nc0);
+            make(ni).load(nr0, nc0, next);
+        }
+        tile.run(r0, c0, cur, flags, nullptr, base);
+        base += tile.N + 2;
+        if (tn >= items) break;
+        if (ni != ii) {
+            tile = make(ni);
+            tile.setup(taps_of(ni), tab);       // its barrier: every wave has read the old fragments long before
+            ii = ni;
+        }
+        cur = next;
+        r0 = nr0;
+        c0 = nc0;
     }
 }
 
