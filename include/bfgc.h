@@ -203,8 +203,9 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
  * FP16/BF16 stacks with radius <= BF_FUSED_MAX_RADIUS; otherwise
  * BF_ERR_UNSUPPORTED) the sub-ranges run on the fused matrix-core tile
  * instead, each 64-row tile only those its own output pixels fall in, with
- * the same partition; the workspace then holds the range words and the
- * sub-range table.
+ * the same partition; the workspace then holds the range words, the
+ * sub-range table, the tiles' sub-range masks, their order and a queue
+ * counter (three launches after the table upload: masks, order, filter).
  *   K: sub-ranges, 1..BF_MAX_PIVOTS (K = 1 is the plain expansion)
  *   N: the degree of every sub-range, or <= 0 for the degree rule at mu_k
  *   other arguments as bf_gc_forward (Chebyshev coefficients only:
