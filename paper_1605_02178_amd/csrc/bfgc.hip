@@ -1054,6 +1054,15 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
 }
 
 // Fused FP16/BF16 form: one persistent kernel per non-empty geometry class.
+// The batched fused kernel of a class: the two-blocks-per-CU form for FP16
+// with Q <= 4 (112-128 VGPRs; BF16 would spill there), else the persistent
+// prefetching form.
+template <class M, int Q, int TC, int QA>
+static const void *batched_fused_kernel() {
+    if constexpr (M::kHalfPlanes && Q <= 4) return (const void *)k_fused_batched2<M, Q, TC, QA>;
+    else return (const void *)k_fused_batched<M, Q, TC, QA>;
+}
+
 template <class M>
 static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dtype, unsigned flags, int *status,
                                    char *ws, size_t ws_bytes, hipStream_t stream) {
@@ -1063,9 +1072,9 @@ static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dt
     if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
     if (B.items == 0) return BF_OK;
     const void *cls[kBatchPhases] = {
-        (const void *)k_fused_batched<M, 3, 64, 0>, (const void *)k_fused_batched<M, 3, 64, 1>,
-        (const void *)k_fused_batched<M, 4, 64, 1>, (const void *)k_fused_batched<M, 4, 64, 2>,
-        (const void *)k_fused_batched<M, 5, 32, 2>, (const void *)k_fused_batched<M, 5, 32, 3>};
+        batched_fused_kernel<M, 3, 64, 0>(), batched_fused_kernel<M, 3, 64, 1>(),
+        batched_fused_kernel<M, 4, 64, 1>(), batched_fused_kernel<M, 4, 64, 2>(),
+        batched_fused_kernel<M, 5, 32, 2>(), batched_fused_kernel<M, 5, 32, 3>()};
     BatchKernels K;
     K.block = 512;
     K.lds = batch_lds_bytes((int)B.img.size());
