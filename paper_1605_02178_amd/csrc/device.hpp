@@ -1579,17 +1579,29 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
             }
         }
     }
-    // s (eq. 17 on the guide) by one fma, 2^K e^{-mu s^2/2} by one exp2
+    // s (eq. 17 on the guide) by one fma, 2^K e^{-mu s^2/2} by one exp2. FP16
+    // (kHalfPlanes, as in FusedTile::filter): s, ft and the running A_n held
+    // in FP16, A_{n+1} = A_n s and B_n = A_n ft as packed FP16 products.
+    constexpr bool kH16 = M::kHalfPlanes;
     const float e2 = -0.5f * mu * 1.4426950408889634f, k2 = __log2f(prescale);
-    float sv[Q][8], hv[Q][8], fv[Q][8];
+    float sv[kH16 ? 1 : Q][8], hv[kH16 ? 1 : Q][8], fv[kH16 ? 1 : Q][8];
+    V sv16[kH16 ? Q : 1], hv16[kH16 ? Q : 1], fv16[kH16 ? Q : 1];
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
             const float s = fmaf(gx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
-            sv[q][jj] = s;
-            hv[q][jj] = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));
-            fv[q][jj] = fmaf(vx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
+            const float h0 = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));
+            const float ft = fmaf(vx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
+            if constexpr (kH16) {
+                sv16[q][jj] = M::cvt(s);
+                hv16[q][jj] = M::cvt(h0);
+                fv16[q][jj] = M::cvt(ft);
+            } else {
+                sv[q][jj] = s;
+                hv[q][jj] = h0;
+                fv[q][jj] = ft;
+            }
         }
     // range check on the lane's own output pixels (each image pixel is one)
     bool bad = false;
@@ -1616,11 +1628,17 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
         V a[Q], bo[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
+            if constexpr (kH16) {
+                a[q] = hv16[q];
+                bo[q] = hv16[q] * fv16[q];
+                hv16[q] = hv16[q] * sv16[q];
+            } else {
 #pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                a[q][jj] = M::cvt(hv[q][jj]);
-                bo[q][jj] = M::cvt(hv[q][jj] * fv[q][jj]);
-                hv[q][jj] *= sv[q][jj];
+                for (int jj = 0; jj < 8; ++jj) {
+                    a[q][jj] = M::cvt(hv[q][jj]);
+                    bo[q][jj] = M::cvt(hv[q][jj] * fv[q][jj]);
+                    hv[q][jj] *= sv[q][jj];
+                }
             }
         }
         E *ya = ybuf_base + (2 * (n & 1)) * kFusedYElems;
