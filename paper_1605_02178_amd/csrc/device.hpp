@@ -1334,16 +1334,19 @@ struct FusedTile {
 
 // Whether the single-image fused kernel of a geometry is persistent with
 // prefetch (see k_fused_mfma): where one block per tile would not fit two
-// blocks per CU anyway (Q = 5; Q = 4 with the FP32 plane state of BF16).
+// blocks per CU anyway (FP16: Q = 5 with QA = 3, 135 VGPRs; BF16, with its
+// FP32 plane state: Q >= 4).
 template <class M>
-__host__ __device__ constexpr bool fused_persistent(int Q) { return Q >= 5 || (Q == 4 && !M::kHalfPlanes); }
+__host__ __device__ constexpr bool fused_persistent(int Q, int QA) {
+    return M::kHalfPlanes ? (Q == 5 && QA == 3) : Q >= 4;
+}
 
 // Single-image fused kernel over the tiles_x-wide grid of 64 x TC tiles.
 // Where a block needs more than 128 VGPRs (one block per CU) it is
 // persistent: block b takes tiles b, b + grid, ..., makes the fragments once,
 // and loads the inputs of its next tile while the current one runs, so that
 // no block waits for its halo at the start of a tile. Where one block per
-// tile fits in 128 (FP16 with Q <= 4, BF16 with Q = 3: 92-124 VGPRs) the
+// tile fits in 128 (FP16 but for W > 40, BF16 with Q = 3: 92-126 VGPRs) the
 // registers of that prefetch would cost the second block per CU, which hides
 // those loads instead (and runs the other block's VALU work beside this
 // one's matrix-core work): one block per tile.
@@ -1358,7 +1361,7 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
     __shared__ E tab[fused_tab_len(Q)];
     T tile(f, out, H, Wd, ld, W, N, mu, prescale, C.b, ybuf);
     tile.setup(C.taps, tab);
-    if constexpr (!fused_persistent<M>(Q)) {
+    if constexpr (!fused_persistent<M>(Q, QA)) {
         const int t = blockIdx.x;
         const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
         typename T::Raw cur;
