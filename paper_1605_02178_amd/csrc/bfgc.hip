@@ -1055,11 +1055,11 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
 
 // Fused FP16/BF16 form: one persistent kernel per non-empty geometry class.
 // The batched fused kernel of a class: the two-blocks-per-CU form for FP16
-// with Q <= 4 (112-128 VGPRs; BF16 would spill there), else the persistent
-// prefetching form.
+// up to W = 40 (112-128 VGPRs; FP16 above W = 40 and BF16 would spill
+// there), else the persistent prefetching form.
 template <class M, int Q, int TC, int QA>
 static const void *batched_fused_kernel() {
-    if constexpr (M::kHalfPlanes && Q <= 4) return (const void *)k_fused_batched2<M, Q, TC, QA>;
+    if constexpr (M::kHalfPlanes && (Q <= 4 || QA == 2)) return (const void *)k_fused_batched2<M, Q, TC, QA>;
     else return (const void *)k_fused_batched<M, Q, TC, QA>;
 }
 

@@ -1013,7 +1013,6 @@ struct FusedTile {
     int lane, wave, li, lg, rb, p, jc0;
     bool one_ref;
     V tf[2 * Q];
-    V rf[TC == 32 ? 4 : 1];
 
     __device__ __forceinline__ FusedTile(const float *f_, float *out_, int H_, int Wd_, int ld_, int W_, int N_,
                                          float mu_, float prescale_, const float *bt_, E *ybuf_)
@@ -1026,8 +1025,8 @@ struct FusedTile {
         // Row-pass assignment: row block rb = wave / 2. With 64-column tiles
         // the wave takes column blocks 2p, 2p+1 (p = wave & 1), which read the
         // halo chunks shifted by p and use the fragments of blocks 0, 1. With
-        // 32-column tiles it takes block jc = p and uses that block's
-        // fragments rf[q].
+        // 32-column tiles it takes block jc = p, whose fragment for chunk q,
+        // w[32q + 8lg + jj - 16p - li], is tf[2q + 1 - p].
         rb = wave >> 1;
         p = wave & 1;
         jc0 = p * JB;
@@ -1048,12 +1047,6 @@ struct FusedTile {
         for (int d = -1; d < 2 * Q - 1; ++d)
 #pragma unroll
             for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = tab[kTabPad + 16 * d + 8 * lg + jj - li];
-        if (TC == 32) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int jj = 0; jj < 8; ++jj) rf[q][jj] = tab[kTabPad + 32 * q + 8 * lg + jj - 16 * p - li];
-        }
     }
 
     __device__ __forceinline__ void load(int r0, int c0, Raw &R) const {
@@ -1208,9 +1201,15 @@ struct FusedTile {
                 z[0] = acc0;
                 z[JB - 1] = acc1;
             } else {
+                // p is uniform: one branch per wave, no fragment selected per lane
                 mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                if (p == 0) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), rf[q], acc);
+                    for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q + 1], acc);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q], acc);
+                }
                 z[0] = acc;
             }
         };
@@ -1334,11 +1333,12 @@ struct FusedTile {
 
 // Whether the single-image fused kernel of a geometry is persistent with
 // prefetch (see k_fused_mfma): where one block per tile would not fit two
-// blocks per CU anyway (FP16: Q = 5 with QA = 3, 135 VGPRs; BF16, with its
-// FP32 plane state: Q >= 4).
+// blocks per CU anyway (BF16, with its FP32 plane state, at Q >= 4; FP16
+// fits everywhere, 92-126 VGPRs).
 template <class M>
 __host__ __device__ constexpr bool fused_persistent(int Q, int QA) {
-    return M::kHalfPlanes ? (Q == 5 && QA == 3) : Q >= 4;
+    (void)QA;
+    return !M::kHalfPlanes && Q >= 4;
 }
 
 // Single-image fused kernel over the tiles_x-wide grid of 64 x TC tiles.
@@ -1346,7 +1346,7 @@ __host__ __device__ constexpr bool fused_persistent(int Q, int QA) {
 // persistent: block b takes tiles b, b + grid, ..., makes the fragments once,
 // and loads the inputs of its next tile while the current one runs, so that
 // no block waits for its halo at the start of a tile. Where one block per
-// tile fits in 128 (FP16 but for W > 40, BF16 with Q = 3: 92-126 VGPRs) the
+// tile fits in 128 (FP16, and BF16 with Q = 3: 92-126 VGPRs) the
 // registers of that prefetch would cost the second block per CU, which hides
 // those loads instead (and runs the other block's VALU work beside this
 // one's matrix-core work): one block per tile.
@@ -1734,8 +1734,8 @@ __host__ __device__ constexpr int fused_class_of_radius(int W) {
     return W <= 16 ? fused_class(3, fused_qa(W)) : W <= 32 ? fused_class(4, fused_qa(W)) : fused_class(5, fused_qa(W));
 }
 
-// Batched fused kernel for the other geometry classes (FP16 with Q = 5, every
-// BF16 class): persistent blocks take the class's (image, tile) items from
+// Batched fused kernel for the other geometry classes (FP16 above W = 40,
+// every BF16 class): persistent blocks take the class's (image, tile) items from
 // a queue (the header's counter, in the order of the item numbering: images
 // by decreasing cost), load the next item's inputs while the current one
 // runs, and rebuild the tap fragments only when the image changes. Items are decoded as in k_batched; the tiles
@@ -1831,7 +1831,7 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
     }
 }
 
-// Batched fused kernel for the FP16 classes with Q <= 4, where the
+// Batched fused kernel for the FP16 classes up to W = 40, where the
 // single-image kernel runs two blocks per CU: blocks take items from the
 // class's queue with nothing carried from one item to the next, and the
 // compiler is held to 128 VGPRs (four waves per SIMD: two blocks per CU).
