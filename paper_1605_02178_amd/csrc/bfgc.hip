@@ -304,7 +304,7 @@ static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int l
     const int tiles_x = (Wd + TC - 1) / TC;
     const long long tiles = (long long)tiles_x * ((H + kFusedRows - 1) / kFusedRows);
     if (tiles > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused path: too many tiles");
-    const int grid = fused_persistent<M>(Q, QA) ? (int)std::min<long long>(tiles, resident_blocks(kernel, &resident))
+    const int grid = fused_persistent<M>(Q) ? (int)std::min<long long>(tiles, resident_blocks(kernel, &resident))
                                          : (int)tiles;
     const float prescale = M::kPrescale;
     note_range_words(ws, kFusedSlots * tiles);

@@ -1336,10 +1336,7 @@ struct FusedTile {
 // blocks per CU anyway (BF16, with its FP32 plane state, at Q >= 4; FP16
 // fits everywhere, 92-126 VGPRs).
 template <class M>
-__host__ __device__ constexpr bool fused_persistent(int Q, int QA) {
-    (void)QA;
-    return !M::kHalfPlanes && Q >= 4;
-}
+__host__ __device__ constexpr bool fused_persistent(int Q) { return !M::kHalfPlanes && Q >= 4; }
 
 // Single-image fused kernel over the tiles_x-wide grid of 64 x TC tiles.
 // Where a block needs more than 128 VGPRs (one block per CU) it is
@@ -1361,7 +1358,7 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
     __shared__ E tab[fused_tab_len(Q)];
     T tile(f, out, H, Wd, ld, W, N, mu, prescale, C.b, ybuf);
     tile.setup(C.taps, tab);
-    if constexpr (!fused_persistent<M>(Q, QA)) {
+    if constexpr (!fused_persistent<M>(Q)) {
         const int t = blockIdx.x;
         const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
         typename T::Raw cur;
