@@ -172,25 +172,27 @@ def test_fused_headline_size_sampled(torch_cuda, N):
         assert err <= BOUND[("f16", 30.0, N)]
 
 
+@pytest.mark.parametrize("dtype,sigma_r,N", [("f16", 30.0, 30), ("bf16", 50.0, 11)])
 @pytest.mark.parametrize("sigma_s", [10.0, 15.0])
-def test_fused_persistent_ragged_sampled(torch_cuda, sigma_s):
+def test_fused_persistent_ragged_sampled(torch_cuda, dtype, sigma_r, N, sigma_s):
     """A ragged 1100 x 2050 image with more tiles than resident blocks (W = 30:
-    594 tiles of 64 x 64; W = 45: 1170 of 64 x 32), so each block of the
-    persistent kernel runs several tiles with the next one's halo in flight:
-    the oracle on crops at the four corners (ragged ones included), the
-    centre and a tile seam."""
+    594 tiles of 64 x 64; W = 45: 1170 of 64 x 32), in both launch forms:
+    FP16, one block per tile with two blocks per CU; BF16, persistent blocks
+    that run several tiles each with the next one's halo in flight. The
+    oracle on crops at the four corners (ragged ones included), the centre
+    and a tile seam."""
     import paper_1605_02178_amd as bf
     from oracle import native as C
     from synth import edge_rich
     f = edge_rich(1100, 2050, seed=41).astype(np.float32).astype(np.float64)
-    y = _np(bf.gc_filter(_gpu(torch_cuda, f), sigma_s, 30.0, 30, stack_dtype="f16", tile_config=bf.TILE_FUSED))
+    y = _np(bf.gc_filter(_gpu(torch_cuda, f), sigma_s, sigma_r, N, stack_dtype=dtype, tile_config=bf.TILE_FUSED))
     assert np.isfinite(y).all()
     for reg in ((0, 70, 0, 70), (0, 70, 1980, 2050), (1030, 1100, 0, 70), (1030, 1100, 1980, 2050),
                 (500, 580, 990, 1070), (630, 650, 0, 2050)):
-        ref = C.gcf(f, sigma_s, 30.0, 30, region=reg)
+        ref = C.gcf(f, sigma_s, sigma_r, N, region=reg)
         err = np.abs(y[reg[0]:reg[1], reg[2]:reg[3]] - ref).max()
-        _log(f"fused f16 1100x2050 sigma_s={sigma_s} crop {reg}: {err:.3e}")
-        assert err <= BOUND[("f16", 30.0, 30)]
+        _log(f"fused {dtype} 1100x2050 sigma_s={sigma_s} crop {reg}: {err:.3e}")
+        assert err <= BOUND[(dtype, sigma_r, N)]
 
 
 def test_fused_centre_value_pixels(torch_cuda):
