@@ -36,6 +36,26 @@ def test_taylor_filter_matches_oracle(torch_cuda, N):
     assert err <= 1e-3
 
 
+@pytest.mark.parametrize("sigma_r,N,bound", [(50.0, 11, 0.5), (30.0, 28, 2.5)])
+def test_taylor_fused_fp16_matches_oracle(torch_cuda, sigma_r, N, bound):
+    """The Taylor coefficients through the fused FP16 kernel (the default tile
+    for a 16-bit stack), against the oracle's polynomial filter with the same
+    coefficients: the FP16 stack's stated bounds (all b_n = mu^n/n! > 0, so
+    kappa = 1 as the library defines it)."""
+    import paper_1605_02178_amd as bf
+    from oracle import coeffs as K
+    from oracle import native as C
+    from synth import edge_rich
+    torch = torch_cuda
+    f = edge_rich(140, 150, seed=72).astype(np.float32).astype(np.float64)
+    y = bf.gc_filter(torch.tensor(f, dtype=torch.float32, device="cuda:0"), 4.0, sigma_r, N, taylor=True,
+                     stack_dtype="f16", tile_config=bf.TILE_FUSED)
+    ref = C.polynomial_filter(f, 4.0, sigma_r, K.taylor_coefficients(N))
+    err = np.abs(y.cpu().double().numpy() - ref).max()
+    _log(f"Taylor fused f16 sr={sigma_r} N={N}: {err:.3e} (bound {bound})")
+    assert err <= bound
+
+
 def test_table1_ordering_on_gpu(torch_cuda, golden):
     """Table 1 (sigma_s = 5, sigma_r = 30): on a 150 x 150 binary checkerboard
     stand-in for the Checker image, the GPU Gauss-polynomial filter is worse
