@@ -237,8 +237,9 @@ bf_status bf_gc_forward_pivots(const float *f, float *out, int height, int width
  *          read only; values in [0, 255] (others set BF_DEVFLAG_RANGE)
  *   out    device, same layout; must overlap neither g nor f
  *   other arguments as bf_gc_forward; 2(N+1) planes per stack. FP16/BF16
- *   stacks with radius <= 32 default to the fused matrix-core kernel (two
- *   operand sets per plane); BF_TILE_FUSED elsewhere is BF_ERR_UNSUPPORTED.
+ *   stacks with radius <= BF_FUSED_MAX_RADIUS default to the fused
+ *   matrix-core kernel (two operand sets per plane); BF_TILE_FUSED elsewhere
+ *   is BF_ERR_UNSUPPORTED.
  *   No staged form (BF_FLAG_STAGED: BF_ERR_INVALID_ARG). ws: at least
  *   bf_gc_joint_workspace_bytes(...) bytes, 256-byte aligned.
  */

@@ -124,7 +124,7 @@ static int tile_config_of(unsigned flags) {
     return c - 1 < BF_TILE_CONFIGS ? (int)(c - 1) : -2;
 }
 
-constexpr int kJointFusedMaxRadius = 32;   // the joint fused tile keeps two operand sets in registers
+constexpr int kJointFusedMaxRadius = BF_FUSED_MAX_RADIUS;   // the joint fused tile: the plain tile's geometries
 
 // The fused matrix-core kernel covers FP16/BF16 stacks up to BF_FUSED_MAX_RADIUS.
 static bool fused_applies(int dtype, double sigma_s) {
@@ -621,26 +621,25 @@ static bf_status run_joint_fused(const float *g, const float *v, float *out, int
     const FusedConsts C = fused_consts(sigma_s, sigma_r, N, kind_of(flags));
     const float mu = (float)fit(sigma_r, N).mu;
     const int W = radius_of(sigma_s), qa = fused_qa(W);
-    dim3 grid((Wd + 63) / 64, (H + kFusedRows - 1) / kFusedRows);
+    const int TC = W <= 32 ? 64 : 32;
+    dim3 grid((Wd + TC - 1) / TC, (H + kFusedRows - 1) / kFusedRows);
     unsigned *slots = (unsigned *)(ws + kFlagBytes);
-    if (W > 32) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above 32");
+    if (W > kJointFusedMaxRadius) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: radius above BF_FUSED_MAX_RADIUS");
     note_range_words(ws, (long long)kFusedSlots * grid.x * grid.y);
     ProfScope prof_("k_fused_joint", stream);
+#define BF_JF(Q, TCC, QA) \
+    hipLaunchKernelGGL((k_fused_joint<M, Q, TCC, QA>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W, N, mu, slots)
     if (W <= 16) {
-        if (qa == 0)
-            hipLaunchKernelGGL((k_fused_joint<M, 3, 0>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
-                               N, mu, slots);
-        else
-            hipLaunchKernelGGL((k_fused_joint<M, 3, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
-                               N, mu, slots);
+        if (qa == 0) BF_JF(3, 64, 0);
+        else BF_JF(3, 64, 1);
+    } else if (W <= 32) {
+        if (qa == 1) BF_JF(4, 64, 1);
+        else BF_JF(4, 64, 2);
     } else {
-        if (qa == 1)
-            hipLaunchKernelGGL((k_fused_joint<M, 4, 1>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
-                               N, mu, slots);
-        else
-            hipLaunchKernelGGL((k_fused_joint<M, 4, 2>), grid, dim3(512), 0, stream, g, v, out, H, Wd, ld, C, W,
-                               N, mu, slots);
+        if (qa == 2) BF_JF(5, 32, 2);
+        else BF_JF(5, 32, 3);
     }
+#undef BF_JF
     return check_launch("k_fused_joint");
 }
 
@@ -1320,7 +1319,7 @@ bf_status bf_gc_joint_forward(const float *g, const float *f, float *out, int he
     if (cfg == -1) cfg = fusable ? BF_TILE_FUSED : 0;
     hipStream_t s = (hipStream_t)stream;
     if (cfg == BF_TILE_FUSED) {
-        if (!fusable) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: FP16/BF16 stacks with radius <= 32 only");
+        if (!fusable) return fail(BF_ERR_UNSUPPORTED, "fused joint filter: FP16/BF16 stacks with radius <= BF_FUSED_MAX_RADIUS only");
         if (stack_dtype == BF_STACK_F16)
             return run_joint_fused<MmaF16>(g, f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags,
                                            (char *)ws, s);

@@ -1499,8 +1499,9 @@ __global__ __launch_bounds__(512) void k_fused_pivots(const float *__restrict__ 
 // B_n = A_n ft (ft = (v - t_c)/t_h from the averaged image v), both filtered
 // (two MFMA chains per block, two LDS buffers per plane), then
 // Q = sum b_n s_i^n Abar_n, P = sum b_n s_i^n Bbar_n, y = t_c + t_h P/Q.
-// Planes n = 0..N. 64-column tiles only (radius <= 32).
-template <class M, int Q, int QA>
+// Planes n = 0..N. Geometries as the plain tile: 64-column tiles for
+// radius <= 32, 32-column tiles (Q = 5) for radius <= 48.
+template <class M, int Q, int TC, int QA>
 __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, const float *__restrict__ v,
                                                  float *__restrict__ out, int H, int Wd, int ld,
                                                  const float *__restrict__ taps, const float *__restrict__ bt,
@@ -1511,10 +1512,10 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     typedef typename M::E E;
     typedef typename M::V V;
     constexpr int QB = Q - 2;
-    constexpr int TC = 64;
+    constexpr int JB = TC / 32;                 // output column blocks per wave in the row pass
     constexpr int kTabPad = kFusedTabPad;
     constexpr int kTab = fused_tab_len(Q);
-    static_assert(Q <= 4, "joint geometry: 64-column tiles");
+    static_assert((TC == 64 && Q <= 4) || (TC == 32 && Q == 5), "joint geometry");
     static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1531,7 +1532,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
         for (int jj = 0; jj < 8; ++jj) tf[d + 1][jj] = tab[kTabPad + 16 * d + 8 * lg + jj - li];
     const int rb = wave >> 1;
     const int p = wave & 1;
-    const int jc0 = 2 * p;
+    const int jc0 = p * JB;
 
     const bool one_ref = W < H && W < Wd;
     const int mc = halo_index(c0 - W + 16 * wave + li, Wd, W, one_ref);
@@ -1539,7 +1540,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     // Inputs: halo column values of g and v, and the lane's own output pixels
     // (as in FusedTile::load: one add per load where everything lies inside
     // the image and byte offsets fit 32 bits).
-    float gx[Q][8], vx[Q][8], gc[2][4], vc[2][4];
+    float gx[Q][8], vx[Q][8], gc[JB][4], vc[JB][4];
     if (r0 - W >= 0 && r0 - W + 32 * Q <= H && r0 + kFusedRows <= H && (long long)H * ld < (1LL << 29)) {
         const unsigned o = 4u * (unsigned)((r0 - W + 8 * lg) * ld + mc), ld4 = 4u * (unsigned)ld;
 #pragma unroll
@@ -1551,7 +1552,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
                 vx[q][jj] = *(const float *)((const char *)v + oo);
             }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < JB; ++b) {
             const unsigned oc = 4u * (unsigned)(cr * ld + min(c0 + 16 * (jc0 + b) + li, Wd - 1));
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
@@ -1569,7 +1570,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
                 vx[q][jj] = v[o];
             }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < JB; ++b) {
             const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
@@ -1606,15 +1607,15 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     // range check on the lane's own output pixels (each image pixel is one)
     bool bad = false;
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < JB; ++b)
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv)
             bad |= !(gc[b][vv] >= 0.0f && gc[b][vv] <= 255.0f) || !(vc[b][vv] >= 0.0f && vc[b][vv] <= 255.0f);
     report_range(bad, nullptr, slot);
 
-    float sc[2][4], pw[2][4], Pa[2][4], Qa[2][4];
+    float sc[JB][4], pw[JB][4], Pa[JB][4], Qa[JB][4];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < JB; ++b) {
 #pragma unroll
         for (int vv = 0; vv < 4; ++vv) {
             sc[b][vv] = fmaf(gc[b][vv], (float)(1.0 / kTh), (float)(-kTc / kTh));
@@ -1665,24 +1666,37 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     };
     auto row_pass = [&](int n) {
         const E *base = ybuf_base + (2 * (n & 1)) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
-        mf_f4 z[2][2];
+        mf_f4 z[2][JB];
 #pragma unroll
         for (int set = 0; set < 2; ++set) {
             const E *src = base + set * kFusedYElems;
-            V ya[QB + 1];
+            if (TC == 64) {
+                V ya[QB + 1];
 #pragma unroll
-            for (int q = 0; q <= QB; ++q) ya[q] = ld_frag<M>(src + 32 * (q + p));
-            mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                for (int q = 0; q <= QB; ++q) ya[q] = ld_frag<M>(src + 32 * (q + p));
+                mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
+                for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
 #pragma unroll
-            for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
-            z[set][0] = acc0;
-            z[set][1] = acc1;
+                for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
+                z[set][0] = acc0;
+                z[set][JB - 1] = acc1;
+            } else {
+                // the wave's column block p: fragment tf[2q + 1 - p] (uniform branch)
+                mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                if (p == 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q + 1], acc);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q], acc);
+                }
+                z[set][0] = acc;
+            }
         }
         const float bn = bt[n];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < JB; ++b) {
 #pragma unroll
             for (int vv = 0; vv < 4; ++vv) {
                 Qa[b][vv] = fmaf(bn, pw[b][vv] * z[0][b][vv], Qa[b][vv]);
@@ -1700,7 +1714,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     }
     row_pass(N);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
+    for (int b = 0; b < JB; ++b) {
         const int c = c0 + 16 * (jc0 + b) + li;
         if (c >= Wd) continue;
 #pragma unroll
@@ -1711,7 +1725,7 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
     }
 }
 
-template <class M, int Q, int QA>
+template <class M, int Q, int TC, int QA>
 __global__ __launch_bounds__(512) void k_fused_joint(const float *__restrict__ g, const float *__restrict__ v,
                                                      float *__restrict__ out, int H, int Wd, int ld,
                                                      FusedConsts C, int W, int N, float mu,
@@ -1719,9 +1733,9 @@ __global__ __launch_bounds__(512) void k_fused_joint(const float *__restrict__ g
     typedef typename M::E E;
     __shared__ __align__(16) E ybuf[4 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    fused_joint_tile<M, Q, QA>(g, v, out, H, Wd, ld, C.taps, C.b, W, N, mu, M::kPrescale,
-                               slots + kFusedSlots * (blockIdx.y * gridDim.x + blockIdx.x), blockIdx.y * kFusedRows,
-                               blockIdx.x * 64, ybuf, tab);
+    fused_joint_tile<M, Q, TC, QA>(g, v, out, H, Wd, ld, C.taps, C.b, W, N, mu, M::kPrescale,
+                                   slots + kFusedSlots * (blockIdx.y * gridDim.x + blockIdx.x),
+                                   blockIdx.y * kFusedRows, blockIdx.x * TC, ybuf, tab);
 }
 
 // Geometry classes of the fused kernel, in the order the batched form keeps

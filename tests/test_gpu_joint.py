@@ -115,7 +115,7 @@ def test_joint_flags_and_errors(torch_cuda):
         bf.gc_joint_filter(ft, gt, 2.0, 30.0, 28, out=gt)
     assert e.value.status == 1
     with pytest.raises(bf.BFError) as e:
-        bf.gc_joint_filter(ft, gt, 11.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)   # W = 33
+        bf.gc_joint_filter(ft, gt, 17.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)   # W = 51 > 48
     assert e.value.status == 2
     with pytest.raises(bf.BFError) as e:
         bf.gc_joint_filter(ft, gt, 2.0, 30.0, 28, stack_dtype="f32", tile_config=bf.TILE_FUSED)
@@ -140,11 +140,13 @@ def test_joint_1024_crops(torch_cuda):
 
 
 @pytest.mark.parametrize("shape,sigma_s", [((150, 170), 2.0), ((150, 170), 5.0), ((65, 129), 10.0), ((1, 77), 2.0),
-                                           ((129, 5), 2.0), ((300, 7), 3.0)])
+                                           ((129, 5), 2.0), ((300, 7), 3.0), ((150, 170), 12.0), ((97, 140), 13.0),
+                                           ((140, 190), 15.0)])
 @pytest.mark.parametrize("dtype,sigma_r,N,bound", [("f16", 30.0, 28, 2.5), ("bf16", 50.0, 11, 3.0)])
 def test_joint_fused_parity(torch_cuda, shape, sigma_s, dtype, sigma_r, N, bound):
-    """The fused matrix-core joint kernel (both radius classes, ragged tiles)
-    against the oracle's joint filter at the stated bounds."""
+    """The fused matrix-core joint kernel (all three geometries: W <= 16 and
+    W <= 32 on 64-column tiles, W = 36, 39, 45 on 32-column tiles; ragged
+    tiles) against the oracle's joint filter at the stated bounds."""
     import paper_1605_02178_amd as bf
     from oracle import filters as F
     f, g = _pair(shape, sum(shape) + 3)
