@@ -896,6 +896,7 @@ struct BatchKernels {
     int n = 0;
     const void *func[kBatchPhases];
     int grid[kBatchPhases];
+    bool items_grid[kBatchPhases] = {};   // grid = the phase's item count (set at every graph launch)
     int block = 256;
     size_t lds = 0;
 };
@@ -905,6 +906,7 @@ struct GraphEntry {
     size_t cap;
     int slot;
     BatchKernels k;
+    hipGraphNode_t nodes[kBatchPhases];
     hipGraphExec_t exec;
     hipGraph_t graph;
 };
@@ -913,11 +915,26 @@ static StageSlot g_slots[2];
 static int g_next_slot = 0;
 static std::vector<GraphEntry> g_graphs;
 
+// Same kernels and launch shape; grids that follow the item count may differ
+// (the cached graph's nodes are updated to the new grid before its launch).
 static bool same_kernels(const BatchKernels &a, const BatchKernels &b) {
     if (a.n != b.n || a.block != b.block || a.lds != b.lds) return false;
     for (int i = 0; i < a.n; ++i)
-        if (a.func[i] != b.func[i] || a.grid[i] != b.grid[i]) return false;
+        if (a.func[i] != b.func[i] || a.items_grid[i] != b.items_grid[i] ||
+            (!a.items_grid[i] && a.grid[i] != b.grid[i]))
+            return false;
     return true;
+}
+
+static hipKernelNodeParams kernel_node(const BatchKernels &K, int p, void **args) {
+    hipKernelNodeParams kp;
+    std::memset(&kp, 0, sizeof kp);
+    kp.func = (void *)K.func[p];
+    kp.gridDim = dim3(K.grid[p]);
+    kp.blockDim = dim3(K.block);
+    kp.sharedMemBytes = (unsigned)K.lds;
+    kp.kernelParams = args;
+    return kp;
 }
 
 static bf_status stage_slot(size_t cap, int *slot_out) {
@@ -974,10 +991,30 @@ static bf_status launch_batch(const BatchPlan &B, const BatchKernels &K, unsigne
     pack_blob(B, g_slots[slot].host);
     hipError_t e = hipSuccess;
     if (flags & BF_FLAG_GRAPH) {
+        char *blob = ws;
+        void *args[] = {&blob};
         GraphEntry *G = nullptr;
-        for (GraphEntry &g : g_graphs)
-            if (g.ws == ws && g.stream == stream && g.cap == B.blob_cap && g.slot == slot && same_kernels(g.k, K))
+        for (size_t i = 0; i < g_graphs.size() && !G; ++i) {
+            GraphEntry &g = g_graphs[i];
+            if (g.ws != ws || g.stream != stream || g.cap != B.blob_cap || g.slot != slot || !same_kernels(g.k, K))
+                continue;
+            bool ok = true;
+            for (int p = 0; p < K.n && ok; ++p)
+                if (K.items_grid[p] && K.grid[p] != g.k.grid[p]) {
+                    const hipKernelNodeParams kp = kernel_node(K, p, args);
+                    ok = hipGraphExecKernelNodeSetParams(g.exec, g.nodes[p], &kp) == hipSuccess;
+                    if (ok) g.k.grid[p] = K.grid[p];
+                }
+            if (ok) {
                 G = &g;
+            } else {                          // not updatable: rebuild below
+                (void)hipGetLastError();
+                (void)hipGraphExecDestroy(g.exec);
+                (void)hipGraphDestroy(g.graph);
+                g_graphs.erase(g_graphs.begin() + i);
+                break;
+            }
+        }
         if (!G) {
             GraphEntry g;
             g.ws = ws;
@@ -990,19 +1027,10 @@ static bf_status launch_batch(const BatchPlan &B, const BatchKernels &K, unsigne
             if (e == hipSuccess)
                 e = hipGraphAddMemcpyNode1D(&prev, g.graph, nullptr, 0, ws, g_slots[slot].host, B.blob_cap,
                                             hipMemcpyHostToDevice);
-            char *blob = ws;
-            void *args[] = {&blob};
             for (int p = 0; p < K.n && e == hipSuccess; ++p) {
-                hipKernelNodeParams kp;
-                std::memset(&kp, 0, sizeof kp);
-                kp.func = (void *)K.func[p];
-                kp.gridDim = dim3(K.grid[p]);
-                kp.blockDim = dim3(K.block);
-                kp.sharedMemBytes = (unsigned)K.lds;
-                kp.kernelParams = args;
-                hipGraphNode_t node;
-                e = hipGraphAddKernelNode(&node, g.graph, &prev, 1, &kp);
-                prev = node;
+                const hipKernelNodeParams kp = kernel_node(K, p, args);
+                e = hipGraphAddKernelNode(&g.nodes[p], g.graph, &prev, 1, &kp);
+                prev = g.nodes[p];
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
             if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("batched graph: ") + hipGetErrorString(e));
@@ -1053,12 +1081,12 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
 }
 
 // Fused FP16/BF16 form: one persistent kernel per non-empty geometry class.
-// The batched fused kernel of a class: the two-blocks-per-CU form for FP16
-// up to W = 40 (112-128 VGPRs; FP16 above W = 40 and BF16 would spill
-// there), else the persistent prefetching form.
+// The batched fused kernel of a class: one block per item for FP16 (two
+// blocks per CU, as the single-image kernel), the persistent prefetching
+// form for BF16.
 template <class M, int Q, int TC, int QA>
 static const void *batched_fused_kernel() {
-    if constexpr (M::kHalfPlanes && (Q <= 4 || QA == 2)) return (const void *)k_fused_batched2<M, Q, TC, QA>;
+    if constexpr (M::kHalfPlanes) return (const void *)k_fused_batched_items<M, Q, TC, QA>;
     else return (const void *)k_fused_batched<M, Q, TC, QA>;
 }
 
@@ -1080,7 +1108,13 @@ static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dt
     for (int c = 0; c < kBatchPhases; ++c)
         if (B.phase_items[c] > 0) {
             K.func[K.n] = cls[c];
-            K.grid[K.n] = phase_grid(cls[c], B.phase_items[c], K.block, K.lds);
+            if (M::kHalfPlanes) {
+                if (B.phase_items[c] > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused batch: too many tiles in a class");
+                K.grid[K.n] = (int)B.phase_items[c];
+                K.items_grid[K.n] = true;
+            } else {
+                K.grid[K.n] = phase_grid(cls[c], B.phase_items[c], K.block, K.lds);
+            }
             ++K.n;
         }
     return launch_batch(B, K, flags, ws, stream);

@@ -1745,8 +1745,8 @@ __host__ __device__ constexpr int fused_class_of_radius(int W) {
     return W <= 16 ? fused_class(3, fused_qa(W)) : W <= 32 ? fused_class(4, fused_qa(W)) : fused_class(5, fused_qa(W));
 }
 
-// Batched fused kernel for the other geometry classes (FP16 above W = 40,
-// every BF16 class): persistent blocks take the class's (image, tile) items from
+// Batched fused kernel for the BF16 classes (FP32 plane state, one block per
+// CU): persistent blocks take the class's (image, tile) items from
 // a queue (the header's counter, in the order of the item numbering: images
 // by decreasing cost), load the next item's inputs while the current one
 // runs, and rebuild the tap fragments only when the image changes. Items are decoded as in k_batched; the tiles
@@ -1842,12 +1842,12 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
     }
 }
 
-// Batched fused kernel for the FP16 classes up to W = 40, where the
-// single-image kernel runs two blocks per CU: blocks take items from the
-// class's queue with nothing carried from one item to the next, and the
-// compiler is held to 128 VGPRs (four waves per SIMD: two blocks per CU).
+// Batched fused kernel for the FP16 classes, where the single-image kernel
+// runs two blocks per CU: one block per (image, tile) item (grid = the
+// class's items, set at every launch), as the single-image kernel, held to
+// 128 VGPRs (four waves per SIMD: two blocks per CU; 94-124 used).
 template <class M, int Q, int TC, int QA>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_batched2(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_batched_items(
     char *__restrict__ blob) {
     typedef typename M::E E;
     typedef FusedTile<M, Q, TC, QA> T;
@@ -1856,8 +1856,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     extern __shared__ long long s_start[];
     __shared__ __align__(16) E ybuf[2 * kFusedYElems];
     __shared__ E tab[fused_tab_len(Q)];
-    __shared__ long long s_ticket[2];
     BatchHeader *hdr = (BatchHeader *)blob;
+    const long long t = blockIdx.x;
+    if (t >= hdr->items[C]) return;
     const BatchImage *img = (const BatchImage *)(blob + sizeof(BatchHeader));
     const int count = hdr->count;
     int *s_order = (int *)(s_start + count);
@@ -1867,37 +1868,25 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         s_start[k] = start[C * count + k];
         s_order[k] = order[C * count + k];
     }
-    const long long items = hdr->items[C];
-    long long *queue = &hdr->queue[C];
-    unsigned *flags = as_global(&hdr->flags);
-    // The ticket barrier also publishes s_start and ends the previous item.
-    for (int step = 0;; ++step) {
-        if (threadIdx.x == 0) s_ticket[step & 1] = (long long)atomicAdd((unsigned long long *)queue, 1ull);
-        __syncthreads();
-        const long long v = s_ticket[step & 1];
-        const long long t = ((long long)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
-                            (unsigned)__builtin_amdgcn_readfirstlane((int)v);
-        if (t >= items) return;
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_start[mid] <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        lo = __builtin_amdgcn_readfirstlane(lo);
-        const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
-        const BatchImage &B = img[ii];
-        const int l = (int)(t - s_start[lo]);
-        const int gvx = uniform(B.gvx);
-        const double *prm = as_global(uniform(B.prm));
-        T tile(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd), uniform(B.ld),
-               uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale,
-               (const float *)(prm + uniform(B.off_bf)), ybuf);
-        tile.setup((const float *)(prm + uniform(B.off_tf)), tab);
-        typename T::Raw raw;
-        tile.load((l / gvx) * kFusedRows, (l % gvx) * TC, raw);
-        tile.run((l / gvx) * kFusedRows, (l % gvx) * TC, raw, flags, nullptr);
+    __syncthreads();
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= t) lo = mid;
+        else hi = mid - 1;
     }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
+    const BatchImage &B = img[ii];
+    const int l = (int)(t - s_start[lo]);
+    const int gvx = uniform(B.gvx);
+    const double *prm = as_global(uniform(B.prm));
+    T tile(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd), uniform(B.ld),
+           uniform(B.W), uniform(B.N), (float)uniform(B.mu), prescale, (const float *)(prm + uniform(B.off_bf)), ybuf);
+    tile.setup((const float *)(prm + uniform(B.off_tf)), tab);
+    typename T::Raw raw;
+    tile.load((l / gvx) * kFusedRows, (l % gvx) * TC, raw);
+    tile.run((l / gvx) * kFusedRows, (l % gvx) * TC, raw, as_global(&hdr->flags), nullptr);
 }
 
 }  // namespace bfgc
