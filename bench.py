@@ -164,10 +164,16 @@ def bench_batched(bf, steps, log, stack="f32"):
     """Uneven batch: 64 edge-rich images, long side uniform over
     {256, 384, ..., 2048}, square or 2:1, sigma_s ~ U[2,16], sigma_r ~ U[10,60],
     N from the degree rule. One graph launch of the batch against a loop of
-    single-image forwards, both with the autotuned tile configuration. Images
-    outside the stack type's domain (sigma_r below about 20 for FP32, about
-    28 for FP16) are still filtered (allow flag), for throughput."""
+    single-image forwards, both with the autotuned tile configuration and both
+    at the same stated accuracy: an image whose own expansion fails the
+    conditioning check for the stack type runs the pivoted form with the
+    route's sub-range count in both (no allow flag). Per image, the max-abs
+    error of the batched output against the FP64 oracle (its fast filter, or
+    the pivoted one for routed images) on two 64 x 64 crops (corner, centre),
+    and against the direct filter of eq. 1 on the same crops."""
+    import numpy as np
     import torch
+    from oracle import native as C
     from paper_1605_02178_amd import autotune
     from synth import batch_specs
     specs = batch_specs()
@@ -175,25 +181,37 @@ def bench_batched(bf, steps, log, stack="f32"):
     ss = [sp.sigma_s for sp in specs]
     sr = [sp.sigma_r for sp in specs]
     deg = [bf.degree_rule(x) for x in sr]
+    routes = [bf.batched_route(x, d, stack) for x, d in zip(sr, deg)]
     px = sum(x.numel() for x in imgs)
     ws = torch.empty(bf.batched_workspace_bytes([tuple(x.shape) for x in imgs], ss, deg, stack), dtype=torch.uint8,
                      device="cuda:0")
     outs = [torch.empty_like(x) for x in imgs]
-    log(f"bench: batched {len(imgs)} images, {px / 1e6:.1f} Mpx, {stack} stack, autotuning")
-    cfg, times = autotune.tune_batched(imgs, ss, sr, deg, stack, repeats=2, allow_ill_conditioned=True, workspace=ws)
+    log(f"bench: batched {len(imgs)} images, {px / 1e6:.1f} Mpx, {stack} stack, "
+        f"{sum(r > 1 for r in routes)} routed to the pivoted form, autotuning")
+    cfg, times = autotune.tune_batched(imgs, ss, sr, deg, stack, repeats=2, workspace=ws)
 
     def run_batch():
-        bf.gc_filter_batched(imgs, ss, sr, deg, stack_dtype=stack, graph=True, tile_config=cfg,
-                             allow_ill_conditioned=True, outs=outs, workspace=ws)
-    single_ws = torch.empty(max(bf.workspace_bytes(x.shape[0], x.shape[1], s_, d, stack)
-                                for x, s_, d in zip(imgs, ss, deg)), dtype=torch.uint8, device="cuda:0")
+        _, st = bf.gc_filter_batched(imgs, ss, sr, deg, stack_dtype=stack, graph=True, tile_config=cfg, outs=outs,
+                                     workspace=ws)
+        return st
+    loop_ws = max(bf.workspace_bytes(x.shape[0], x.shape[1], s_, d, stack) if r == 1 else
+                  bf.pivots_workspace_bytes(x.shape[0], x.shape[1], s_, r_, r, None, stack)
+                  for x, s_, r_, d, r in zip(imgs, ss, sr, deg, routes))
+    single_ws = torch.empty(loop_ws, dtype=torch.uint8, device="cuda:0")
+    loop_outs = [torch.empty_like(x) for x in imgs]
 
     def run_loop():
         for k, x in enumerate(imgs):
-            bf.gc_filter(x, ss[k], sr[k], deg[k], stack_dtype=stack, out=outs[k], workspace=single_ws,
-                         tile_config=cfg, allow_ill_conditioned=True)
+            if routes[k] == 1:
+                bf.gc_filter(x, ss[k], sr[k], deg[k], stack_dtype=stack, out=loop_outs[k], workspace=single_ws,
+                             tile_config=cfg)
+            else:
+                bf.gc_filter_pivots(x, ss[k], sr[k], K=routes[k], stack_dtype=stack, out=loop_outs[k],
+                                    workspace=single_ws, tile_config=cfg)
 
     res = {}
+    status = run_batch()
+    assert status == [0] * len(imgs), status
     for name, fn in (("batched_graph", run_batch), ("per_image_loop", run_loop)):
         fn()
         torch.cuda.synchronize()
@@ -208,9 +226,34 @@ def bench_batched(bf, steps, log, stack="f32"):
         res[name] = {"ms": round(ms, 3), "mpx_s": round(px / 1e6 / (ms / 1e3), 1)}
         log(f"bench: {stack} {name} {ms:.2f} ms")
     res["speedup"] = round(res["per_image_loop"]["ms"] / res["batched_graph"]["ms"], 3)
+    same = all(torch.equal(a, b) for a, b in zip(outs, loop_outs))
+    # accuracy of every image (the batched outputs)
+    per_image = []
+    for k, sp in enumerate(specs):
+        y = outs[k].cpu().double().numpy()
+        f64 = imgs[k].cpu().double().numpy()
+        e_or = e_dir = 0.0
+        c = min(64, sp.height), min(64, sp.width)
+        r0, c0 = (sp.height - c[0]) // 2, (sp.width - c[1]) // 2
+        for reg in ((0, c[0], 0, c[1]), (r0, r0 + c[0], c0, c0 + c[1])):
+            ref = (C.gcf(f64, ss[k], sr[k], deg[k], region=reg) if routes[k] == 1 else
+                   C.pivot_gcf(f64, ss[k], sr[k], routes[k], region=reg))
+            d = C.direct_bf(f64, ss[k], sr[k], region=reg)
+            yc = y[reg[0]:reg[1], reg[2]:reg[3]]
+            e_or = max(e_or, float(np.abs(yc - ref).max()))
+            e_dir = max(e_dir, float(np.abs(yc - d).max()))
+        per_image.append({"shape": [sp.height, sp.width], "sigma_s": round(ss[k], 3), "sigma_r": round(sr[k], 3),
+                          "N": deg[k], "sub_ranges": routes[k], "max_abs_vs_oracle": e_or,
+                          "max_abs_vs_direct": e_dir})
+    log(f"bench: {stack} batch errors: worst vs oracle {max(p['max_abs_vs_oracle'] for p in per_image):.3e}, "
+        f"vs direct {max(p['max_abs_vs_direct'] for p in per_image):.3e}")
     res.update({"stack": stack, "images": len(imgs), "megapixels": round(px / 1e6, 2), "tile_config": cfg,
                 "tile_times_ms": [None if t is None else round(t, 3) for t in times], "steps": steps,
-                "mean_degree_px_weighted": round(sum(d * x.numel() for d, x in zip(deg, imgs)) / px, 1)})
+                "mean_degree_px_weighted": round(sum(d * x.numel() for d, x in zip(deg, imgs)) / px, 1),
+                "routed_images": sum(r > 1 for r in routes), "loop_equals_batch_bitwise": same,
+                "max_abs_vs_oracle_64c": max(p["max_abs_vs_oracle"] for p in per_image),
+                "max_abs_vs_direct_64c": max(p["max_abs_vs_direct"] for p in per_image),
+                "per_image": per_image})
     return res
 
 

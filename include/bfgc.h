@@ -314,10 +314,24 @@ bf_status bf_gc_combine(const float *f, const void *stack, int height, int width
  * (radius ranges with their own tile shape), striding over the class's tiles.
  * descs and per_image_status are host arrays, read and written before
  * return. Each image gets the status its own bf_gc_forward would return from
- * the host checks; images whose status is not BF_OK are skipped (their out is
- * untouched) and the call still returns BF_OK. Tiles are the per-image
- * kernels' blocks, so each output equals the single-image forward's bit for
- * bit under the same tile configuration. BF_FLAG_GRAPH launches through a
+ * the host checks, with one exception: an image whose own expansion lies
+ * outside the stack type's accuracy domain (sigma_r too small for it,
+ * Section III-B: mu grows as 1/sigma_r^2; kappa times the rounding unit above
+ * 1e-5 for FP32, where its 1e-3 max-abs error holds, and above the
+ * conditioning check's 1e-2 for FP16/BF16) is routed to the pivoted form of
+ * bf_gc_forward_pivots with the sub-range count bf_gc_batched_route returns
+ * and the rule's degree per sub-range, and gets BF_OK (without
+ * BF_FLAG_ALLOW_ILL_CONDITIONED, Chebyshev coefficients only; where no count
+ * up to BF_MAX_PIVOTS reaches the domain, the image keeps its own expansion,
+ * or BF_ERR_ILL_CONDITIONED if that fails the conditioning check). Images whose status is
+ * not BF_OK are skipped (their out is untouched) and the call still returns
+ * BF_OK. Tiles are the per-image kernels' blocks, so each output equals the
+ * single-image forward's (a routed image: bf_gc_forward_pivots's) bit for
+ * bit under the same tile configuration. On the fused tile a routed image
+ * runs in a class of its own (one block per tile, each running the
+ * sub-ranges present among its output pixels); in the three-kernel form each
+ * of its sub-ranges runs as an image of its own that writes only its pixels
+ * (at most 2 BF_MAX_BATCH such descriptors, BF_ERR_UNSUPPORTED beyond). BF_FLAG_GRAPH launches through a
  * hipGraph cached per (workspace, stream, capacity, tile configuration,
  * stack type) and replayed with the new descriptors. ws: device, 256-byte
  * aligned, at least bf_gc_batched_workspace_bytes(descs, count, stack_dtype)
@@ -335,9 +349,18 @@ typedef struct {
 } bf_image_desc;
 
 /* Workspace for a batch: sizes every image with valid dimensions and
- * parameters (pointers are not read), whatever its conditioning, for the
- * three-kernel form (which needs more than the fused form). */
+ * parameters (pointers are not read), whatever its conditioning (as its own
+ * expansion and as routed to the pivoted form), for the three-kernel form
+ * (which needs more than the fused form). */
 size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int stack_dtype);
+
+/* How bf_gc_batched runs an image with these parameters under `flags`:
+ * 1 = its own expansion of degree N; K >= 2 = the pivoted form with K
+ * sub-ranges (the smallest power of two whose sub-ranges, at the rule's
+ * degree each, lie in the stack type's accuracy domain); 0 = skipped
+ * (invalid sigma_r, N or stack type, or no well-conditioned form). Host
+ * only. */
+int bf_gc_batched_route(double sigma_r, int N, int stack_dtype, unsigned flags);
 bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, unsigned flags,
                         int *per_image_status, void *ws, size_t ws_bytes, void *stream);
 

@@ -25,7 +25,7 @@ __all__ = [
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
     "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
     "gc_joint_filter", "joint_workspace_bytes", "gc_filter_pivots", "pivot_count", "pivot_plan",
-    "pivots_workspace_bytes",
+    "pivots_workspace_bytes", "batched_route",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -390,6 +390,15 @@ def _descs(images, outs, sigmas_s, sigmas_r, degrees):
         arr[i].ld = max(f.stride(0) if H > 1 else Wd, Wd)
         arr[i].sigma_s, arr[i].sigma_r, arr[i].N = float(sigmas_s[i]), float(sigmas_r[i]), int(degrees[i])
     return arr
+
+
+def batched_route(sigma_r: float, degree: int, stack_dtype="f32", allow_ill_conditioned: bool = False,
+                  coeffs=None) -> int:
+    """How gc_filter_batched runs an image with these parameters: 1 = its own
+    expansion, K >= 2 = the pivoted form with K sub-ranges (its own expansion
+    is ill-conditioned for the stack type), 0 = skipped."""
+    flags = (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0) | _coeff_flags(coeffs)
+    return int(_lib.load().bf_gc_batched_route(float(sigma_r), int(degree), _dtype_code(stack_dtype), flags))
 
 
 def batched_workspace_bytes(shapes, sigmas_s, degrees, stack_dtype="f32") -> int:

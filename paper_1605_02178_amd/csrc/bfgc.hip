@@ -422,6 +422,48 @@ static int pivot_nmax(const std::vector<Pivot> &plan) {
     return n;
 }
 
+// Whether K sub-ranges at the rule's degree each have kappa times the stack
+// type's rounding unit at most `limit` (1e-2: the conditioning check).
+static bool pivots_conditioned(double sigma_r, int K, int dtype, double limit = 1e-2) {
+    for (const Pivot &p : pivot_plan(sigma_r, K, 0, BF_MAX_DEGREE)) {
+        if (p.N < 1) return false;
+        const double kappa = fit_mu(p.mu, p.N).kappa;
+        if (!std::isfinite(kappa) || kappa * unit_roundoff(dtype) > limit) return false;
+    }
+    return true;
+}
+
+// Accuracy domain of a stack type in a batch, as a limit on kappa times its
+// rounding unit. The storage rounding reaches the output as about
+// kappa u t_h (measured 0.1-1.3 kappa u t_h over the uneven batch), so FP32
+// holds a 1e-3 max-abs error where kappa u <= 1e-5 (sigma_r >= 25 at the
+// rule's degree); the 16-bit stacks, whose own rounding is far above that,
+// keep the conditioning check's 1e-2.
+static double batch_limit(int dtype) { return dtype == BF_STACK_F32 ? 1e-5 : 1e-2; }
+
+// Route of one image of a batch whose host checks passed except, possibly,
+// the conditioning check: 1 = its own expansion (degree N); K >= 2 = the
+// pivoted form with K sub-ranges at the rule's degree each, for an image
+// whose own expansion lies outside the stack type's accuracy domain
+// (Chebyshev coefficients, no BF_FLAG_ALLOW_ILL_CONDITIONED), K the smallest
+// power of two whose sub-ranges lie inside; 0 = neither (the image keeps its
+// conditioning status, BF_ERR_ILL_CONDITIONED if its own expansion fails the
+// check, else it runs its own expansion). *st: the image's status.
+static int batch_route(double sigma_r, int N, int dtype, unsigned flags, bf_status *st) {
+    *st = check_conditioning(sigma_r, N, dtype, flags);
+    if ((*st != BF_OK && *st != BF_ERR_ILL_CONDITIONED) || (flags & BF_FLAG_ALLOW_ILL_CONDITIONED) ||
+        (flags & (BF_FLAG_TAYLOR | BF_FLAG_MINIMAX)))
+        return *st == BF_OK ? 1 : 0;
+    const double limit = batch_limit(dtype);
+    if (*st == BF_OK && fit(sigma_r, N).kappa * unit_roundoff(dtype) <= limit) return 1;
+    for (int K = 2; K <= BF_MAX_PIVOTS; K *= 2)
+        if (pivots_conditioned(sigma_r, K, dtype, limit)) {
+            *st = BF_OK;
+            return K;
+        }
+    return *st == BF_OK ? 1 : 0;
+}
+
 // Fused pivoted form: the range words of the tiles, then the sub-range table
 // (K FusedPivot entries, the taps, the coefficients of every sub-range), the
 // tiles' sub-range masks, their order and the queue counter.
@@ -523,19 +565,18 @@ static bf_status launch_fused_pivots_q(const float *f, float *out, int H, int Wd
     return check_launch("k_fused_pivots");
 }
 
-template <class M>
-static bf_status run_fused_pivots(const float *f, float *out, int H, int Wd, int ld, double sigma_s,
-                                  const std::vector<Pivot> &plan, char *ws, hipStream_t stream) {
-    const int W = radius_of(sigma_s), qa = fused_qa(W);
+// Host image of the fused pivoted form's sub-range table: K FusedPivot
+// entries, the taps as floats (padded to a multiple of 4), then each
+// sub-range's coefficients b_n c^{-n}, n = 0..N_k+1 (b_{N_k+1} = 0), as
+// floats. prescale: the stack type's common plane scale 2^K.
+static std::vector<char> fused_pivot_table(double sigma_s, const std::vector<Pivot> &plan, float prescale) {
+    const int W = radius_of(sigma_s);
     const int K = (int)plan.size();
-    const long long tiles = fused_pivot_tiles(H, Wd, W);
-    char *table = ws + kFlagBytes + align256(sizeof(unsigned) * kFusedSlots * (size_t)tiles);
-    // host image of the table
     std::vector<FusedPivot> piv(K);
     const std::vector<double> w = spatial_taps(sigma_s);
     const int ntap = ((2 * W + 1) + 3) & ~3;
     std::vector<float> coef;
-    const double k2 = std::log2((double)M::kPrescale);
+    const double k2 = std::log2((double)prescale);
     for (int k = 0; k < K; ++k) {
         const Pivot &p = plan[k];
         const int n1 = p.N + 1;
@@ -563,6 +604,17 @@ static bf_status run_fused_pivots(const float *f, float *out, int H, int Wd, int
     float *tp = (float *)(bytes.data() + sizeof(FusedPivot) * K);
     for (int t = 0; t <= 2 * W; ++t) tp[t] = (float)w[t];
     std::memcpy(tp + ntap, coef.data(), sizeof(float) * coef.size());
+    return bytes;
+}
+
+template <class M>
+static bf_status run_fused_pivots(const float *f, float *out, int H, int Wd, int ld, double sigma_s,
+                                  const std::vector<Pivot> &plan, char *ws, hipStream_t stream) {
+    const int W = radius_of(sigma_s), qa = fused_qa(W);
+    const int K = (int)plan.size();
+    const long long tiles = fused_pivot_tiles(H, Wd, W);
+    char *table = ws + kFlagBytes + align256(sizeof(unsigned) * kFusedSlots * (size_t)tiles);
+    const std::vector<char> bytes = fused_pivot_table(sigma_s, plan, M::kPrescale);
     std::vector<double> host((bytes.size() + 7) / 8, 0.0);
     std::memcpy(host.data(), bytes.data(), bytes.size());
     bf_status st = upload_vector((double *)table, nullptr, host, false, stream);
@@ -736,7 +788,7 @@ struct BatchPlan {
     std::vector<int> order;             // [kBatchPhases][n] images in each phase's visiting order
     std::vector<std::vector<double>> prm;
     size_t blob_bytes = 0, blob_cap = 0, total = 0;
-    long long items = 0, phase_items[kBatchPhases] = {0, 0, 0, 0, 0, 0};
+    long long items = 0, phase_items[kBatchPhases] = {};
 };
 
 static size_t batch_blob_cap(size_t bytes) {
@@ -752,45 +804,92 @@ static size_t batch_head_bytes(size_t n) {
 // Plans a batch: per-image status, descriptors, parameter blocks and the
 // workspace layout [blob (capacity blob_cap) | per image: stack A, stack B]
 // (three-kernel form) or [blob] (fused form, phases = geometry classes).
+// An image whose single expansion fails the conditioning check is routed to
+// the pivoted form (batch_route): on the fused tile one descriptor in the
+// pivoted class of its geometry, carrying the sub-range table; in the
+// three-kernel form one descriptor per sub-range (its centring, degree and
+// coefficients, stacks of its own), each writing only its own pixels. When
+// sizing, pointers are not read.
 static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned flags, int RV, int RH, bool fused,
                        char *ws, BatchPlan &B, bool sizing = false) {
     B.status.assign(count, BF_OK);
     B.img.clear();
     B.prm.clear();
-    std::vector<int> ok;
+    std::vector<int> ok, route;
     for (int i = 0; i < count; ++i) {
         const bf_image_desc &x = d[i];
         bf_status st = check_common(x.height, x.width, x.sigma_s, x.sigma_r, x.N, dtype);
         if (st == BF_OK && fused && radius_of(x.sigma_s) > BF_FUSED_MAX_RADIUS)
             st = fail(BF_ERR_UNSUPPORTED, "fused tile: radius above BF_FUSED_MAX_RADIUS");
-        if (st == BF_OK && x.height > 0 && x.width > 0 && !sizing) {
-            if (!x.f || !x.out) st = fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
-            else if (x.ld < x.width) st = fail(BF_ERR_INVALID_ARG, "ld must be >= width");
-            else {
+        int K = 1;
+        if (st == BF_OK && x.height > 0 && x.width > 0) {
+            if (!sizing) {
                 const size_t img = ((size_t)(x.height - 1) * x.ld + x.width) * sizeof(float);
-                if (overlaps(x.f, img, x.out, img)) st = fail(BF_ERR_INVALID_ARG, "out overlaps f");
-                else st = check_conditioning(x.sigma_r, x.N, dtype, flags);
+                if (!x.f || !x.out) st = fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
+                else if (x.ld < x.width) st = fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+                else if (overlaps(x.f, img, x.out, img)) st = fail(BF_ERR_INVALID_ARG, "out overlaps f");
             }
+            if (st == BF_OK) K = batch_route(x.sigma_r, x.N, dtype, flags, &st);
         }
         B.status[i] = st;
-        if (st == BF_OK && x.height > 0 && x.width > 0) ok.push_back(i);
+        if (st == BF_OK && x.height > 0 && x.width > 0) {
+            ok.push_back(i);
+            route.push_back(K);
+        }
     }
-    const int n = (int)ok.size();
+    // descriptors: (image, pivot plan) pairs; an empty plan is the plain expansion
+    struct Entry {
+        int i;
+        std::vector<Pivot> plan;   // fused: all sub-ranges; three-kernel: the one sub-range
+        int k;                     // three-kernel: its index, for the output mask
+    };
+    std::vector<Entry> ent;
+    for (size_t j = 0; j < ok.size(); ++j) {
+        const bf_image_desc &x = d[ok[j]];
+        if (route[j] == 1) {
+            ent.push_back({ok[j], {}, 0});
+            continue;
+        }
+        const std::vector<Pivot> plan = pivot_plan(x.sigma_r, route[j], 0, BF_MAX_DEGREE);
+        if (fused) ent.push_back({ok[j], plan, 0});
+        else
+            for (int k = 0; k < route[j]; ++k) ent.push_back({ok[j], {plan[k]}, k});
+    }
+    const int n = (int)ent.size();
+    const float prescale = dtype == BF_STACK_F16 ? MmaF16::kPrescale : MmaBF16::kPrescale;
+    // parameter blocks
+    for (int e = 0; e < n; ++e) {
+        const bf_image_desc &x = d[ent[e].i];
+        const int W = radius_of(x.sigma_s);
+        std::vector<double> pv;
+        if (ent[e].plan.empty()) {
+            fill_params(param_layout(W, x.N), x.sigma_s, x.sigma_r, dtype, pv, kind_of(flags));
+        } else if (fused) {
+            const std::vector<char> bytes = fused_pivot_table(x.sigma_s, ent[e].plan, prescale);
+            pv.assign((bytes.size() + 7) / 8, 0.0);
+            std::memcpy(pv.data(), bytes.data(), bytes.size());
+        } else {
+            const Pivot &p = ent[e].plan[0];
+            fill_params_pivot(param_layout(W, p.N), x.sigma_s, p.mu, p.nu, dtype, pv);
+        }
+        B.prm.push_back(pv);
+    }
     size_t prm_bytes = 0;
-    for (int k = 0; k < n; ++k) prm_bytes += align256(sizeof(double) * param_layout(radius_of(d[ok[k]].sigma_s), d[ok[k]].N).total);
+    for (const std::vector<double> &pv : B.prm) prm_bytes += align256(sizeof(double) * pv.size());
     const size_t head_bytes = batch_head_bytes(n);
     B.blob_bytes = head_bytes + prm_bytes;
     B.blob_cap = batch_blob_cap(B.blob_bytes);
     size_t off = B.blob_cap;
     size_t poff = head_bytes;
     std::vector<long long> cnt[kBatchPhases], cost[kBatchPhases];
-    for (int k = 0; k < n; ++k) {
-        const bf_image_desc &x = d[ok[k]];
+    for (int e = 0; e < n; ++e) {
+        const Entry &E = ent[e];
+        const bf_image_desc &x = d[E.i];
+        const bool piv = !E.plan.empty();
+        const int Ne = piv && !fused ? E.plan[0].N : x.N;
+        const ParamLayout L = param_layout(radius_of(x.sigma_s), Ne);
         BatchImage I;
         std::memset(&I, 0, sizeof I);
-        const ParamLayout L = param_layout(radius_of(x.sigma_s), x.N);
-        std::vector<double> pv;
-        fill_params(L, x.sigma_s, x.sigma_r, dtype, pv, kind_of(flags));
         I.f = x.f;
         I.out = x.out;
         I.H = x.height;
@@ -799,30 +898,51 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
         I.lds = lds_of(x.width);
         I.ldt = ldt_of(x.height);
         I.W = L.W;
-        I.N = x.N;
-        I.P = x.N + 2;
+        I.N = Ne;
+        I.P = Ne + 2;
         I.ps = (long long)I.H * I.lds;
         I.pst = (long long)I.Wd * I.ldt;
-        I.mu = fit(x.sigma_r, x.N).mu;
+        I.mu = piv ? (fused ? 0.0 : E.plan[0].nu) : fit(x.sigma_r, x.N).mu;
         I.off_taps = L.off_taps;
         I.off_cq = L.off_cq;
         I.off_cp = L.off_cp;
         I.off_scale = L.off_scale;
         I.off_bf = L.off_bf;
         I.off_tf = L.off_tf;
+        I.C = plain_centring();
+        I.K = 1;
         I.prm = (const double *)((uintptr_t)ws + poff);   // ws may be null when only sizing
-        poff += align256(sizeof(double) * L.total);
+        poff += align256(sizeof(double) * B.prm[e].size());
         for (int p = 0; p < kBatchPhases; ++p) {
             cnt[p].push_back(0);
             cost[p].push_back(0);
         }
         if (fused) {
             const int TC = L.W <= 32 ? 64 : 32;
-            const int c = fused_class_of_radius(L.W);
+            int c = fused_class_of_radius(L.W);
             I.gvx = (I.Wd + TC - 1) / TC;
+            if (!piv) {
+                cost[c].back() = I.P;                             // per tile: planes
+            } else {
+                const int K = (int)E.plan.size();
+                c += kFusedClasses;
+                I.K = K;
+                I.kscale = (float)(K / (kTc + kTh));
+                I.off_piv = 0;
+                I.off_tf = (int)(sizeof(FusedPivot) * K / sizeof(double));
+                I.off_bf = I.off_tf + (((2 * L.W + 1) + 3) & ~3) / 2;
+                long long planes = 0;
+                for (const Pivot &p : E.plan) planes += p.N + 2;
+                cost[c].back() = planes;                          // per tile: at most every sub-range's planes
+            }
             cnt[c].back() = (long long)I.gvx * ((I.H + kFusedRows - 1) / kFusedRows);
-            cost[c].back() = I.P;                                 // per tile: planes
         } else {
+            if (piv) {
+                const Pivot &p = E.plan[0];
+                const int K = route[std::find(ok.begin(), ok.end(), E.i) - ok.begin()];
+                const int mask = E.k == 0 ? 2 : E.k == K - 1 ? 3 : 1;
+                I.C = Centring{p.t, 1.0 / p.R, 1.0 / p.h, p.R, (float)p.lo, (float)p.hi, mask};
+            }
             I.stackA = (void *)((uintptr_t)ws + off);
             off += align256((size_t)I.P * I.ps * esize(dtype));
             I.stackB = (void *)((uintptr_t)ws + off);
@@ -840,7 +960,6 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
             cost[2].back() = (long long)I.P * (2LL * L.W + 1);      // planes x taps per output
         }
         B.img.push_back(I);
-        B.prm.push_back(pv);
     }
     B.start.assign((size_t)kBatchPhases * n, 0);
     B.order.assign((size_t)kBatchPhases * n, 0);
@@ -1067,6 +1186,9 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
     BatchPlan B;
     plan_batch(descs, count, dtype, flags, RV, RH, false, ws, B);
     for (int i = 0; i < count; ++i) status[i] = B.status[i];
+    // descriptors (sub-ranges of routed images count one each) bound the item table in LDS
+    if (B.img.size() > 2 * (size_t)kMaxBatch)
+        return fail(BF_ERR_UNSUPPORTED, "batch: more than 2 BF_MAX_BATCH descriptors after the pivoted routing");
     if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
     if (B.items == 0) return BF_OK;
     BatchKernels K;
@@ -1101,14 +1223,17 @@ static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dt
     const void *cls[kBatchPhases] = {
         batched_fused_kernel<M, 3, 64, 0>(), batched_fused_kernel<M, 3, 64, 1>(),
         batched_fused_kernel<M, 4, 64, 1>(), batched_fused_kernel<M, 4, 64, 2>(),
-        batched_fused_kernel<M, 5, 32, 2>(), batched_fused_kernel<M, 5, 32, 3>()};
+        batched_fused_kernel<M, 5, 32, 2>(), batched_fused_kernel<M, 5, 32, 3>(),
+        (const void *)k_fused_batched_pivot_items<M, 3, 64, 0>, (const void *)k_fused_batched_pivot_items<M, 3, 64, 1>,
+        (const void *)k_fused_batched_pivot_items<M, 4, 64, 1>, (const void *)k_fused_batched_pivot_items<M, 4, 64, 2>,
+        (const void *)k_fused_batched_pivot_items<M, 5, 32, 2>, (const void *)k_fused_batched_pivot_items<M, 5, 32, 3>};
     BatchKernels K;
     K.block = 512;
     K.lds = batch_lds_bytes((int)B.img.size());
     for (int c = 0; c < kBatchPhases; ++c)
         if (B.phase_items[c] > 0) {
             K.func[K.n] = cls[c];
-            if (M::kHalfPlanes) {
+            if (M::kHalfPlanes || c >= kFusedClasses) {   // one block per item
                 if (B.phase_items[c] > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused batch: too many tiles in a class");
                 K.grid[K.n] = (int)B.phase_items[c];
                 K.items_grid[K.n] = true;
@@ -1232,16 +1357,15 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
 
 int bf_gc_pivot_count(double sigma_r, int stack_dtype) {
     if (!finite_pos(sigma_r) || stack_dtype < BF_STACK_F32 || stack_dtype > BF_STACK_BF16) return -1;
-    for (int K = 1; K <= BF_MAX_PIVOTS; K *= 2) {
-        bool ok = true;
-        for (const Pivot &p : pivot_plan(sigma_r, K, 0, BF_MAX_DEGREE)) {
-            if (p.N < 1) { ok = false; break; }
-            const double kappa = fit_mu(p.mu, p.N).kappa;
-            if (!std::isfinite(kappa) || kappa * unit_roundoff(stack_dtype) > 1e-2) { ok = false; break; }
-        }
-        if (ok) return K;
-    }
+    for (int K = 1; K <= BF_MAX_PIVOTS; K *= 2)
+        if (pivots_conditioned(sigma_r, K, stack_dtype)) return K;
     return -1;
+}
+
+int bf_gc_batched_route(double sigma_r, int N, int stack_dtype, unsigned flags) {
+    if (check_common(1, 1, 1.0, sigma_r, N, stack_dtype) != BF_OK) return 0;
+    bf_status st;
+    return batch_route(sigma_r, N, stack_dtype, flags, &st);
 }
 
 bf_status bf_gc_pivot_plan(double sigma_r, int K, int N, int *N_out, double *mu_out, double *kappa_out) {
@@ -1488,10 +1612,13 @@ size_t bf_gc_batched_workspace_bytes(const bf_image_desc *descs, int count, int 
     if (count < 0 || count > kMaxBatch || (count > 0 && !descs) || stack_dtype < BF_STACK_F32 ||
         stack_dtype > BF_STACK_BF16)
         return 0;
-    BatchPlan B;
-    // the three-kernel layout (blob and stacks) covers the fused one (blob only)
-    plan_batch(descs, count, stack_dtype, BF_FLAG_ALLOW_ILL_CONDITIONED, 16, 8, false, nullptr, B, true);
-    return B.total;
+    // the three-kernel layout (blob and stacks) covers the fused one (blob
+    // only); images are sized both as their own expansion and as routed to
+    // the pivoted form
+    BatchPlan A, B;
+    plan_batch(descs, count, stack_dtype, BF_FLAG_ALLOW_ILL_CONDITIONED, 16, 8, false, nullptr, A, true);
+    plan_batch(descs, count, stack_dtype, 0, 16, 8, false, nullptr, B, true);
+    return std::max(A.total, B.total);
 }
 
 bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, unsigned flags,

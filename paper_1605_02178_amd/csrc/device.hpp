@@ -391,11 +391,22 @@ struct BatchImage {
     int H, Wd, ld, lds, ldt, W, N, P;
     int off_taps, off_cq, off_cp, off_scale, off_bf, off_tf;
     int gbx, gvx, gvy, ghx;    // tile grid widths: build, column pass, row pass (fused form: gvx = tiles per row)
+    // Three-kernel form: the centring and output mask of the image's expansion
+    // (the plain one, or one sub-range of the pivoted form, which then runs as
+    // an image of its own writing only its pixels). Fused pivoted classes: K
+    // sub-ranges, K / 255 for pivot_of, and the FusedPivot table at prm +
+    // off_piv (taps at off_tf, coefficients at off_bf, as floats).
+    Centring C;
+    int K, off_piv;
+    float kscale;
 };
 
 // Phases of the three-kernel form (build, column pass, row pass + combine) or
-// geometry classes of the fused form; a form uses the first 3 or all 6.
-constexpr int kBatchPhases = 6;
+// classes of the fused form: the six geometry classes of the plain tile, then
+// the same six for images routed to the pivoted form. A form uses the first 3
+// or all 12.
+constexpr int kFusedClasses = 6;
+constexpr int kBatchPhases = 2 * kFusedClasses;
 
 struct BatchHeader {
     unsigned flags;            // BF_DEVFLAG_RANGE from the builds
@@ -403,8 +414,8 @@ struct BatchHeader {
     long long items[kBatchPhases];   // items in each phase
     long long queue[kBatchPhases];   // fused form: next item of each class (zero in every upload)
 };
-// device blob: BatchHeader | BatchImage[count] | long long start[6][count] |
-//              int order[6][count] | parameter blocks
+// device blob: BatchHeader | BatchImage[count] | long long start[12][count] |
+//              int order[12][count] | parameter blocks
 // In phase p the images are visited in order[p][0..count): item t belongs to
 // image order[p][k] for the last k with start[p][k] <= t. The host orders each
 // phase by decreasing cost per item (images with no items in a phase last), so
@@ -455,7 +466,7 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
             const int r0 = rb * kBuildRows;
             build_tile<S>(as_global(B.f), B.H, B.Wd, B.ld, as_global((T *)B.stackA), B.ps, B.lds, B.P,
                           prm + B.off_scale, B.mu, as_global(&hdr->flags), cb, r0, min(B.H, r0 + kBuildRows),
-                          plain_centring());
+                          B.C);
         } else if (PHASE == 1) {
             const int per_plane = B.gvx * B.gvy;
             const int n = l / per_plane, rem = l - n * per_plane;
@@ -465,7 +476,7 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
             hpass_tile<S, RH, true>(as_global((const T *)B.stackB), (T *)nullptr, as_global(B.f),
                                     as_global(B.out), nullptr, nullptr, B.H, B.Wd, B.ld, 0LL, 0, B.pst, B.ldt, B.P,
                                     B.N, prm + B.off_taps, prm + B.off_cq, prm + B.off_cp, B.W, l % B.ghx,
-                                    l / B.ghx, plain_centring());
+                                    l / B.ghx, B.C);
         }
     }
 }
@@ -1297,6 +1308,28 @@ struct FusedTile {
         store(r0, c0, y);
     }
 
+    // Mask of the sub-ranges present among the tile's output pixels (the
+    // lane's pixels, clamped into the image as load() reads them), or-ed over
+    // the block through m2 (two LDS words, zero on entry); one barrier. The
+    // same set k_pivot_masks finds for the tile.
+    __device__ __forceinline__ unsigned long long pivot_mask(const Raw &R, const float *lo, int K, float kscale,
+                                                             unsigned *m2) const {
+        unsigned long long m = 0;
+#pragma unroll
+        for (int b = 0; b < JB; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) m |= 1ull << pivot_of(R.c[b][v], lo, K, kscale);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) m |= __shfl_xor(m, off);
+        if (lane == 0) {
+            if ((unsigned)m) atomicOr(&m2[0], (unsigned)m);
+            if ((unsigned)(m >> 32)) atomicOr(&m2[1], (unsigned)(m >> 32));
+        }
+        __syncthreads();
+        return ((unsigned long long)__builtin_amdgcn_readfirstlane(m2[1]) << 32) |
+               (unsigned)__builtin_amdgcn_readfirstlane(m2[0]);
+    }
+
     // Pivoted form: the sub-range of each of the lane's output pixels
     // (pivot_of), then the planes of each sub-range in the tile's mask (every
     // sub-range some output pixel of the tile falls in, uniform), every pixel
@@ -1305,8 +1338,9 @@ struct FusedTile {
     __device__ __forceinline__ void run_pivots(int r0, int c0, const Raw &R, const FusedPivot *__restrict__ piv,
                                                const float *__restrict__ coef, int K, float kscale,
                                                const float *lo, unsigned long long todo,
-                                               unsigned *__restrict__ slot, int &base) {
-        check_range(R, nullptr, slot);
+                                               unsigned *__restrict__ flag, unsigned *__restrict__ slot,
+                                               int &base) {
+        check_range(R, flag, slot);
         int kb[JB][4];
 #pragma unroll
         for (int b = 0; b < JB; ++b)
@@ -1483,10 +1517,10 @@ __global__ __launch_bounds__(512) void k_fused_pivots(const float *__restrict__ 
         if constexpr (kPrefetch) {
             typename T::Raw next;
             if (tn >= 0) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, next);
-            tile.run_pivots(r0, c0, cur, piv, coef, K, kscale, s_lo, todo, slots + kFusedSlots * t, base);
+            tile.run_pivots(r0, c0, cur, piv, coef, K, kscale, s_lo, todo, nullptr, slots + kFusedSlots * t, base);
             cur = next;
         } else {
-            tile.run_pivots(r0, c0, cur, piv, coef, K, kscale, s_lo, todo, slots + kFusedSlots * t, base);
+            tile.run_pivots(r0, c0, cur, piv, coef, K, kscale, s_lo, todo, nullptr, slots + kFusedSlots * t, base);
             if (tn >= 0) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, cur);
         }
         if (tn < 0) break;
@@ -1887,6 +1921,65 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     typename T::Raw raw;
     tile.load((l / gvx) * kFusedRows, (l % gvx) * TC, raw);
     tile.run((l / gvx) * kFusedRows, (l % gvx) * TC, raw, as_global(&hdr->flags), nullptr);
+}
+
+// Batched fused kernel for images routed to the pivoted form (their single
+// expansion fails the conditioning check): one block per (image, tile) item
+// of the class, as k_fused_batched_items. The block finds the sub-ranges its
+// tile's output pixels fall in (FusedTile::pivot_mask, the set k_pivot_masks
+// gives the single-image form) and runs them with the image's sub-range
+// table (FusedTile::run_pivots), so each image equals its
+// bf_gc_forward_pivots result bit for bit.
+template <class M, int Q, int TC, int QA>
+__global__ __launch_bounds__(512) void k_fused_batched_pivot_items(char *__restrict__ blob) {
+    typedef typename M::E E;
+    typedef FusedTile<M, Q, TC, QA> T;
+    constexpr int C = kFusedClasses + fused_class(Q, QA);
+    extern __shared__ long long s_start[];
+    __shared__ __align__(16) E ybuf[2 * kFusedYElems];
+    __shared__ E tab[fused_tab_len(Q)];
+    __shared__ float s_lo[BF_MAX_PIVOTS];
+    __shared__ unsigned s_mask[2];
+    BatchHeader *hdr = (BatchHeader *)blob;
+    const long long t = blockIdx.x;
+    if (t >= hdr->items[C]) return;
+    const BatchImage *img = (const BatchImage *)(blob + sizeof(BatchHeader));
+    const int count = hdr->count;
+    int *s_order = (int *)(s_start + count);
+    const long long *start = (const long long *)(blob + sizeof(BatchHeader) + sizeof(BatchImage) * count);
+    const int *order = (const int *)(start + kBatchPhases * count);
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        s_start[k] = start[C * count + k];
+        s_order[k] = order[C * count + k];
+    }
+    if (threadIdx.x < 2) s_mask[threadIdx.x] = 0u;
+    __syncthreads();
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
+    const BatchImage &B = img[ii];
+    const int l = (int)(t - s_start[lo]);
+    const int gvx = uniform(B.gvx);
+    const int K = uniform(B.K);
+    const float kscale = __builtin_bit_cast(float, uniform(__builtin_bit_cast(int, B.kscale)));
+    const double *prm = as_global(uniform(B.prm));
+    const FusedPivot *piv = (const FusedPivot *)(prm + uniform(B.off_piv));
+    for (int i = threadIdx.x; i < K; i += blockDim.x) s_lo[i] = piv[i].lo;
+    T tile(as_global(uniform(B.f)), as_global(uniform(B.out)), uniform(B.H), uniform(B.Wd), uniform(B.ld),
+           uniform(B.W), 0, 0.0f, M::kPrescale, nullptr, ybuf);
+    tile.setup((const float *)(prm + uniform(B.off_tf)), tab);   // its barrier publishes s_lo
+    const int r0 = (l / gvx) * kFusedRows, c0 = (l % gvx) * TC;
+    typename T::Raw raw;
+    tile.load(r0, c0, raw);
+    const unsigned long long todo = tile.pivot_mask(raw, s_lo, K, kscale, s_mask);
+    int base = 0;
+    tile.run_pivots(r0, c0, raw, piv, (const float *)(prm + uniform(B.off_bf)), K, kscale, s_lo, todo,
+                    as_global(&hdr->flags), nullptr, base);
 }
 
 }  // namespace bfgc

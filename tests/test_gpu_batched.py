@@ -69,8 +69,9 @@ def test_batched_statuses_and_skips(torch_cuda):
     imgs, ss, sr = _batch(300, n=4)
     fs = [torch.tensor(a, device="cuda:0") for a in imgs]
     degrees = [bf.degree_rule(x) for x in sr]
-    sr[1], degrees[1] = 12.0, 170          # ill-conditioned in FP32
+    sr[1], degrees[1] = 2.0, 100           # ill-conditioned in FP32, and no sub-range count helps
     ss[2] = -1.0                           # invalid
+    assert bf.batched_route(2.0, 100, "f32") == 0
     outs = [torch.full_like(f, -7.0) for f in fs]
     outs, status = bf.gc_filter_batched(fs, ss, sr, degrees, outs=outs)
     assert status[0] == 0 and status[1] == 3 and status[2] == 1 and status[3] == 0
@@ -193,3 +194,85 @@ def test_fused_batched_graph_replays(torch_cuda):
             assert torch.equal(outs[k], bf.gc_filter(f, ss[k], 30.0, 28, stack_dtype="f16")), (rep, k)
         assert bf.read_flags(ws) == 0
         del junk
+
+
+# Images routed to the pivoted form: sigma_r below the stack type's domain,
+# one per geometry class of the fused tile, plus ragged and degenerate shapes.
+ROUTED_SIGMAS = [(2.0, 12.0), (4.0, 15.0), (7.0, 20.0), (10.0, 12.0), (12.0, 25.0), (15.0, 10.0),
+                 (2.0, 20.0), (1.0, 15.0), (15.0, 12.0)]
+
+
+def _routed_batch(seed):
+    from synth import edge_rich
+    rng = np.random.default_rng(seed)
+    shapes = [(int(rng.integers(40, 260)), int(rng.integers(40, 260))) for _ in range(6)]
+    shapes += [(1, 70), (97, 3), (300, 70)]
+    imgs = [edge_rich(h, w, seed=seed + k).astype(np.float32) for k, (h, w) in enumerate(shapes)]
+    ss = [a for a, _ in ROUTED_SIGMAS]
+    sr = [b for _, b in ROUTED_SIGMAS]
+    return imgs, ss, sr
+
+
+@pytest.mark.parametrize("dtype,cfg", [("f16", None), ("bf16", None), ("f32", 0), ("f32", 3), ("f16", 0)])
+@pytest.mark.parametrize("graph", [False, True])
+def test_routed_images_equal_pivoted_forward_bitwise(torch_cuda, dtype, cfg, graph):
+    """Images whose own expansion is ill-conditioned for the stack type run
+    the pivoted form inside the batch, next to plain images; each equals
+    bf_gc_forward_pivots with the route's sub-range count (rule degrees) bit
+    for bit under the same tile configuration (fused tile for the 16-bit
+    stacks by default, three-kernel tiles with cfg)."""
+    import paper_1605_02178_amd as bf
+    torch = torch_cuda
+    imgs, ss, sr = _routed_batch(1100)
+    # two plain images in the same call
+    imgs += [imgs[0].copy(), imgs[3].copy()]
+    ss += [3.0, 9.0]
+    sr += [50.0, 60.0]
+    fs = [torch.tensor(a, device="cuda:0") for a in imgs]
+    deg = [bf.degree_rule(x) for x in sr]
+    routes = [bf.batched_route(sr[k], deg[k], dtype) for k in range(len(fs))]
+    _log(f"routes {dtype}: {routes}")
+    assert all(r >= 2 for r in routes[:-2]) and routes[-2:] == [1, 1]
+    outs, status = bf.gc_filter_batched(fs, ss, sr, deg, stack_dtype=dtype, graph=graph, tile_config=cfg)
+    assert status == [0] * len(fs)
+    for k, f in enumerate(fs):
+        if routes[k] == 1:
+            ref = bf.gc_filter(f, ss[k], sr[k], deg[k], stack_dtype=dtype, tile_config=cfg)
+        else:
+            ref = bf.gc_filter_pivots(f, ss[k], sr[k], K=routes[k], stack_dtype=dtype, tile_config=cfg)
+        assert torch.equal(outs[k], ref), (k, f.shape, ss[k], sr[k], float((outs[k] - ref).abs().max()))
+
+
+def test_routed_images_graph_replays_and_flags(torch_cuda):
+    """One cached graph replayed over three routed batches (eager work between
+    replays), each replay against the pivoted forward; then a batch with an
+    out-of-range pixel in a routed image raises the range flag."""
+    import paper_1605_02178_amd as bf
+    torch = torch_cuda
+    ws = None
+    for rep in range(3):
+        imgs, ss, sr = _routed_batch(1200 + rep)
+        fs = [torch.tensor(a, device="cuda:0") for a in imgs]
+        deg = [bf.degree_rule(x) for x in sr]
+        if ws is None:
+            ws = torch.empty(4 * bf.batched_workspace_bytes([a.shape for a in imgs], ss, deg, "f16") + (1 << 24),
+                             dtype=torch.uint8, device="cuda:0")
+        outs, status = bf.gc_filter_batched(fs, ss, sr, deg, stack_dtype="f16", graph=True, workspace=ws)
+        junk = torch.randn(1 << 20, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        assert status == [0] * len(fs)
+        for k, f in enumerate(fs):
+            K = bf.batched_route(sr[k], deg[k], "f16")
+            assert torch.equal(outs[k], bf.gc_filter_pivots(f, ss[k], sr[k], K=K, stack_dtype="f16")), (rep, k)
+        assert bf.read_flags(ws) == 0
+        del junk
+    imgs, ss, sr = _routed_batch(1300)
+    imgs[3][5, 7] = 300.0
+    fs = [torch.tensor(a, device="cuda:0") for a in imgs]
+    deg = [bf.degree_rule(x) for x in sr]
+    outs, status = bf.gc_filter_batched(fs, ss, sr, deg, stack_dtype="f16", graph=True, workspace=ws)
+    assert status == [0] * len(fs)
+    assert bf.read_flags(ws) & bf.DEVFLAG_RANGE
+    K = bf.batched_route(sr[3], deg[3], "f16")
+    ref = bf.gc_filter_pivots(fs[3], ss[3], sr[3], K=K, stack_dtype="f16")
+    assert torch.equal(torch.nan_to_num(outs[3]), torch.nan_to_num(ref))
