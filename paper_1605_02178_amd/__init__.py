@@ -62,6 +62,8 @@ def tile_configs_for(stack_dtype, sigma_s) -> list:
     return cfgs
 MAX_DEGREE = 320
 MAX_RADIUS = 96
+# storage rounding unit of each stack type (FP32, FP16, BF16)
+_UNIT_ROUNDOFF = {0: 2.0 ** -24, 1: 2.0 ** -11, 2: 2.0 ** -8}
 
 
 def _dtype_code(stack_dtype) -> int:
@@ -143,6 +145,26 @@ def _stream_ptr(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def _on_stream(fn):
+    """Runs the wrapped call with `stream` (if given) as torch's current
+    stream, so that every tensor the call allocates (outputs, workspaces,
+    contiguous copies) and every copy it makes belong to the stream the
+    library launches on. The caching allocator then hands a freed workspace
+    only to later work on that stream, which runs after the kernels that use
+    it. Inputs must be ready on `stream` (the caller orders them), as for
+    any torch operation on a side stream."""
+    import functools
+
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kw):
+        if stream is None:
+            return fn(*args, stream=None, **kw)
+        import torch
+        with torch.cuda.stream(stream):
+            return fn(*args, stream=stream, **kw)
+    return wrapper
+
+
 def _check_image(f, name="f"):
     import torch
     if not isinstance(f, torch.Tensor) or not f.is_cuda:
@@ -153,6 +175,7 @@ def _check_image(f, name="f"):
         raise ValueError(f"{name} must have unit column stride")
 
 
+@_on_stream
 def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
               staged: bool = False, allow_ill_conditioned: bool = False, out=None, workspace=None,
               stream=None, tile_config: int | None = None, taylor: bool = False, coeffs=None,
@@ -217,6 +240,7 @@ def pivots_workspace_bytes(height, width, sigma_s, sigma_r, K, degree=None, stac
                                                         int(K), int(degree or 0), _dtype_code(stack_dtype)))
 
 
+@_on_stream
 def gc_filter_pivots(f, sigma_s: float, sigma_r: float, K: int | None = None, degree: int | None = None,
                      stack_dtype="f32", allow_ill_conditioned: bool = False, out=None, workspace=None,
                      stream=None, tile_config: int | None = None):
@@ -257,6 +281,7 @@ def joint_workspace_bytes(height, width, sigma_s, N, stack_dtype="f32") -> int:
                                                        _dtype_code(stack_dtype)))
 
 
+@_on_stream
 def gc_joint_filter(f, guide, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f32",
                     allow_ill_conditioned: bool = False, out=None, workspace=None, stream=None,
                     tile_config: int | None = None, coeffs=None):
@@ -290,10 +315,14 @@ def gc_joint_filter(f, guide, sigma_s: float, sigma_r: float, degree: int | None
     return out
 
 
+@_on_stream
 def gc_backward(f, grad_out, sigma_s: float, sigma_r: float, degree: int | None = None,
-                allow_ill_conditioned: bool = False, workspace=None, stream=None, coeffs=None):
-    """(dL/df, dL/dsigma_r) for L = sum(grad_out * gc_filter(f, ...)) with an
-    FP32 stack. Returns a float32 tensor like f and a 0-d float64 tensor."""
+                allow_ill_conditioned: bool = False, workspace=None, stream=None, coeffs=None, grad_f=None,
+                grad_sigma_r=None):
+    """(dL/df, dL/dsigma_r) for L = sum(grad_out * gc_filter(f, ...)), the
+    filter recomputed in FP64. Returns a float32 tensor like f and a 0-d
+    float64 tensor (or writes grad_f, contiguous like f, and grad_sigma_r, a
+    float64 device element)."""
     import torch
     _check_image(f)
     _check_image(grad_out, "grad_out")
@@ -301,8 +330,16 @@ def gc_backward(f, grad_out, sigma_s: float, sigma_r: float, degree: int | None 
     N = degree_rule(sigma_r) if degree is None else int(degree)
     f = f.contiguous()
     grad_out = grad_out.contiguous()
-    grad_f = torch.empty_like(f)
-    grad_sr = torch.empty((), dtype=torch.float64, device=f.device)
+    if grad_f is None:
+        grad_f = torch.empty_like(f)
+    elif tuple(grad_f.shape) != (H, Wd) or grad_f.dtype != torch.float32 or not grad_f.is_contiguous():
+        raise ValueError("grad_f must be a contiguous float32 tensor shaped like f")
+    if grad_sigma_r is None:
+        grad_sr = torch.empty((), dtype=torch.float64, device=f.device)
+    elif grad_sigma_r.numel() != 1 or grad_sigma_r.dtype != torch.float64 or not grad_sigma_r.is_cuda:
+        raise ValueError("grad_sigma_r must be one float64 device element")
+    else:
+        grad_sr = grad_sigma_r
     ld = f.stride(0) if H > 1 else Wd
     need = workspace_bytes(H, Wd, sigma_s, N, 0, for_backward=True)
     if workspace is None or workspace.numel() < need:
@@ -320,26 +357,43 @@ def _autograd_class():
     import torch
 
     class GaussChebyshevBF(torch.autograd.Function):
-        """y = GaussChebyshevBF.apply(f, sigma_r, sigma_s, degree, stack_dtype)
+        """y = GaussChebyshevBF.apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs, sigma_r_host)
 
         f: float32 CUDA tensor (H, W) or (..., H, W); sigma_r: 0-d tensor
-        (differentiable); sigma_s, degree: constants. Saves only f and sigma_r;
-        the backward recomputes the stack (bf_gc_backward, FP32 stack)."""
+        (differentiable); sigma_s, degree: constants; sigma_r_host: the value
+        of sigma_r as a Python float, if the caller has it (else it is read
+        from the tensor, a device sync when sigma_r lives on the GPU; a CPU
+        tensor is read without one). The forward filters the whole batch in
+        one bf_gc_batched launch. Saves only f and sigma_r; the backward
+        recomputes the filter in FP64 per image (bf_gc_backward), so the
+        gradient is that of the Gauss-Chebyshev filter itself, whatever stack
+        type the forward used: for an FP16/BF16 forward it is the gradient of
+        the function the 16-bit stack approximates."""
 
         @staticmethod
-        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None):
-            sr = float(sigma_r)
+        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None, sigma_r_host=None):
+            sr = float(sigma_r_host) if sigma_r_host is not None else float(sigma_r)
             N = degree_rule(sr) if degree is None else int(degree)
             shape = f.shape
             x = f.reshape(-1, shape[-2], shape[-1])
+            if not x.is_contiguous():
+                x = x.contiguous()
             y = torch.empty_like(x)
-            ws = torch.empty(max(workspace_bytes(shape[-2], shape[-1], sigma_s, N, stack_dtype), 256),
-                             dtype=torch.uint8, device=f.device)
-            for b in range(x.shape[0]):
-                gc_filter(x[b].contiguous(), sigma_s, sr, N, stack_dtype=stack_dtype, out=y[b], workspace=ws,
-                          coeffs=coeffs)
+            B = x.shape[0]
+            # the single-image forward's conditioning check (the batch would
+            # route such an image to the pivoted form, whose gradient the
+            # backward does not compute)
+            kappa = fit(sr, N, coeffs)["kappa"]
+            if not kappa * _UNIT_ROUNDOFF[_dtype_code(stack_dtype)] <= 1e-2:
+                raise ValueError(f"GaussChebyshevBF: ill-conditioned at sigma_r={sr}, N={N} for the "
+                                 f"{stack_dtype} stack (kappa={kappa:.3g})")
+            _, status = gc_filter_batched([x[b] for b in range(B)], [sigma_s] * B, [sr] * B, [N] * B,
+                                          stack_dtype=stack_dtype, graph=False, outs=[y[b] for b in range(B)],
+                                          coeffs=coeffs, allow_ill_conditioned=True)
+            if any(status):
+                raise BFError(next(v for v in status if v), "GaussChebyshevBF forward")
             ctx.save_for_backward(f, sigma_r)
-            ctx.sigma_s, ctx.N, ctx.coeffs = float(sigma_s), N, coeffs
+            ctx.sigma_s, ctx.sigma_r, ctx.N, ctx.coeffs = float(sigma_s), sr, N, coeffs
             return y.reshape(shape)
 
         @staticmethod
@@ -348,20 +402,18 @@ def _autograd_class():
             shape = f.shape
             x = f.reshape(-1, shape[-2], shape[-1])
             g = grad_y.reshape(-1, shape[-2], shape[-1]).contiguous()
+            B = x.shape[0]
             gf = torch.empty_like(x)
-            gsr = torch.zeros((), dtype=torch.float64, device=f.device)
+            gsr = torch.empty(B, dtype=torch.float64, device=f.device)
             ws = torch.empty(max(workspace_bytes(shape[-2], shape[-1], ctx.sigma_s, ctx.N, 0, True), 256),
                              dtype=torch.uint8, device=f.device)
-            for b in range(x.shape[0]):
-                gfb, gsb = gc_backward(x[b].contiguous(), g[b], ctx.sigma_s, float(sigma_r), ctx.N,
-                                       workspace=ws, coeffs=ctx.coeffs)
-                gf[b].copy_(gfb)
-                gsr = gsr + gsb
-            return gf.reshape(shape), gsr.to(sigma_r.dtype).reshape(sigma_r.shape), None, None, None, None
+            for b in range(B):
+                gc_backward(x[b].contiguous(), g[b], ctx.sigma_s, ctx.sigma_r, ctx.N, workspace=ws,
+                            coeffs=ctx.coeffs, grad_f=gf[b], grad_sigma_r=gsr[b])
+            gs = gsr.sum().to(device=sigma_r.device, dtype=sigma_r.dtype).reshape(sigma_r.shape)
+            return gf.reshape(shape), gs, None, None, None, None, None
 
     return GaussChebyshevBF
-
-
 _GCBF = None
 
 
@@ -374,9 +426,10 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None):
-    """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor."""
-    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs)
+def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None, sigma_r_host=None):
+    """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor
+    (sigma_r_host: its value as a float, which spares a device sync)."""
+    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs, sigma_r_host)
 
 
 def _descs(images, outs, sigmas_s, sigmas_r, degrees):
@@ -409,6 +462,7 @@ def batched_workspace_bytes(shapes, sigmas_s, degrees, stack_dtype="f32") -> int
     return int(_lib.load().bf_gc_batched_workspace_bytes(arr, len(shapes), _dtype_code(stack_dtype)))
 
 
+@_on_stream
 def gc_filter_batched(images, sigmas_s, sigmas_r, degrees=None, stack_dtype="f32", graph: bool = True,
                       tile_config: int | None = None, allow_ill_conditioned: bool = False, outs=None,
                       workspace=None, stream=None, coeffs=None):
@@ -468,6 +522,7 @@ class StackLayout:
         return self.data[:, :, : self.width]
 
 
+@_on_stream
 def stack_build(f, sigma_r, N, stack_dtype="f32", stack: StackLayout | None = None, prm=None, devflag=None,
                 stream=None) -> StackLayout:
     import torch
@@ -485,6 +540,7 @@ def stack_build(f, sigma_r, N, stack_dtype="f32", stack: StackLayout | None = No
     return stack
 
 
+@_on_stream
 def gauss_planes(stack: StackLayout, sigma_s, tmp=None, prm=None, stream=None):
     """Filters every plane of `stack` in place (eq. 7). `tmp`: optional uint8
     device scratch of at least bf_gc_gauss_tmp_bytes bytes."""
@@ -504,6 +560,7 @@ def gauss_planes(stack: StackLayout, sigma_s, tmp=None, prm=None, stream=None):
     return stack
 
 
+@_on_stream
 def combine(f, stack: StackLayout, sigma_r, out=None, want_pq=False, prm=None, stream=None):
     """Returns y, or (y, P', Q') with want_pq."""
     import torch

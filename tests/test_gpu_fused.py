@@ -14,7 +14,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-BOUND = {("f16", 30.0, 28): 2.5, ("f16", 30.0, 30): 2.5, ("f16", 50.0, 11): 0.5, ("bf16", 50.0, 11): 3.0}
+BOUND = {("f16", 30.0, 28): 2.5, ("f16", 30.0, 30): 2.5, ("f16", 30.0, 32): 0.35, ("f16", 50.0, 11): 0.5,
+         ("bf16", 50.0, 11): 3.0}
 
 
 @pytest.fixture(scope="module")
@@ -155,7 +156,7 @@ def test_fused_range_flag_follows_the_last_call(torch_cuda):
         assert bool(got) == flagged, (k, cfg, flagged)
 
 
-@pytest.mark.parametrize("N", [28, 30])
+@pytest.mark.parametrize("N", [28, 30, 32])
 def test_fused_headline_size_sampled(torch_cuda, N):
     """4096^2 edge-rich, sigma_s = 10, sigma_r = 30, FP16 stack, fused tile (the
     configuration the benchmark times for the FP16 stack): the oracle on a
