@@ -3,19 +3,24 @@ planes made in registers, both passes of eq. 7 as banded Toeplitz products on
 the matrix cores with FP32 accumulation, eqs. 8-10 folded in) against the FP64
 oracle, element by element, through the C ABI.
 
-Stated bounds (max |gpu - oracle| on the 0-255 scale), the same as for the
-three-kernel reduced-precision path. Storage rounding of the planes
-dominates: FP16 at sigma_r = 30 carries kappa * 2^-11 ~ 7e-3 of kernel error.
-The tap rounding to the stack type and the FP32 sums add little beside it
-(a CPU emulation of exactly this arithmetic gives 0.05-0.2 at sigma_r = 30).
+Bars (max |gpu - oracle| on the 0-255 scale) per (stack, sigma_r, N), about
+three times the largest error measured over every test that uses the
+configuration (in the comments). Storage rounding of the planes dominates:
+FP16 at sigma_r = 30, N = 28 carries kappa 2^-11 ~ 7e-3 of kernel error,
+which falls with N as kappa does (15 at N = 28, 1.6 at N = 34).
 """
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
-BOUND = {("f16", 30.0, 28): 2.5, ("f16", 30.0, 30): 2.5, ("f16", 30.0, 32): 0.35, ("f16", 50.0, 11): 0.5,
-         ("bf16", 50.0, 11): 3.0}
+BOUND = {
+    ("f16", 30.0, 28): 2.4,     # measured 0.78 (65 x 129, sigma_s = 10); 0.44 on the 4096^2 centre crop
+    ("f16", 30.0, 30): 0.7,     # measured 0.23 (4096^2 centre crop)
+    ("f16", 30.0, 32): 0.35,    # measured 0.108 (4096^2 centre crop, the benchmark's FP16 configuration)
+    ("f16", 50.0, 11): 0.05,    # measured 0.0156
+    ("bf16", 50.0, 11): 1.0,    # measured 0.34 (1100 x 2050 corner)
+}
 
 
 @pytest.fixture(scope="module")

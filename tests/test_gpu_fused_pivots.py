@@ -6,14 +6,16 @@ Each 64-row tile runs only the sub-ranges its own output pixels fall in, so
 the cases include tiles that hold one sub-range, tiles that hold all of them,
 pixels on every sub-range boundary, every geometry class of the fused tile
 (W = 6, 12, 21, 30, 36, 45), ragged tails and images narrower or shorter than
-the radius. Bars: the 16-bit stacks' stated bounds at small sigma_r, FP16 2.5
-and BF16 3.0 on the 0-255 scale (as for the three-kernel pivoted form)."""
+the radius. Bars on the 0-255 scale, about three times the largest error
+measured over these tests: FP16 0.02 (measured 6.95e-3), BF16 0.12 (measured
+3.95e-2); every sub-range has kappa near 1, so its rounding stays near the
+stack's own unit."""
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
-BAR = {"f16": 2.5, "bf16": 3.0}
+BAR = {"f16": 0.02, "bf16": 0.12}
 
 
 @pytest.fixture(scope="module")
@@ -68,7 +70,7 @@ def test_fused_pivots_match_three_kernel_tiles(torch_cuda):
     ref = C.pivot_gcf(f, 5.0, 10.0, K)
     ea, eb, eab = (float(np.abs(x).max()) for x in (a - ref, b - ref, a - b))
     _log(f"fused pivots K={K}: fused {ea:.3e}, three-kernel {eb:.3e}, between {eab:.3e}")
-    assert ea <= 2.5 and eb <= 2.5 and eab <= 2.5
+    assert ea <= BAR["f16"] and eb <= BAR["f16"] and eab <= BAR["f16"]
 
 
 def test_fused_pivots_tiles_with_one_and_all_subranges(torch_cuda):
@@ -95,7 +97,7 @@ def test_fused_pivots_tiles_with_one_and_all_subranges(torch_cuda):
     ref = C.pivot_gcf(f, 2.0, 10.0, K)
     err = np.abs(out - ref).max()
     _log(f"fused pivots one/all sub-ranges per tile: {err:.3e}")
-    assert err <= 2.5
+    assert err <= BAR["f16"]
     for by in range(3):
         for bx in range(4):
             if (by + bx) % 2 == 0:
@@ -115,7 +117,7 @@ def test_fused_pivots_small_and_ragged(torch_cuda, shape, sigma_s):
                                 tile_config=bf.TILE_FUSED))
     err = np.abs(y - C.pivot_gcf(f, sigma_s, 10.0, K)).max()
     _log(f"fused pivots {shape} ss={sigma_s}: {err:.3e}")
-    assert err <= 2.5
+    assert err <= BAR["f16"]
 
 
 def test_fused_pivots_boundaries_flags_and_every_output(torch_cuda):
@@ -145,7 +147,7 @@ def test_fused_pivots_boundaries_flags_and_every_output(torch_cuda):
     y = _np(out)
     err = np.abs(y - C.pivot_gcf(clean, 3.0, 10.0, K)).max()
     _log(f"fused pivots boundaries: {err:.3e}")
-    assert err <= 2.5
+    assert err <= BAR["f16"]
 
 
 def test_fused_pivots_errors_and_fallback(torch_cuda):
@@ -186,4 +188,4 @@ def test_fused_pivots_4096_sampled(torch_cuda):
     for reg in ((1984, 2112, 1984, 2112), (0, 96, 0, 96), (4000, 4096, 4020, 4096)):
         err = np.abs(_np(y[reg[0]:reg[1], reg[2]:reg[3]]) - C.pivot_gcf(f, 10.0, 10.0, K, region=reg)).max()
         _log(f"fused pivots 4096^2 crop {reg}: {err:.3e}")
-        assert err <= 2.5
+        assert err <= BAR["f16"]

@@ -1,7 +1,7 @@
 """GPU parity of the joint (cross) bilateral filter (bf_gc_joint_forward)
-against the FP64 oracle's joint filter, through the C ABI. Bars: the FP32
-stack as for the plain filter (1e-3 on the 0-255 scale, times kappa/15 where
-kappa > 15); FP16/BF16 stacks the plain filter's stated bounds."""
+against the FP64 oracle's joint filter, through the C ABI. Bars on the 0-255
+scale: the FP32 stack 1e-3 (measured at most 1.8e-4); the 16-bit stacks about
+three times the largest error measured per configuration (in the comments)."""
 import numpy as np
 import pytest
 
@@ -34,9 +34,7 @@ def _pair(shape, seed):
     return f, g
 
 
-def _fp32_tol(sigma_r, N):
-    import paper_1605_02178_amd as bf
-    return 1e-3 * max(1.0, bf.query(sigma_r, N)[1] / 15.0)
+FP32_TOL = 1e-3
 
 
 SHAPES = [((150, 170), 3.0), ((65, 129), 10.0), ((1, 77), 2.0), ((129, 5), 2.0), ((7, 300), 5.0),
@@ -51,7 +49,7 @@ def test_joint_fp32_parity(torch_cuda, shape, sigma_s):
     y = _np(bf.gc_joint_filter(_gpu(torch_cuda, f), _gpu(torch_cuda, g), sigma_s, 30.0, 28))
     err = np.abs(y - F.joint_gcf(f, g, sigma_s, 30.0, 28)).max()
     _log(f"joint f32 {shape} ss={sigma_s}: {err:.3e}")
-    assert err <= _fp32_tol(30.0, 28)
+    assert err <= FP32_TOL
 
 
 def test_joint_reductions(torch_cuda):
@@ -72,8 +70,9 @@ def test_joint_reductions(torch_cuda):
     assert np.abs(y - ref).max() <= 1e-3
 
 
-@pytest.mark.parametrize("dtype,sigma_r,N,bound", [("f16", 30.0, 28, 2.5), ("f16", 50.0, 11, 0.5),
-                                                   ("bf16", 50.0, 11, 3.0)])
+# three-kernel tiles: measured 0.156, 0.0218, 0.23
+@pytest.mark.parametrize("dtype,sigma_r,N,bound", [("f16", 30.0, 28, 0.5), ("f16", 50.0, 11, 0.07),
+                                                   ("bf16", 50.0, 11, 0.7)])
 def test_joint_reduced_precision_bounds(torch_cuda, dtype, sigma_r, N, bound):
     import paper_1605_02178_amd as bf
     from oracle import filters as F
@@ -142,7 +141,8 @@ def test_joint_1024_crops(torch_cuda):
 @pytest.mark.parametrize("shape,sigma_s", [((150, 170), 2.0), ((150, 170), 5.0), ((65, 129), 10.0), ((1, 77), 2.0),
                                            ((129, 5), 2.0), ((300, 7), 3.0), ((150, 170), 12.0), ((97, 140), 13.0),
                                            ((140, 190), 15.0)])
-@pytest.mark.parametrize("dtype,sigma_r,N,bound", [("f16", 30.0, 28, 2.5), ("bf16", 50.0, 11, 3.0)])
+# fused tile: measured at most 0.80 (FP16) and 0.91 (BF16), both on 65 x 129 at sigma_s = 10
+@pytest.mark.parametrize("dtype,sigma_r,N,bound", [("f16", 30.0, 28, 2.4), ("bf16", 50.0, 11, 2.7)])
 def test_joint_fused_parity(torch_cuda, shape, sigma_s, dtype, sigma_r, N, bound):
     """The fused matrix-core joint kernel (all three geometries: W <= 16 and
     W <= 32 on 64-column tiles, W = 36, 39, 45 on 32-column tiles; ragged
@@ -167,5 +167,6 @@ def test_joint_fused_guide_f_matches_plain_fused(torch_cuda):
     ft = _gpu(torch, f)
     a = _np(bf.gc_joint_filter(ft, ft.clone(), 4.0, 30.0, 28, stack_dtype="f16"))
     b = _np(bf.gc_filter(ft, 4.0, 30.0, 28, stack_dtype="f16"))
-    assert np.abs(a - b).max() <= 2.5
+    _log(f"joint fused with g = f against the plain fused kernel: {np.abs(a - b).max():.3e}")
+    assert np.abs(a - b).max() <= 2.4
     assert np.array_equal(a, _np(bf.gc_joint_filter(ft, ft.clone(), 4.0, 30.0, 28, stack_dtype="f16")))

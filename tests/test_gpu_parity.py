@@ -1,12 +1,17 @@
 """GPU parity: the HIP library against the FP64 CPU oracle, element by element
 on the same seeded inputs, through the C ABI.
 
-Bar for the FP32 stack: max |gpu - oracle| <= 1e-3 on the 0-255 scale at the
-paper's operating point (sigma_r = 30, N = 28, kappa = 15) and wherever the
-conditioning kappa = max_y e^{-mu|y|} sum |b_n| |y|^n is no larger. FP32
-rounding of the stored planes is amplified by kappa, so for 25 <= sigma_r < 30
-the bar is 1e-3 * kappa / 15. Reduced-precision stacks are held to the stated
-bounds below."""
+Bar for the FP32 stack: max |gpu - oracle| <= 1e-3 on the 0-255 scale. FP32
+rounding of the stored planes reaches the output amplified by the
+conditioning kappa = max_y e^{-mu|y|} sum |b_n| |y|^n (about kappa 2^-24 t_h),
+so the bar holds where kappa 2^-24 <= 1e-5 (sigma_r >= 25 at the rule's
+degree). The cases outside it are numbered exceptions with bars of their own,
+about three times the measured error:
+  E1  W = 1, sigma_r = 25, N = 40 (kappa 150), staged: measured 1.5e-3, bar 5e-3;
+  E2  the degree sweep at N = 4, 8, 12, 16 (kappa 2e5, 1.3e5, 2.5e4, 2e3),
+      bars in SWEEP_Y (test_degree_sweep_edge_rich).
+Reduced-precision stacks are held to bars per configuration, about three
+times the measured error."""
 import math
 
 import numpy as np
@@ -17,10 +22,8 @@ pytestmark = pytest.mark.gpu
 FP32_TOL = 1e-3
 
 
-def fp32_tol(sigma_r, N):
-    import paper_1605_02178_amd as bf
-    _, kappa = bf.query(sigma_r, N)
-    return FP32_TOL * max(1.0, kappa / 15.0)
+# numbered exception E1 (module docstring): (shape, sigma_s, sigma_r, N) -> bar
+FP32_EXCEPTIONS = {((64, 65), 0.3, 25.0, 40): 5e-3}
 
 
 @pytest.fixture(scope="module")
@@ -81,7 +84,7 @@ def test_ragged_and_degenerate_shapes(torch_cuda, shape, sigma_s, sigma_r, N, st
     y = _np(bf.gc_filter(_gpu(torch_cuda, f), sigma_s, sigma_r, N, staged=staged))
     ref = C.gcf(f, sigma_s, sigma_r, N)
     err = np.abs(y - ref).max()
-    tol = fp32_tol(sigma_r, N)
+    tol = FP32_EXCEPTIONS.get((shape, sigma_s, sigma_r, N), FP32_TOL)
     _log(f"{shape} ss={sigma_s} sr={sigma_r} N={N} staged={staged}: {err:.3e} (tol {tol:.2e})")
     assert err <= tol
 
@@ -161,12 +164,14 @@ def test_fp16_plane_scaling_in_stack(torch_cuda):
     assert np.abs(planes).max() <= 2 ** 15
 
 
-# Stated bounds for the reduced-precision stacks (FP32 accumulation, FP64
-# combine): FP16 at sigma_r = 30 carries kappa * 2^-11 ~ 7e-3 of kernel error.
+# Bars for the reduced-precision stacks on the three-kernel tiles (FP64
+# accumulation and combine), about three times the larger of the fused and
+# staged errors measured: 0.49, 0.040, 0.35. FP16 at sigma_r = 30 carries
+# kappa 2^-11 ~ 7e-3 of kernel error.
 REDUCED = [
-    ("f16", 30.0, 28, 2.5),
-    ("f16", 50.0, 11, 0.5),
-    ("bf16", 50.0, 11, 3.0),
+    ("f16", 30.0, 28, 1.5),
+    ("f16", 50.0, 11, 0.12),
+    ("bf16", 50.0, 11, 1.05),
 ]
 
 
@@ -222,32 +227,52 @@ def test_ill_conditioned_refused(torch_cuda):
     assert e.value.status == 3
 
 
+# Degree sweep bars on y (max-abs, 0-255 scale), about three times the measured
+# error; N <= 16 is exception E2 (kappa >= 2e3 puts FP32's rounding above
+# 1e-3): measured 0.83, 0.088, 0.36, 0.025, 3.1e-4, 1.1e-4, 2.7e-5, 8.1e-6.
+SWEEP_Y = {4: 2.5, 8: 0.27, 12: 1.1, 16: 0.075, 20: FP32_TOL, 24: FP32_TOL, 28: FP32_TOL, 34: FP32_TOL}
+# Bars on P' and Q' (eqs. 8-9) at every pixel, relative to the crop's largest
+# |Q'|, about three times the measured 7.6e-8, 1.1e-7, 8.1e-7, 5.1e-6, 4.3e-6,
+# 1.5e-6, 3.3e-7, 8.9e-8.
+SWEEP_PQ = {4: 2.5e-7, 8: 3.5e-7, 12: 2.5e-6, 16: 1.6e-5, 20: 1.3e-5, 24: 4.5e-6, 28: 1e-6, 34: 2.7e-7}
+
+
 @pytest.mark.parametrize("N", [4, 8, 12, 16, 20, 24, 28, 34])
 def test_degree_sweep_edge_rich(torch_cuda, N):
-    """1024^2 edge-rich image, sigma_s = 5, sigma_r = 30, on a 256^2 crop:
-    against the approximation oracle (held) and against the direct filter
-    (reported: below N ~ 24 the polynomial's kernel error exceeds 1 and the
-    filter is far from the direct one, as the paper's choice of N = 28
-    implies). For N < 28 kappa grows (kappa(20) ~ 2e2, kappa(4) ~ 2e5), and so
-    does the FP32 rounding the filter carries: tolerance
-    1e-3 * max(1, kappa/15). At low N the polynomial can also make Q cancel,
-    and P/Q there is conditioned by the cancellation, not by kappa: pixels
-    whose oracle Q is below 1% of the crop's median Q are left out (none at
-    N >= 24). N = 4 (kappa ~ 2e5) is outside the domain the library accepts
-    and is refused without the allow flag."""
+    """1024^2 edge-rich image, sigma_s = 5, sigma_r = 30, on a 256^2 crop,
+    against the approximation oracle (held) and the direct filter (reported:
+    below N ~ 24 the polynomial's kernel error exceeds 1 and the filter is far
+    from the direct one, as the paper's choice of N = 28 implies). For N < 28
+    kappa grows (kappa(20) ~ 2e2, kappa(4) ~ 2e5), and so does the FP32
+    rounding the filter carries. Every pixel's P' and Q' (eqs. 8-9, from the
+    staged kernels) is held to the oracle's, relative to the crop's scale of
+    Q'. At low N the polynomial can make Q cancel, and y = t_c + t_h P'/Q'
+    there is conditioned by the cancellation, not by kappa: y is held at the
+    pixels whose oracle Q' is at least 1% of the crop's median (every pixel
+    for N >= 24), and reported at the others. N = 4 (kappa ~ 2e5) is outside
+    the domain the library accepts and is refused without the allow flag."""
     import paper_1605_02178_amd as bf
+    from oracle import filters as F
     from oracle import native as C
     from synth import edge_rich
+    torch = torch_cuda
     f = edge_rich(1024, 1024, seed=2).astype(np.float32).astype(np.float64)
     _, kappa = bf.query(30.0, N)
     in_domain = kappa * 2.0 ** -24 <= 1e-2
     if not in_domain:
         with pytest.raises(bf.BFError) as e:
-            bf.gc_filter(_gpu(torch_cuda, f[:64, :64]), 5.0, 30.0, N)
+            bf.gc_filter(_gpu(torch, f[:64, :64]), 5.0, 30.0, N)
         assert e.value.status == 3
-    y = _np(bf.gc_filter(_gpu(torch_cuda, f), 5.0, 30.0, N, allow_ill_conditioned=True))
+    ft = _gpu(torch, f)
+    y = _np(bf.gc_filter(ft, 5.0, 30.0, N, allow_ill_conditioned=True))
+    st = bf.gauss_planes(bf.stack_build(ft, 30.0, N), 5.0)
+    _, Pg, Qg = bf.combine(ft, st, 30.0, want_pq=True)
     reg = (384, 640, 384, 640)
     ref, P, Q = C.gcf(f, 5.0, 30.0, N, region=reg, return_pq=True)
+    S = F.spatial_kernel_1d(5.0).sum() ** 2
+    Pr, Qr = P / (127.5 * S), Q / S
+    scale = np.abs(Qr).max()
+    ePQ = max(np.abs(_np(Pg)[384:640, 384:640] - Pr).max(), np.abs(_np(Qg)[384:640, 384:640] - Qr).max()) / scale
     direct = C.direct_bf(f, 5.0, 30.0, region=reg)
     ok = Q >= 1e-2 * np.median(Q[Q > 0])
     if N >= 24:
@@ -255,10 +280,12 @@ def test_degree_sweep_edge_rich(torch_cuda, N):
     yc = y[384:640, 384:640]
     err = np.abs(yc - ref)[ok].max()
     ed = np.abs(yc - direct)[ok].max()
+    e_rest = float(np.abs(yc - ref)[~ok].max()) if (~ok).any() else 0.0
     _log(f"sweep N={N}: max err {err:.3e} against the approximation oracle, {ed:.3e} against the direct "
-         f"filter, kappa {kappa:.3g}, pixels with cancelled Q {int((~ok).sum())}"
-         f"{'' if in_domain else ' (outside the domain)'}")
-    assert err <= fp32_tol(30.0, N)
+         f"filter, P'/Q' {ePQ:.3e} of max|Q'|, kappa {kappa:.3g}, pixels with cancelled Q {int((~ok).sum())} "
+         f"(y there {e_rest:.3e}){'' if in_domain else ' (outside the domain)'}")
+    assert ePQ <= SWEEP_PQ[N]
+    assert err <= SWEEP_Y[N]
 
 
 def test_headline_size_sampled(torch_cuda):
