@@ -364,6 +364,30 @@ int bf_gc_batched_route(double sigma_r, int N, int stack_dtype, unsigned flags);
 bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, unsigned flags,
                         int *per_image_status, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * forward of bf_gc_forward on the fused tile (FP16/BF16 stacks, radius
+ * ceil(3 sigma_s) <= BF_FUSED_MAX_RADIUS; other stacks or radii:
+ * BF_ERR_UNSUPPORTED; staged, recursive or three-kernel tile flags:
+ * BF_ERR_INVALID_ARG), with no workspace argument. Its only scratch, the
+ * per-wave range words of the launch (32 bytes per 64-row tile), lives in a
+ * library-owned device array of BF_NOALLOC_SCRATCH_BYTES per GPU, held until
+ * the process ends; an image that needs more gets BF_ERR_UNSUPPORTED. The call
+ * allocates no device memory and calls no allocating routine; the array's
+ * device address is looked up once per device on the first call there.
+ * Every word the call reads back is written by the same launch, so nothing
+ * needs clearing. Arguments, checks and output as bf_gc_forward; out equals
+ * bf_gc_forward's bit for bit. range_flag: device unsigned or NULL; if given,
+ * it receives BF_DEVFLAG_RANGE or 0 (a plain store, after the filter, on
+ * `stream`). Calls that overlap on one GPU share its scratch and race (their
+ * range flags may mix; outputs are unaffected); order them on one stream.
+ */
+#define BF_NOALLOC_SCRATCH_BYTES (4u << 20)
+bf_status bf_gc_forward_noalloc(const float *f, float *out, int height, int width, int ld, double sigma_s,
+                                double sigma_r, int N, int stack_dtype, unsigned flags, unsigned *range_flag,
+                                void *stream);
+
 /* Reads the range flags of the last call that used workspace ws
  * (bf_gc_forward, bf_gc_joint_forward, bf_gc_forward_pivots, bf_gc_backward
  * or bf_gc_batched): the flag word, or the or of the per-wave words a fused

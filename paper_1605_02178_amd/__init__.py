@@ -25,7 +25,7 @@ __all__ = [
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
     "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
     "gc_joint_filter", "joint_workspace_bytes", "gc_filter_pivots", "pivot_count", "pivot_plan",
-    "pivots_workspace_bytes", "batched_route",
+    "pivots_workspace_bytes", "batched_route", "gc_filter_noalloc", "NOALLOC_SCRATCH_BYTES",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -216,6 +216,37 @@ def gc_filter(f, sigma_s: float, sigma_r: float, degree: int | None = None, stac
                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                                    _stream_ptr(stream))
     _lib.check(st, "bf_gc_forward")
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 4 << 20
+
+
+@_on_stream
+def gc_filter_noalloc(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f16", out=None,
+                      range_flag=None, stream=None):
+    """bf_gc_forward_noalloc: the fused-tile forward (FP16/BF16 stacks,
+    radius <= FUSED_MAX_RADIUS) with no workspace; the library's own device
+    scratch holds the range words. `out` must be given where nothing may be
+    allocated; range_flag: optional int32/uint32 device tensor of one element
+    that receives DEVFLAG_RANGE or 0."""
+    import torch
+    _check_image(f)
+    H, Wd = f.shape
+    N = degree_rule(sigma_r) if degree is None else int(degree)
+    if out is None:
+        out = torch.empty_like(f, memory_format=torch.contiguous_format)
+    _check_image(out, "out")
+    if out.stride(0) != f.stride(0) and H > 1:
+        raise ValueError("out must have the row stride of f")
+    if range_flag is not None and (not range_flag.is_cuda or range_flag.numel() != 1 or range_flag.element_size() != 4):
+        raise ValueError("range_flag must be one 4-byte device element")
+    ld = f.stride(0) if H > 1 else Wd
+    st = _lib.load().bf_gc_forward_noalloc(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), H, Wd,
+                                           max(ld, Wd), float(sigma_s), float(sigma_r), N, _dtype_code(stack_dtype),
+                                           0, ctypes.c_void_p(range_flag.data_ptr() if range_flag is not None else 0),
+                                           _stream_ptr(stream))
+    _lib.check(st, "bf_gc_forward_noalloc")
     return out
 
 

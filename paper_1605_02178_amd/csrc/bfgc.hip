@@ -335,6 +335,35 @@ static bf_status run_fused(const float *f, float *out, int H, int Wd, int ld, do
     return fail(BF_ERR_UNSUPPORTED, "fused path: radius above BF_FUSED_MAX_RADIUS");
 }
 
+// Scratch of bf_gc_forward_noalloc: the range words of one fused launch in a
+// file-scope device array (each device that runs the library holds its own
+// copy until the process ends). Host code uses the device address that
+// hipGetSymbolAddress returns for the current device, never the array's
+// name, which is a host-side stand-in.
+constexpr size_t kNoAllocScratchBytes = (size_t)BF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+static std::mutex g_scratch_mtx;
+static std::unordered_map<int, void *> g_scratch_ptr;
+
+static bf_status noalloc_scratch(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(BF_ERR_DEVICE, std::string("bf_gc_forward_noalloc: ") + hipGetErrorString(e));
+    std::lock_guard<std::mutex> lock(g_scratch_mtx);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return BF_OK;
+    }
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(BF_ERR_DEVICE, std::string("bf_gc_forward_noalloc: scratch address: ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
+    return BF_OK;
+}
+
 template <class S, int RV, int RH>
 static bf_status run_forward(const float *f, float *out, int H, int Wd, int ld, double sigma_s, double sigma_r,
                              int N, int dtype, unsigned flags, char *ws, hipStream_t stream) {
@@ -1353,6 +1382,44 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
     }
 #undef BF_FWD_CFG
 #undef BF_FWD
+}
+
+bf_status bf_gc_forward_noalloc(const float *f, float *out, int height, int width, int ld, double sigma_s,
+                                double sigma_r, int N, int stack_dtype, unsigned flags, unsigned *range_flag,
+                                void *stream) {
+    bf_status st = check_common(height, width, sigma_s, sigma_r, N, stack_dtype);
+    if (st != BF_OK) return st;
+    const int cfg = tile_config_of(flags);
+    if (cfg == -2 || (cfg != -1 && cfg != BF_TILE_FUSED) || (flags & (BF_FLAG_STAGED | BF_FLAG_RECURSIVE)))
+        return fail(BF_ERR_INVALID_ARG, "bf_gc_forward_noalloc runs the fused tile only (no staged, recursive or "
+                                        "three-kernel tile flags)");
+    if (!fused_applies(stack_dtype, sigma_s))
+        return fail(BF_ERR_UNSUPPORTED, "bf_gc_forward_noalloc: FP16/BF16 stacks with radius <= "
+                                        "BF_FUSED_MAX_RADIUS only");
+    if (height == 0 || width == 0) return BF_OK;
+    const int W = radius_of(sigma_s);
+    const int TC = W <= 32 ? 64 : 32;
+    const long long tiles = (long long)((width + TC - 1) / TC) * ((height + kFusedRows - 1) / kFusedRows);
+    const long long words = kFusedSlots * tiles;
+    if (kFlagBytes + sizeof(unsigned) * (size_t)words > kNoAllocScratchBytes)
+        return fail(BF_ERR_UNSUPPORTED, "bf_gc_forward_noalloc: image needs more than BF_NOALLOC_SCRATCH_BYTES of "
+                                        "scratch (32 bytes per 64 x 64 tile, per 64 x 32 tile above radius 32)");
+    if (!f || !out) return fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    const size_t img = ((size_t)(height - 1) * ld + width) * sizeof(float);
+    if (overlaps(f, img, out, img)) return fail(BF_ERR_INVALID_ARG, "out overlaps f");
+    if ((st = check_conditioning(sigma_r, N, stack_dtype, flags)) != BF_OK) return st;
+    void *ws = nullptr;
+    if ((st = noalloc_scratch(&ws)) != BF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    st = stack_dtype == BF_STACK_F16
+             ? run_fused<MmaF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s)
+             : run_fused<MmaBF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
+    if (st != BF_OK || !range_flag) return st;
+    ProfScope prof_("k_or_range_words", s);
+    hipLaunchKernelGGL(k_or_range_words, dim3(1), dim3(256), 0, s, (const unsigned *)((char *)ws + kFlagBytes),
+                       (int)words, range_flag);
+    return check_launch("k_or_range_words");
 }
 
 int bf_gc_pivot_count(double sigma_r, int stack_dtype) {

@@ -1414,6 +1414,20 @@ __global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f,
     }
 }
 
+// The or of `words` range words into *flag (one block of 256 threads; a
+// plain store of 0 or BF_DEVFLAG_RANGE, so *flag needs no clearing).
+__global__ __launch_bounds__(256) void k_or_range_words(const unsigned *__restrict__ words, int count,
+                                                        unsigned *__restrict__ flag) {
+    __shared__ unsigned s_or;
+    if (threadIdx.x == 0) s_or = 0u;
+    __syncthreads();
+    unsigned acc = 0u;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) acc |= words[i];
+    if (acc) atomicOr(&s_or, acc);
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = s_or;
+}
+
 // Pivoted form on the fused tile, in three launches.
 // k_pivot_masks: the mask of the sub-ranges present among each tile's output
 // pixels (one block of 256 threads per tile).
