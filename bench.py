@@ -103,11 +103,13 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, stack_tag, profile_name):
+def measured_traffic(kernel, stack_tag, profile_name, counters=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
     copy of known size), or None when that summary is missing or was taken on
-    a different kernel source."""
+    a different kernel source. `counters` (a dict) receives the summary's SQ
+    figures for the kernel (VALU and MFMA busy per SIMD, waiting share), if it
+    has them."""
     path = os.path.join(ROOT, "profiles", profile_name + "_traffic.json")
     if not os.path.exists(path):
         return None
@@ -115,6 +117,8 @@ def measured_traffic(kernel, stack_tag, profile_name):
         rec = json.load(fh)
     if rec.get("source_sha256_16") != source_hash():
         return None
+    if counters is not None:
+        counters.update(rec.get("sq", {}))
     base = {"k_hpass_combine": "k_hpass<", "k_hpass": "k_hpass<", "k_vpass": "k_vpass<",
             "k_stack_build": "k_stack_build<", "k_combine": "k_combine<", "k_fused_mfma": "k_fused_mfma<"}[kernel]
     for name, v in rec["kernels"].items():
@@ -446,9 +450,18 @@ def cpu_baseline(f64, sigma_s, sigma_r, N, rows):
     C.gcf(f64, sigma_s, sigma_r, N, region=(0, rows, 0, f64.shape[1]))
     dt = time.perf_counter() - t
     px = rows * f64.shape[1]
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": px / 1e6 / dt, "unit": "Mpixel/s", "cores": cores, "kind": "oracle",
             "sample": f"rows 0..{rows} of the {f64.shape[0]}x{f64.shape[1]} image ({px} px, all {N + 2} planes), "
-                      f"{dt:.1f} s", "seconds": dt}
+                      f"{dt:.1f} s", "seconds": dt, "cpu_model": model,
+            "paper_context": {"value": 1.04, "unit": "Mpixel/s",
+                              "what": "the paper's GCF timing in Table 2 at sigma_s = 10, sigma_r = 30, N = 28 "
+                                      "(1.01 s for a 1024x1024 image, Matlab on a 3.4 GHz Intel 8-core machine)"}}
 
 
 def main():
@@ -534,11 +547,18 @@ def main():
         roof = {"kernel": dom, **roof}
         roof["frac"] = roof["achieved"] / roof["peak"]
         prof_name = f"forward_{H}_s{ss:g}_n{n}_{stack}"
+        sq = {}
         roof["traffic"] = measured_traffic(dom, {"f32": "StF32", "f16": "MmaF16", "bf16": "MmaBF16"}[stack]
                                            if dom == "k_fused_mfma" else {"f32": "StF32", "f16": "StF16",
-                                                                          "bf16": "StBF16"}[stack], prof_name)
+                                                                          "bf16": "StBF16"}[stack], prof_name, sq)
         roof["traffic_source"] = f"profiles/{prof_name}.md"
         roof["avg_ms"] = kernels[dom]["avg_ms"]
+        # the same launch against HBM: algorithmic bytes, and the counters' bytes when taken on these sources
+        roof["hbm_frac_algorithmic"] = roof["bytes_per_launch"] / (roof["avg_ms"] * 1e-3) / (PEAK_HBM_GBS * 1e9)
+        roof["hbm_frac_traffic"] = (None if roof["traffic"] is None else
+                                    roof["traffic"] / (roof["avg_ms"] * 1e-3) / (PEAK_HBM_GBS * 1e9))
+        roof["valu_busy"] = sq.get("valu_busy")
+        roof["mfma_busy"] = sq.get("mfma_busy")
         rec.update({"ms_per_step": round(ms, 4), "value": round(H * Wd / 1e6 / (ms / 1e3), 2), "unit": "Mpixel/s",
                     "tile_config": cfg, "tile_config_ms": [None if t is None else round(t, 3) for t in tune],
                     "kernels": kernels, "roofline": roof})
@@ -581,7 +601,7 @@ def main():
     result = {
         "metric": METRIC, "value": head["value"], "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f16" if head_stack == "f16" else "f64", "data": "synthetic",
+        "vs_baseline": None, "dtype": head_stack, "data": "synthetic",
         "config": {"workload": f"edge-rich {H}x{Wd}, sigma_s={ss:g} (W={W}), sigma_r={sr:g}, "
                                f"{head_stack.upper()} stack at N={head['degree']} ({head['planes']} planes), "
                                f"same error against the direct filter as the FP32 stack at N={N}",
