@@ -187,8 +187,8 @@ def bench_batched(bf, steps, log, stack="f32"):
     deg = [bf.degree_rule(x) for x in sr]
     routes = [bf.batched_route(x, d, stack) for x, d in zip(sr, deg)]
     px = sum(x.numel() for x in imgs)
-    ws = torch.empty(bf.batched_workspace_bytes([tuple(x.shape) for x in imgs], ss, deg, stack), dtype=torch.uint8,
-                     device="cuda:0")
+    ws = torch.empty(bf.batched_workspace_bytes([tuple(x.shape) for x in imgs], ss, deg, stack, sigmas_r=sr),
+                     dtype=torch.uint8, device="cuda:0")
     outs = [torch.empty_like(x) for x in imgs]
     log(f"bench: batched {len(imgs)} images, {px / 1e6:.1f} Mpx, {stack} stack, "
         f"{sum(r > 1 for r in routes)} routed to the pivoted form, autotuning")

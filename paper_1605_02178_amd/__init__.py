@@ -485,11 +485,15 @@ def batched_route(sigma_r: float, degree: int, stack_dtype="f32", allow_ill_cond
     return int(_lib.load().bf_gc_batched_route(float(sigma_r), int(degree), _dtype_code(stack_dtype), flags))
 
 
-def batched_workspace_bytes(shapes, sigmas_s, degrees, stack_dtype="f32") -> int:
+def batched_workspace_bytes(shapes, sigmas_s, degrees, stack_dtype="f32", sigmas_r=None) -> int:
+    """Workspace bytes for gc_filter_batched on images of these shapes and
+    parameters. sigmas_r decides which images run the pivoted form; without
+    it every image is sized at sigma_r = 30 (its own expansion only)."""
     arr = (_lib.ImageDesc * max(len(shapes), 1))()
     for i, (H, Wd) in enumerate(shapes):
         arr[i].height, arr[i].width, arr[i].ld = H, Wd, Wd
-        arr[i].sigma_s, arr[i].sigma_r, arr[i].N = float(sigmas_s[i]), 30.0, int(degrees[i])
+        sr = 30.0 if sigmas_r is None else float(sigmas_r[i])
+        arr[i].sigma_s, arr[i].sigma_r, arr[i].N = float(sigmas_s[i]), sr, int(degrees[i])
     return int(_lib.load().bf_gc_batched_workspace_bytes(arr, len(shapes), _dtype_code(stack_dtype)))
 
 
@@ -512,8 +516,9 @@ def gc_filter_batched(images, sigmas_s, sigmas_r, degrees=None, stack_dtype="f32
     arr = _descs(images, outs, sigmas_s, sigmas_r, degrees)
     code = _dtype_code(stack_dtype)
     lib = _lib.load()
-    need = int(lib.bf_gc_batched_workspace_bytes(arr, n, code))
-    if workspace is None or workspace.numel() < need:
+    if workspace is None:
+        # (a caller's workspace is checked by the library: BF_ERR_WORKSPACE if too small)
+        need = int(lib.bf_gc_batched_workspace_bytes(arr, n, code))
         dev = images[0].device if n else "cuda"
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     status = (ctypes.c_int * max(n, 1))()

@@ -16,7 +16,10 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <type_traits>
 #include <unordered_map>
@@ -478,7 +481,7 @@ static double batch_limit(int dtype) { return dtype == BF_STACK_F32 ? 1e-5 : 1e-
 // power of two whose sub-ranges lie inside; 0 = neither (the image keeps its
 // conditioning status, BF_ERR_ILL_CONDITIONED if its own expansion fails the
 // check, else it runs its own expansion). *st: the image's status.
-static int batch_route(double sigma_r, int N, int dtype, unsigned flags, bf_status *st) {
+static int batch_route_uncached(double sigma_r, int N, int dtype, unsigned flags, bf_status *st) {
     *st = check_conditioning(sigma_r, N, dtype, flags);
     if ((*st != BF_OK && *st != BF_ERR_ILL_CONDITIONED) || (flags & BF_FLAG_ALLOW_ILL_CONDITIONED) ||
         (flags & (BF_FLAG_TAYLOR | BF_FLAG_MINIMAX)))
@@ -491,6 +494,28 @@ static int batch_route(double sigma_r, int N, int dtype, unsigned flags, bf_stat
             return K;
         }
     return *st == BF_OK ? 1 : 0;
+}
+
+// batch_route with its results cached per (sigma_r, N, stack type, the flags
+// that matter): a batch asks for the same images on every call.
+static int batch_route(double sigma_r, int N, int dtype, unsigned flags, bf_status *st) {
+    static std::mutex mtx;
+    static std::map<std::tuple<double, int, int, unsigned>, std::pair<int, bf_status>> cache;
+    const unsigned f = flags & (BF_FLAG_ALLOW_ILL_CONDITIONED | BF_FLAG_TAYLOR | BF_FLAG_MINIMAX);
+    const auto key = std::make_tuple(sigma_r, N, dtype, f);
+    {
+        std::lock_guard<std::mutex> lock(mtx);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            *st = it->second.second;
+            if (*st != BF_OK) fail(*st, "ill-conditioned or unsupported coefficients for this image");
+            return it->second.first;
+        }
+    }
+    const int K = batch_route_uncached(sigma_r, N, dtype, flags, st);
+    std::lock_guard<std::mutex> lock(mtx);
+    cache.emplace(key, std::make_pair(K, *st));
+    return K;
 }
 
 // Fused pivoted form: the range words of the tiles, then the sub-range table
@@ -1011,6 +1036,40 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
     B.total = off;
 }
 
+// The last few plans, reused when a call repeats one exactly (the same
+// descriptor bytes, stack type, flags, tile form and workspace): a serving
+// loop filters batches of the same images, and planning them costs host time
+// that would otherwise sit in front of every launch.
+struct PlanKey {
+    std::vector<char> descs;
+    int dtype, RV, RH;
+    unsigned flags;
+    bool fused;
+    const char *ws;
+    bool operator==(const PlanKey &o) const {
+        return dtype == o.dtype && RV == o.RV && RH == o.RH && flags == o.flags && fused == o.fused && ws == o.ws &&
+               descs == o.descs;
+    }
+};
+static std::mutex g_plan_mtx;
+static std::vector<std::pair<PlanKey, std::shared_ptr<const BatchPlan>>> g_plans;
+
+static std::shared_ptr<const BatchPlan> cached_plan(const bf_image_desc *d, int count, int dtype, unsigned flags,
+                                                    int RV, int RH, bool fused, char *ws) {
+    PlanKey key{std::vector<char>((const char *)d, (const char *)(d + count)), dtype, RV, RH, flags, fused, ws};
+    {
+        std::lock_guard<std::mutex> lock(g_plan_mtx);
+        for (size_t i = 0; i < g_plans.size(); ++i)
+            if (g_plans[i].first == key) return g_plans[i].second;
+    }
+    auto B = std::make_shared<BatchPlan>();
+    plan_batch(d, count, dtype, flags, RV, RH, fused, ws, *B);
+    std::lock_guard<std::mutex> lock(g_plan_mtx);
+    if (g_plans.size() >= 8) g_plans.erase(g_plans.begin());
+    g_plans.emplace_back(std::move(key), B);
+    return B;
+}
+
 static void pack_blob(const BatchPlan &B, char *host) {
     std::memset(host, 0, B.blob_bytes);
     const size_t n = B.img.size();
@@ -1212,8 +1271,8 @@ static bf_status launch_batch(const BatchPlan &B, const BatchKernels &K, unsigne
 template <class S, int RV, int RH>
 static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, unsigned flags, int *status,
                              char *ws, size_t ws_bytes, hipStream_t stream) {
-    BatchPlan B;
-    plan_batch(descs, count, dtype, flags, RV, RH, false, ws, B);
+    const std::shared_ptr<const BatchPlan> plan = cached_plan(descs, count, dtype, flags, RV, RH, false, ws);
+    const BatchPlan &B = *plan;
     for (int i = 0; i < count; ++i) status[i] = B.status[i];
     // descriptors (sub-ranges of routed images count one each) bound the item table in LDS
     if (B.img.size() > 2 * (size_t)kMaxBatch)
@@ -1244,8 +1303,8 @@ static const void *batched_fused_kernel() {
 template <class M>
 static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dtype, unsigned flags, int *status,
                                    char *ws, size_t ws_bytes, hipStream_t stream) {
-    BatchPlan B;
-    plan_batch(descs, count, dtype, flags, 0, 0, true, ws, B);
+    const std::shared_ptr<const BatchPlan> plan = cached_plan(descs, count, dtype, flags, 0, 0, true, ws);
+    const BatchPlan &B = *plan;
     for (int i = 0; i < count; ++i) status[i] = B.status[i];
     if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
     if (B.items == 0) return BF_OK;

@@ -30,14 +30,43 @@ static long double bessel_i(int nu, long double x) {
     return sum;
 }
 
+// The rule's threshold: the geometric mean of the first neglected Chebyshev
+// coefficients at N = 28 and 29 for sigma_r = 30.
+static long double rule_eps0() {
+    static const long double eps0 = [] {
+        const long double mu30 = (long double)kTh * kTh / (30.0L * 30.0L);
+        return std::sqrt(2.0L * bessel_i(28, mu30) * 2.0L * bessel_i(29, mu30));
+    }();
+    return eps0;
+}
+
+// Smallest N <= max_degree with 2 I_{N+1}(mu) <= eps0, else -1; results are
+// cached per (mu, max_degree): the batch planner asks for the same values
+// on every call.
+static int rule_at_mu(long double mu, int max_degree) {
+    static std::mutex mtx;
+    static std::map<std::pair<long double, int>, int> cache;
+    const auto key = std::make_pair(mu, max_degree);
+    {
+        std::lock_guard<std::mutex> lock(mtx);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const long double eps0 = rule_eps0();
+    int n = -1;
+    for (int N = 1; N <= max_degree; ++N)
+        if (2.0L * bessel_i(N + 1, mu) <= eps0) {
+            n = N;
+            break;
+        }
+    std::lock_guard<std::mutex> lock(mtx);
+    cache.emplace(key, n);
+    return n;
+}
+
 int degree_rule(double sigma_r, int max_degree) {
     if (!(sigma_r > 0.0) || !std::isfinite(sigma_r)) return -1;
-    const long double mu30 = (long double)kTh * kTh / (30.0L * 30.0L);
-    const long double eps0 = std::sqrt(2.0L * bessel_i(28, mu30) * 2.0L * bessel_i(29, mu30));
-    const long double mu = (long double)kTh * kTh / ((long double)sigma_r * sigma_r);
-    for (int N = 1; N <= max_degree; ++N)
-        if (2.0L * bessel_i(N + 1, mu) <= eps0) return N;
-    return -1;
+    return rule_at_mu((long double)kTh * kTh / ((long double)sigma_r * sigma_r), max_degree);
 }
 
 // Conditioning of the double coefficients the kernels use, on a grid of y:
@@ -362,11 +391,7 @@ const Fit &fit_mu(double mu, int N) {
 
 int degree_rule_mu(double mu, int max_degree) {
     if (!(mu > 0.0) || !std::isfinite(mu)) return -1;
-    const long double mu30 = (long double)kTh * kTh / (30.0L * 30.0L);
-    const long double eps0 = std::sqrt(2.0L * bessel_i(28, mu30) * 2.0L * bessel_i(29, mu30));
-    for (int N = 1; N <= max_degree; ++N)
-        if (2.0L * bessel_i(N + 1, (long double)mu) <= eps0) return N;
-    return -1;
+    return rule_at_mu((long double)mu, max_degree);
 }
 
 std::vector<Pivot> pivot_plan(double sigma_r, int K, int N, int max_degree) {

@@ -255,7 +255,8 @@ def test_routed_images_graph_replays_and_flags(torch_cuda):
         fs = [torch.tensor(a, device="cuda:0") for a in imgs]
         deg = [bf.degree_rule(x) for x in sr]
         if ws is None:
-            ws = torch.empty(4 * bf.batched_workspace_bytes([a.shape for a in imgs], ss, deg, "f16") + (1 << 24),
+            ws = torch.empty(4 * bf.batched_workspace_bytes([a.shape for a in imgs], ss, deg, "f16", sigmas_r=sr)
+                             + (1 << 24),
                              dtype=torch.uint8, device="cuda:0")
         outs, status = bf.gc_filter_batched(fs, ss, sr, deg, stack_dtype="f16", graph=True, workspace=ws)
         junk = torch.randn(1 << 20, device="cuda:0").sum()

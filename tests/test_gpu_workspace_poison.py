@@ -90,7 +90,7 @@ def test_batched(torch_cuda, dtype, cfg):
     ss = [2.0, 1.0, 7.0, 12.0, 4.0]
     sr = [30.0, 50.0, 12.0, 20.0, 45.0]
     deg = [bf.degree_rule(x) for x in sr]
-    need = bf.batched_workspace_bytes(shapes, ss, deg, dtype)
+    need = bf.batched_workspace_bytes(shapes, ss, deg, dtype, sigmas_r=sr)
     for graph in (False, True):
         ws_p, ws_z = _two(torch, need)
         a, sa = bf.gc_filter_batched(fs, ss, sr, deg, stack_dtype=dtype, graph=graph, tile_config=cfg,
