@@ -47,24 +47,29 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def fused_mfma_count(H, Wd, W, P):
+def fused_mfma_count(H, Wd, W, P, stack="f16"):
     """Matrix-core instructions one launch of the fused kernel issues (16x16x32
-    each): per tile and plane, the column pass runs the chunks each of its 4
-    row blocks needs for each of the 8 halo-column blocks, the row pass the
-    chunks each output column block needs for each of the 4 row blocks."""
-    Q = 3 if W <= 16 else 4 if W <= 32 else 5
-    TC = 64 if W <= 32 else 32
-    QA, QB = (2 * W + 15) // 32, Q - 2
-    col = 8 * sum(min(Q - 1, j // 2 + (QB if j % 2 else QA)) - j // 2 + 1 for j in range(4))
-    if TC == 64:
-        row = 4 * 2 * ((QA + 1) + (QB + 1))
+    each), for the tile geometry the library picks (FP16: 16 waves, 64 x 128
+    tiles up to radius 32, 64 x 64 up to 48, 32 x 128 above; BF16: 8 waves,
+    64 x 64 and 64 x 32): per tile and plane, the column pass runs on the
+    column waves (those whose 16 halo columns the row pass reads), each
+    over the chunks of every row block, and the row pass over the chunks of
+    every output block (QA + 1 for even blocks, QB + 1 for odd ones)."""
+    if stack == "f16":
+        NW, TR, TC = (16, 64, 128) if W <= 32 else (16, 64, 64) if W <= 48 else (16, 32, 128)
     else:
-        row = 4 * 2 * 4
-    tiles = math.ceil(H / 64) * math.ceil(Wd / TC)
+        NW, TR, TC = (8, 64, 64) if W <= 32 else (8, 64, 32)
+    Q = math.ceil((TR + 2 * W) / 32)
+    QA, QB = (2 * W + 15) // 32, Q - TR // 32
+    nrb, ncb = TR // 16, TC // 16
+    ncw = ncb + 2 * QB
+    col = ncw * sum(min(Q - 1, j // 2 + (QB if j % 2 else QA)) - j // 2 + 1 for j in range(nrb))
+    row = nrb * sum((QB + 1) if jc % 2 else (QA + 1) for jc in range(ncb))
+    tiles = math.ceil(H / TR) * math.ceil(Wd / TC)
     return tiles * P * (col + row)
 
 
-def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch):
+def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch, stack="f32"):
     """Algorithmic bytes and flops of one launch of `name` and the bound it
     sits against. Convolution work: 2 (2W+1) flops per pixel, plane and pass;
     stack bytes: esize per pixel and plane for each write or read."""
@@ -72,7 +77,7 @@ def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch):
     taps = 2 * W + 1
     if name == "k_fused_mfma":
         flops = 2.0 * 2.0 * taps * P * px
-        issued = fused_mfma_count(H, Wd, W, P) * 16 * 16 * 32 * 2.0
+        issued = fused_mfma_count(H, Wd, W, P, stack) * 16 * 16 * 32 * 2.0
         return {"bound": "mfma", "achieved": flops / ms_per_launch / 1e9, "peak": PEAK_F16_MFMA_TFS,
                 "unit": "TFLOP/s", "flops_per_launch": flops, "bytes_per_launch": px * 8,
                 "mfma_issued_tflops": issued / ms_per_launch / 1e9,
@@ -543,7 +548,7 @@ def main():
         kernels = {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}
         dom = max((k for k in kernels if k != "k_put_params"),
                   key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
-        roof = kernel_roofline(dom, H, Wd, W, n + 2, 4 if stack == "f32" else 2, kernels[dom]["avg_ms"])
+        roof = kernel_roofline(dom, H, Wd, W, n + 2, 4 if stack == "f32" else 2, kernels[dom]["avg_ms"], stack)
         roof = {"kernel": dom, **roof}
         roof["frac"] = roof["achieved"] / roof["peak"]
         prof_name = f"forward_{H}_s{ss:g}_n{n}_{stack}"

@@ -101,6 +101,11 @@ typedef enum {
 #define BF_TILE_CONFIGS 5
 #define BF_TILE_FUSED   4
 #define BF_FUSED_MAX_RADIUS 48
+/* bf_gc_forward and bf_gc_forward_noalloc run FP16 stacks on the fused tile up
+ * to this radius (64 x 128 tiles on 16 waves up to radius 32, 64 x 64 up to
+ * 48, 32 x 128 above); BF16 stacks, and the other entry points, up to
+ * BF_FUSED_MAX_RADIUS. */
+#define BF_FUSED_F16_MAX_RADIUS 64
 #define BF_FLAG_TILE(c)               ((((unsigned)(c)) + 1u) << 8)
 
 /* device flag word bits (read with bf_gc_read_flags) */
@@ -367,11 +372,13 @@ bf_status bf_gc_batched(const bf_image_desc *descs, int count, int stack_dtype, 
 /*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
- * forward of bf_gc_forward on the fused tile (FP16/BF16 stacks, radius
- * ceil(3 sigma_s) <= BF_FUSED_MAX_RADIUS; other stacks or radii:
- * BF_ERR_UNSUPPORTED; staged, recursive or three-kernel tile flags:
- * BF_ERR_INVALID_ARG), with no workspace argument. Its only scratch, the
- * per-wave range words of the launch (32 bytes per 64-row tile), lives in a
+ * forward of bf_gc_forward on the fused tile (FP16 stacks with radius
+ * ceil(3 sigma_s) <= BF_FUSED_F16_MAX_RADIUS, BF16 with radius <=
+ * BF_FUSED_MAX_RADIUS; other stacks or radii: BF_ERR_UNSUPPORTED; staged,
+ * recursive or three-kernel tile flags: BF_ERR_INVALID_ARG), with no
+ * workspace argument. Its only scratch, the per-wave range words of the
+ * launch (4 bytes per wave and tile: 32 bytes per 4096 output pixels, per
+ * 2048 for BF16 above radius 32), lives in a
  * library-owned device array of BF_NOALLOC_SCRATCH_BYTES per GPU, held until
  * the process ends; an image that needs more gets BF_ERR_UNSUPPORTED. The call
  * allocates no device memory and calls no allocating routine; the array's

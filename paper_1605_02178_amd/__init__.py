@@ -23,7 +23,7 @@ __all__ = [
     "degree_rule", "coefficients", "query", "plane_scales", "workspace_bytes", "param_bytes",
     "gc_filter", "gc_backward", "GaussChebyshevBF", "gc_filter_autograd", "stack_build", "gauss_planes",
     "combine", "read_flags", "radius", "StackLayout", "gc_filter_batched", "batched_workspace_bytes",
-    "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
+    "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "FUSED_F16_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
     "gc_joint_filter", "joint_workspace_bytes", "gc_filter_pivots", "pivot_count", "pivot_plan",
     "pivots_workspace_bytes", "batched_route", "gc_filter_noalloc", "NOALLOC_SCRATCH_BYTES",
 ]
@@ -42,10 +42,12 @@ COEFFS = {"chebyshev": 0, "taylor": FLAG_TAYLOR, "minimax": FLAG_MINIMAX}
 DEVFLAG_RANGE = 0x1
 # Tile configurations: 0-3 are the three-kernel path, (column-pass rows,
 # row-pass columns) per lane; TILE_FUSED is the fused matrix-core kernel for
-# FP16/BF16 stacks with radius <= FUSED_MAX_RADIUS.
+# FP16/BF16 stacks with radius <= FUSED_MAX_RADIUS (the single-image forward:
+# FP16 up to FUSED_F16_MAX_RADIUS).
 TILE_CONFIGS = ((16, 8), (8, 8), (16, 4), (8, 4), "fused")
 TILE_FUSED = 4
 FUSED_MAX_RADIUS = 48
+FUSED_F16_MAX_RADIUS = 64
 
 
 def flag_tile(c: int) -> int:
@@ -57,7 +59,7 @@ def tile_configs_for(stack_dtype, sigma_s) -> list:
     """Tile configurations bf_gc_forward accepts for this stack type and sigma_s."""
     code = _dtype_code(stack_dtype)
     cfgs = [0, 1, 2, 3]
-    if code != 0 and radius(sigma_s) <= FUSED_MAX_RADIUS:
+    if radius(sigma_s) <= {0: -1, 1: FUSED_F16_MAX_RADIUS, 2: FUSED_MAX_RADIUS}[code]:
         cfgs.append(TILE_FUSED)
     return cfgs
 MAX_DEGREE = 320
@@ -225,8 +227,9 @@ NOALLOC_SCRATCH_BYTES = 4 << 20
 @_on_stream
 def gc_filter_noalloc(f, sigma_s: float, sigma_r: float, degree: int | None = None, stack_dtype="f16", out=None,
                       range_flag=None, stream=None):
-    """bf_gc_forward_noalloc: the fused-tile forward (FP16/BF16 stacks,
-    radius <= FUSED_MAX_RADIUS) with no workspace; the library's own device
+    """bf_gc_forward_noalloc: the fused-tile forward (FP16 stacks with radius
+    <= FUSED_F16_MAX_RADIUS, BF16 with radius <= FUSED_MAX_RADIUS) with no
+    workspace; the library's own device
     scratch holds the range words. `out` must be given where nothing may be
     allocated; range_flag: optional int32/uint32 device tensor of one element
     that receives DEVFLAG_RANGE or 0."""

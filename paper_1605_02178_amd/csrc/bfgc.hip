@@ -129,9 +129,14 @@ static int tile_config_of(unsigned flags) {
 
 constexpr int kJointFusedMaxRadius = BF_FUSED_MAX_RADIUS;   // the joint fused tile: the plain tile's geometries
 
-// The fused matrix-core kernel covers FP16/BF16 stacks up to BF_FUSED_MAX_RADIUS.
+// The fused matrix-core kernels cover FP16/BF16 stacks up to
+// BF_FUSED_MAX_RADIUS; the single-image forward takes FP16 stacks up to
+// BF_FUSED_F16_MAX_RADIUS.
 static bool fused_applies(int dtype, double sigma_s) {
     return dtype != BF_STACK_F32 && radius_of(sigma_s) <= BF_FUSED_MAX_RADIUS;
+}
+static bool fused_forward_applies(int dtype, double sigma_s) {
+    return fused_applies(dtype, sigma_s) || (dtype == BF_STACK_F16 && radius_of(sigma_s) <= BF_FUSED_F16_MAX_RADIUS);
 }
 
 static size_t esize(int dtype) { return dtype == BF_STACK_F32 ? 4 : 2; }
@@ -299,22 +304,40 @@ static int resident_blocks(const void *kernel, int *cache) {
     return *cache;
 }
 
-template <class M, int Q, int TC, int QA>
+template <class M, int Q, int TC, int QA, int NW = 8, int TR = kFusedRows>
 static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const FusedConsts &C, int W,
                                 int N, float mu, char *ws, hipStream_t stream) {
     static int resident = 0;
-    const void *kernel = (const void *)k_fused_mfma<M, Q, TC, QA>;
+    const void *kernel = (const void *)k_fused_mfma<M, Q, TC, QA, NW, TR>;
     const int tiles_x = (Wd + TC - 1) / TC;
-    const long long tiles = (long long)tiles_x * ((H + kFusedRows - 1) / kFusedRows);
+    const long long tiles = (long long)tiles_x * ((H + TR - 1) / TR);
     if (tiles > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused path: too many tiles");
-    const int grid = fused_persistent<M>(Q) ? (int)std::min<long long>(tiles, resident_blocks(kernel, &resident))
-                                         : (int)tiles;
+    const bool persistent = fused_persistent<M>(Q) && NW == 8;
+    const int grid = persistent ? (int)std::min<long long>(tiles, resident_blocks(kernel, &resident)) : (int)tiles;
     const float prescale = M::kPrescale;
-    note_range_words(ws, kFusedSlots * tiles);
+    note_range_words(ws, (long long)NW * tiles);
     ProfScope prof_("k_fused_mfma", stream);
-    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA>), dim3(grid), dim3(512), 0, stream, f, out, H, Wd, ld, C, W, N,
-                       mu, prescale, (unsigned *)(ws + kFlagBytes), tiles_x, (int)tiles);
+    hipLaunchKernelGGL((k_fused_mfma<M, Q, TC, QA, NW, TR>), dim3(grid), dim3(NW * 64), 0, stream, f, out, H, Wd, ld,
+                       C, W, N, mu, prescale, (unsigned *)(ws + kFlagBytes), tiles_x, (int)tiles);
     return check_launch("k_fused_mfma");
+}
+
+// Tile geometry of the single-image fused forward: waves per block, tile
+// rows and columns. FP16 (FP16 plane state, at most 128 VGPRs at 16 waves):
+// 64 x 128 tiles up to radius 32, 64 x 64 up to 48, 32 x 128 up to 64, all
+// on 16 waves, whose halo of 256 columns keeps the column pass's share of
+// halo columns low; BF16 (FP32 plane state): 64 x 64 tiles up to radius 32
+// and 64 x 32 up to 48 on 8 waves.
+struct FusedGeom {
+    int NW, TR, TC;
+};
+static FusedGeom fused_geom(int dtype, int W) {
+    if (dtype == BF_STACK_F16) return W <= 32 ? FusedGeom{16, 64, 128} : W <= 48 ? FusedGeom{16, 64, 64}
+                                                                        : FusedGeom{16, 32, 128};
+    return W <= 32 ? FusedGeom{8, 64, 64} : FusedGeom{8, 64, 32};
+}
+static long long fused_tiles(const FusedGeom &G, int H, int Wd) {
+    return (long long)((Wd + G.TC - 1) / G.TC) * ((H + G.TR - 1) / G.TR);
 }
 
 // Fused FP16/BF16 forward: one kernel (see k_fused_mfma), its constants
@@ -327,15 +350,24 @@ static bf_status run_fused(const float *f, float *out, int H, int Wd, int ld, do
     const FusedConsts C = fused_consts(sigma_s, sigma_r, N, kind_of(flags));
     const float mu = (float)fit(sigma_r, N).mu;
     const int W = radius_of(sigma_s), qa = fused_qa(W);
-    // geometry: TC + 2W <= 128 halo columns, 64 + 2W <= 32Q halo rows
-#define BF_FUSED(Q, TC)                                                                             \
-    return qa == (Q) - 3 ? launch_fused_q<M, Q, TC, (Q) - 3>(f, out, H, Wd, ld, C, W, N, mu, ws, stream) \
-                         : launch_fused_q<M, Q, TC, (Q) - 2>(f, out, H, Wd, ld, C, W, N, mu, ws, stream)
-    if (W <= 16) BF_FUSED(3, 64);
-    if (W <= 32) BF_FUSED(4, 64);
-    if (W <= 48) BF_FUSED(5, 32);
+    // geometry (fused_geom): TC + 2W halo columns within the block's 16 NW,
+    // TR + 2W halo rows within 32 Q; QA = (2W + 15)/32 is QB - 1 or QB
+#define BF_FUSED(Q, TC, NW, TR)                                                                                   \
+    return qa == (Q) - (TR) / 32 - 1                                                                              \
+               ? launch_fused_q<M, Q, TC, (Q) - (TR) / 32 - 1, NW, TR>(f, out, H, Wd, ld, C, W, N, mu, ws, stream) \
+               : launch_fused_q<M, Q, TC, (Q) - (TR) / 32, NW, TR>(f, out, H, Wd, ld, C, W, N, mu, ws, stream)
+    if constexpr (M::kHalfPlanes) {
+        if (W <= 16) BF_FUSED(3, 128, 16, 64);
+        if (W <= 32) BF_FUSED(4, 128, 16, 64);
+        if (W <= 48) BF_FUSED(5, 64, 16, 64);
+        if (W <= BF_FUSED_F16_MAX_RADIUS) BF_FUSED(5, 128, 16, 32);
+    } else {
+        if (W <= 16) BF_FUSED(3, 64, 8, 64);
+        if (W <= 32) BF_FUSED(4, 64, 8, 64);
+        if (W <= 48) BF_FUSED(5, 32, 8, 64);
+    }
 #undef BF_FUSED
-    return fail(BF_ERR_UNSUPPORTED, "fused path: radius above BF_FUSED_MAX_RADIUS");
+    return fail(BF_ERR_UNSUPPORTED, "fused path: radius above the stack type's fused maximum");
 }
 
 // Scratch of bf_gc_forward_noalloc: the range words of one fused launch in a
@@ -1417,10 +1449,11 @@ bf_status bf_gc_forward(const float *f, float *out, int height, int width, int l
             return fail(BF_ERR_INVALID_ARG, "the recursive variant has its own kernels (no tile or staged flag)");
         return run_recursive<StF32>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
     }
-    if (cfg == -1) cfg = (fused_applies(stack_dtype, sigma_s) && !(flags & BF_FLAG_STAGED)) ? BF_TILE_FUSED : 0;
+    if (cfg == -1) cfg = (fused_forward_applies(stack_dtype, sigma_s) && !(flags & BF_FLAG_STAGED)) ? BF_TILE_FUSED : 0;
     if (cfg == BF_TILE_FUSED) {
-        if (!fused_applies(stack_dtype, sigma_s))
-            return fail(BF_ERR_UNSUPPORTED, "fused tile: FP16/BF16 stacks with radius <= BF_FUSED_MAX_RADIUS only");
+        if (!fused_forward_applies(stack_dtype, sigma_s))
+            return fail(BF_ERR_UNSUPPORTED, "fused tile: FP16 stacks with radius <= BF_FUSED_F16_MAX_RADIUS or BF16 "
+                                            "with radius <= BF_FUSED_MAX_RADIUS only");
         if (flags & BF_FLAG_STAGED) return fail(BF_ERR_INVALID_ARG, "fused tile and BF_FLAG_STAGED exclude each other");
         if (stack_dtype == BF_STACK_F16)
             return run_fused<MmaF16>(f, out, height, width, ld, sigma_s, sigma_r, N, stack_dtype, flags, (char *)ws, s);
@@ -1452,17 +1485,16 @@ bf_status bf_gc_forward_noalloc(const float *f, float *out, int height, int widt
     if (cfg == -2 || (cfg != -1 && cfg != BF_TILE_FUSED) || (flags & (BF_FLAG_STAGED | BF_FLAG_RECURSIVE)))
         return fail(BF_ERR_INVALID_ARG, "bf_gc_forward_noalloc runs the fused tile only (no staged, recursive or "
                                         "three-kernel tile flags)");
-    if (!fused_applies(stack_dtype, sigma_s))
-        return fail(BF_ERR_UNSUPPORTED, "bf_gc_forward_noalloc: FP16/BF16 stacks with radius <= "
-                                        "BF_FUSED_MAX_RADIUS only");
+    if (!fused_forward_applies(stack_dtype, sigma_s))
+        return fail(BF_ERR_UNSUPPORTED, "bf_gc_forward_noalloc: FP16 stacks with radius <= BF_FUSED_F16_MAX_RADIUS "
+                                        "or BF16 with radius <= BF_FUSED_MAX_RADIUS only");
     if (height == 0 || width == 0) return BF_OK;
-    const int W = radius_of(sigma_s);
-    const int TC = W <= 32 ? 64 : 32;
-    const long long tiles = (long long)((width + TC - 1) / TC) * ((height + kFusedRows - 1) / kFusedRows);
-    const long long words = kFusedSlots * tiles;
+    const FusedGeom G = fused_geom(stack_dtype, radius_of(sigma_s));
+    const long long words = (long long)G.NW * fused_tiles(G, height, width);
     if (kFlagBytes + sizeof(unsigned) * (size_t)words > kNoAllocScratchBytes)
         return fail(BF_ERR_UNSUPPORTED, "bf_gc_forward_noalloc: image needs more than BF_NOALLOC_SCRATCH_BYTES of "
-                                        "scratch (32 bytes per 64 x 64 tile, per 64 x 32 tile above radius 32)");
+                                        "scratch (4 bytes per wave and tile: 32 bytes per 4096 output pixels for FP16, per 4096 "
+                                        "up to radius 32 and 2048 above for BF16)");
     if (!f || !out) return fail(BF_ERR_INVALID_ARG, "f and out must be non-null");
     if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
     const size_t img = ((size_t)(height - 1) * ld + width) * sizeof(float);

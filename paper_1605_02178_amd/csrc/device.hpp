@@ -945,7 +945,7 @@ constexpr int kFusedTabPad = 32;             // zero taps below t = 0 in the LDS
 // Constants of one fused launch, passed by value (kernel arguments): taps
 // w[t], t = 0..2W (tap t - W), and b_n, n = 0..N+1 with b_{N+1} = 0.
 struct FusedConsts {
-    float taps[2 * BF_FUSED_MAX_RADIUS + 1];
+    float taps[2 * BF_FUSED_F16_MAX_RADIUS + 1];
     float b[BF_MAX_DEGREE + 2];
 };
 
@@ -992,20 +992,40 @@ __device__ __forceinline__ int pivot_of(float x, const float *lo, int K, float k
     return g;
 }
 
-// Fused tile machinery; all 512 threads of the block use it together.
+// Fused tile machinery; all 64 NW threads of the block use it together.
 // setup() makes the Toeplitz fragments of one image (through the LDS tap
 // table tab, fused_tab_len(Q) elements); load() issues the global loads of
-// one 64 x TC output tile's inputs (halo column values and the lane's own
-// output pixels) into registers; run() filters that tile through ybuf (two
-// LDS buffers of kFusedYElems elements) and stores it.
-template <class M, int Q, int TC, int QA>
+// one TR x TC output tile's inputs (halo column values and the lane's own
+// output pixels) into registers; run() filters that tile through ybuf
+// (kBufs LDS buffers of kYElems elements) and stores it. Blocks that run
+// several tiles or centrings back to back continue the buffer parity (base)
+// and use two buffers (the 8-wave forms).
+// Geometry: NW waves (8 or 16) per block; output tiles of TR rows (64 or 32)
+// by TC columns. The column pass runs on the first kNCW waves, each over 16
+// halo columns and the tile's TR/16 row blocks; the row pass gives each wave
+// JB of the tile's (TR/16) x (TC/16) output blocks, in one row block rb.
+template <class M, int Q, int TC, int QA, int NW = 8, int TR = kFusedRows>
 struct FusedTile {
     typedef typename M::E E;
     typedef typename M::V V;
-    static constexpr int QB = Q - 2;
-    static constexpr int JB = TC / 32;          // output column blocks per wave in the row pass
-    static_assert((TC == 64 && Q <= 4) || (TC == 32 && Q == 5), "geometry");
-    static_assert(QA == Q - 3 || QA == Q - 2, "chunk range");
+    static constexpr int QB = Q - TR / 32;       // chunk range of odd row blocks (see fused_qa)
+    static constexpr int kNRB = TR / 16;         // row blocks
+    static constexpr int kNCB = TC / 16;         // output column blocks
+    static constexpr int kWPR = NW / kNRB;       // waves per row block in the row pass
+    static constexpr int JB = kNCB / kWPR;       // output column blocks per wave in the row pass
+    // halo columns the row pass reads: column blocks up to kNCB - 1 from
+    // their 32-column chunk base, QB + 1 chunks each
+    static constexpr int kNCW = kNCB + 2 * QB;
+    static constexpr int kPitch = 16 * NW + 12;  // LDS row pitch (elements): 6 words mod 32
+    static constexpr int kYElems = TR * kPitch;
+    static constexpr int kSlots = NW;            // range words per tile (one per wave)
+    // LDS buffers of the column-pass result: 64-row tiles on 16 waves run two
+    // planes per barrier phase (four buffers); the others one (two buffers)
+    static constexpr int kBufs = (NW == 16 && TR == 64) ? 4 : 2;
+    static_assert(TR == 64 || TR == 32, "tile rows");
+    static_assert(JB == 1 || JB == 2, "row-pass blocks per wave");
+    static_assert(kNCW <= NW, "halo columns");
+    static_assert(QA == QB - 1 || QA == QB, "chunk range");
 
     // Inputs of one tile: h[q][jj] = f at halo column 16 wave + li, halo row
     // 32q + 8lg + jj; c[b][v] = f at output row 16 rb + 4 lg + v, column
@@ -1033,13 +1053,14 @@ struct FusedTile {
         wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         li = lane & 15;
         lg = lane >> 4;
-        // Row-pass assignment: row block rb = wave / 2. With 64-column tiles
-        // the wave takes column blocks 2p, 2p+1 (p = wave & 1), which read the
-        // halo chunks shifted by p and use the fragments of blocks 0, 1. With
-        // 32-column tiles it takes block jc = p, whose fragment for chunk q,
-        // w[32q + 8lg + jj - 16p - li], is tf[2q + 1 - p].
-        rb = wave >> 1;
-        p = wave & 1;
+        // Row-pass assignment: row block rb = wave / kWPR, m = wave % kWPR.
+        // With JB = 2 the wave takes column blocks 2m, 2m+1, which read the
+        // halo chunks from column 32m and use the fragments of blocks 0, 1.
+        // With JB = 1 it takes block jc = m, reading chunks from 32 (m / 2);
+        // its fragment for chunk q, w[32q + 8lg + jj - 16 (m & 1) - li], is
+        // tf[2q + 1 - (m & 1)].
+        rb = wave / kWPR;
+        p = wave % kWPR;
         jc0 = p * JB;
         one_ref = W < H && W < Wd;
     }
@@ -1063,17 +1084,26 @@ struct FusedTile {
     __device__ __forceinline__ void load(int r0, int c0, Raw &R) const {
         const int mc = halo_index(c0 - W + 16 * wave + li, Wd, W, one_ref);
         const int cr = r0 + 16 * rb + 4 * lg;                    // first output row of the lane
-        if (r0 - W >= 0 && r0 - W + 32 * Q <= H && r0 + kFusedRows <= H && (long long)H * ld < (1LL << 29)) {
+        const bool colw = kNCW == NW || wave < kNCW;              // (uniform) a column-pass wave
+        if (r0 - W >= 0 && r0 - W + 32 * Q <= H && r0 + TR <= H && (long long)H * ld < (1LL << 29)) {
             // Most tiles: every halo row and output row inside the image, and
             // byte offsets within 32 bits, so each load is one add from the
             // lane's first offset (the row steps are uniform).
             const char *base = (const char *)f;
             const unsigned o = 4u * (unsigned)((r0 - W + 8 * lg) * ld + mc);
             const unsigned ld4 = 4u * (unsigned)ld;
+            if (colw) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
+                for (int q = 0; q < Q; ++q)
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj) R.h[q][jj] = *(const float *)(base + o + (unsigned)(32 * q + jj) * ld4);
+                    for (int jj = 0; jj < 8; ++jj)
+                        R.h[q][jj] = *(const float *)(base + o + (unsigned)(32 * q + jj) * ld4);
+            } else {
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) R.h[q][jj] = 0.0f;
+            }
 #pragma unroll
             for (int b = 0; b < JB; ++b) {
                 const unsigned oc = 4u * (unsigned)(cr * ld + min(c0 + 16 * (jc0 + b) + li, Wd - 1));
@@ -1083,11 +1113,18 @@ struct FusedTile {
         } else {
             // symmetric extension of the halo rows; output rows clamped
             const float *col = f + mc;
+            if (colw) {
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
+                for (int q = 0; q < Q; ++q)
 #pragma unroll
-                for (int jj = 0; jj < 8; ++jj)
-                    R.h[q][jj] = col[(long long)halo_index(r0 - W + 32 * q + 8 * lg + jj, H, W, one_ref) * ld];
+                    for (int jj = 0; jj < 8; ++jj)
+                        R.h[q][jj] = col[(long long)halo_index(r0 - W + 32 * q + 8 * lg + jj, H, W, one_ref) * ld];
+            } else {
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+#pragma unroll
+                    for (int jj = 0; jj < 8; ++jj) R.h[q][jj] = 0.0f;
+            }
 #pragma unroll
             for (int b = 0; b < JB; ++b) {
                 const int c = min(c0 + 16 * (jc0 + b) + li, Wd - 1);
@@ -1169,7 +1206,9 @@ struct FusedTile {
         }
 
         // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
+        // Waves past kNCW hold no halo columns the row pass reads.
         auto column_pass = [&](int n) {
+            if (kNCW < NW && wave >= kNCW) return;
             V a[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
@@ -1184,9 +1223,10 @@ struct FusedTile {
                     }
                 }
             }
-            E *yb = ybuf + ((n + base) & 1) * kFusedYElems;
+            E *yb = ybuf + ((n + base) & (kBufs - 1)) * kYElems;
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < kNRB; ++j) {
                 const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
                 mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -1194,13 +1234,14 @@ struct FusedTile {
                 typename M::V4 o;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
-                *(typename M::V4 *)(yb + (16 * j + li) * kFusedPitch + 16 * wave + 4 * lg) = o;
+                *(typename M::V4 *)(yb + (16 * j + li) * kPitch + 16 * wave + 4 * lg) = o;
             }
+            __builtin_amdgcn_s_setprio(0);
         };
         // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
         auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
-            const E *src = ybuf + ((n + base) & 1) * kFusedYElems + (16 * rb + li) * kFusedPitch + 8 * lg;
-            if (TC == 64) {
+            const E *src = ybuf + ((n + base) & (kBufs - 1)) * kYElems + (16 * rb + li) * kPitch + 8 * lg;
+            if constexpr (JB == 2) {
                 V ya[QB + 1];
 #pragma unroll
                 for (int q = 0; q <= QB; ++q) ya[q] = ld_frag<M>(src + 32 * (q + p));
@@ -1213,13 +1254,14 @@ struct FusedTile {
                 z[JB - 1] = acc1;
             } else {
                 // p is uniform: one branch per wave, no fragment selected per lane
+                src += 32 * (p >> 1);
                 mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
-                if (p == 0) {
+                if ((p & 1) == 0) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q + 1], acc);
+                    for (int q = 0; q <= QA; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q + 1], acc);
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q], acc);
+                    for (int q = 0; q <= QB; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q], acc);
                 }
                 z[0] = acc;
             }
@@ -1240,32 +1282,62 @@ struct FusedTile {
             }
         };
 
-        // Software pipeline: the row pass of plane n-1 and the column pass of
-        // plane n sit between the same two barriers (different LDS buffers).
-        column_pass(0);
-        __syncthreads();
-        column_pass(1);
-        {
-            mf_f4 z[JB];
-            row_pass(0, z);
+        // Eq. 9's first term (plane 0).
+        auto first = [&](const mf_f4 (&z)[JB]) {
             const float b0 = bt[0];
 #pragma unroll
             for (int b = 0; b < JB; ++b)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) Qa[b][v] = b0 * z[b][v];
-        }
-        __syncthreads();
-        for (int n = 2; n < P; ++n) {
-            column_pass(n);
-            mf_f4 z[JB];
-            row_pass(n - 1, z);
-            combine(n - 1, z);
+        };
+        if constexpr (kBufs == 4) {
+            // Software pipeline, two planes per phase: the row passes of
+            // planes 2k-2, 2k-1 and the column passes of 2k, 2k+1 sit between
+            // the same two barriers (four LDS buffers), which halves the
+            // barriers of a 16-wave block.
+            column_pass(0);
+            column_pass(1);
             __syncthreads();
-        }
-        {
-            mf_f4 z[JB];
-            row_pass(P - 1, z);
-            combine(P - 1, z);
+            for (int k = 1; 2 * k - 2 < P; ++k) {
+                if (2 * k < P) column_pass(2 * k);
+                if (2 * k + 1 < P) column_pass(2 * k + 1);
+                {
+                    mf_f4 z[JB];
+                    row_pass(2 * k - 2, z);
+                    if (k == 1) first(z);
+                    else combine(2 * k - 2, z);
+                }
+                if (2 * k - 1 < P) {
+                    mf_f4 z[JB];
+                    row_pass(2 * k - 1, z);
+                    combine(2 * k - 1, z);
+                }
+                if (2 * k < P) __syncthreads();
+            }
+        } else {
+            // Software pipeline: the row pass of plane n-1 and the column pass of
+            // plane n sit between the same two barriers (different LDS buffers).
+            column_pass(0);
+            __syncthreads();
+            column_pass(1);
+            {
+                mf_f4 z[JB];
+                row_pass(0, z);
+                first(z);
+            }
+            __syncthreads();
+            for (int n = 2; n < P; ++n) {
+                column_pass(n);
+                mf_f4 z[JB];
+                row_pass(n - 1, z);
+                combine(n - 1, z);
+                __syncthreads();
+            }
+            {
+                mf_f4 z[JB];
+                row_pass(P - 1, z);
+                combine(P - 1, z);
+            }
         }
 
 #pragma unroll
@@ -1372,7 +1444,8 @@ struct FusedTile {
 template <class M>
 __host__ __device__ constexpr bool fused_persistent(int Q) { return !M::kHalfPlanes && Q >= 4; }
 
-// Single-image fused kernel over the tiles_x-wide grid of 64 x TC tiles.
+// Single-image fused kernel over the tiles_x-wide grid of TR x TC tiles,
+// NW waves per block (FusedTile).
 // Where a block needs more than 128 VGPRs (one block per CU) it is
 // persistent: block b takes tiles b, b + grid, ..., makes the fragments once,
 // and loads the inputs of its next tile while the current one runs, so that
@@ -1381,23 +1454,23 @@ __host__ __device__ constexpr bool fused_persistent(int Q) { return !M::kHalfPla
 // registers of that prefetch would cost the second block per CU, which hides
 // those loads instead (and runs the other block's VALU work beside this
 // one's matrix-core work): one block per tile.
-template <class M, int Q, int TC, int QA>
-__global__ __launch_bounds__(512) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
-                                                    int Wd, int ld, FusedConsts C, int W, int N, float mu,
-                                                    float prescale, unsigned *__restrict__ slots, int tiles_x,
-                                                    int tiles) {
+template <class M, int Q, int TC, int QA, int NW = 8, int TR = kFusedRows>
+__global__ __launch_bounds__(NW * 64) void k_fused_mfma(const float *__restrict__ f, float *__restrict__ out, int H,
+                                                        int Wd, int ld, FusedConsts C, int W, int N, float mu,
+                                                        float prescale, unsigned *__restrict__ slots, int tiles_x,
+                                                        int tiles) {
     typedef typename M::E E;
-    typedef FusedTile<M, Q, TC, QA> T;
-    __shared__ __align__(16) E ybuf[2 * kFusedYElems];
+    typedef FusedTile<M, Q, TC, QA, NW, TR> T;
+    __shared__ __align__(16) E ybuf[T::kBufs * T::kYElems];
     __shared__ E tab[fused_tab_len(Q)];
     T tile(f, out, H, Wd, ld, W, N, mu, prescale, C.b, ybuf);
     tile.setup(C.taps, tab);
-    if constexpr (!fused_persistent<M>(Q)) {
+    if constexpr (!fused_persistent<M>(Q) || NW != 8) {
         const int t = blockIdx.x;
-        const int r0 = (t / tiles_x) * kFusedRows, c0 = (t % tiles_x) * TC;
+        const int r0 = (t / tiles_x) * TR, c0 = (t % tiles_x) * TC;
         typename T::Raw cur;
         tile.load(r0, c0, cur);
-        tile.run(r0, c0, cur, nullptr, slots + kFusedSlots * t);
+        tile.run(r0, c0, cur, nullptr, slots + T::kSlots * t);
     } else {
         typename T::Raw next;
         int t = blockIdx.x;

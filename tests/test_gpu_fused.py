@@ -42,13 +42,16 @@ def _log(msg):
     print(msg, flush=True)
 
 
-# (shape, sigma_s): W = 3, 9, 15, 30, 45 covers the three kernel geometries
-# (W <= 16, W <= 32 with 64-column tiles, W <= 48 with 32-column tiles);
-# ragged tails in both directions, single rows and columns, W above a side.
+# (shape, sigma_s): W = 3, 9, 15, 30, 45, 50-64 covers the FP16 geometries
+# (64 x 128 tiles up to W = 32, 64 x 64 up to 48, 32 x 128 up to 64, all on
+# 16 waves); ragged tails in both directions, single rows and columns, W
+# above a side.
 SHAPES = [
     ((130, 200), 1.0), ((130, 200), 3.0), ((130, 200), 5.0), ((130, 200), 10.0), ((130, 200), 15.0),
     ((64, 64), 10.0), ((65, 129), 10.0), ((1, 77), 2.0), ((129, 5), 2.0), ((7, 300), 5.0), ((300, 7), 5.0),
     ((2, 2), 3.0), ((1, 1), 1.0),
+    # FP16 radii 49-64 (32 x 128 tiles on 16 waves): ragged, taller and wider than the radius, and not
+    ((150, 290), 16.5), ((200, 300), 20.0), ((97, 131), 21.0), ((1, 77), 20.0), ((300, 40), 17.0), ((33, 260), 21.3),
 ]
 
 
@@ -109,7 +112,10 @@ def test_fused_argument_errors_and_fallback(torch_cuda):
         bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f32", tile_config=bf.TILE_FUSED)
     assert e.value.status == 2
     with pytest.raises(bf.BFError) as e:
-        bf.gc_filter(f, 17.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)   # W = 51
+        bf.gc_filter(f, 22.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED)   # W = 66 > 64
+    assert e.value.status == 2
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_filter(f, 17.0, 50.0, 11, stack_dtype="bf16", tile_config=bf.TILE_FUSED)  # W = 51 > 48 for BF16
     assert e.value.status == 2
     with pytest.raises(bf.BFError) as e:
         bf.gc_filter(f, 4.0, 30.0, 28, stack_dtype="f16", tile_config=bf.TILE_FUSED, staged=True)
@@ -117,9 +123,11 @@ def test_fused_argument_errors_and_fallback(torch_cuda):
     with pytest.raises(bf.BFError) as e:
         bf.gc_filter_batched([f], [4.0], [30.0], [28], stack_dtype="f32", tile_config=bf.TILE_FUSED)
     assert e.value.status == 2
-    # W = 51 without a tile flag takes the three-kernel path
-    y = _np(bf.gc_filter(f, 17.0, 30.0, 28, stack_dtype="f16"))
-    assert np.abs(y - C.gcf(f64, 17.0, 30.0, 28)).max() <= BOUND[("f16", 30.0, 28)]
+    # W = 66 (FP16) and W = 51 (BF16) without a tile flag take the three-kernel path
+    y = _np(bf.gc_filter(f, 22.0, 30.0, 28, stack_dtype="f16"))
+    assert np.abs(y - C.gcf(f64, 22.0, 30.0, 28)).max() <= BOUND[("f16", 30.0, 28)]
+    y = _np(bf.gc_filter(f, 17.0, 50.0, 11, stack_dtype="bf16"))
+    assert np.abs(y - C.gcf(f64, 17.0, 50.0, 11)).max() <= BOUND[("bf16", 50.0, 11)]
 
 
 def test_fused_range_flag(torch_cuda):
@@ -199,6 +207,27 @@ def test_fused_persistent_ragged_sampled(torch_cuda, dtype, sigma_r, N, sigma_s)
         err = np.abs(y[reg[0]:reg[1], reg[2]:reg[3]] - ref).max()
         _log(f"fused {dtype} 1100x2050 sigma_s={sigma_s} crop {reg}: {err:.3e}")
         assert err <= BOUND[(dtype, sigma_r, N)]
+
+
+@pytest.mark.parametrize("shape,seed", [((4096, 4096), 3), ((1100, 2050), 41)])
+def test_fused_f16_wide_radius_sampled(torch_cuda, shape, seed):
+    """FP16 at sigma_s = 20 (W = 60: 32 x 128 tiles on 16 waves, the fused
+    tile's widest geometry) at N = 32: the 4096^2 headline image and a ragged
+    1100 x 2050 image against the oracle on crops at the corners, the centre
+    and a tile seam."""
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    H, Wd = shape
+    f = edge_rich(H, Wd, seed=seed).astype(np.float32).astype(np.float64)
+    y = _np(bf.gc_filter(_gpu(torch_cuda, f), 20.0, 30.0, 32, stack_dtype="f16", tile_config=bf.TILE_FUSED))
+    assert np.isfinite(y).all()
+    for reg in ((0, 70, 0, 70), (0, 70, Wd - 70, Wd), (H - 70, H, 0, 70), (H - 70, H, Wd - 70, Wd),
+                (H // 2 - 40, H // 2 + 40, Wd // 2 - 40, Wd // 2 + 40), (30, 34, 0, Wd)):
+        ref = C.gcf(f, 20.0, 30.0, 32, region=reg)
+        err = np.abs(y[reg[0]:reg[1], reg[2]:reg[3]] - ref).max()
+        _log(f"fused f16 W=60 {shape} crop {reg}: {err:.3e}")
+        assert err <= BOUND[("f16", 30.0, 32)]
 
 
 def test_fused_centre_value_pixels(torch_cuda):

@@ -74,7 +74,8 @@ def test_noalloc_refusals(torch_cuda):
         ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()), 64, 64, 64, ss, sr, N, dt, flags, None,
         None)
     assert code(3.0, 30.0, 28, 0) == 2               # FP32 stack: not on the fused tile
-    assert code(17.0, 30.0, 28, 1) == 2              # radius 51 > 48
+    assert code(22.0, 30.0, 28, 1) == 2              # FP16 radius 66 > 64
+    assert code(17.0, 50.0, 11, 2) == 2              # BF16 radius 51 > 48
     assert code(3.0, 30.0, 28, 1, 0x2) == 1          # staged flag
     assert code(3.0, 30.0, 28, 1, (0 + 1) << 8) == 1  # a three-kernel tile
     assert code(3.0, 12.0, 170, 1) == 3              # ill-conditioned
