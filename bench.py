@@ -412,6 +412,58 @@ def bench_small_sigma_r(bf, f, f64, sigma_s, steps, log, sigma_r=10.0):
     return res
 
 
+def bench_wide_radius(bf, f, f64, steps, log, sigma_s=20.0, sigma_r=30.0, N=28):
+    """The headline image at sigma_s = 20 (W = 60), FP32 stack at N = 28 (three
+    kernels) against the FP16 stack on the fused tile (32 x 128 tiles on 16
+    waves) at the smallest N >= 28 whose max-abs error and PSNR against the
+    direct filter (eq. 1) on the 256^2 centre crop are no worse than FP32's."""
+    import numpy as np
+    import torch
+    from oracle import native as C
+    H, Wd = f.shape
+    c0 = H // 2 - 128
+    reg = (c0, c0 + 256, c0, c0 + 256)
+    direct = C.direct_bf(f64, sigma_s, sigma_r, region=reg)
+
+    def err(y):
+        e = y.cpu().double().numpy()[c0:c0 + 256, c0:c0 + 256] - direct
+        return float(np.abs(e).max()), round(10.0 * math.log10(255.0 ** 2 / float(np.mean(e * e))), 3)
+
+    def timed(stack, n):
+        out = torch.empty_like(f)
+        ws = torch.empty(bf.workspace_bytes(H, Wd, sigma_s, n, stack), dtype=torch.uint8, device="cuda:0")
+        bf.gc_filter(f, sigma_s, sigma_r, n, stack_dtype=stack, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            bf.gc_filter(f, sigma_s, sigma_r, n, stack_dtype=stack, out=out, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, out
+
+    ms32, y32 = timed("f32", N)
+    e32, db32 = err(y32)
+    n16 = N
+    while True:
+        ms16, y16 = timed("f16", n16)
+        e16, db16 = err(y16)
+        log(f"bench: sigma_s={sigma_s:g} FP16 N={n16}: {ms16:.3f} ms, max abs {e16:.4f}, {db16:.2f} dB "
+            f"(FP32 N={N}: {ms32:.3f} ms, {e32:.4f}, {db32:.2f} dB)")
+        if (e16 <= e32 and db16 >= db32) or n16 >= N + 8:
+            break
+        n16 += 1
+    px = H * Wd
+    return {"sigma_s": sigma_s, "radius": bf.radius(sigma_s), "sigma_r": sigma_r, "steps": steps,
+            "f32": {"degree": N, "ms_per_step": round(ms32, 4), "mpx_s": round(px / 1e6 / (ms32 / 1e3), 1),
+                    "max_abs_vs_direct_256c": e32, "psnr_vs_direct_256c": db32, "path": "three kernels"},
+            "f16": {"degree": n16, "ms_per_step": round(ms16, 4), "mpx_s": round(px / 1e6 / (ms16 / 1e3), 1),
+                    "max_abs_vs_direct_256c": e16, "psnr_vs_direct_256c": db16,
+                    "path": "fused matrix-core tile, 32 x 128 tiles on 16 waves"},
+            "same_error": e16 <= e32 and db16 >= db32, "speedup_f16": round(ms32 / ms16, 2)}
+
+
 def bench_recursive(bf, f, sigma_r, N, steps, log):
     """The recursive variant of eq. 7 (FP32 stack) against the truncated
     convolution (FP32 stack, three kernels) at the headline size, for
@@ -491,6 +543,7 @@ def main():
     ap.add_argument("--no-joint", action="store_true", help="skip the joint-filter timing")
     ap.add_argument("--no-small-sigma-r", action="store_true", help="skip the pivoted small-sigma_r timing")
     ap.add_argument("--no-recursive", action="store_true", help="skip the recursive-variant timing")
+    ap.add_argument("--no-wide", action="store_true", help="skip the sigma_s = 20 FP32 vs FP16 comparison")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -622,6 +675,9 @@ def main():
         result["batched"] = bench_batched(bf, args.batch_steps, log, "f32")
         if not args.no_fp16:
             result["batched_fp16"] = bench_batched(bf, args.batch_steps, log, "f16")
+
+    if not args.no_wide:
+        result["wide_radius"] = bench_wide_radius(bf, f, f64, args.batch_steps, log)
 
     if not args.no_recursive:
         result["recursive"] = bench_recursive(bf, f, sr, N, args.batch_steps, log)
