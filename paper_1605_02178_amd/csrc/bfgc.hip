@@ -1004,7 +1004,9 @@ static void plan_batch(const bf_image_desc *d, int count, int dtype, unsigned fl
             cost[p].push_back(0);
         }
         if (fused) {
-            const int TC = L.W <= 32 ? 64 : 32;
+            // tile columns of the class kernel (batched_fused_kernel,
+            // k_fused_batched_pivot_items): wider FP16 tiles on 16 waves
+            const int TC = dtype == BF_STACK_F16 && !piv ? (L.W <= 32 ? 128 : 64) : (L.W <= 32 ? 64 : 32);
             int c = fused_class_of_radius(L.W);
             I.gvx = (I.Wd + TC - 1) / TC;
             if (!piv) {
@@ -1136,7 +1138,7 @@ struct BatchKernels {
     const void *func[kBatchPhases];
     int grid[kBatchPhases];
     bool items_grid[kBatchPhases] = {};   // grid = the phase's item count (set at every graph launch)
-    int block = 256;
+    int block[kBatchPhases];
     size_t lds = 0;
 };
 struct GraphEntry {
@@ -1157,9 +1159,9 @@ static std::vector<GraphEntry> g_graphs;
 // Same kernels and launch shape; grids that follow the item count may differ
 // (the cached graph's nodes are updated to the new grid before its launch).
 static bool same_kernels(const BatchKernels &a, const BatchKernels &b) {
-    if (a.n != b.n || a.block != b.block || a.lds != b.lds) return false;
+    if (a.n != b.n || a.lds != b.lds) return false;
     for (int i = 0; i < a.n; ++i)
-        if (a.func[i] != b.func[i] || a.items_grid[i] != b.items_grid[i] ||
+        if (a.func[i] != b.func[i] || a.block[i] != b.block[i] || a.items_grid[i] != b.items_grid[i] ||
             (!a.items_grid[i] && a.grid[i] != b.grid[i]))
             return false;
     return true;
@@ -1170,7 +1172,7 @@ static hipKernelNodeParams kernel_node(const BatchKernels &K, int p, void **args
     std::memset(&kp, 0, sizeof kp);
     kp.func = (void *)K.func[p];
     kp.gridDim = dim3(K.grid[p]);
-    kp.blockDim = dim3(K.block);
+    kp.blockDim = dim3(K.block[p]);
     kp.sharedMemBytes = (unsigned)K.lds;
     kp.kernelParams = args;
     return kp;
@@ -1290,7 +1292,7 @@ static bf_status launch_batch(const BatchPlan &B, const BatchKernels &K, unsigne
             char *blob = ws;
             void *args[] = {&blob};
             for (int p = 0; p < K.n && e == hipSuccess; ++p)
-                e = hipLaunchKernel(K.func[p], dim3(K.grid[p]), dim3(K.block), args, K.lds, stream);
+                e = hipLaunchKernel(K.func[p], dim3(K.grid[p]), dim3(K.block[p]), args, K.lds, stream);
             if (e == hipSuccess) e = hipGetLastError();
         }
     }
@@ -1316,20 +1318,22 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
     K.func[0] = (const void *)k_batched<S, RV, RH, 0>;
     K.func[1] = (const void *)k_batched<S, RV, RH, 1>;
     K.func[2] = (const void *)k_batched<S, RV, RH, 2>;
-    K.block = 256;
     K.lds = batch_lds_bytes((int)B.img.size());
-    for (int p = 0; p < 3; ++p) K.grid[p] = phase_grid(K.func[p], B.phase_items[p], K.block, K.lds);
+    for (int p = 0; p < 3; ++p) {
+        K.block[p] = 256;
+        K.grid[p] = phase_grid(K.func[p], B.phase_items[p], K.block[p], K.lds);
+    }
     return launch_batch(B, K, flags, ws, stream);
 }
 
-// Fused FP16/BF16 form: one persistent kernel per non-empty geometry class.
-// The batched fused kernel of a class: one block per item for FP16 (two
-// blocks per CU, as the single-image kernel), the persistent prefetching
-// form for BF16.
-template <class M, int Q, int TC, int QA>
+// Fused FP16/BF16 form: one kernel per non-empty geometry class.
+// The batched fused kernel of a plain class: one 16-wave block per item for
+// FP16, on the single-image kernel's tiles (fused_geom: 64 x 128 to radius
+// 32, 64 x 64 to 48), the persistent prefetching 8-wave form for BF16.
+template <class M, int Q, int QA>
 static const void *batched_fused_kernel() {
-    if constexpr (M::kHalfPlanes) return (const void *)k_fused_batched_items<M, Q, TC, QA>;
-    else return (const void *)k_fused_batched<M, Q, TC, QA>;
+    if constexpr (M::kHalfPlanes) return (const void *)k_fused_batched_items<M, Q, (Q <= 4 ? 128 : 64), QA, 16>;
+    else return (const void *)k_fused_batched<M, Q, (Q <= 4 ? 64 : 32), QA>;
 }
 
 template <class M>
@@ -1341,24 +1345,24 @@ static bf_status run_batched_fused(const bf_image_desc *descs, int count, int dt
     if (ws_bytes < B.total) return fail(BF_ERR_WORKSPACE, "workspace smaller than bf_gc_batched_workspace_bytes()");
     if (B.items == 0) return BF_OK;
     const void *cls[kBatchPhases] = {
-        batched_fused_kernel<M, 3, 64, 0>(), batched_fused_kernel<M, 3, 64, 1>(),
-        batched_fused_kernel<M, 4, 64, 1>(), batched_fused_kernel<M, 4, 64, 2>(),
-        batched_fused_kernel<M, 5, 32, 2>(), batched_fused_kernel<M, 5, 32, 3>(),
+        batched_fused_kernel<M, 3, 0>(), batched_fused_kernel<M, 3, 1>(),
+        batched_fused_kernel<M, 4, 1>(), batched_fused_kernel<M, 4, 2>(),
+        batched_fused_kernel<M, 5, 2>(), batched_fused_kernel<M, 5, 3>(),
         (const void *)k_fused_batched_pivot_items<M, 3, 64, 0>, (const void *)k_fused_batched_pivot_items<M, 3, 64, 1>,
         (const void *)k_fused_batched_pivot_items<M, 4, 64, 1>, (const void *)k_fused_batched_pivot_items<M, 4, 64, 2>,
         (const void *)k_fused_batched_pivot_items<M, 5, 32, 2>, (const void *)k_fused_batched_pivot_items<M, 5, 32, 3>};
     BatchKernels K;
-    K.block = 512;
     K.lds = batch_lds_bytes((int)B.img.size());
     for (int c = 0; c < kBatchPhases; ++c)
         if (B.phase_items[c] > 0) {
             K.func[K.n] = cls[c];
+            K.block[K.n] = M::kHalfPlanes && c < kFusedClasses ? 1024 : 512;
             if (M::kHalfPlanes || c >= kFusedClasses) {   // one block per item
                 if (B.phase_items[c] > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "fused batch: too many tiles in a class");
                 K.grid[K.n] = (int)B.phase_items[c];
                 K.items_grid[K.n] = true;
             } else {
-                K.grid[K.n] = phase_grid(cls[c], B.phase_items[c], K.block, K.lds);
+                K.grid[K.n] = phase_grid(cls[c], B.phase_items[c], K.block[K.n], K.lds);
             }
             ++K.n;
         }

@@ -1004,7 +1004,8 @@ __device__ __forceinline__ int pivot_of(float x, const float *lo, int K, float k
 // by TC columns. The column pass runs on the first kNCW waves, each over 16
 // halo columns and the tile's TR/16 row blocks; the row pass gives each wave
 // JB of the tile's (TR/16) x (TC/16) output blocks, in one row block rb.
-template <class M, int Q, int TC, int QA, int NW = 8, int TR = kFusedRows>
+template <class M, int Q, int TC, int QA, int NW = 8, int TR = kFusedRows,
+          int BUFS = (NW == 16 && TR == 64) ? 4 : 2>
 struct FusedTile {
     typedef typename M::E E;
     typedef typename M::V V;
@@ -1019,9 +1020,11 @@ struct FusedTile {
     static constexpr int kPitch = 16 * NW + 12;  // LDS row pitch (elements): 6 words mod 32
     static constexpr int kYElems = TR * kPitch;
     static constexpr int kSlots = NW;            // range words per tile (one per wave)
-    // LDS buffers of the column-pass result: 64-row tiles on 16 waves run two
-    // planes per barrier phase (four buffers); the others one (two buffers)
-    static constexpr int kBufs = (NW == 16 && TR == 64) ? 4 : 2;
+    // LDS buffers of the column-pass result: with four, two planes per
+    // barrier phase (the single-image 64-row tiles on 16 waves); with two,
+    // one (every other form)
+    static constexpr int kBufs = BUFS;
+    static_assert(BUFS == 2 || BUFS == 4, "buffers");
     static_assert(TR == 64 || TR == 32, "tile rows");
     static_assert(JB == 1 || JB == 2, "row-pass blocks per wave");
     static_assert(kNCW <= NW, "halo columns");
@@ -1967,15 +1970,15 @@ __global__ __launch_bounds__(512) void k_fused_batched(char *__restrict__ blob) 
 // runs two blocks per CU: one block per (image, tile) item (grid = the
 // class's items, set at every launch), as the single-image kernel, held to
 // 128 VGPRs (four waves per SIMD: two blocks per CU; 94-124 used).
-template <class M, int Q, int TC, int QA>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_batched_items(
+template <class M, int Q, int TC, int QA, int NW = 8>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_fused_batched_items(
     char *__restrict__ blob) {
     typedef typename M::E E;
-    typedef FusedTile<M, Q, TC, QA> T;
+    typedef FusedTile<M, Q, TC, QA, NW, kFusedRows, 2> T;
     constexpr int C = fused_class(Q, QA);
     const float prescale = M::kPrescale;
     extern __shared__ long long s_start[];
-    __shared__ __align__(16) E ybuf[2 * kFusedYElems];
+    __shared__ __align__(16) E ybuf[2 * T::kYElems];
     __shared__ E tab[fused_tab_len(Q)];
     BatchHeader *hdr = (BatchHeader *)blob;
     const long long t = blockIdx.x;
