@@ -788,14 +788,23 @@ struct BwdLayout {
     size_t params, stackA, stackB, perpx, partial, total;
 };
 
+// Radii up to kAdjMaxRadius run the two fused tile kernels (no plane stacks;
+// one partial sum per 64 x 32 tile); larger radii the staged passes over two
+// FP64 stacks.
+static bool bwd_fused(double sigma_s) { return radius_of(sigma_s) <= kAdjMaxRadius; }
+static long long bwd_tiles(int H, int Wd) {
+    return (long long)((Wd + kAdjCols - 1) / kAdjCols) * ((H + kAdjRows - 1) / kAdjRows);
+}
+
 static BwdLayout bwd_layout(int H, int Wd, double sigma_s, int N) {
     BwdLayout B;
     const size_t P = (size_t)N + 2;
+    const bool fused = bwd_fused(sigma_s);
     B.params = align256(sizeof(double) * (size_t)param_layout(radius_of(sigma_s), N).total);
-    B.stackA = align256(P * H * lds_of(Wd) * sizeof(double));
-    B.stackB = align256(P * Wd * ldt_of(H) * sizeof(double));
+    B.stackA = fused ? 0 : align256(P * H * lds_of(Wd) * sizeof(double));
+    B.stackB = fused ? 0 : align256(P * Wd * ldt_of(H) * sizeof(double));
     B.perpx = align256((size_t)H * Wd * sizeof(double));
-    B.partial = align256(kNeighborBlocks * sizeof(double));
+    B.partial = align256((size_t)(fused ? bwd_tiles(H, Wd) : kNeighborBlocks) * sizeof(double));
     B.total = kFlagBytes + B.params + B.stackA + B.stackB + 4 * B.perpx + B.partial;
     return B;
 }
@@ -820,6 +829,49 @@ static bf_status run_backward(const float *f, const float *ybar, float *grad_f, 
     const int lds = lds_of(Wd), ldt = ldt_of(H);
     const long long ps = (long long)H * lds, pst = (long long)Wd * ldt;
     const double mu = fit(sigma_r, N).mu;
+    if (bwd_fused(sigma_s)) {
+        // The forward recomputed in FP64 (the derivative sums cancel strongly;
+        // FP32 planes cost them three to four digits), fused with the
+        // adjoint's first step, then the adjoint planes, both per tile.
+        const long long tiles = bwd_tiles(H, Wd);
+        const dim3 g((Wd + kAdjCols - 1) / kAdjCols, (H + kAdjRows - 1) / kAdjRows);
+        const double *taps = prm + L.off_taps + (kTapPad - 1);
+        {
+            ProfScope prof_("k_adj_forward_tile", stream);
+#define BF_ADJ_F(WW)                                                                                               \
+    case WW:                                                                                                       \
+        hipLaunchKernelGGL(k_adj_forward_tile<WW>, g, dim3(kAdjThreads), 0, stream, f, ybar, H, Wd, ld, N, mu, taps, \
+                           prm + L.off_cq, prm + L.off_cp, prm + L.off_bd, alpha, beta, gdir, gmu);                 \
+        break;
+            switch (L.W) {
+                BF_ADJ_F(1) BF_ADJ_F(2) BF_ADJ_F(3) BF_ADJ_F(4) BF_ADJ_F(5) BF_ADJ_F(6) BF_ADJ_F(7) BF_ADJ_F(8)
+                BF_ADJ_F(9) BF_ADJ_F(10) BF_ADJ_F(11) BF_ADJ_F(12) BF_ADJ_F(13) BF_ADJ_F(14) BF_ADJ_F(15) BF_ADJ_F(16)
+                default: return fail(BF_ERR_UNSUPPORTED, "fused backward: radius out of range");
+            }
+#undef BF_ADJ_F
+            if ((st = check_launch("k_adj_forward_tile")) != BF_OK) return st;
+        }
+        {
+            ProfScope prof_("k_adj_backward_tile", stream);
+#define BF_ADJ_B(WW)                                                                                                 \
+    case WW:                                                                                                         \
+        hipLaunchKernelGGL(k_adj_backward_tile<WW>, g, dim3(kAdjThreads), 0, stream, f, H, Wd, ld, N, mu, taps,      \
+                           prm + L.off_cq, prm + L.off_cp, (const double *)alpha, (const double *)beta,              \
+                           (const double *)gdir, (const double *)gmu, grad_f, partial);                              \
+        break;
+            switch (L.W) {
+                BF_ADJ_B(1) BF_ADJ_B(2) BF_ADJ_B(3) BF_ADJ_B(4) BF_ADJ_B(5) BF_ADJ_B(6) BF_ADJ_B(7) BF_ADJ_B(8)
+                BF_ADJ_B(9) BF_ADJ_B(10) BF_ADJ_B(11) BF_ADJ_B(12) BF_ADJ_B(13) BF_ADJ_B(14) BF_ADJ_B(15) BF_ADJ_B(16)
+                default: return fail(BF_ERR_UNSUPPORTED, "fused backward: radius out of range");
+            }
+#undef BF_ADJ_B
+            if ((st = check_launch("k_adj_backward_tile")) != BF_OK) return st;
+        }
+        ProfScope prof_("k_reduce_f64", stream);
+        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, stream, (const double *)partial, (int)tiles,
+                           -2.0 * mu / sigma_r, grad_sr);
+        return check_launch("k_reduce_f64");
+    }
     // Recompute the forward stack and its column pass in FP64: the derivative
     // sums below cancel strongly, and FP32 planes cost them three to four
     // digits (measured against the FP64 gradient oracle).

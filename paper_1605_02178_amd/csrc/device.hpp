@@ -808,6 +808,312 @@ __global__ __launch_bounds__(256) void k_adj_neighbor(const float *__restrict__ 
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// ---------------------------------------------------------------------------
+// Fused FP64 adjoint tiles (radius W <= 16). One 1024-thread block per 64 x 32
+// output tile (rows x columns). The planes (H_n in the first kernel, R_m in the second) are
+// generated one at a time over the tile and its W-halo, filtered in LDS
+// (column pass, then row pass) and folded into per-pixel sums, so no plane
+// stack goes through HBM. Each thread holds the generator state of up to
+// six halo pixels in registers (halo row 16k + wave, halo column lane) and
+// writes the next plane between the column and the row pass. The tap
+// loops are unrolled for the compile-time radius.
+// ---------------------------------------------------------------------------
+constexpr int kAdjRows = 64;
+constexpr int kAdjCols = 32;
+constexpr int kAdjMaxRadius = 16;
+constexpr int kAdjPitch = kAdjCols + 2 * kAdjMaxRadius + 1;   // 65: odd in doubles, so lanes on consecutive rows start in distinct banks
+constexpr int kAdjThreads = 1024;
+constexpr int kAdjWaves = kAdjThreads / 64;
+constexpr int kAdjRV = kAdjRows / kAdjWaves;                   // rows per lane in the column pass: 4
+constexpr int kAdjRH = kAdjRows * kAdjCols / kAdjThreads;      // columns per thread in the row pass: 2
+
+struct AdjLds {
+    double pl[(kAdjRows + 2 * kAdjMaxRadius) * kAdjPitch];   // the current plane over the halo
+    double vt[kAdjRows * kAdjPitch];                         // its column pass: 64 rows x (32 + 2W) columns
+};
+
+template <int W>
+constexpr int adj_own_count() {
+    return (kAdjRows + 2 * W + kAdjWaves - 1) / kAdjWaves;
+}
+
+// Halo pixel k of this thread: halo row 16k + wave, halo column lane, at
+// pl[(16k + wave) * kAdjPitch + lane]. adj_own_in: whether it lies in the
+// halo; adj_own_at: its mirrored image coordinates ((0, 0) if it does not).
+template <int W>
+__device__ __forceinline__ bool adj_own_in(int k) {
+    return kAdjWaves * k + (int)(threadIdx.x >> 6) < kAdjRows + 2 * W && (int)(threadIdx.x & 63) < kAdjCols + 2 * W;
+}
+template <int W>
+__device__ __forceinline__ void adj_own_at(int k, int r0, int c0, int H, int Wd, int &gi, int &gj) {
+    const int row = kAdjWaves * k + (int)(threadIdx.x >> 6);
+    if (!adj_own_in<W>(k)) {
+        gi = gj = 0;
+        return;
+    }
+    gi = mirror(r0 - W + row, H);
+    gj = mirror(c0 - W + (int)(threadIdx.x & 63), Wd);
+}
+
+// The W + 1 distinct taps (offsets -W..0; the Gaussian is symmetric), loaded
+// once per block into (scalar) registers; tap t (offset t - W) of 2W + 1.
+template <int W>
+struct AdjTaps {
+    double v[W + 1];
+    __device__ __forceinline__ explicit AdjTaps(const double *__restrict__ w) {
+#pragma unroll
+        for (int t = 0; t <= W; ++t) v[t] = w[t];
+    }
+    __device__ __forceinline__ double operator[](int t) const { return v[t <= W ? t : 2 * W - t]; }
+};
+
+// acc[r] = sum_t tap(t - r) x(t), t in [0, R + 2W), x(t) = ld(t) from LDS:
+// loads in chunks of U, the next chunk's loads issued before the current
+// chunk's FMAs. Compiler and scheduling barriers between the chunks keep the
+// loads from being merged and hoisted all ahead (2 registers per value).
+template <int W, int R, int U, class LD>
+__device__ __forceinline__ void adj_conv(LD ld, const AdjTaps<W> &w, double (&acc)[R]) {
+    constexpr int T = R + 2 * W;
+    constexpr int NC = (T + U - 1) / U;
+    double buf[2][U];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (u < T) buf[0][u] = ld(u);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c + 1 < NC) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if ((c + 1) * U + u < T) buf[(c + 1) & 1][u] = ld((c + 1) * U + u);
+        }
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = c * U + u;
+            if (t < T) {
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    if (t - r >= 0 && t - r <= 2 * W) acc[r] = fma(w[t - r], buf[c & 1][u], acc[r]);
+            }
+        }
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// Column pass of the plane in pl (eq. 7 along columns): wave v gives tile rows
+// [4v, 4v + 4), lane = halo column; w points at the tap of offset -W.
+template <int W>
+__device__ __forceinline__ void adj_column_pass(AdjLds &S, const AdjTaps<W> &w) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (lane < kAdjCols + 2 * W) {
+        double acc[kAdjRV];
+        const double *src = S.pl + wave * kAdjRV * kAdjPitch + lane;
+        adj_conv<W, kAdjRV, 4>([&](int t) { return src[t * kAdjPitch]; }, w, acc);
+#pragma unroll
+        for (int r = 0; r < kAdjRV; ++r) S.vt[(wave * kAdjRV + r) * kAdjPitch + lane] = acc[r];
+    }
+}
+
+// Row pass of the column-filtered plane: thread -> tile row lane, columns
+// 2 wave and the next.
+template <int W>
+__device__ __forceinline__ void adj_row_pass(const AdjLds &S, const AdjTaps<W> &w, double (&x)[kAdjRH]) {
+    const int i = threadIdx.x & 63;
+    const int j0 = (threadIdx.x >> 6) * kAdjRH;
+    const double *src = S.vt + i * kAdjPitch + j0;
+    adj_conv<W, kAdjRH, 4>([&](int t) { return src[t]; }, w, x);
+}
+
+// Recomputed forward, fused: the filtered planes Hbar_n at each output pixel,
+// folded in ascending n into the six sums of k_hpass_adj (with explicit
+// powers s^n, s^{n-1}, s^{n-2} of the output pixel); writes alpha, beta, the
+// direct term of dL/ds and the coefficient term of dL/dmu (FP64, pitch Wd).
+template <int W>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_forward_tile(
+    const float *__restrict__ f, const float *__restrict__ ybar, int H, int Wd, int ld, int N, double mu,
+    const double *__restrict__ taps, const double *__restrict__ cq, const double *__restrict__ cp,
+    const double *__restrict__ bd, double *__restrict__ alpha, double *__restrict__ beta, double *__restrict__ gdir,
+    double *__restrict__ gmu) {
+    constexpr int OWN = adj_own_count<W>();
+    __shared__ AdjLds S;
+    const int r0 = blockIdx.y * kAdjRows, c0 = blockIdx.x * kAdjCols;
+    const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
+    double *own = S.pl + (threadIdx.x >> 6) * kAdjPitch + (threadIdx.x & 63);
+    double s[OWN], h[OWN];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        int gi, gj;
+        adj_own_at<W>(k, r0, c0, H, Wd, gi, gj);
+        const double sv = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
+        s[k] = sv;
+        h[k] = exp(-0.5 * mu * sv * sv);                                 // H_0
+        if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = h[k];
+    }
+    const int i = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * kAdjRH;
+    const int gr = min(r0 + i, H - 1);
+    double so[kAdjRH], p2[kAdjRH];   // s and s^{max(n-2,0)} of the output pixel
+    double Pa[kAdjRH], Qa[kAdjRH], dP[kAdjRH], dQ[kAdjRH], Pm[kAdjRH], Qm[kAdjRH];
+#pragma unroll
+    for (int q = 0; q < kAdjRH; ++q) {
+        const int gc = min(c0 + j0 + q, Wd - 1);
+        so[q] = ((double)f[(long long)gr * ld + gc] - kTc) * (1.0 / kTh);
+        p2[q] = 1.0;
+        Pa[q] = Qa[q] = dP[q] = dQ[q] = Pm[q] = Qm[q] = 0.0;
+    }
+    __syncthreads();
+    const int P = N + 2;
+    for (int n = 0; n < P; ++n) {
+        // this plane's coefficients, loaded unconditionally (clamped index) so
+        // that no branch separates the row pass from the fold
+        const double cqn = n <= N ? cq[min(n, N)] : 0.0, bqn = n <= N ? bd[min(n, N)] : 0.0;
+        const double cpn = n >= 1 ? cp[max(n - 1, 0)] : 0.0, bpn = n >= 1 ? bd[max(n - 1, 0)] : 0.0;
+        adj_column_pass<W>(S, w);
+        __syncthreads();
+        // the column pass is done with plane n: the next one is written now
+        // (before the row pass, which then sits in one basic block with the
+        // fold below and keeps its load/FMA interleave)
+        if (n + 1 < P) {
+#pragma unroll
+            for (int k = 0; k < OWN; ++k) {
+                h[k] *= s[k];                                             // H_{n+1} = H_n s
+                if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = h[k];
+            }
+        }
+        double x[kAdjRH];
+        adj_row_pass<W>(S, w, x);
+        const double ncq = (double)n * cqn, ncp = (double)(n - 1) * cpn;
+#pragma unroll
+        for (int q = 0; q < kAdjRH; ++q) {
+            // v0 = s^n x, v1 = s^{n-1} x, v2 = s^{n-2} x (p2 = s^{max(n-2,0)}).
+            // Below n = 2 a missing (negative) power is replaced by the next
+            // one: only zero coefficients meet it (cpn and ncq at n = 0, ncp
+            // at n <= 1). The selects are on n, uniform: no branches.
+            const double v2 = p2[q] * x[q];
+            const double v1 = n >= 2 ? so[q] * v2 : v2;
+            const double v0 = n >= 1 ? so[q] * v1 : v1;
+            if (n >= 2) p2[q] *= so[q];
+            Qa[q] = fma(cqn, v0, Qa[q]);
+            Qm[q] = fma(bqn, v0, Qm[q]);
+            dQ[q] = fma(ncq, v1, dQ[q]);
+            Pa[q] = fma(cpn, v1, Pa[q]);
+            Pm[q] = fma(bpn, v1, Pm[q]);
+            dP[q] = fma(ncp, v2, dP[q]);
+        }
+        __syncthreads();
+    }
+    const int r = r0 + i;
+#pragma unroll
+    for (int q = 0; q < kAdjRH; ++q) {
+        const int c = c0 + j0 + q;
+        if (r < H && c < Wd) {
+            const double yb = (double)ybar[(long long)r * ld + c];
+            const double a = yb * kTh / Qa[q];
+            const double b = -a * Pa[q] / Qa[q];
+            const long long o = (long long)r * Wd + c;
+            alpha[o] = a;
+            beta[o] = b;
+            gdir[o] = a * dP[q] + b * dQ[q];
+            gmu[o] = a * Pm[q] + b * Qm[q];
+        }
+    }
+}
+
+// Adjoint, fused: the planes R_m (from alpha, beta of the halo pixels)
+// filtered by the same mirrored Gaussian, folded at each output pixel j with
+// H_m(j) recomputed in FP64 into dL/df_j; one partial sum of the dL/dmu terms
+// per tile (summed in a fixed order by k_reduce_f64).
+template <int W>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_backward_tile(
+    const float *__restrict__ f, int H, int Wd, int ld, int N, double mu, const double *__restrict__ taps,
+    const double *__restrict__ cq, const double *__restrict__ cp, const double *__restrict__ alpha,
+    const double *__restrict__ beta, const double *__restrict__ gdir, const double *__restrict__ gmu,
+    float *__restrict__ grad_f, double *__restrict__ partial) {
+    constexpr int OWN = adj_own_count<W>();
+    __shared__ AdjLds S;
+    const int r0 = blockIdx.y * kAdjRows, c0 = blockIdx.x * kAdjCols;
+    const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
+    double *own = S.pl + (threadIdx.x >> 6) * kAdjPitch + (threadIdx.x & 63);
+    double s[OWN], A[OWN], B[OWN];   // A = alpha s^{m-1} (from m = 1), B = beta s^m
+    const double cq0 = cq[0];
+#pragma unroll
+    for (int k = 0; k < OWN; ++k) {
+        int gi, gj;
+        adj_own_at<W>(k, r0, c0, H, Wd, gi, gj);
+        s[k] = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
+        const long long o = (long long)gi * Wd + gj;
+        A[k] = alpha[o];
+        B[k] = beta[o];
+        if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = cq0 * B[k];   // R_0
+    }
+    const int i = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * kAdjRH;
+    const int gr = min(r0 + i, H - 1);
+    double so[kAdjRH], hm1[kAdjRH], h0[kAdjRH], h1[kAdjRH], h2[kAdjRH], gs[kAdjRH], gm[kAdjRH];
+#pragma unroll
+    for (int q = 0; q < kAdjRH; ++q) {
+        const int gc = min(c0 + j0 + q, Wd - 1);
+        const double sv = ((double)f[(long long)gr * ld + gc] - kTc) * (1.0 / kTh);
+        const double E = exp(-0.5 * mu * sv * sv);
+        so[q] = sv;
+        hm1[q] = 0.0;                                                     // H_{m-1}, H_m, H_{m+1}, H_{m+2}
+        h0[q] = E;
+        h1[q] = E * sv;
+        h2[q] = E * sv * sv;
+        gs[q] = gm[q] = 0.0;
+    }
+    __syncthreads();
+    const int P = N + 2;
+    for (int m = 0; m < P; ++m) {
+        adj_column_pass<W>(S, w);
+        __syncthreads();
+        if (m + 1 < P) {
+            const double cpm = cp[min(m, N)], cqm = m + 1 <= N ? cq[min(m + 1, N)] : 0.0;
+#pragma unroll
+            for (int k = 0; k < OWN; ++k) {
+                if (m >= 1) A[k] *= s[k];
+                B[k] *= s[k];
+                if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = fma(cpm, A[k], cqm * B[k]);   // R_{m+1}
+            }
+        }
+        double x[kAdjRH];
+        adj_row_pass<W>(S, w, x);
+        const double md = (double)m;
+#pragma unroll
+        for (int q = 0; q < kAdjRH; ++q) {
+            gs[q] = fma(x[q], fma(md, hm1[q], -mu * h1[q]), gs[q]);
+            gm[q] = fma(x[q], h2[q], gm[q]);
+            hm1[q] = h0[q];
+            h0[q] = h1[q];
+            h1[q] = h2[q];
+            h2[q] *= so[q];
+        }
+        __syncthreads();
+    }
+    const int r = r0 + i;
+    double local = 0.0;
+#pragma unroll
+    for (int q = 0; q < kAdjRH; ++q) {
+        const int c = c0 + j0 + q;
+        if (r < H && c < Wd) {
+            const long long o = (long long)r * Wd + c;
+            grad_f[(long long)r * ld + c] = (float)((gdir[o] + gs[q]) * (1.0 / kTh));
+            local += gmu[o] - 0.5 * gm[q];
+        }
+    }
+    double *red = S.pl;
+    red[threadIdx.x] = local;
+    __syncthreads();
+    for (int v = kAdjThreads / 2; v > 0; v >>= 1) {
+        if ((int)threadIdx.x < v) red[threadIdx.x] += red[threadIdx.x + v];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
 // dL/dsigma_r = (sum of the partials) (-2 mu / sigma_r); fixed summation order.
 __global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ partial, int n, double scale,
                                                      double *__restrict__ out) {
