@@ -270,7 +270,12 @@ def bench_differentiation(bf, steps, log):
     """Differentiation workload: batch 8 x 1 x 1024 x 1024 edge-rich images,
     sigma_s = 5, sigma_r = 30, N = 28, loss = mean((y - target)^2) with i.i.d.
     U[0,255] targets; one step = forward + backward through
-    GaussChebyshevBF (gradients with respect to f and sigma_r)."""
+    GaussChebyshevBF (gradients with respect to f and sigma_r), in its
+    default form at this radius: FP64 planes, the forward keeping six sums
+    per pixel (bf_gc_forward_saving), the backward from them
+    (bf_gc_backward_saving), one launch each for the batch. Also timed: the
+    FP32-stack forward (bf_gc_batched) with the recomputing backward
+    (bf_gc_backward per image)."""
     import numpy as np
     import torch
     from synth import diff_batch
@@ -279,10 +284,10 @@ def bench_differentiation(bf, steps, log):
     tgt = torch.tensor(tgts[:, None].astype(np.float32), device="cuda:0")
     sr = torch.tensor(30.0, dtype=torch.float64, device="cuda:0")
 
-    def step():
+    def step(stack=None):
         x = f.detach().requires_grad_(True)
         s_ = sr.detach().requires_grad_(True)
-        y = bf.gc_filter_autograd(x, s_, 5.0, 28)
+        y = bf.gc_filter_autograd(x, s_, 5.0, 28, stack_dtype=stack, sigma_r_host=30.0)
         loss = ((y - tgt) ** 2).mean()
         loss.backward()
         return x.grad, s_.grad
@@ -303,9 +308,20 @@ def bench_differentiation(bf, steps, log):
     ms = e0.elapsed_time(e1) / steps
     px = f.numel()
     log(f"bench: differentiation 8x1024^2 forward+backward {ms:.2f} ms")
+    step("f32")
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step("f32")
+    e1.record()
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1) / steps
+    log(f"bench: differentiation, FP32-stack forward + recomputing backward {ms32:.2f} ms")
     return {"ms_per_step": round(ms, 3), "mpx_s": round(px / 1e6 / (ms / 1e3), 1), "images": 8,
             "shape": "8x1x1024x1024", "sigma_s": 5.0, "sigma_r": 30.0, "degree": 28, "steps": steps,
-            "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()}}
+            "form": "f64 planes, saved sums (bf_gc_forward_saving + bf_gc_backward_saving)",
+            "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()},
+            "f32_forward_recompute_backward_ms": round(ms32, 3)}
 
 
 def bench_joint(bf, f, f64, sigma_s, sigma_r, N, steps, log):

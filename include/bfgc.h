@@ -260,7 +260,9 @@ bf_status bf_gc_joint_forward(const float *g, const float *f, float *out, int he
  * written, not accumulated). sigma_s and N are constants. The stack is
  * recomputed in FP64 (nothing is kept from the forward); the adjoint planes
  * R_m = dL/dHbar_m are filtered with the same Gaussian, which is its own
- * adjoint under the symmetric extension. Arguments as bf_gc_forward;
+ * adjoint under the symmetric extension (radius <= BF_ADJ_MAX_RADIUS: two
+ * fused FP64 tile kernels; larger radii: staged passes over two FP64 plane
+ * stacks in the workspace). Arguments as bf_gc_forward;
  * stack_dtype must be BF_STACK_F32, the forward's stack type the gradient is
  * taken for (BF_ERR_UNSUPPORTED otherwise); ws of at
  * least bf_gc_workspace_bytes(..., 1) bytes. grad_f must not overlap f or
@@ -269,6 +271,47 @@ bf_status bf_gc_joint_forward(const float *g, const float *f, float *out, int he
 bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, double *grad_sigma_r,
                          int height, int width, int ld, double sigma_s, double sigma_r, int N,
                          int stack_dtype, unsigned flags, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Training pair (not in the paper): a forward that keeps what the backward
+ * needs, and that backward. Radius W = ceil(3 sigma_s) <= BF_ADJ_MAX_RADIUS;
+ * larger radii are BF_ERR_UNSUPPORTED (bf_gc_forward / bf_gc_backward serve
+ * them). Both run on count images of one shape: image z starts image_stride
+ * floats after image z - 1 (f, out, grad_out, grad_f alike; image_stride >=
+ * (height - 1) ld + width when count > 1), count in [0, 65535].
+ *
+ * bf_gc_forward_saving: the filter of eqs. 7-10 (plain centring, coefficients
+ * as flags select, the conditioning check of the FP32 stack) with the planes
+ * H_n = e^{-mu s^2/2} s^n generated and filtered in FP64, tile by tile; y to
+ * out (FP32, as bf_gc_forward) and six sums per pixel to saved (device
+ * doubles, count x 6 x height x width, [count][6][height][width],
+ * caller-allocated): P' = sum b_n s^n Hbar_{n+1}, Q = sum b_n s^n Hbar_n,
+ * their derivatives in the explicit powers of s, and the same sums with
+ * db_n/dmu. Inputs outside [0, 255] set BF_DEVFLAG_RANGE in the workspace's
+ * flag word. out and saved must overlap neither f nor each other.
+ *
+ * bf_gc_backward_saving: for L = sum_z sum_i grad_out_{z,i} y_{z,i}, grad_f =
+ * dL/df (FP32, layout of f) and *grad_sigma_r = dL/dsigma_r summed over the
+ * count images (one device double; written, not accumulated; 0 for an empty
+ * batch), from f, grad_out and the saved sums of the forward with the same
+ * f, sigma_s, sigma_r, N and flags. The adjoint planes R_m are filtered in FP64
+ * tile by tile (as in bf_gc_backward). grad_f must not overlap f, grad_out
+ * or saved.
+ *
+ * ws (both): device, 256-byte aligned, at least
+ * bf_gc_saving_workspace_bytes(count, height, width, sigma_s, N) bytes (0 for
+ * invalid sizes); it holds the flag word, the parameters and one partial sum
+ * per 64 x 32 tile and image.
+ */
+#define BF_ADJ_MAX_RADIUS 16
+size_t bf_gc_saving_workspace_bytes(int count, int height, int width, double sigma_s, int N);
+bf_status bf_gc_forward_saving(const float *f, float *out, double *saved, int count, long long image_stride,
+                               int height, int width, int ld, double sigma_s, double sigma_r, int N,
+                               unsigned flags, void *ws, size_t ws_bytes, void *stream);
+bf_status bf_gc_backward_saving(const float *f, const float *grad_out, const double *saved, float *grad_f,
+                                double *grad_sigma_r, int count, long long image_stride, int height, int width,
+                                int ld, double sigma_s, double sigma_r, int N, unsigned flags, void *ws,
+                                size_t ws_bytes, void *stream);
 
 /*
  * Stages of the forward filter, for callers that want the stack itself. These

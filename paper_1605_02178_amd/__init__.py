@@ -26,6 +26,7 @@ __all__ = [
     "TILE_CONFIGS", "TILE_FUSED", "FUSED_MAX_RADIUS", "FUSED_F16_MAX_RADIUS", "flag_tile", "tile_configs_for", "COEFFS", "fit",
     "gc_joint_filter", "joint_workspace_bytes", "gc_filter_pivots", "pivot_count", "pivot_plan",
     "pivots_workspace_bytes", "batched_route", "gc_filter_noalloc", "NOALLOC_SCRATCH_BYTES",
+    "gc_forward_saving", "gc_backward_saving", "saving_workspace_bytes", "ADJ_MAX_RADIUS",
 ]
 
 STACK_DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
@@ -387,6 +388,90 @@ def gc_backward(f, grad_out, sigma_s: float, sigma_r: float, degree: int | None 
     return grad_f, grad_sr
 
 
+ADJ_MAX_RADIUS = 16   # BF_ADJ_MAX_RADIUS: largest radius of the saving forward / backward pair
+
+
+def saving_workspace_bytes(count, height, width, sigma_s, N) -> int:
+    return int(_lib.load().bf_gc_saving_workspace_bytes(int(count), int(height), int(width), float(sigma_s),
+                                                        int(N)))
+
+
+def _check_batch(x, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.float32 or x.dim() != 3 or not x.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous (count, H, W) float32 tensor")
+
+
+@_on_stream
+def gc_forward_saving(f, sigma_s: float, sigma_r: float, degree: int | None = None, allow_ill_conditioned=False,
+                      coeffs=None, out=None, saved=None, workspace=None, stream=None):
+    """bf_gc_forward_saving on a contiguous (count, H, W) float32 batch: the
+    filter with FP64 planes (radius <= ADJ_MAX_RADIUS). Returns (y, saved):
+    y like f, saved the (count, 6, H, W) float64 sums that gc_backward_saving
+    takes."""
+    import torch
+    _check_batch(f, "f")
+    B, H, Wd = f.shape
+    N = degree_rule(sigma_r) if degree is None else int(degree)
+    if out is None:
+        out = torch.empty_like(f)
+    else:
+        _check_batch(out, "out")
+    if saved is None:
+        saved = torch.empty((B, 6, H, Wd), dtype=torch.float64, device=f.device)
+    elif saved.dtype != torch.float64 or tuple(saved.shape) != (B, 6, H, Wd) or not saved.is_contiguous():
+        raise ValueError("saved must be a contiguous (count, 6, H, W) float64 tensor")
+    need = saving_workspace_bytes(B, H, Wd, sigma_s, N)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    flags = (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0) | _coeff_flags(coeffs)
+    st = _lib.load().bf_gc_forward_saving(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(saved.data_ptr()), B, H * Wd, H, Wd, Wd, float(sigma_s),
+                                          float(sigma_r), N, flags, ctypes.c_void_p(workspace.data_ptr()),
+                                          workspace.numel(), _stream_ptr(stream))
+    _lib.check(st, "bf_gc_forward_saving")
+    return out, saved
+
+
+@_on_stream
+def gc_backward_saving(f, grad_out, saved, sigma_s: float, sigma_r: float, degree: int | None = None,
+                       allow_ill_conditioned=False, coeffs=None, grad_f=None, grad_sigma_r=None, workspace=None,
+                       stream=None):
+    """bf_gc_backward_saving: (dL/df, dL/dsigma_r summed over the batch) for
+    L = sum(grad_out * y), y = gc_forward_saving(f, ...), from its saved sums."""
+    import torch
+    _check_batch(f, "f")
+    _check_batch(grad_out, "grad_out")
+    B, H, Wd = f.shape
+    N = degree_rule(sigma_r) if degree is None else int(degree)
+    if tuple(grad_out.shape) != (B, H, Wd):
+        raise ValueError("grad_out must be shaped like f")
+    if saved.dtype != torch.float64 or tuple(saved.shape) != (B, 6, H, Wd) or not saved.is_contiguous():
+        raise ValueError("saved must be the contiguous (count, 6, H, W) float64 sums of gc_forward_saving")
+    if grad_f is None:
+        grad_f = torch.empty_like(f)
+    else:
+        _check_batch(grad_f, "grad_f")
+    if grad_sigma_r is None:
+        grad_sigma_r = torch.empty((), dtype=torch.float64, device=f.device)
+    elif grad_sigma_r.numel() != 1 or grad_sigma_r.dtype != torch.float64 or not grad_sigma_r.is_cuda:
+        raise ValueError("grad_sigma_r must be one float64 device element")
+    need = saving_workspace_bytes(B, H, Wd, sigma_s, N)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
+    flags = (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0) | _coeff_flags(coeffs)
+    st = _lib.load().bf_gc_backward_saving(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(grad_out.data_ptr()),
+                                           ctypes.c_void_p(saved.data_ptr()), ctypes.c_void_p(grad_f.data_ptr()),
+                                           ctypes.c_void_p(grad_sigma_r.data_ptr()), B, H * Wd, H, Wd, Wd,
+                                           float(sigma_s), float(sigma_r), N, flags,
+                                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                           _stream_ptr(stream))
+    _lib.check(st, "bf_gc_backward_saving")
+    return grad_f, grad_sigma_r
+
+
 def _autograd_class():
     import torch
 
@@ -397,45 +482,66 @@ def _autograd_class():
         (differentiable); sigma_s, degree: constants; sigma_r_host: the value
         of sigma_r as a Python float, if the caller has it (else it is read
         from the tensor, a device sync when sigma_r lives on the GPU; a CPU
-        tensor is read without one). The forward filters the whole batch in
-        one bf_gc_batched launch. Saves only f and sigma_r; the backward
-        recomputes the filter in FP64 per image (bf_gc_backward), so the
-        gradient is that of the Gauss-Chebyshev filter itself, whatever stack
-        type the forward used: for an FP16/BF16 forward it is the gradient of
-        the function the 16-bit stack approximates."""
+        tensor is read without one).
+
+        stack_dtype "f64" (the default up to radius ADJ_MAX_RADIUS): the whole
+        batch in one bf_gc_forward_saving launch, FP64 planes, the six sums
+        per pixel kept for the backward, which is one bf_gc_backward_saving
+        launch. "f32", "f16", "bf16" (the default above that radius): the
+        batch in one bf_gc_batched launch with that stack, only f and sigma_r
+        kept; the backward recomputes the filter in FP64 per image
+        (bf_gc_backward), so the gradient is that of the Gauss-Chebyshev
+        filter itself, whatever stack type the forward used: for an FP16/BF16
+        forward it is the gradient of the function the 16-bit stack
+        approximates."""
 
         @staticmethod
-        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None, sigma_r_host=None):
+        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype=None, coeffs=None, sigma_r_host=None):
             sr = float(sigma_r_host) if sigma_r_host is not None else float(sigma_r)
             N = degree_rule(sr) if degree is None else int(degree)
+            if stack_dtype is None:
+                stack_dtype = "f64" if radius(sigma_s) <= ADJ_MAX_RADIUS else "f32"
             shape = f.shape
             x = f.reshape(-1, shape[-2], shape[-1])
             if not x.is_contiguous():
                 x = x.contiguous()
-            y = torch.empty_like(x)
-            B = x.shape[0]
-            # the single-image forward's conditioning check (the batch would
-            # route such an image to the pivoted form, whose gradient the
-            # backward does not compute)
+            ctx.sigma_s, ctx.sigma_r, ctx.N, ctx.coeffs = float(sigma_s), sr, N, coeffs
+            ctx.saving = stack_dtype == "f64"
+            # the conditioning check of the single-image forward (the FP32 stack's
+            # for the f64 form, as its C call; the batch would route such an
+            # image to the pivoted form, whose gradient the backward does not
+            # compute)
             kappa = fit(sr, N, coeffs)["kappa"]
-            if not kappa * _UNIT_ROUNDOFF[_dtype_code(stack_dtype)] <= 1e-2:
+            if not kappa * _UNIT_ROUNDOFF[_dtype_code("f32" if ctx.saving else stack_dtype)] <= 1e-2:
                 raise ValueError(f"GaussChebyshevBF: ill-conditioned at sigma_r={sr}, N={N} for the "
                                  f"{stack_dtype} stack (kappa={kappa:.3g})")
+            if ctx.saving:
+                if radius(sigma_s) > ADJ_MAX_RADIUS:
+                    raise ValueError(f"GaussChebyshevBF: the f64 form takes radius <= {ADJ_MAX_RADIUS}")
+                y, saved = gc_forward_saving(x, sigma_s, sr, N, coeffs=coeffs)
+                ctx.save_for_backward(f, sigma_r, saved)
+                return y.reshape(shape)
+            y = torch.empty_like(x)
+            B = x.shape[0]
             _, status = gc_filter_batched([x[b] for b in range(B)], [sigma_s] * B, [sr] * B, [N] * B,
                                           stack_dtype=stack_dtype, graph=False, outs=[y[b] for b in range(B)],
                                           coeffs=coeffs, allow_ill_conditioned=True)
             if any(status):
                 raise BFError(next(v for v in status if v), "GaussChebyshevBF forward")
             ctx.save_for_backward(f, sigma_r)
-            ctx.sigma_s, ctx.sigma_r, ctx.N, ctx.coeffs = float(sigma_s), sr, N, coeffs
             return y.reshape(shape)
 
         @staticmethod
         def backward(ctx, grad_y):
-            f, sigma_r = ctx.saved_tensors
+            f, sigma_r = ctx.saved_tensors[:2]
             shape = f.shape
             x = f.reshape(-1, shape[-2], shape[-1])
             g = grad_y.reshape(-1, shape[-2], shape[-1]).contiguous()
+            if ctx.saving:
+                gf, gs = gc_backward_saving(x.contiguous(), g, ctx.saved_tensors[2], ctx.sigma_s, ctx.sigma_r, ctx.N,
+                                            coeffs=ctx.coeffs)
+                gs = gs.to(device=sigma_r.device, dtype=sigma_r.dtype).reshape(sigma_r.shape)
+                return gf.reshape(shape), gs, None, None, None, None, None
             B = x.shape[0]
             gf = torch.empty_like(x)
             gsr = torch.empty(B, dtype=torch.float64, device=f.device)
@@ -460,9 +566,10 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype="f32", coeffs=None, sigma_r_host=None):
+def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype=None, coeffs=None, sigma_r_host=None):
     """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor
-    (sigma_r_host: its value as a float, which spares a device sync)."""
+    (sigma_r_host: its value as a float, which spares a device sync);
+    stack_dtype None = "f64" up to radius ADJ_MAX_RADIUS, else "f32"."""
     return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs, sigma_r_host)
 
 

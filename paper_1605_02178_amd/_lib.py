@@ -28,6 +28,11 @@ SIGNATURES = {
                                 _c_int, _c_uint, _vp, _c_size_t, _vp]),
     "bf_gc_forward_noalloc": (_c_int, [_vp, _vp, _c_int, _c_int, _c_int, _c_double, _c_double, _c_int, _c_int,
                                        _c_uint, _vp, _vp]),
+    "bf_gc_saving_workspace_bytes": (_c_size_t, [_c_int, _c_int, _c_int, _c_double, _c_int]),
+    "bf_gc_forward_saving": (_c_int, [_vp, _vp, _vp, _c_int, _c_ll, _c_int, _c_int, _c_int, _c_double,
+                                      _c_double, _c_int, _c_uint, _vp, _c_size_t, _vp]),
+    "bf_gc_backward_saving": (_c_int, [_vp, _vp, _vp, _vp, _vp, _c_int, _c_ll, _c_int, _c_int, _c_int,
+                                       _c_double, _c_double, _c_int, _c_uint, _vp, _c_size_t, _vp]),
     "bf_gc_pivot_count": (_c_int, [_c_double, _c_int]),
     "bf_gc_batched_route": (_c_int, [_c_double, _c_int, _c_int, _c_uint]),
     "bf_gc_pivot_plan": (_c_int, [_c_double, _c_int, _c_int, _ip, _dp, _dp]),

@@ -796,6 +796,8 @@ static long long bwd_tiles(int H, int Wd) {
     return (long long)((Wd + kAdjCols - 1) / kAdjCols) * ((H + kAdjRows - 1) / kAdjRows);
 }
 
+// Fused form: the six saved sums per pixel (k_adj_forward_tile) take the
+// place of the four per-pixel arrays.
 static BwdLayout bwd_layout(int H, int Wd, double sigma_s, int N) {
     BwdLayout B;
     const size_t P = (size_t)N + 2;
@@ -805,8 +807,60 @@ static BwdLayout bwd_layout(int H, int Wd, double sigma_s, int N) {
     B.stackB = fused ? 0 : align256(P * Wd * ldt_of(H) * sizeof(double));
     B.perpx = align256((size_t)H * Wd * sizeof(double));
     B.partial = align256((size_t)(fused ? bwd_tiles(H, Wd) : kNeighborBlocks) * sizeof(double));
-    B.total = kFlagBytes + B.params + B.stackA + B.stackB + 4 * B.perpx + B.partial;
+    B.total = kFlagBytes + B.params + B.stackA + B.stackB + (fused ? 6 : 4) * B.perpx + B.partial;
     return B;
+}
+
+// The fused FP64 tile kernels over `count` images of one shape (image z at
+// image_stride floats from image z - 1; saved sums 6 H Wd doubles apart).
+static bf_status launch_adj_forward(const float *f, float *out, double *saved, int count, long long stride, int H,
+                                    int Wd, int ld, int N, double mu, const double *prm, const ParamLayout &L,
+                                    unsigned *flag, hipStream_t stream) {
+    const dim3 g((Wd + kAdjCols - 1) / kAdjCols, (H + kAdjRows - 1) / kAdjRows, count);
+    const double *taps = prm + L.off_taps + (kTapPad - 1);
+    ProfScope prof_("k_adj_forward_tile", stream);
+#define BF_ADJ_F(WW)                                                                                              \
+    case WW:                                                                                                      \
+        hipLaunchKernelGGL(k_adj_forward_tile<WW>, g, dim3(kAdjThreads), 0, stream, f, out, saved, H, Wd, ld,      \
+                           stride, N, mu, taps, prm + L.off_cq, prm + L.off_cp, prm + L.off_bd, flag);              \
+        break;
+    switch (L.W) {
+        BF_ADJ_F(1) BF_ADJ_F(2) BF_ADJ_F(3) BF_ADJ_F(4) BF_ADJ_F(5) BF_ADJ_F(6) BF_ADJ_F(7) BF_ADJ_F(8)
+        BF_ADJ_F(9) BF_ADJ_F(10) BF_ADJ_F(11) BF_ADJ_F(12) BF_ADJ_F(13) BF_ADJ_F(14) BF_ADJ_F(15) BF_ADJ_F(16)
+        default: return fail(BF_ERR_UNSUPPORTED, "fused FP64 tiles: radius above BF_ADJ_MAX_RADIUS");
+    }
+#undef BF_ADJ_F
+    return check_launch("k_adj_forward_tile");
+}
+
+// The adjoint tiles and the fixed-order sum of their partials:
+// grad_sr = sum over the count images of dL/dsigma_r.
+static bf_status launch_adj_backward(const float *f, const float *ybar, const double *saved, float *grad_f,
+                                     double *grad_sr, double *partial, int count, long long stride, int H, int Wd,
+                                     int ld, int N, double mu, double sigma_r, const double *prm,
+                                     const ParamLayout &L, hipStream_t stream) {
+    const dim3 g((Wd + kAdjCols - 1) / kAdjCols, (H + kAdjRows - 1) / kAdjRows, count);
+    const double *taps = prm + L.off_taps + (kTapPad - 1);
+    {
+        ProfScope prof_("k_adj_backward_tile", stream);
+#define BF_ADJ_B(WW)                                                                                              \
+    case WW:                                                                                                      \
+        hipLaunchKernelGGL(k_adj_backward_tile<WW>, g, dim3(kAdjThreads), 0, stream, f, ybar, saved, grad_f,       \
+                           partial, H, Wd, ld, stride, N, mu, taps, prm + L.off_cq, prm + L.off_cp);                \
+        break;
+        switch (L.W) {
+            BF_ADJ_B(1) BF_ADJ_B(2) BF_ADJ_B(3) BF_ADJ_B(4) BF_ADJ_B(5) BF_ADJ_B(6) BF_ADJ_B(7) BF_ADJ_B(8)
+            BF_ADJ_B(9) BF_ADJ_B(10) BF_ADJ_B(11) BF_ADJ_B(12) BF_ADJ_B(13) BF_ADJ_B(14) BF_ADJ_B(15) BF_ADJ_B(16)
+            default: return fail(BF_ERR_UNSUPPORTED, "fused FP64 tiles: radius above BF_ADJ_MAX_RADIUS");
+        }
+#undef BF_ADJ_B
+        bf_status st = check_launch("k_adj_backward_tile");
+        if (st != BF_OK) return st;
+    }
+    ProfScope prof_("k_reduce_f64", stream);
+    hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, stream, (const double *)partial,
+                       (long long)count * bwd_tiles(H, Wd), -2.0 * mu / sigma_r, grad_sr);
+    return check_launch("k_reduce_f64");
 }
 
 static bf_status run_backward(const float *f, const float *ybar, float *grad_f, double *grad_sr, int H, int Wd,
@@ -831,46 +885,14 @@ static bf_status run_backward(const float *f, const float *ybar, float *grad_f, 
     const double mu = fit(sigma_r, N).mu;
     if (bwd_fused(sigma_s)) {
         // The forward recomputed in FP64 (the derivative sums cancel strongly;
-        // FP32 planes cost them three to four digits), fused with the
-        // adjoint's first step, then the adjoint planes, both per tile.
-        const long long tiles = bwd_tiles(H, Wd);
-        const dim3 g((Wd + kAdjCols - 1) / kAdjCols, (H + kAdjRows - 1) / kAdjRows);
-        const double *taps = prm + L.off_taps + (kTapPad - 1);
-        {
-            ProfScope prof_("k_adj_forward_tile", stream);
-#define BF_ADJ_F(WW)                                                                                               \
-    case WW:                                                                                                       \
-        hipLaunchKernelGGL(k_adj_forward_tile<WW>, g, dim3(kAdjThreads), 0, stream, f, ybar, H, Wd, ld, N, mu, taps, \
-                           prm + L.off_cq, prm + L.off_cp, prm + L.off_bd, alpha, beta, gdir, gmu);                 \
-        break;
-            switch (L.W) {
-                BF_ADJ_F(1) BF_ADJ_F(2) BF_ADJ_F(3) BF_ADJ_F(4) BF_ADJ_F(5) BF_ADJ_F(6) BF_ADJ_F(7) BF_ADJ_F(8)
-                BF_ADJ_F(9) BF_ADJ_F(10) BF_ADJ_F(11) BF_ADJ_F(12) BF_ADJ_F(13) BF_ADJ_F(14) BF_ADJ_F(15) BF_ADJ_F(16)
-                default: return fail(BF_ERR_UNSUPPORTED, "fused backward: radius out of range");
-            }
-#undef BF_ADJ_F
-            if ((st = check_launch("k_adj_forward_tile")) != BF_OK) return st;
-        }
-        {
-            ProfScope prof_("k_adj_backward_tile", stream);
-#define BF_ADJ_B(WW)                                                                                                 \
-    case WW:                                                                                                         \
-        hipLaunchKernelGGL(k_adj_backward_tile<WW>, g, dim3(kAdjThreads), 0, stream, f, H, Wd, ld, N, mu, taps,      \
-                           prm + L.off_cq, prm + L.off_cp, (const double *)alpha, (const double *)beta,              \
-                           (const double *)gdir, (const double *)gmu, grad_f, partial);                              \
-        break;
-            switch (L.W) {
-                BF_ADJ_B(1) BF_ADJ_B(2) BF_ADJ_B(3) BF_ADJ_B(4) BF_ADJ_B(5) BF_ADJ_B(6) BF_ADJ_B(7) BF_ADJ_B(8)
-                BF_ADJ_B(9) BF_ADJ_B(10) BF_ADJ_B(11) BF_ADJ_B(12) BF_ADJ_B(13) BF_ADJ_B(14) BF_ADJ_B(15) BF_ADJ_B(16)
-                default: return fail(BF_ERR_UNSUPPORTED, "fused backward: radius out of range");
-            }
-#undef BF_ADJ_B
-            if ((st = check_launch("k_adj_backward_tile")) != BF_OK) return st;
-        }
-        ProfScope prof_("k_reduce_f64", stream);
-        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, stream, (const double *)partial, (int)tiles,
-                           -2.0 * mu / sigma_r, grad_sr);
-        return check_launch("k_reduce_f64");
+        // FP32 planes cost them three to four digits) into the six saved sums,
+        // then the adjoint planes, both per tile.
+        double *saved = alpha;
+        double *psum = (double *)((char *)saved + 6 * B.perpx);
+        if ((st = launch_adj_forward(f, nullptr, saved, 1, 0, H, Wd, ld, N, mu, prm, L, nullptr, stream)) != BF_OK)
+            return st;
+        return launch_adj_backward(f, ybar, saved, grad_f, grad_sr, psum, 1, 0, H, Wd, ld, N, mu, sigma_r, prm, L,
+                                   stream);
     }
     // Recompute the forward stack and its column pass in FP64: the derivative
     // sums below cancel strongly, and FP32 planes cost them three to four
@@ -904,7 +926,7 @@ static bf_status run_backward(const float *f, const float *ybar, float *grad_f, 
     }
     {
         ProfScope prof_("k_reduce_f64", stream);
-        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, stream, (const double *)partial, nb,
+        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, stream, (const double *)partial, (long long)nb,
                            -2.0 * mu / sigma_r, grad_sr);
         return check_launch("k_reduce_f64");
     }
@@ -1723,8 +1745,8 @@ bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, d
     if (stack_dtype != BF_STACK_F32) return fail(BF_ERR_UNSUPPORTED, "the backward runs with an FP32 stack only");
     if (!grad_sigma_r) return fail(BF_ERR_INVALID_ARG, "grad_sigma_r must be non-null");
     if (height == 0 || width == 0) {   // empty image: dL/dsigma_r = 0 (a kernel, so the call can be graph-captured)
-        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, (hipStream_t)stream, (const double *)nullptr, 0, 0.0,
-                           grad_sigma_r);
+        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, (hipStream_t)stream, (const double *)nullptr, 0LL,
+                           0.0, grad_sigma_r);
         return check_launch("k_reduce_f64");
     }
     if (!f || !grad_out || !grad_f) return fail(BF_ERR_INVALID_ARG, "f, grad_out and grad_f must be non-null");
@@ -1737,6 +1759,88 @@ bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, d
     if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
     return run_backward(f, grad_out, grad_f, grad_sigma_r, height, width, ld, sigma_s, sigma_r, N, flags,
                         (char *)ws, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Forward with saved sums + backward from them (the fused FP64 tiles)
+// ---------------------------------------------------------------------------
+
+static size_t saving_partial_bytes(int count, int height, int width) {
+    return align256((size_t)count * bwd_tiles(height, width) * sizeof(double));
+}
+
+size_t bf_gc_saving_workspace_bytes(int count, int height, int width, double sigma_s, int N) {
+    if (count < 0 || check_common(height, width, sigma_s, 30.0, N, BF_STACK_F32) != BF_OK) return 0;
+    const size_t params = align256(sizeof(double) * (size_t)param_layout(radius_of(sigma_s), N).total);
+    return kFlagBytes + params + saving_partial_bytes(count, height, width);
+}
+
+// Shared argument checks of the two calls; *empty when there is nothing to do.
+static bf_status check_saving(const float *f, const void *out, const void *saved, int count, long long stride,
+                              int height, int width, int ld, double sigma_s, double sigma_r, int N, unsigned flags,
+                              void *ws, size_t ws_bytes, bool *empty) {
+    bf_status st = check_common(height, width, sigma_s, sigma_r, N, BF_STACK_F32);
+    if (st != BF_OK) return st;
+    if (count < 0 || count > 65535) return fail(BF_ERR_INVALID_ARG, "count out of [0, 65535]");
+    if (radius_of(sigma_s) > kAdjMaxRadius) return fail(BF_ERR_UNSUPPORTED, "radius W above BF_ADJ_MAX_RADIUS");
+    *empty = count == 0 || height == 0 || width == 0;
+    if (*empty) return BF_OK;
+    if (!f || !out || !saved) return fail(BF_ERR_INVALID_ARG, "image, output and saved pointers must be non-null");
+    if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
+    const long long img = (long long)(height - 1) * ld + width;
+    if (count > 1 && stride < img) return fail(BF_ERR_INVALID_ARG, "image_stride smaller than one image");
+    if ((st = check_conditioning(sigma_r, N, BF_STACK_F32, flags)) != BF_OK) return st;
+    const size_t need = bf_gc_saving_workspace_bytes(count, height, width, sigma_s, N);
+    if (!ws || ws_bytes < need || ((uintptr_t)ws & 255)) return fail(BF_ERR_WORKSPACE, "workspace null, misaligned or too small");
+    return BF_OK;
+}
+
+bf_status bf_gc_forward_saving(const float *f, float *out, double *saved, int count, long long image_stride,
+                               int height, int width, int ld, double sigma_s, double sigma_r, int N, unsigned flags,
+                               void *ws, size_t ws_bytes, void *stream) {
+    bool empty = false;
+    bf_status st = check_saving(f, out, saved, count, image_stride, height, width, ld, sigma_s, sigma_r, N, flags,
+                                ws, ws_bytes, &empty);
+    if (st != BF_OK || empty) return st;
+    const size_t span = ((size_t)(count - 1) * image_stride + (size_t)(height - 1) * ld + width) * sizeof(float);
+    const size_t sbytes = (size_t)count * 6 * height * width * sizeof(double);
+    if (overlaps(f, span, out, span) || overlaps(saved, sbytes, f, span) || overlaps(saved, sbytes, out, span))
+        return fail(BF_ERR_INVALID_ARG, "out, saved and f overlap");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)((char *)ws + kFlagBytes);
+    ParamLayout L;
+    if ((st = upload_params(prm, flag, sigma_s, sigma_r, N, BF_STACK_F32, s, &L, kind_of(flags))) != BF_OK) return st;
+    return launch_adj_forward(f, out, saved, count, image_stride, height, width, ld, N, fit(sigma_r, N).mu, prm, L,
+                              flag, s);
+}
+
+bf_status bf_gc_backward_saving(const float *f, const float *grad_out, const double *saved, float *grad_f,
+                                double *grad_sigma_r, int count, long long image_stride, int height, int width,
+                                int ld, double sigma_s, double sigma_r, int N, unsigned flags, void *ws,
+                                size_t ws_bytes, void *stream) {
+    if (!grad_sigma_r) return fail(BF_ERR_INVALID_ARG, "grad_sigma_r must be non-null");
+    bool empty = false;
+    bf_status st = check_saving(f, grad_f, saved, count, image_stride, height, width, ld, sigma_s, sigma_r, N, flags,
+                                ws, ws_bytes, &empty);
+    if (st != BF_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (empty) {   // dL/dsigma_r = 0 (a kernel, so the call can be graph-captured)
+        hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(256), 0, s, (const double *)nullptr, 0LL, 0.0, grad_sigma_r);
+        return check_launch("k_reduce_f64");
+    }
+    if (!grad_out) return fail(BF_ERR_INVALID_ARG, "grad_out must be non-null");
+    const size_t span = ((size_t)(count - 1) * image_stride + (size_t)(height - 1) * ld + width) * sizeof(float);
+    if (overlaps(f, span, grad_f, span) || overlaps(grad_out, span, grad_f, span) ||
+        overlaps(saved, (size_t)count * 6 * height * width * sizeof(double), grad_f, span))
+        return fail(BF_ERR_INVALID_ARG, "grad_f overlaps f, grad_out or saved");
+    unsigned *flag = (unsigned *)ws;
+    double *prm = (double *)((char *)ws + kFlagBytes);
+    ParamLayout L;
+    if ((st = upload_params(prm, flag, sigma_s, sigma_r, N, BF_STACK_F32, s, &L, kind_of(flags))) != BF_OK) return st;
+    double *partial = (double *)((char *)prm + align256(sizeof(double) * (size_t)L.total));
+    return launch_adj_backward(f, grad_out, saved, grad_f, grad_sigma_r, partial, count, image_stride, height, width,
+                               ld, N, fit(sigma_r, N).mu, sigma_r, prm, L, s);
 }
 
 bf_status bf_gc_plane_scales(double sigma_r, int N, int stack_dtype, int *k_out) {

@@ -820,7 +820,7 @@ __global__ __launch_bounds__(256) void k_adj_neighbor(const float *__restrict__ 
 // ---------------------------------------------------------------------------
 constexpr int kAdjRows = 64;
 constexpr int kAdjCols = 32;
-constexpr int kAdjMaxRadius = 16;
+constexpr int kAdjMaxRadius = BF_ADJ_MAX_RADIUS;
 constexpr int kAdjPitch = kAdjCols + 2 * kAdjMaxRadius + 1;   // 65: odd in doubles, so lanes on consecutive rows start in distinct banks
 constexpr int kAdjThreads = 1024;
 constexpr int kAdjWaves = kAdjThreads / 64;
@@ -929,19 +929,26 @@ __device__ __forceinline__ void adj_row_pass(const AdjLds &S, const AdjTaps<W> &
     adj_conv<W, kAdjRH, 4>([&](int t) { return src[t]; }, w, x);
 }
 
-// Recomputed forward, fused: the filtered planes Hbar_n at each output pixel,
-// folded in ascending n into the six sums of k_hpass_adj (with explicit
-// powers s^n, s^{n-1}, s^{n-2} of the output pixel); writes alpha, beta, the
-// direct term of dL/ds and the coefficient term of dL/dmu (FP64, pitch Wd).
+// Forward in FP64, fused: the filtered planes Hbar_n at each output pixel,
+// folded in ascending n into six sums (with explicit powers s^n, s^{n-1},
+// s^{n-2} of the output pixel):
+//   P' = sum cp_{n-1} s^{n-1} Hbar_n,  Q = sum cq_n s^n Hbar_n,
+//   dP'/ds, dQ/ds (the explicit powers only),
+//   Pm = sum bd_{n-1} s^{n-1} Hbar_n,  Qm = sum bd_n s^n Hbar_n,
+// written to saved ([6][H][Wd] per image, FP64), and y = t_c + t_h P'/Q to
+// out when out is non-null. Image z = blockIdx.z of a strided batch.
 template <int W>
 __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_forward_tile(
-    const float *__restrict__ f, const float *__restrict__ ybar, int H, int Wd, int ld, int N, double mu,
-    const double *__restrict__ taps, const double *__restrict__ cq, const double *__restrict__ cp,
-    const double *__restrict__ bd, double *__restrict__ alpha, double *__restrict__ beta, double *__restrict__ gdir,
-    double *__restrict__ gmu) {
+    const float *__restrict__ f, float *__restrict__ out, double *__restrict__ saved, int H, int Wd, int ld,
+    long long image_stride, int N, double mu, const double *__restrict__ taps, const double *__restrict__ cq,
+    const double *__restrict__ cp, const double *__restrict__ bd, unsigned *__restrict__ flag) {
     constexpr int OWN = adj_own_count<W>();
     __shared__ AdjLds S;
     const int r0 = blockIdx.y * kAdjRows, c0 = blockIdx.x * kAdjCols;
+    const long long npx = (long long)H * Wd;
+    f += blockIdx.z * image_stride;
+    if (out) out += blockIdx.z * image_stride;
+    saved += blockIdx.z * 6 * npx;
     const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
     double *own = S.pl + (threadIdx.x >> 6) * kAdjPitch + (threadIdx.x & 63);
     double s[OWN], h[OWN];
@@ -1007,35 +1014,51 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
         __syncthreads();
     }
     const int r = r0 + i;
+    bool bad = false;
 #pragma unroll
     for (int q = 0; q < kAdjRH; ++q) {
         const int c = c0 + j0 + q;
         if (r < H && c < Wd) {
-            const double yb = (double)ybar[(long long)r * ld + c];
-            const double a = yb * kTh / Qa[q];
-            const double b = -a * Pa[q] / Qa[q];
             const long long o = (long long)r * Wd + c;
-            alpha[o] = a;
-            beta[o] = b;
-            gdir[o] = a * dP[q] + b * dQ[q];
-            gmu[o] = a * Pm[q] + b * Qm[q];
+            saved[o] = Pa[q];
+            saved[npx + o] = Qa[q];
+            saved[2 * npx + o] = dP[q];
+            saved[3 * npx + o] = dQ[q];
+            saved[4 * npx + o] = Pm[q];
+            saved[5 * npx + o] = Qm[q];
+            if (out) out[(long long)r * ld + c] = (float)(kTc + kTh * (Pa[q] / Qa[q]));   // eq. 10
+            const float fv = f[(long long)r * ld + c];
+            bad |= !(fv >= 0.0f && fv <= 255.0f);
         }
     }
+    if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1)
+        atomicOr(flag, BF_DEVFLAG_RANGE);
 }
 
-// Adjoint, fused: the planes R_m (from alpha, beta of the halo pixels)
-// filtered by the same mirrored Gaussian, folded at each output pixel j with
-// H_m(j) recomputed in FP64 into dL/df_j; one partial sum of the dL/dmu terms
-// per tile (summed in a fixed order by k_reduce_f64).
+// alpha = dL/dP' = ybar t_h / Q and beta = dL/dQ = -alpha P'/Q of one pixel.
+__device__ __forceinline__ void adj_alpha_beta(double yb, double Pa, double Qa, double &a, double &b) {
+    a = yb * kTh / Qa;
+    b = -a * Pa / Qa;
+}
+
+// Adjoint, fused: the planes R_m (from alpha, beta of the halo pixels, formed
+// from the saved sums and ybar) filtered by the same mirrored Gaussian, folded
+// at each output pixel j with H_m(j) recomputed in FP64 into dL/df_j; one
+// partial sum of the dL/dmu terms per tile and image (summed in a fixed order
+// by k_reduce_f64). Image z = blockIdx.z of a strided batch.
 template <int W>
 __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_backward_tile(
-    const float *__restrict__ f, int H, int Wd, int ld, int N, double mu, const double *__restrict__ taps,
-    const double *__restrict__ cq, const double *__restrict__ cp, const double *__restrict__ alpha,
-    const double *__restrict__ beta, const double *__restrict__ gdir, const double *__restrict__ gmu,
-    float *__restrict__ grad_f, double *__restrict__ partial) {
+    const float *__restrict__ f, const float *__restrict__ ybar, const double *__restrict__ saved,
+    float *__restrict__ grad_f, double *__restrict__ partial, int H, int Wd, int ld, long long image_stride, int N,
+    double mu, const double *__restrict__ taps, const double *__restrict__ cq, const double *__restrict__ cp) {
     constexpr int OWN = adj_own_count<W>();
     __shared__ AdjLds S;
     const int r0 = blockIdx.y * kAdjRows, c0 = blockIdx.x * kAdjCols;
+    const long long npx = (long long)H * Wd;
+    f += blockIdx.z * image_stride;
+    ybar += blockIdx.z * image_stride;
+    grad_f += blockIdx.z * image_stride;
+    saved += blockIdx.z * 6 * npx;
     const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
     double *own = S.pl + (threadIdx.x >> 6) * kAdjPitch + (threadIdx.x & 63);
     double s[OWN], A[OWN], B[OWN];   // A = alpha s^{m-1} (from m = 1), B = beta s^m
@@ -1046,8 +1069,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
         adj_own_at<W>(k, r0, c0, H, Wd, gi, gj);
         s[k] = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
         const long long o = (long long)gi * Wd + gj;
-        A[k] = alpha[o];
-        B[k] = beta[o];
+        adj_alpha_beta((double)ybar[(long long)gi * ld + gj], saved[o], saved[npx + o], A[k], B[k]);
         if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = cq0 * B[k];   // R_0
     }
     const int i = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * kAdjRH;
@@ -1100,8 +1122,12 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
         const int c = c0 + j0 + q;
         if (r < H && c < Wd) {
             const long long o = (long long)r * Wd + c;
-            grad_f[(long long)r * ld + c] = (float)((gdir[o] + gs[q]) * (1.0 / kTh));
-            local += gmu[o] - 0.5 * gm[q];
+            double a, b;
+            adj_alpha_beta((double)ybar[(long long)r * ld + c], saved[o], saved[npx + o], a, b);
+            const double gdir = a * saved[2 * npx + o] + b * saved[3 * npx + o];   // alpha dP'/ds + beta dQ/ds
+            const double gmu = a * saved[4 * npx + o] + b * saved[5 * npx + o];    // coefficient term of dL/dmu
+            grad_f[(long long)r * ld + c] = (float)((gdir + gs[q]) * (1.0 / kTh));
+            local += gmu - 0.5 * gm[q];
         }
     }
     double *red = S.pl;
@@ -1111,15 +1137,16 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
         if ((int)threadIdx.x < v) red[threadIdx.x] += red[threadIdx.x + v];
         __syncthreads();
     }
-    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (threadIdx.x == 0)
+        partial[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
 }
 
 // dL/dsigma_r = (sum of the partials) (-2 mu / sigma_r); fixed summation order.
-__global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ partial, int n, double scale,
+__global__ __launch_bounds__(256) void k_reduce_f64(const double *__restrict__ partial, long long n, double scale,
                                                      double *__restrict__ out) {
     __shared__ double red[256];
     double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) v += partial[i];
     red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {

@@ -2,6 +2,9 @@
 oracle (torch autograd of the paper's algorithm) and against central finite
 differences of the FP64 C oracle.
 
+Also the saving forward and the backward from its sums (gc_forward_saving,
+gc_backward_saving), and that pair against the recomputing backward.
+
 Stated bounds (stack recomputed in FP64, FP64 adjoint planes, FP64 sums):
   dL/df       max |gpu - oracle| <= 1e-6 * max |oracle|
   dL/dsigma_r |gpu - oracle| <= 1e-6 * |oracle| + 1e-9 * sum |ybar|
@@ -182,3 +185,103 @@ def test_backward_argument_errors(torch_cuda):
     e = torch.empty((0, 5), device="cuda:0")
     gf, gs = bf.gc_backward(e, e.clone(), 2.0, 30.0, 28)
     assert gf.shape == (0, 5) and float(gs.item()) == 0.0
+
+
+# Forward with saved sums and the backward from them (count images in one
+# launch each). Shapes: several 64 x 32 tiles with ragged edges, one row, one
+# column band, radii 1..16 (sigma_s = 5.3: W = 16, the largest).
+SAVING_CASES = [
+    ((130, 70), 2.0, 30.0, 28),
+    ((65, 33), 5.0, 40.0, 16),
+    ((1, 40), 1.0, 30.0, 28),
+    ((7, 200), 5.3, 30.0, 28),
+    ((200, 9), 0.3, 25.0, 40),
+]
+
+
+def _batch(shape, count, seed):
+    from synth import edge_rich
+    return np.stack([edge_rich(*shape, seed=seed + b) for b in range(count)]).astype(np.float32)
+
+
+@pytest.mark.parametrize("shape,sigma_s,sigma_r,N", SAVING_CASES)
+def test_forward_saving_matches_oracle(torch_cuda, shape, sigma_s, sigma_r, N):
+    """y within 1e-5 of the FP64 oracle (the FP32 rounding of a value below
+    256 is at most 7.6e-6); the saved Q and t_h P' against the oracle's Q and
+    P (eqs. 8-9 in the paper's unscaled form: the scaled coefficients are
+    b_n = c_n (t_h / sigma_r)^{2n}, so these sums agree term by term; the
+    oracle's Gaussian of eq. 7 is not normalised, the library's taps sum to
+    1 along each axis, hence the factor (sum of the 1-D weights)^2) to 1e-11
+    of their largest magnitude."""
+    import paper_1605_02178_amd as bf
+    from oracle import filters as F
+    torch = torch_cuda
+    imgs = _batch(shape, 3, sum(shape) + 90)
+    y, saved = bf.gc_forward_saving(_gpu(torch, imgs), sigma_s, sigma_r, N)
+    y = y.cpu().double().numpy()
+    saved = saved.cpu().numpy()
+    norm = F.spatial_kernel_1d(sigma_s).sum() ** 2
+    for b in range(3):
+        ref, parts = F.gcf(imgs[b].astype(np.float64), sigma_s, sigma_r, N, return_parts=True)
+        ey = np.abs(y[b] - ref).max()
+        eq = np.abs(norm * saved[b, 1] - parts["Q"]).max() / np.abs(parts["Q"]).max()
+        ep = np.abs(norm * 127.5 * saved[b, 0] - parts["P"]).max() / np.abs(parts["P"]).max()
+        _log(f"saving {shape} ss={sigma_s} image {b}: y {ey:.3e}, Q rel {eq:.3e}, P rel {ep:.3e}")
+        assert ey <= 1e-5 and eq <= 1e-11 and ep <= 1e-11
+
+
+@pytest.mark.parametrize("shape,sigma_s,sigma_r,N", SAVING_CASES)
+def test_backward_saving_matches_fp64_oracle(torch_cuda, shape, sigma_s, sigma_r, N):
+    """Three images in one launch: dL/df per image against the FP64 autograd
+    oracle, dL/dsigma_r against the sum of the per-image oracle values."""
+    import paper_1605_02178_amd as bf
+    from oracle import adjoint as A
+    torch = torch_cuda
+    imgs = _batch(shape, 3, sum(shape) + 95)
+    ybar = np.random.default_rng(sum(shape) + 5).uniform(-1, 1, size=imgs.shape).astype(np.float32)
+    x = _gpu(torch, imgs)
+    _, saved = bf.gc_forward_saving(x, sigma_s, sigma_r, N)
+    gf, gs = bf.gc_backward_saving(x, _gpu(torch, ybar), saved, sigma_s, sigma_r, N)
+    gf = gf.cpu().double().numpy()
+    rsum = 0.0
+    for b in range(3):
+        rf, rs = A.gcf_grad(imgs[b].astype(np.float64), sigma_s, sigma_r, N, ybar[b].astype(np.float64))
+        ef = np.abs(gf[b] - rf).max()
+        assert ef <= REL * np.abs(rf).max(), (b, ef)
+        rsum += rs
+    _log(f"saving backward {shape} ss={sigma_s}: dL/dsr gpu {float(gs.item()):.6e} oracle {rsum:.6e}")
+    assert abs(float(gs.item()) - rsum) <= REL * abs(rsum) + 1e-9 * np.abs(ybar).sum()
+
+
+def test_saving_pair_equals_recompute_backward(torch_cuda):
+    """bf_gc_backward recomputes the same six sums with the same tile kernel,
+    so on one image the two backward forms agree bit for bit."""
+    import paper_1605_02178_amd as bf
+    torch = torch_cuda
+    imgs = _batch((150, 100), 1, 123)
+    ybar = np.random.default_rng(124).uniform(-1, 1, size=imgs.shape).astype(np.float32)
+    x, g = _gpu(torch, imgs), _gpu(torch, ybar)
+    _, saved = bf.gc_forward_saving(x, 4.0, 30.0, 28)
+    gf, gs = bf.gc_backward_saving(x, g, saved, 4.0, 30.0, 28)
+    rf, rs = bf.gc_backward(x[0], g[0], 4.0, 30.0, 28)
+    assert torch.equal(gf[0], rf) and torch.equal(gs.reshape(()), rs.reshape(()))
+
+
+def test_saving_errors_and_empty(torch_cuda):
+    import paper_1605_02178_amd as bf
+    torch = torch_cuda
+    x = _gpu(torch, _batch((40, 40), 2, 130))
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_forward_saving(x, 5.4, 30.0, 28)             # W = 17 > 16
+    assert e.value.status == 2
+    with pytest.raises(bf.BFError) as e:
+        bf.gc_forward_saving(x, 2.0, 12.0, 170)            # ill-conditioned
+    assert e.value.status == 3
+    empty = torch.empty((0, 40, 40), device="cuda:0")
+    y, saved = bf.gc_forward_saving(empty, 2.0, 30.0, 28)
+    assert y.shape == (0, 40, 40) and saved.shape == (0, 6, 40, 40)
+    gf, gs = bf.gc_backward_saving(empty, empty.clone(), saved, 2.0, 30.0, 28)
+    assert gf.shape == (0, 40, 40) and float(gs.item()) == 0.0
+    # the autograd function's f64 form refuses radii above 16, like the call
+    with pytest.raises(ValueError):
+        bf.gc_filter_autograd(x, torch.tensor(30.0, dtype=torch.float64), 5.4, 28, stack_dtype="f64")

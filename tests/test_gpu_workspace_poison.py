@@ -111,3 +111,20 @@ def test_backward(torch_cuda):
     ga, sa = bf.gc_backward(f, g, 3.0, 30.0, 28, workspace=ws_p)
     gb, sb = bf.gc_backward(f, g, 3.0, 30.0, 28, workspace=ws_z)
     assert torch.equal(ga, gb) and torch.equal(sa, sb)
+
+
+def test_saving_pair(torch_cuda):
+    """The saving forward and its backward (flag word, parameters, per-tile
+    partial sums in the workspace) on a 0xFF workspace and a zeroed one."""
+    import paper_1605_02178_amd as bf
+    torch = torch_cuda
+    x = torch.tensor(np.stack([_image((70, 90), 7 + b) for b in range(2)]), device="cuda:0")
+    g = torch.tensor(np.random.default_rng(7).uniform(-1, 1, (2, 70, 90)).astype(np.float32), device="cuda:0")
+    ws_p, ws_z = _two(torch, bf.saving_workspace_bytes(2, 70, 90, 3.0, 28))
+    ya, sva = bf.gc_forward_saving(x, 3.0, 30.0, 28, workspace=ws_p)
+    yb, svb = bf.gc_forward_saving(x, 3.0, 30.0, 28, workspace=ws_z)
+    assert torch.equal(ya, yb) and torch.equal(sva, svb)
+    assert bf.read_flags(ws_p) == 0
+    ga, sa = bf.gc_backward_saving(x, g, sva, 3.0, 30.0, 28, workspace=ws_p)
+    gb, sb = bf.gc_backward_saving(x, g, svb, 3.0, 30.0, 28, workspace=ws_z)
+    assert torch.equal(ga, gb) and torch.equal(sa, sb)
