@@ -231,13 +231,30 @@ static bf_status launch_build(const float *f, int H, int Wd, int ld, void *stack
 
 static int ldt_of(int height) { return (height + 63) & ~63; }
 
+// LDS bytes of a staged pass over 4R lines plus the 2W halo, 64 elements
+// each; 0 where the unstaged kernel runs instead (above the 64 KiB of
+// dynamic LDS a launch gets without an attribute: FP64 planes at large radii).
+template <class S>
+static size_t staged_lds_bytes(int R, int W) {
+    const size_t b = (size_t)(4 * R + 2 * W) * 64 * sizeof(typename S::T);
+    return b <= 65536 ? b : 0;
+}
+
+// The column pass: k_vpass_lds where its 64-element line segments stay inside
+// each row (lds a multiple of 64, as the library's own stacks), else k_vpass;
+// the two give identical outputs.
 template <class S, int RV = kVR>
 static bf_status launch_vpass(const void *stack, void *tmpT, int planes, int H, int Wd, long long ps, int lds,
                               long long pst, int ldt, const double *prm, const ParamLayout &L, hipStream_t stream) {
     dim3 gv((Wd + 63) / 64, (H + 4 * RV - 1) / (4 * RV), planes);
     ProfScope prof_("k_vpass", stream);
-    hipLaunchKernelGGL((k_vpass<S, RV>), gv, dim3(256), 0, stream, (const typename S::T *)stack,
-                       (typename S::T *)tmpT, H, Wd, ps, lds, pst, ldt, prm + L.off_taps, L.W);
+    const size_t sh = (lds & 63) == 0 ? staged_lds_bytes<S>(RV, L.W) : 0;
+    if (sh)
+        hipLaunchKernelGGL((k_vpass_lds<S, RV>), gv, dim3(256), sh, stream, (const typename S::T *)stack,
+                           (typename S::T *)tmpT, H, Wd, ps, lds, pst, ldt, prm + L.off_taps, L.W);
+    else
+        hipLaunchKernelGGL((k_vpass<S, RV>), gv, dim3(256), 0, stream, (const typename S::T *)stack,
+                           (typename S::T *)tmpT, H, Wd, ps, lds, pst, ldt, prm + L.off_taps, L.W);
     return check_launch("k_vpass");
 }
 
@@ -250,10 +267,17 @@ static bf_status launch_gauss(void *stack, void *tmpT, int planes, int H, int Wd
     if (st != BF_OK) return st;
     dim3 gh((H + 63) / 64, (Wd + 4 * kHR - 1) / (4 * kHR));
     ProfScope prof_("k_hpass", stream);
-    hipLaunchKernelGGL((k_hpass<S, kHR, false>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
-                       (typename S::T *)stack, (const float *)nullptr, (float *)nullptr, (float *)nullptr,
-                       (float *)nullptr, H, Wd, 0, ps, lds, pst, ldt, planes, 0, prm + L.off_taps,
-                       prm + L.off_cq, prm + L.off_cp, L.W, plain_centring());
+    const size_t sh = staged_lds_bytes<S>(kHR, L.W);
+    if (sh)
+        hipLaunchKernelGGL((k_hpass_lds<S, kHR, false>), gh, dim3(256), sh, stream, (const typename S::T *)tmpT,
+                           (typename S::T *)stack, (const float *)nullptr, (float *)nullptr, (float *)nullptr,
+                           (float *)nullptr, H, Wd, 0, ps, lds, pst, ldt, planes, 0, prm + L.off_taps,
+                           prm + L.off_cq, prm + L.off_cp, L.W, plain_centring());
+    else
+        hipLaunchKernelGGL((k_hpass<S, kHR, false>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
+                           (typename S::T *)stack, (const float *)nullptr, (float *)nullptr, (float *)nullptr,
+                           (float *)nullptr, H, Wd, 0, ps, lds, pst, ldt, planes, 0, prm + L.off_taps,
+                           prm + L.off_cq, prm + L.off_cp, L.W, plain_centring());
     return check_launch("k_hpass");
 }
 
@@ -264,9 +288,15 @@ static bf_status launch_hpass_combine(const void *tmpT, const float *f, float *o
                                       const Centring &C = plain_centring()) {
     dim3 gh((H + 63) / 64, (Wd + 4 * RH - 1) / (4 * RH));
     ProfScope prof_("k_hpass_combine", stream);
-    hipLaunchKernelGGL((k_hpass<S, RH, true>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
-                       (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, 0LL, 0, pst, ldt, L.N + 2, L.N,
-                       prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W, C);
+    const size_t sh = staged_lds_bytes<S>(RH, L.W);
+    if (sh)
+        hipLaunchKernelGGL((k_hpass_lds<S, RH, true>), gh, dim3(256), sh, stream, (const typename S::T *)tmpT,
+                           (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, 0LL, 0, pst, ldt, L.N + 2, L.N,
+                           prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W, C);
+    else
+        hipLaunchKernelGGL((k_hpass<S, RH, true>), gh, dim3(256), 0, stream, (const typename S::T *)tmpT,
+                           (typename S::T *)nullptr, f, out, Pout, Qout, H, Wd, ld, 0LL, 0, pst, ldt, L.N + 2, L.N,
+                           prm + L.off_taps, prm + L.off_cq, prm + L.off_cp, L.W, C);
     return check_launch("k_hpass(combine)");
 }
 

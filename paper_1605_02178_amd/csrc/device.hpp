@@ -144,19 +144,11 @@ __global__ __launch_bounds__(256) void k_stack_build(const float *__restrict__ f
 // time) and FMA'd in FP64 into every output it reaches; the head and tail of
 // the window touch only the outputs inside the band, so no zero tap is
 // multiplied. `w` points at tap t = 0 inside the zero-padded tap array.
-template <class S, int R, int U>
-__device__ __forceinline__ void conv_line(const typename S::T *__restrict__ plane, int laneoff, long long stride,
-                                          int o0, int len, int W, const double *__restrict__ w, double (&acc)[R]) {
-    // o0, len, W, stride and plane are wave-uniform: the line position p and
-    // the row pointer stay in scalar registers, each load is a uniform base
-    // plus the lane's own offset.
-    const int p0 = o0 - W;
-    const bool interior = p0 >= 0 && o0 + R + W <= len;
-    auto ld = [&](int i) -> double {
-        const int p = interior ? p0 + i : mirror(p0 + i, len);
-        const typename S::T *row = plane + (long long)p * stride;
-        return (double)S::dec(row[laneoff]);
-    };
+// The accumulation itself, with ld(i) giving input p0 + i (already through
+// the symmetric extension): conv_line reads the plane in global memory, the
+// LDS-staged passes read their tile, in the same FMA order.
+template <int R, int U, class LD>
+__device__ __forceinline__ void conv_core(LD ld, int W, const double *__restrict__ w, double (&acc)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
     const int T = 2 * W;
@@ -222,6 +214,22 @@ __device__ __forceinline__ void conv_line(const typename S::T *__restrict__ plan
             for (int r = 0; r < R; ++r) acc[r] = fma(w[i - r], x, acc[r]);
         }
     }
+}
+
+template <class S, int R, int U>
+__device__ __forceinline__ void conv_line(const typename S::T *__restrict__ plane, int laneoff, long long stride,
+                                          int o0, int len, int W, const double *__restrict__ w, double (&acc)[R]) {
+    // o0, len, W, stride and plane are wave-uniform: the line position p and
+    // the row pointer stay in scalar registers, each load is a uniform base
+    // plus the lane's own offset.
+    const int p0 = o0 - W;
+    const bool interior = p0 >= 0 && o0 + R + W <= len;
+    auto ld = [&](int i) -> double {
+        const int p = interior ? p0 + i : mirror(p0 + i, len);
+        const typename S::T *row = plane + (long long)p * stride;
+        return (double)S::dec(row[laneoff]);
+    };
+    conv_core<R, U>(ld, W, w, acc);
 }
 
 // Stores R consecutive elements (dst 16-byte aligned when full).
@@ -341,6 +349,136 @@ __global__ __launch_bounds__(256) void k_hpass(const typename S::T *__restrict__
                                                 int W, Centring C) {
     hpass_tile<S, R, COMBINE>(inT, out_stack, f, out, Pout, Qout, H, Wd, ld, ps, lds, pst, ldt, P, N, taps, cq, cp,
                               W, blockIdx.x, blockIdx.y, C);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-staged column and row passes (single image). A block first copies the
+// input lines it needs (its 64-element segment of each line, through the
+// symmetric extension) into LDS with 16-byte loads, all of them in flight at
+// once, then convolves from there with conv_core in the FMA order of
+// vpass_tile / hpass_tile: the outputs are bit-identical to those kernels
+// (which the batched phases use). Reading from LDS takes the global-load
+// latency off the FMA loop, the limit of the unstaged passes.
+// ---------------------------------------------------------------------------
+
+// Copies lines [0, nlines) of a 64-element-wide tile into LDS (line k from
+// rowp(k): 64 elements, 16-byte aligned, inside the allocation), UNROLL
+// 16-byte loads in flight per thread (256 threads).
+template <class T, int UNROLL, class ROWP>
+__device__ __forceinline__ void stage_lines(T *__restrict__ tile, int nlines, ROWP rowp) {
+    constexpr int EPL = 16 / (int)sizeof(T);   // elements per 16-byte load
+    constexpr int LPL = 64 / EPL;              // threads per line
+    constexpr int LPB = 256 / LPL;             // lines per block-wide load
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // stays in registers (a uint4 array did not)
+    const int lk = threadIdx.x / LPL, cc = (threadIdx.x % LPL) * EPL;
+    for (int k0 = 0; k0 < nlines; k0 += LPB * UNROLL) {
+        u32x4 v[UNROLL];
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int k = k0 + u * LPB + lk;
+            v[u] = k < nlines ? *reinterpret_cast<const u32x4 *>(rowp(k) + cc) : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u) {
+            const int k = k0 + u * LPB + lk;
+            if (k < nlines) *reinterpret_cast<u32x4 *>(tile + k * 64 + cc) = v[u];
+        }
+    }
+}
+
+// Column pass (as k_vpass): block = 64 columns x 4R rows of plane
+// blockIdx.z; LDS (4R + 2W) x 64 elements (dynamic).
+template <class S, int R>
+__global__ __launch_bounds__(256) void k_vpass_lds(const typename S::T *__restrict__ in,
+                                                    typename S::T *__restrict__ outT, int H, int Wd, long long ps,
+                                                    int lds, long long pst, int ldt,
+                                                    const double *__restrict__ taps, int W) {
+    typedef typename S::T T;
+    extern __shared__ __align__(16) unsigned char s_lds[];
+    T *tile = reinterpret_cast<T *>(s_lds);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 4 * R, n = blockIdx.z;
+    const T *plane = in + (long long)n * ps + c0;
+    stage_lines<T, 8>(tile, 4 * R + 2 * W,
+                      [&](int k) { return plane + (long long)mirror(r0 - W + k, H) * lds; });
+    __syncthreads();
+    const int rw = r0 + wave * R;
+    if (rw >= H) return;
+    const T *col = tile + wave * R * 64 + lane;
+    double acc[R];
+    conv_core<R, 8>([&](int i) { return (double)S::dec(col[i * 64]); }, W, taps + (kTapPad - 1), acc);
+    const int c = c0 + lane;
+    if (c < Wd) store_run<S, R>(outT + (long long)n * pst + (long long)c * ldt + rw, acc, H - rw);
+}
+
+// Row pass (as k_hpass): block = 64 rows x 4R columns, planes visited as in
+// hpass_tile, each staged as (4R + 2W) lines of 64 rows; LDS (4R + 2W) x 64
+// elements (dynamic).
+template <class S, int R, bool COMBINE>
+__global__ __launch_bounds__(256) void k_hpass_lds(const typename S::T *__restrict__ inT,
+                                                    typename S::T *__restrict__ out_stack,
+                                                    const float *__restrict__ f, float *__restrict__ out,
+                                                    float *__restrict__ Pout, float *__restrict__ Qout, int H,
+                                                    int Wd, int ld, long long ps, int lds, long long pst, int ldt,
+                                                    int P, int N, const double *__restrict__ taps,
+                                                    const double *__restrict__ cq, const double *__restrict__ cp,
+                                                    int W, Centring C) {
+    typedef typename S::T T;
+    extern __shared__ __align__(16) unsigned char s_lds[];
+    T *tile = reinterpret_cast<T *>(s_lds);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int r0 = blockIdx.x * 64, cb = blockIdx.y * 4 * R;
+    const int r = r0 + lane;
+    const int c0 = cb + wave * R;
+    const bool active = c0 < Wd;   // wave-uniform; inactive waves still stage and meet the barriers
+    const int rl = r < H ? r : H - 1;
+    double s[R], Pa[R], Qa[R];
+    if (COMBINE) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int cc = c0 + q < Wd ? c0 + q : Wd - 1;
+            s[q] = ((double)f[(long long)rl * ld + cc] - C.tc) * C.inv_c;
+            Pa[q] = 0.0;
+            Qa[q] = 0.0;
+        }
+    }
+    const T *line = tile + wave * R * 64 + lane;
+    for (int k = 0; k < P; ++k) {
+        const int n = COMBINE ? P - 1 - k : k;
+        const T *plane = inT + (long long)n * pst + r0;
+        if (k > 0) __syncthreads();   // every wave is done with the previous plane's tile
+        stage_lines<T, 8>(tile, 4 * R + 2 * W,
+                          [&](int j) { return plane + (long long)mirror(cb - W + j, Wd) * ldt; });
+        __syncthreads();
+        if (!active) continue;
+        double acc[R];
+        conv_core<R, 8>([&](int i) { return (double)S::dec(line[i * 64]); }, W, taps + (kTapPad - 1), acc);
+        if (COMBINE) {
+            const double cpn = n >= 1 ? cp[n - 1] : 0.0;
+            const double cqn = n <= N ? cq[n] : 0.0;
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                if (n >= 1) Pa[q] = fma(Pa[q], s[q], cpn * acc[q]);
+                if (n <= N) Qa[q] = fma(Qa[q], s[q], cqn * acc[q]);
+            }
+        } else if (r < H) {
+            store_run<S, R>(out_stack + (long long)n * ps + (long long)r * lds + c0, acc, Wd - c0);
+        }
+    }
+    if (COMBINE && active && r < H) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            if (c0 + q < Wd) {
+                const long long o = (long long)r * ld + c0 + q;
+                if (C.mask != 0 && !centring_keeps(C, f[o])) continue;
+                out[o] = (float)(C.tc + C.out_scale * (Pa[q] / Qa[q]));
+                if (Pout) Pout[o] = (float)Pa[q];
+                if (Qout) Qout[o] = (float)Qa[q];
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
