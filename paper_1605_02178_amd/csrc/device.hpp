@@ -948,50 +948,30 @@ __global__ __launch_bounds__(256) void k_adj_neighbor(const float *__restrict__ 
 
 // ---------------------------------------------------------------------------
 // Fused FP64 adjoint tiles (radius W <= 16). One 1024-thread block per 64 x 32
-// output tile (rows x columns). The planes (H_n in the first kernel, R_m in the second) are
-// generated one at a time over the tile and its W-halo, filtered in LDS
-// (column pass, then row pass) and folded into per-pixel sums, so no plane
-// stack goes through HBM. Each thread holds the generator state of up to
-// six halo pixels in registers (halo row 16k + wave, halo column lane) and
-// writes the next plane between the column and the row pass. The tap
-// loops are unrolled for the compile-time radius.
+// output tile (rows x columns). The planes (H_n in k_adj_forward_tile, R_m in
+// k_adj_backward_tile) are generated one at a time over the tile and its
+// W-halo, filtered in LDS (column pass, then row pass) and folded into
+// per-pixel sums, so no plane stack goes through HBM. The tap loops are
+// unrolled for the compile-time radius.
+//
+// The 16 waves take two roles. Waves 0-7 keep the generator state of the halo
+// pixels in registers (halo row 8k + wave, halo column lane) and run the
+// column pass with 8 rows per lane; waves 8-15 run the row pass with 4
+// columns per lane and keep the output sums, one plane behind, reading the
+// other of two column-pass buffers. Each role has its own loop (the role is
+// wave-uniform, so each wave branches as a whole) with the same barriers:
+//   step t:  generators: column pass of plane t (pl -> vt[t & 1])
+//            row waves:  row pass + fold of plane t - 1 (vt[(t - 1) & 1])
+//            barrier
+//            generators: plane t + 1 into pl
+//            barrier
+// for t = 0..P, so every wave meets 1 + 2(P + 1) barriers.
 // ---------------------------------------------------------------------------
 constexpr int kAdjRows = 64;
 constexpr int kAdjCols = 32;
 constexpr int kAdjMaxRadius = BF_ADJ_MAX_RADIUS;
 constexpr int kAdjPitch = kAdjCols + 2 * kAdjMaxRadius + 1;   // 65: odd in doubles, so lanes on consecutive rows start in distinct banks
 constexpr int kAdjThreads = 1024;
-constexpr int kAdjWaves = kAdjThreads / 64;
-constexpr int kAdjRV = kAdjRows / kAdjWaves;                   // rows per lane in the column pass: 4
-constexpr int kAdjRH = kAdjRows * kAdjCols / kAdjThreads;      // columns per thread in the row pass: 2
-
-struct AdjLds {
-    double pl[(kAdjRows + 2 * kAdjMaxRadius) * kAdjPitch];   // the current plane over the halo
-    double vt[kAdjRows * kAdjPitch];                         // its column pass: 64 rows x (32 + 2W) columns
-};
-
-template <int W>
-constexpr int adj_own_count() {
-    return (kAdjRows + 2 * W + kAdjWaves - 1) / kAdjWaves;
-}
-
-// Halo pixel k of this thread: halo row 16k + wave, halo column lane, at
-// pl[(16k + wave) * kAdjPitch + lane]. adj_own_in: whether it lies in the
-// halo; adj_own_at: its mirrored image coordinates ((0, 0) if it does not).
-template <int W>
-__device__ __forceinline__ bool adj_own_in(int k) {
-    return kAdjWaves * k + (int)(threadIdx.x >> 6) < kAdjRows + 2 * W && (int)(threadIdx.x & 63) < kAdjCols + 2 * W;
-}
-template <int W>
-__device__ __forceinline__ void adj_own_at(int k, int r0, int c0, int H, int Wd, int &gi, int &gj) {
-    const int row = kAdjWaves * k + (int)(threadIdx.x >> 6);
-    if (!adj_own_in<W>(k)) {
-        gi = gj = 0;
-        return;
-    }
-    gi = mirror(r0 - W + row, H);
-    gj = mirror(c0 - W + (int)(threadIdx.x & 63), Wd);
-}
 
 // The W + 1 distinct taps (offsets -W..0; the Gaussian is symmetric), loaded
 // once per block into (scalar) registers; tap t (offset t - W) of 2W + 1.
@@ -1042,29 +1022,50 @@ __device__ __forceinline__ void adj_conv(LD ld, const AdjTaps<W> &w, double (&ac
     }
 }
 
-// Column pass of the plane in pl (eq. 7 along columns): wave v gives tile rows
-// [4v, 4v + 4), lane = halo column; w points at the tap of offset -W.
+// alpha = dL/dP' = ybar t_h / Q and beta = dL/dQ = -alpha P'/Q of one pixel.
+__device__ __forceinline__ void adj_alpha_beta(double yb, double Pa, double Qa, double &a, double &b) {
+    a = yb * kTh / Qa;
+    b = -a * Pa / Qa;
+}
+
+constexpr int kSplitWaves = 8;                                // waves per role
+constexpr int kSplitRV = kAdjRows / kSplitWaves;              // 8 rows per lane, column pass
+constexpr int kSplitRH = kAdjCols / kSplitWaves;              // 4 columns per lane, row pass
+
+struct AdjLds {
+    double pl[(kAdjRows + 2 * kAdjMaxRadius) * kAdjPitch];   // the current plane over the halo
+    double vt[2][kAdjRows * kAdjPitch];                      // two column-pass results
+};
+
 template <int W>
-__device__ __forceinline__ void adj_column_pass(AdjLds &S, const AdjTaps<W> &w) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+constexpr int adj_own() {
+    return (kAdjRows + 2 * W + kSplitWaves - 1) / kSplitWaves;
+}
+
+// Generator wave g, lane: its halo pixels k (halo row 8k + g, column lane).
+template <int W>
+__device__ __forceinline__ bool adj_split_in(int k, int g, int lane) {
+    return kSplitWaves * k + g < kAdjRows + 2 * W && lane < kAdjCols + 2 * W;
+}
+
+// Column pass of the generator wave g: tile rows [8g, 8g + 8), lane = halo column.
+template <int W>
+__device__ __forceinline__ void adj_split_column(AdjLds &S, const AdjTaps<W> &w, int g, int lane, int b) {
     if (lane < kAdjCols + 2 * W) {
-        double acc[kAdjRV];
-        const double *src = S.pl + wave * kAdjRV * kAdjPitch + lane;
-        adj_conv<W, kAdjRV, 4>([&](int t) { return src[t * kAdjPitch]; }, w, acc);
+        double acc[kSplitRV];
+        const double *src = S.pl + g * kSplitRV * kAdjPitch + lane;
+        adj_conv<W, kSplitRV, 4>([&](int t) { return src[t * kAdjPitch]; }, w, acc);
 #pragma unroll
-        for (int r = 0; r < kAdjRV; ++r) S.vt[(wave * kAdjRV + r) * kAdjPitch + lane] = acc[r];
+        for (int r = 0; r < kSplitRV; ++r) S.vt[b][(g * kSplitRV + r) * kAdjPitch + lane] = acc[r];
     }
 }
 
-// Row pass of the column-filtered plane: thread -> tile row lane, columns
-// 2 wave and the next.
+// Row pass of the row wave v: tile row lane, columns [4v, 4v + 4).
 template <int W>
-__device__ __forceinline__ void adj_row_pass(const AdjLds &S, const AdjTaps<W> &w, double (&x)[kAdjRH]) {
-    const int i = threadIdx.x & 63;
-    const int j0 = (threadIdx.x >> 6) * kAdjRH;
-    const double *src = S.vt + i * kAdjPitch + j0;
-    adj_conv<W, kAdjRH, 4>([&](int t) { return src[t]; }, w, x);
+__device__ __forceinline__ void adj_split_row(const AdjLds &S, const AdjTaps<W> &w, int v, int lane, int b,
+                                              double (&x)[kSplitRH]) {
+    const double *src = S.vt[b] + lane * kAdjPitch + v * kSplitRH;
+    adj_conv<W, kSplitRH, 4>([&](int t) { return src[t]; }, w, x);
 }
 
 // Forward in FP64, fused: the filtered planes Hbar_n at each output pixel,
@@ -1080,7 +1081,6 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
     const float *__restrict__ f, float *__restrict__ out, double *__restrict__ saved, int H, int Wd, int ld,
     long long image_stride, int N, double mu, const double *__restrict__ taps, const double *__restrict__ cq,
     const double *__restrict__ cp, const double *__restrict__ bd, unsigned *__restrict__ flag) {
-    constexpr int OWN = adj_own_count<W>();
     __shared__ AdjLds S;
     const int r0 = blockIdx.y * kAdjRows, c0 = blockIdx.x * kAdjCols;
     const long long npx = (long long)H * Wd;
@@ -1088,95 +1088,101 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
     if (out) out += blockIdx.z * image_stride;
     saved += blockIdx.z * 6 * npx;
     const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
-    double *own = S.pl + (threadIdx.x >> 6) * kAdjPitch + (threadIdx.x & 63);
-    double s[OWN], h[OWN];
-#pragma unroll
-    for (int k = 0; k < OWN; ++k) {
-        int gi, gj;
-        adj_own_at<W>(k, r0, c0, H, Wd, gi, gj);
-        const double sv = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
-        s[k] = sv;
-        h[k] = exp(-0.5 * mu * sv * sv);                                 // H_0
-        if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = h[k];
-    }
-    const int i = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * kAdjRH;
-    const int gr = min(r0 + i, H - 1);
-    double so[kAdjRH], p2[kAdjRH];   // s and s^{max(n-2,0)} of the output pixel
-    double Pa[kAdjRH], Qa[kAdjRH], dP[kAdjRH], dQ[kAdjRH], Pm[kAdjRH], Qm[kAdjRH];
-#pragma unroll
-    for (int q = 0; q < kAdjRH; ++q) {
-        const int gc = min(c0 + j0 + q, Wd - 1);
-        so[q] = ((double)f[(long long)gr * ld + gc] - kTc) * (1.0 / kTh);
-        p2[q] = 1.0;
-        Pa[q] = Qa[q] = dP[q] = dQ[q] = Pm[q] = Qm[q] = 0.0;
-    }
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = N + 2;
-    for (int n = 0; n < P; ++n) {
-        // this plane's coefficients, loaded unconditionally (clamped index) so
-        // that no branch separates the row pass from the fold
-        const double cqn = n <= N ? cq[min(n, N)] : 0.0, bqn = n <= N ? bd[min(n, N)] : 0.0;
-        const double cpn = n >= 1 ? cp[max(n - 1, 0)] : 0.0, bpn = n >= 1 ? bd[max(n - 1, 0)] : 0.0;
-        adj_column_pass<W>(S, w);
-        __syncthreads();
-        // the column pass is done with plane n: the next one is written now
-        // (before the row pass, which then sits in one basic block with the
-        // fold below and keeps its load/FMA interleave)
-        if (n + 1 < P) {
+    if (wave < kSplitWaves) {
+        constexpr int OWN = adj_own<W>();
+        const int g = wave;
+        double *own = S.pl + g * kAdjPitch + lane;
+        double s[OWN], h[OWN];
 #pragma unroll
-            for (int k = 0; k < OWN; ++k) {
-                h[k] *= s[k];                                             // H_{n+1} = H_n s
-                if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = h[k];
+        for (int k = 0; k < OWN; ++k) {
+            const bool in = adj_split_in<W>(k, g, lane);
+            const int gi = in ? mirror(r0 - W + kSplitWaves * k + g, H) : 0;
+            const int gj = in ? mirror(c0 - W + lane, Wd) : 0;
+            const double sv = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
+            s[k] = sv;
+            h[k] = exp(-0.5 * mu * sv * sv);                                 // H_0
+            if (in) own[k * kSplitWaves * kAdjPitch] = h[k];
+        }
+        __syncthreads();
+        for (int t = 0; t <= P; ++t) {
+            if (t < P) adj_split_column<W>(S, w, g, lane, t & 1);
+            __syncthreads();
+            if (t + 1 < P) {
+#pragma unroll
+                for (int k = 0; k < OWN; ++k) {
+                    h[k] *= s[k];                                             // H_{t+1} = H_t s
+                    if (adj_split_in<W>(k, g, lane)) own[k * kSplitWaves * kAdjPitch] = h[k];
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        const int v = wave - kSplitWaves;
+        const int i = lane, j0 = v * kSplitRH;
+        const int gr = min(r0 + i, H - 1);
+        double so[kSplitRH], p2[kSplitRH];   // s and s^{max(n-2,0)} of the output pixel
+        double Pa[kSplitRH], Qa[kSplitRH], dP[kSplitRH], dQ[kSplitRH], Pm[kSplitRH], Qm[kSplitRH];
+#pragma unroll
+        for (int q = 0; q < kSplitRH; ++q) {
+            const int gc = min(c0 + j0 + q, Wd - 1);
+            so[q] = ((double)f[(long long)gr * ld + gc] - kTc) * (1.0 / kTh);
+            p2[q] = 1.0;
+            Pa[q] = Qa[q] = dP[q] = dQ[q] = Pm[q] = Qm[q] = 0.0;
+        }
+        __syncthreads();
+        for (int t = 0; t <= P; ++t) {
+            if (t >= 1) {
+                const int n = t - 1;
+                const double cqn = n <= N ? cq[min(n, N)] : 0.0, bqn = n <= N ? bd[min(n, N)] : 0.0;
+                const double cpn = n >= 1 ? cp[max(n - 1, 0)] : 0.0, bpn = n >= 1 ? bd[max(n - 1, 0)] : 0.0;
+                double x[kSplitRH];
+                adj_split_row<W>(S, w, v, lane, n & 1, x);
+                const double ncq = (double)n * cqn, ncp = (double)(n - 1) * cpn;
+#pragma unroll
+                for (int q = 0; q < kSplitRH; ++q) {
+                    // v0 = s^n x, v1 = s^{n-1} x, v2 = s^{n-2} x (p2 = s^{max(n-2,0)}).
+                    // Below n = 2 a missing (negative) power is replaced by the next
+                    // one: only zero coefficients meet it (cpn and ncq at n = 0, ncp
+                    // at n <= 1). The selects are on n, uniform: no branches.
+                    const double v2 = p2[q] * x[q];
+                    const double v1 = n >= 2 ? so[q] * v2 : v2;
+                    const double v0 = n >= 1 ? so[q] * v1 : v1;
+                    if (n >= 2) p2[q] *= so[q];
+                    Qa[q] = fma(cqn, v0, Qa[q]);
+                    Qm[q] = fma(bqn, v0, Qm[q]);
+                    dQ[q] = fma(ncq, v1, dQ[q]);
+                    Pa[q] = fma(cpn, v1, Pa[q]);
+                    Pm[q] = fma(bpn, v1, Pm[q]);
+                    dP[q] = fma(ncp, v2, dP[q]);
+                }
+            }
+            __syncthreads();
+            __syncthreads();
+        }
+        const int r = r0 + i;
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < kSplitRH; ++q) {
+            const int c = c0 + j0 + q;
+            if (r < H && c < Wd) {
+                const long long o = (long long)r * Wd + c;
+                saved[o] = Pa[q];
+                saved[npx + o] = Qa[q];
+                saved[2 * npx + o] = dP[q];
+                saved[3 * npx + o] = dQ[q];
+                saved[4 * npx + o] = Pm[q];
+                saved[5 * npx + o] = Qm[q];
+                if (out) out[(long long)r * ld + c] = (float)(kTc + kTh * (Pa[q] / Qa[q]));   // eq. 10
+                const float fv = f[(long long)r * ld + c];
+                bad |= !(fv >= 0.0f && fv <= 255.0f);
             }
         }
-        double x[kAdjRH];
-        adj_row_pass<W>(S, w, x);
-        const double ncq = (double)n * cqn, ncp = (double)(n - 1) * cpn;
-#pragma unroll
-        for (int q = 0; q < kAdjRH; ++q) {
-            // v0 = s^n x, v1 = s^{n-1} x, v2 = s^{n-2} x (p2 = s^{max(n-2,0)}).
-            // Below n = 2 a missing (negative) power is replaced by the next
-            // one: only zero coefficients meet it (cpn and ncq at n = 0, ncp
-            // at n <= 1). The selects are on n, uniform: no branches.
-            const double v2 = p2[q] * x[q];
-            const double v1 = n >= 2 ? so[q] * v2 : v2;
-            const double v0 = n >= 1 ? so[q] * v1 : v1;
-            if (n >= 2) p2[q] *= so[q];
-            Qa[q] = fma(cqn, v0, Qa[q]);
-            Qm[q] = fma(bqn, v0, Qm[q]);
-            dQ[q] = fma(ncq, v1, dQ[q]);
-            Pa[q] = fma(cpn, v1, Pa[q]);
-            Pm[q] = fma(bpn, v1, Pm[q]);
-            dP[q] = fma(ncp, v2, dP[q]);
-        }
-        __syncthreads();
+        if (flag && __any(bad) && lane == __ffsll((unsigned long long)__ballot(bad)) - 1)
+            atomicOr(flag, BF_DEVFLAG_RANGE);
     }
-    const int r = r0 + i;
-    bool bad = false;
-#pragma unroll
-    for (int q = 0; q < kAdjRH; ++q) {
-        const int c = c0 + j0 + q;
-        if (r < H && c < Wd) {
-            const long long o = (long long)r * Wd + c;
-            saved[o] = Pa[q];
-            saved[npx + o] = Qa[q];
-            saved[2 * npx + o] = dP[q];
-            saved[3 * npx + o] = dQ[q];
-            saved[4 * npx + o] = Pm[q];
-            saved[5 * npx + o] = Qm[q];
-            if (out) out[(long long)r * ld + c] = (float)(kTc + kTh * (Pa[q] / Qa[q]));   // eq. 10
-            const float fv = f[(long long)r * ld + c];
-            bad |= !(fv >= 0.0f && fv <= 255.0f);
-        }
-    }
-    if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1)
-        atomicOr(flag, BF_DEVFLAG_RANGE);
-}
-
-// alpha = dL/dP' = ybar t_h / Q and beta = dL/dQ = -alpha P'/Q of one pixel.
-__device__ __forceinline__ void adj_alpha_beta(double yb, double Pa, double Qa, double &a, double &b) {
-    a = yb * kTh / Qa;
-    b = -a * Pa / Qa;
 }
 
 // Adjoint, fused: the planes R_m (from alpha, beta of the halo pixels, formed
@@ -1189,7 +1195,6 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
     const float *__restrict__ f, const float *__restrict__ ybar, const double *__restrict__ saved,
     float *__restrict__ grad_f, double *__restrict__ partial, int H, int Wd, int ld, long long image_stride, int N,
     double mu, const double *__restrict__ taps, const double *__restrict__ cq, const double *__restrict__ cp) {
-    constexpr int OWN = adj_own_count<W>();
     __shared__ AdjLds S;
     const int r0 = blockIdx.y * kAdjRows, c0 = blockIdx.x * kAdjCols;
     const long long npx = (long long)H * Wd;
@@ -1198,76 +1203,95 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
     grad_f += blockIdx.z * image_stride;
     saved += blockIdx.z * 6 * npx;
     const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
-    double *own = S.pl + (threadIdx.x >> 6) * kAdjPitch + (threadIdx.x & 63);
-    double s[OWN], A[OWN], B[OWN];   // A = alpha s^{m-1} (from m = 1), B = beta s^m
-    const double cq0 = cq[0];
-#pragma unroll
-    for (int k = 0; k < OWN; ++k) {
-        int gi, gj;
-        adj_own_at<W>(k, r0, c0, H, Wd, gi, gj);
-        s[k] = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
-        const long long o = (long long)gi * Wd + gj;
-        adj_alpha_beta((double)ybar[(long long)gi * ld + gj], saved[o], saved[npx + o], A[k], B[k]);
-        if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = cq0 * B[k];   // R_0
-    }
-    const int i = threadIdx.x & 63, j0 = (threadIdx.x >> 6) * kAdjRH;
-    const int gr = min(r0 + i, H - 1);
-    double so[kAdjRH], hm1[kAdjRH], h0[kAdjRH], h1[kAdjRH], h2[kAdjRH], gs[kAdjRH], gm[kAdjRH];
-#pragma unroll
-    for (int q = 0; q < kAdjRH; ++q) {
-        const int gc = min(c0 + j0 + q, Wd - 1);
-        const double sv = ((double)f[(long long)gr * ld + gc] - kTc) * (1.0 / kTh);
-        const double E = exp(-0.5 * mu * sv * sv);
-        so[q] = sv;
-        hm1[q] = 0.0;                                                     // H_{m-1}, H_m, H_{m+1}, H_{m+2}
-        h0[q] = E;
-        h1[q] = E * sv;
-        h2[q] = E * sv * sv;
-        gs[q] = gm[q] = 0.0;
-    }
-    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = N + 2;
-    for (int m = 0; m < P; ++m) {
-        adj_column_pass<W>(S, w);
-        __syncthreads();
-        if (m + 1 < P) {
-            const double cpm = cp[min(m, N)], cqm = m + 1 <= N ? cq[min(m + 1, N)] : 0.0;
+    double local = 0.0;
+    if (wave < kSplitWaves) {
+        constexpr int OWN = adj_own<W>();
+        const int g = wave;
+        double *own = S.pl + g * kAdjPitch + lane;
+        double s[OWN], A[OWN], B[OWN];   // A = alpha s^{m-1} (from m = 1), B = beta s^m
+        const double cq0 = cq[0];
 #pragma unroll
-            for (int k = 0; k < OWN; ++k) {
-                if (m >= 1) A[k] *= s[k];
-                B[k] *= s[k];
-                if (adj_own_in<W>(k)) own[k * kAdjWaves * kAdjPitch] = fma(cpm, A[k], cqm * B[k]);   // R_{m+1}
+        for (int k = 0; k < OWN; ++k) {
+            const bool in = adj_split_in<W>(k, g, lane);
+            const int gi = in ? mirror(r0 - W + kSplitWaves * k + g, H) : 0;
+            const int gj = in ? mirror(c0 - W + lane, Wd) : 0;
+            s[k] = ((double)f[(long long)gi * ld + gj] - kTc) * (1.0 / kTh);
+            const long long o = (long long)gi * Wd + gj;
+            adj_alpha_beta((double)ybar[(long long)gi * ld + gj], saved[o], saved[npx + o], A[k], B[k]);
+            if (in) own[k * kSplitWaves * kAdjPitch] = cq0 * B[k];          // R_0
+        }
+        __syncthreads();
+        for (int t = 0; t <= P; ++t) {
+            if (t < P) adj_split_column<W>(S, w, g, lane, t & 1);
+            __syncthreads();
+            if (t + 1 < P) {
+                const double cpm = cp[min(t, N)], cqm = t + 1 <= N ? cq[min(t + 1, N)] : 0.0;
+#pragma unroll
+                for (int k = 0; k < OWN; ++k) {
+                    if (t >= 1) A[k] *= s[k];
+                    B[k] *= s[k];
+                    if (adj_split_in<W>(k, g, lane))
+                        own[k * kSplitWaves * kAdjPitch] = fma(cpm, A[k], cqm * B[k]);   // R_{t+1}
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        const int v = wave - kSplitWaves;
+        const int i = lane, j0 = v * kSplitRH;
+        const int gr = min(r0 + i, H - 1);
+        double so[kSplitRH], hm1[kSplitRH], h0[kSplitRH], h1[kSplitRH], h2[kSplitRH], gs[kSplitRH], gm[kSplitRH];
+#pragma unroll
+        for (int q = 0; q < kSplitRH; ++q) {
+            const int gc = min(c0 + j0 + q, Wd - 1);
+            const double sv = ((double)f[(long long)gr * ld + gc] - kTc) * (1.0 / kTh);
+            const double E = exp(-0.5 * mu * sv * sv);
+            so[q] = sv;
+            hm1[q] = 0.0;                                                     // H_{m-1}, H_m, H_{m+1}, H_{m+2}
+            h0[q] = E;
+            h1[q] = E * sv;
+            h2[q] = E * sv * sv;
+            gs[q] = gm[q] = 0.0;
+        }
+        __syncthreads();
+        for (int t = 0; t <= P; ++t) {
+            if (t >= 1) {
+                const int m = t - 1;
+                double x[kSplitRH];
+                adj_split_row<W>(S, w, v, lane, m & 1, x);
+                const double md = (double)m;
+#pragma unroll
+                for (int q = 0; q < kSplitRH; ++q) {
+                    gs[q] = fma(x[q], fma(md, hm1[q], -mu * h1[q]), gs[q]);
+                    gm[q] = fma(x[q], h2[q], gm[q]);
+                    hm1[q] = h0[q];
+                    h0[q] = h1[q];
+                    h1[q] = h2[q];
+                    h2[q] *= so[q];
+                }
+            }
+            __syncthreads();
+            __syncthreads();
+        }
+        const int r = r0 + i;
+#pragma unroll
+        for (int q = 0; q < kSplitRH; ++q) {
+            const int c = c0 + j0 + q;
+            if (r < H && c < Wd) {
+                const long long o = (long long)r * Wd + c;
+                double a, b;
+                adj_alpha_beta((double)ybar[(long long)r * ld + c], saved[o], saved[npx + o], a, b);
+                const double gdir = a * saved[2 * npx + o] + b * saved[3 * npx + o];   // alpha dP'/ds + beta dQ/ds
+                const double gmu = a * saved[4 * npx + o] + b * saved[5 * npx + o];    // coefficient term of dL/dmu
+                grad_f[(long long)r * ld + c] = (float)((gdir + gs[q]) * (1.0 / kTh));
+                local += gmu - 0.5 * gm[q];
             }
         }
-        double x[kAdjRH];
-        adj_row_pass<W>(S, w, x);
-        const double md = (double)m;
-#pragma unroll
-        for (int q = 0; q < kAdjRH; ++q) {
-            gs[q] = fma(x[q], fma(md, hm1[q], -mu * h1[q]), gs[q]);
-            gm[q] = fma(x[q], h2[q], gm[q]);
-            hm1[q] = h0[q];
-            h0[q] = h1[q];
-            h1[q] = h2[q];
-            h2[q] *= so[q];
-        }
-        __syncthreads();
     }
-    const int r = r0 + i;
-    double local = 0.0;
-#pragma unroll
-    for (int q = 0; q < kAdjRH; ++q) {
-        const int c = c0 + j0 + q;
-        if (r < H && c < Wd) {
-            const long long o = (long long)r * Wd + c;
-            double a, b;
-            adj_alpha_beta((double)ybar[(long long)r * ld + c], saved[o], saved[npx + o], a, b);
-            const double gdir = a * saved[2 * npx + o] + b * saved[3 * npx + o];   // alpha dP'/ds + beta dQ/ds
-            const double gmu = a * saved[4 * npx + o] + b * saved[5 * npx + o];    // coefficient term of dL/dmu
-            grad_f[(long long)r * ld + c] = (float)((gdir + gs[q]) * (1.0 / kTh));
-            local += gmu - 0.5 * gm[q];
-        }
-    }
+    // every wave has met the loop's last barrier: the LDS is free
     double *red = S.pl;
     red[threadIdx.x] = local;
     __syncthreads();
