@@ -386,50 +386,51 @@ __device__ __forceinline__ void stage_lines(T *__restrict__ tile, int nlines, RO
     }
 }
 
-// Column pass (as k_vpass): block = 64 columns x 4R rows of plane
-// blockIdx.z; LDS (4R + 2W) x 64 elements (dynamic).
+// Column pass (as vpass_tile) through the block's LDS tile: 64 columns
+// [64 bx, 64 bx + 64) x 4R rows [4R by, 4R by + 4R) of plane n; the tile holds
+// (4R + 2W) x 64 elements. Every thread meets the one barrier.
 template <class S, int R>
-__global__ __launch_bounds__(256) void k_vpass_lds(const typename S::T *__restrict__ in,
-                                                    typename S::T *__restrict__ outT, int H, int Wd, long long ps,
-                                                    int lds, long long pst, int ldt,
-                                                    const double *__restrict__ taps, int W) {
+__device__ __forceinline__ void vpass_tile_lds(typename S::T *__restrict__ tile,
+                                               const typename S::T *__restrict__ in,
+                                               typename S::T *__restrict__ outT, int H, int Wd, long long ps,
+                                               int lds, long long pst, int ldt, const double *__restrict__ taps,
+                                               int W, int bx, int by, int n) {
     typedef typename S::T T;
-    extern __shared__ __align__(16) unsigned char s_lds[];
-    T *tile = reinterpret_cast<T *>(s_lds);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 4 * R, n = blockIdx.z;
+    const int c0 = bx * 64, r0 = by * 4 * R;
     const T *plane = in + (long long)n * ps + c0;
     stage_lines<T, 8>(tile, 4 * R + 2 * W,
                       [&](int k) { return plane + (long long)mirror(r0 - W + k, H) * lds; });
     __syncthreads();
     const int rw = r0 + wave * R;
-    if (rw >= H) return;
-    const T *col = tile + wave * R * 64 + lane;
-    double acc[R];
-    conv_core<R, 8>([&](int i) { return (double)S::dec(col[i * 64]); }, W, taps + (kTapPad - 1), acc);
-    const int c = c0 + lane;
-    if (c < Wd) store_run<S, R>(outT + (long long)n * pst + (long long)c * ldt + rw, acc, H - rw);
+    if (rw < H) {
+        const T *col = tile + wave * R * 64 + lane;
+        double acc[R];
+        conv_core<R, 8>([&](int i) { return (double)S::dec(col[i * 64]); }, W, taps + (kTapPad - 1), acc);
+        const int c = c0 + lane;
+        if (c < Wd) store_run<S, R>(outT + (long long)n * pst + (long long)c * ldt + rw, acc, H - rw);
+    }
 }
 
-// Row pass (as k_hpass): block = 64 rows x 4R columns, planes visited as in
-// hpass_tile, each staged as (4R + 2W) lines of 64 rows; LDS (4R + 2W) x 64
-// elements (dynamic).
+// Row pass (as hpass_tile) through the block's LDS tile: 64 rows
+// [64 bx, 64 bx + 64) x 4R columns [4R by, 4R by + 4R), planes in
+// hpass_tile's order, each staged as (4R + 2W) lines of 64 rows, with a
+// barrier before each staging after the first; every thread meets all of them.
 template <class S, int R, bool COMBINE>
-__global__ __launch_bounds__(256) void k_hpass_lds(const typename S::T *__restrict__ inT,
-                                                    typename S::T *__restrict__ out_stack,
-                                                    const float *__restrict__ f, float *__restrict__ out,
-                                                    float *__restrict__ Pout, float *__restrict__ Qout, int H,
-                                                    int Wd, int ld, long long ps, int lds, long long pst, int ldt,
-                                                    int P, int N, const double *__restrict__ taps,
-                                                    const double *__restrict__ cq, const double *__restrict__ cp,
-                                                    int W, Centring C) {
+__device__ __forceinline__ void hpass_tile_lds(typename S::T *__restrict__ tile,
+                                               const typename S::T *__restrict__ inT,
+                                               typename S::T *__restrict__ out_stack, const float *__restrict__ f,
+                                               float *__restrict__ out, float *__restrict__ Pout,
+                                               float *__restrict__ Qout, int H, int Wd, int ld, long long ps,
+                                               int lds, long long pst, int ldt, int P, int N,
+                                               const double *__restrict__ taps, const double *__restrict__ cq,
+                                               const double *__restrict__ cp, int W, int bx, int by,
+                                               const Centring &C) {
     typedef typename S::T T;
-    extern __shared__ __align__(16) unsigned char s_lds[];
-    T *tile = reinterpret_cast<T *>(s_lds);
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int r0 = blockIdx.x * 64, cb = blockIdx.y * 4 * R;
+    const int r0 = bx * 64, cb = by * 4 * R;
     const int r = r0 + lane;
     const int c0 = cb + wave * R;
     const bool active = c0 < Wd;   // wave-uniform; inactive waves still stage and meet the barriers
@@ -479,6 +480,32 @@ __global__ __launch_bounds__(256) void k_hpass_lds(const typename S::T *__restri
             }
         }
     }
+}
+
+// Column pass (as k_vpass), LDS-staged: dynamic LDS (4R + 2W) x 64 elements.
+template <class S, int R>
+__global__ __launch_bounds__(256) void k_vpass_lds(const typename S::T *__restrict__ in,
+                                                    typename S::T *__restrict__ outT, int H, int Wd, long long ps,
+                                                    int lds, long long pst, int ldt,
+                                                    const double *__restrict__ taps, int W) {
+    extern __shared__ __align__(16) unsigned char s_lds[];
+    vpass_tile_lds<S, R>(reinterpret_cast<typename S::T *>(s_lds), in, outT, H, Wd, ps, lds, pst, ldt, taps, W,
+                         blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Row pass (as k_hpass), LDS-staged: dynamic LDS (4R + 2W) x 64 elements.
+template <class S, int R, bool COMBINE>
+__global__ __launch_bounds__(256) void k_hpass_lds(const typename S::T *__restrict__ inT,
+                                                    typename S::T *__restrict__ out_stack,
+                                                    const float *__restrict__ f, float *__restrict__ out,
+                                                    float *__restrict__ Pout, float *__restrict__ Qout, int H,
+                                                    int Wd, int ld, long long ps, int lds, long long pst, int ldt,
+                                                    int P, int N, const double *__restrict__ taps,
+                                                    const double *__restrict__ cq, const double *__restrict__ cp,
+                                                    int W, Centring C) {
+    extern __shared__ __align__(16) unsigned char s_lds[];
+    hpass_tile_lds<S, R, COMBINE>(reinterpret_cast<typename S::T *>(s_lds), inT, out_stack, f, out, Pout, Qout, H,
+                                  Wd, ld, ps, lds, pst, ldt, P, N, taps, cq, cp, W, blockIdx.x, blockIdx.y, C);
 }
 
 // ---------------------------------------------------------------------------

@@ -38,6 +38,10 @@ CASES = [
     ((9, 70), 4.0, 30.0, 28),      # W = 12 > height
     ((1, 33), 1.0, 30.0, 28),
     ((64, 64), 0.3, 25.0, 40),
+    # radii above 16: the staged passes over FP64 plane stacks (LDS-staged up to
+    # W = 32, unstaged above)
+    ((40, 58), 6.0, 30.0, 20),     # W = 18
+    ((75, 36), 11.0, 30.0, 16),    # W = 33 > width
 ]
 
 
