@@ -666,59 +666,146 @@ struct IirCoef {
 };
 
 // Columns: one thread per column (coalesced along rows), plane blockIdx.y.
+// The recursion is serial along the column and there are only Wd x P
+// columns, so the inputs of the next kIirPrefetch samples are loaded while the
+// current ones are processed (their latency would otherwise be paid per
+// sample); the arithmetic is the plain sample-by-sample recursion.
+constexpr int kIirPrefetch = 16;
 template <class S>
 __global__ __launch_bounds__(256) void k_iir_col(const typename S::T *__restrict__ in, typename S::T *__restrict__ out,
                                                   int H, int Wd, long long ps, int lds, IirCoef c) {
+    typedef typename S::T T;
+    constexpr int U = kIirPrefetch;
     const int col = blockIdx.x * 256 + threadIdx.x;
     if (col >= Wd) return;
-    const typename S::T *src = in + (long long)blockIdx.y * ps + col;
-    typename S::T *dst = out + (long long)blockIdx.y * ps + col;
+    const T *src = in + (long long)blockIdx.y * ps + col;
+    T *dst = out + (long long)blockIdx.y * ps + col;
     double x1 = 0, x2 = 0, x3 = 0, x4 = 0, y1 = 0, y2 = 0, y3 = 0, y4 = 0;
-    for (int i = -c.P; i < H; ++i) {                        // causal
-        const double x = S::dec(src[(long long)mirror(i, H) * lds]);
-        const double y = c.n0 * x + c.n1 * x1 + c.n2 * x2 + c.n3 * x3 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
-        x3 = x2; x2 = x1; x1 = x;
-        y4 = y3; y3 = y2; y2 = y1; y1 = y;
-        if (i >= 0) dst[(long long)i * lds] = S::enc(y);
+    T cur[U], nxt[U];
+    // causal, rows -P .. H-1 (through the symmetric extension)
+    const int i0 = -c.P;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (i0 + u < H) cur[u] = src[(long long)mirror(i0 + u, H) * lds];
+    for (int ib = i0; ib < H; ib += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (ib + U + u < H) nxt[u] = src[(long long)mirror(ib + U + u, H) * lds];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = ib + u;
+            if (i < H) {
+                const double x = S::dec(cur[u]);
+                const double y = c.n0 * x + c.n1 * x1 + c.n2 * x2 + c.n3 * x3 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 -
+                                 c.d4 * y4;
+                x3 = x2; x2 = x1; x1 = x;
+                y4 = y3; y3 = y2; y2 = y1; y1 = y;
+                if (i >= 0) dst[(long long)i * lds] = S::enc(y);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
     }
+    // anticausal, rows H+P-1 .. 0; y+ read back from dst (this thread wrote it)
     x1 = x2 = x3 = x4 = y1 = y2 = y3 = y4 = 0;
-    for (int i = H + c.P - 1; i >= 0; --i) {                // anticausal
-        const double y = c.m1 * x1 + c.m2 * x2 + c.m3 * x3 + c.m4 * x4 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
-        const double x = S::dec(src[(long long)mirror(i, H) * lds]);
-        x4 = x3; x3 = x2; x2 = x1; x1 = x;
-        y4 = y3; y3 = y2; y2 = y1; y1 = y;
-        if (i < H) dst[(long long)i * lds] = S::enc(c.k * ((double)S::dec(dst[(long long)i * lds]) + y));
+    T ycur[U], ynxt[U];
+    const int j0 = H + c.P - 1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int i = j0 - u;
+        if (i >= 0) {
+            cur[u] = src[(long long)mirror(i, H) * lds];
+            if (i < H) ycur[u] = dst[(long long)i * lds];
+        }
     }
+    for (int ib = j0; ib >= 0; ib -= U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = ib - U - u;
+            if (i >= 0) {
+                nxt[u] = src[(long long)mirror(i, H) * lds];
+                if (i < H) ynxt[u] = dst[(long long)i * lds];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = ib - u;
+            if (i >= 0) {
+                const double y = c.m1 * x1 + c.m2 * x2 + c.m3 * x3 + c.m4 * x4 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 -
+                                 c.d4 * y4;
+                const double x = S::dec(cur[u]);
+                x4 = x3; x3 = x2; x2 = x1; x1 = x;
+                y4 = y3; y3 = y2; y2 = y1; y1 = y;
+                if (i < H) dst[(long long)i * lds] = S::enc(c.k * ((double)S::dec(ycur[u]) + y));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cur[u] = nxt[u];
+            ycur[u] = ynxt[u];
+        }
+    }
+}
+
+// Ordering of a one-wave block's LDS accesses: a wave issues its LDS operations
+// in order, so a counter wait and a compiler barrier suffice; unlike
+// __syncthreads() this does not wait for the global loads in flight (the next
+// tile's prefetch).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0), other counters unconstrained (gfx9 encoding)
+    __builtin_amdgcn_wave_barrier();
 }
 
 // Rows: one wave per block owns 64 rows; 64 x 32 tiles of the line are staged
 // through LDS (coalesced loads and stores, row pitch 33 so a lane walking its
-// row hits its own bank), and each lane runs the recursion along its row.
+// row hits its own bank), and each lane runs the recursion along its row. The
+// next tile's loads are issued before the current tile is processed.
 constexpr int kIirChunk = 32;
 template <class S>
 __global__ __launch_bounds__(64) void k_iir_row(const typename S::T *__restrict__ in, typename S::T *__restrict__ out,
                                                  int H, int Wd, long long ps, int lds, IirCoef c) {
+    typedef typename S::T T;
     __shared__ float X[64][kIirChunk + 1];
     __shared__ float Y[64][kIirChunk + 1];
     const int lane = threadIdx.x;
     const int r0 = blockIdx.x * 64;                         // < H by the grid
-    const typename S::T *src = in + (long long)blockIdx.y * ps;
-    typename S::T *dst = out + (long long)blockIdx.y * ps;
-    const int half = lane >> 5, cc = lane & 31;            // two rows of 32 columns per access
-    auto load_x = [&](int j0) {
+    const T *src = in + (long long)blockIdx.y * ps;
+    T *dst = out + (long long)blockIdx.y * ps;
+    constexpr int RPA = 64 / kIirChunk;                     // rows per access (kIirChunk lanes per row)
+    constexpr int NR = 64 / RPA;                            // rows per lane per tile
+    const int half = lane / kIirChunk, cc = lane % kIirChunk;
+    auto row_of = [&](int q) { return (long long)min(r0 + half + RPA * q, H - 1) * lds; };
+    // tile loads into registers: x (columns j0 + cc through the symmetric extension), and y+ when asked
+    auto load_x = [&](int j0, T (&v)[NR]) {
         const int jm = mirror(j0 + cc, Wd);
-        for (int rr = half; rr < 64; rr += 2) X[rr][cc] = S::dec(src[(long long)min(r0 + rr, H - 1) * lds + jm]);
+#pragma unroll
+        for (int q = 0; q < NR; ++q) v[q] = src[row_of(q) + jm];
+    };
+    auto load_y = [&](int j0, T (&v)[NR]) {
+        if (j0 + cc < Wd) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) v[q] = dst[row_of(q) + j0 + cc];
+        }
+    };
+    auto put = [&](float (&A)[64][kIirChunk + 1], const T (&v)[NR]) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) A[half + RPA * q][cc] = S::dec(v[q]);
     };
     auto store_y = [&](int j0) {
         if (j0 + cc >= 0 && j0 + cc < Wd)
-            for (int rr = half; rr < 64; rr += 2)
-                if (r0 + rr < H) dst[(long long)(r0 + rr) * lds + j0 + cc] = S::enc(Y[rr][cc]);
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (r0 + half + RPA * q < H)
+                    dst[(long long)(r0 + half + RPA * q) * lds + j0 + cc] = S::enc(Y[half + RPA * q][cc]);
     };
     const int jlo = -((c.P + kIirChunk - 1) / kIirChunk) * kIirChunk;
     double x1 = 0, x2 = 0, x3 = 0, x4 = 0, y1 = 0, y2 = 0, y3 = 0, y4 = 0;
+    T vx[NR], vy[NR];
+    load_x(jlo, vx);
     for (int j0 = jlo; j0 < Wd; j0 += kIirChunk) {         // causal, left to right
-        load_x(j0);
-        __syncthreads();
+        put(X, vx);
+        if (j0 + kIirChunk < Wd) load_x(j0 + kIirChunk, vx);
+        wave_lds_sync();
         for (int k = 0; k < kIirChunk; ++k) {
             const double x = X[lane][k];
             const double y = c.n0 * x + c.n1 * x1 + c.n2 * x2 + c.n3 * x3 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
@@ -726,17 +813,22 @@ __global__ __launch_bounds__(64) void k_iir_row(const typename S::T *__restrict_
             y4 = y3; y3 = y2; y2 = y1; y1 = y;
             Y[lane][k] = (float)S::dec(S::enc(y));
         }
-        __syncthreads();
+        wave_lds_sync();
         store_y(j0);
-        __syncthreads();
+        wave_lds_sync();
     }
     const int jhi = ((Wd + c.P + kIirChunk - 1) / kIirChunk) * kIirChunk;
     x1 = x2 = x3 = x4 = y1 = y2 = y3 = y4 = 0;
+    load_x(jhi - kIirChunk, vx);
+    load_y(jhi - kIirChunk, vy);
     for (int j0 = jhi - kIirChunk; j0 >= 0; j0 -= kIirChunk) {   // anticausal, right to left
-        load_x(j0);
-        if (j0 + cc < Wd)
-            for (int rr = half; rr < 64; rr += 2) Y[rr][cc] = S::dec(dst[(long long)min(r0 + rr, H - 1) * lds + j0 + cc]);
-        __syncthreads();
+        put(X, vx);
+        if (j0 + cc < Wd) put(Y, vy);
+        if (j0 - kIirChunk >= 0) {
+            load_x(j0 - kIirChunk, vx);
+            load_y(j0 - kIirChunk, vy);
+        }
+        wave_lds_sync();
         for (int k = kIirChunk - 1; k >= 0; --k) {
             const double y = c.m1 * x1 + c.m2 * x2 + c.m3 * x3 + c.m4 * x4 - c.d1 * y1 - c.d2 * y2 - c.d3 * y3 - c.d4 * y4;
             const double x = X[lane][k];
@@ -744,9 +836,9 @@ __global__ __launch_bounds__(64) void k_iir_row(const typename S::T *__restrict_
             y4 = y3; y3 = y2; y2 = y1; y1 = y;
             Y[lane][k] = (float)(c.k * ((double)Y[lane][k] + y));
         }
-        __syncthreads();
+        wave_lds_sync();
         store_y(j0);
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
