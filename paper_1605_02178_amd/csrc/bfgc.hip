@@ -813,6 +813,7 @@ static bf_status run_joint_fused(const float *g, const float *v, float *out, int
 
 constexpr int kAdjR = 4;            // columns per lane in k_hpass_adj
 constexpr int kNeighborBlocks = 2048;
+constexpr size_t kBatchItemsMaxTable = 256;   // descriptors up to which the three-kernel batch runs one block per item
 
 struct BwdLayout {
     size_t params, stackA, stackB, perpx, partial, total;
@@ -1426,6 +1427,24 @@ static bf_status run_batched(const bf_image_desc *descs, int count, int dtype, u
     for (int p = 0; p < 3; ++p) {
         K.block[p] = 256;
         K.grid[p] = phase_grid(K.func[p], B.phase_items[p], K.block[p], K.lds);
+    }
+    // Small item tables: the column and row passes one block per item on the
+    // LDS-staged tiles (the single-image kernels' form; the persistent
+    // phases would wait on every item's staging in turn).
+    int wmax = 0;
+    for (const BatchImage &I : B.img) wmax = std::max(wmax, I.W);
+    const size_t table = (batch_lds_bytes((int)B.img.size()) + 15) & ~(size_t)15;
+    const size_t tile = (size_t)(4 * std::max(RV, RH) + 2 * wmax) * 64 * sizeof(typename S::T);
+    if (B.img.size() <= kBatchItemsMaxTable && table + tile <= 65536) {
+        K.func[1] = (const void *)k_batched_items<S, RV, RH, 1>;
+        K.func[2] = (const void *)k_batched_items<S, RV, RH, 2>;
+        K.lds = table + tile;   // the build phase needs only the table; one LDS size serves the graph's nodes
+        for (int p = 1; p < 3; ++p) {
+            if (B.phase_items[p] > INT_MAX) return fail(BF_ERR_UNSUPPORTED, "batch: too many tiles in a phase");
+            K.grid[p] = (int)std::max(1LL, B.phase_items[p]);
+            K.items_grid[p] = true;
+        }
+        K.grid[0] = phase_grid(K.func[0], B.phase_items[0], K.block[0], K.lds);
     }
     return launch_batch(B, K, flags, ws, stream);
 }

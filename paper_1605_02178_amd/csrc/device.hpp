@@ -646,6 +646,55 @@ __global__ __launch_bounds__(256) void k_batched(char *__restrict__ blob) {
     }
 }
 
+// Column and row passes of a batch (PHASE 1, 2) with one block per item
+// (grid = the phase's items, set at every launch) and the LDS-staged tile
+// functions of the single-image kernels, so each image equals its
+// single-image result bit for bit. The phase's item table (starts and visiting
+// order) is copied into LDS, the staged tile follows it (16-byte aligned; the
+// launch sizes both). For batches whose table is small (the persistent
+// k_batched serves the others).
+template <class S, int RV, int RH, int PHASE>
+__global__ __launch_bounds__(256) void k_batched_items(char *__restrict__ blob) {
+    typedef typename S::T T;
+    extern __shared__ long long s_start[];
+    BatchHeader *hdr = (BatchHeader *)blob;
+    const long long t = blockIdx.x;
+    if (t >= hdr->items[PHASE]) return;
+    const BatchImage *img = (const BatchImage *)(blob + sizeof(BatchHeader));
+    const int count = hdr->count;
+    int *s_order = (int *)(s_start + count);
+    T *stile = reinterpret_cast<T *>((reinterpret_cast<uintptr_t>(s_order + count) + 15) & ~(uintptr_t)15);
+    const long long *start = (const long long *)(blob + sizeof(BatchHeader) + sizeof(BatchImage) * count);
+    const int *order = (const int *)(start + kBatchPhases * count);
+    for (int k = threadIdx.x; k < count; k += blockDim.x) {
+        s_start[k] = start[PHASE * count + k];
+        s_order[k] = order[PHASE * count + k];
+    }
+    __syncthreads();
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_start[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const int ii = __builtin_amdgcn_readfirstlane(s_order[lo]);
+    const BatchImage &B = img[ii];
+    const int l = (int)(t - s_start[lo]);
+    const double *prm = as_global(B.prm);
+    if (PHASE == 1) {
+        const int per_plane = B.gvx * B.gvy;
+        const int n = l / per_plane, rem = l - n * per_plane;
+        vpass_tile_lds<S, RV>(stile, as_global((const T *)B.stackA), as_global((T *)B.stackB), B.H, B.Wd, B.ps,
+                              B.lds, B.pst, B.ldt, prm + B.off_taps, B.W, rem % B.gvx, rem / B.gvx, n);
+    } else {
+        hpass_tile_lds<S, RH, true>(stile, as_global((const T *)B.stackB), (T *)nullptr, as_global(B.f),
+                                    as_global(B.out), nullptr, nullptr, B.H, B.Wd, B.ld, 0LL, 0, B.pst, B.ldt, B.P,
+                                    B.N, prm + B.off_taps, prm + B.off_cq, prm + B.off_cp, B.W, l % B.ghx,
+                                    l / B.ghx, B.C);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Recursive variant of eq. 7 (Section I names recursion as the O(1) way to
 // apply the Gaussian): Deriche's recursive Gaussian, a causal 4th-order
