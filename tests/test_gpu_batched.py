@@ -48,6 +48,31 @@ def test_batched_equals_single_image_bitwise(torch_cuda, dtype, graph, cfg):
         assert torch.equal(outs[k], ref), (k, f.shape, float((outs[k] - ref).abs().max()))
 
 
+@pytest.mark.parametrize("form", ["many", "wide"])
+def test_persistent_three_kernel_batch_equals_single_image_bitwise(torch_cuda, form):
+    """The persistent column and row phases (more than 256 descriptors, or an
+    item table plus the staged tile of the widest radius above 64 KiB) against
+    the single-image kernels (LDS-staged), bit for bit."""
+    import paper_1605_02178_amd as bf
+    from synth import edge_rich
+    torch = torch_cuda
+    rng = np.random.default_rng(77 if form == "many" else 78)
+    if form == "many":
+        shapes = [(int(rng.integers(4, 40)), int(rng.integers(4, 40))) for _ in range(300)]
+        ss = [float(rng.uniform(0.5, 3.0)) for _ in shapes]
+    else:
+        shapes = [(70, 90), (130, 40), (33, 200)]
+        ss = [32.0, 2.0, 5.0]                      # W = 96: (64 + 192) x 64 x 4 B of tile alone
+    fs = [torch.tensor(edge_rich(h, w, seed=k).astype(np.float32), device="cuda:0") for k, (h, w) in enumerate(shapes)]
+    sr = [float(rng.uniform(30.0, 60.0)) for _ in shapes]
+    degrees = [bf.degree_rule(x) for x in sr]
+    outs, status = bf.gc_filter_batched(fs, ss, sr, degrees, stack_dtype="f32", tile_config=0)
+    assert status == [0] * len(fs)
+    for k, f in enumerate(fs):
+        ref = bf.gc_filter(f, ss[k], sr[k], degrees[k], stack_dtype="f32", tile_config=0)
+        assert torch.equal(outs[k], ref), (k, f.shape)
+
+
 def test_batched_parity_with_oracle(torch_cuda):
     import paper_1605_02178_amd as bf
     from oracle import native as C
