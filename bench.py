@@ -275,7 +275,8 @@ def bench_differentiation(bf, steps, log):
     per pixel (bf_gc_forward_saving), the backward from them
     (bf_gc_backward_saving), one launch each for the batch. Also timed: the
     FP32-stack forward (bf_gc_batched) with the recomputing backward
-    (bf_gc_backward per image)."""
+    (bf_gc_backward per image), and the f64 form keeping only f and sigma_r
+    (the backward recomputes the sums: one more forward tile launch)."""
     import numpy as np
     import torch
     from synth import diff_batch
@@ -284,10 +285,10 @@ def bench_differentiation(bf, steps, log):
     tgt = torch.tensor(tgts[:, None].astype(np.float32), device="cuda:0")
     sr = torch.tensor(30.0, dtype=torch.float64, device="cuda:0")
 
-    def step(stack=None):
+    def step(stack=None, keep=True):
         x = f.detach().requires_grad_(True)
         s_ = sr.detach().requires_grad_(True)
-        y = bf.gc_filter_autograd(x, s_, 5.0, 28, stack_dtype=stack, sigma_r_host=30.0)
+        y = bf.gc_filter_autograd(x, s_, 5.0, 28, stack_dtype=stack, sigma_r_host=30.0, keep_sums=keep)
         loss = ((y - tgt) ** 2).mean()
         loss.backward()
         return x.grad, s_.grad
@@ -317,11 +318,21 @@ def bench_differentiation(bf, steps, log):
     torch.cuda.synchronize()
     ms32 = e0.elapsed_time(e1) / steps
     log(f"bench: differentiation, FP32-stack forward + recomputing backward {ms32:.2f} ms")
+    step(None, False)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step(None, False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_nokeep = e0.elapsed_time(e1) / steps
+    log(f"bench: differentiation, f64 tiles keeping only f and sigma_r (sums recomputed) {ms_nokeep:.2f} ms")
     return {"ms_per_step": round(ms, 3), "mpx_s": round(px / 1e6 / (ms / 1e3), 1), "images": 8,
             "shape": "8x1x1024x1024", "sigma_s": 5.0, "sigma_r": 30.0, "degree": 28, "steps": steps,
             "form": "f64 planes, saved sums (bf_gc_forward_saving + bf_gc_backward_saving)",
             "kernels": {k: {"launches": c, "avg_ms": t / c} for k, (c, t) in prof.items()},
-            "f32_forward_recompute_backward_ms": round(ms32, 3)}
+            "f32_forward_recompute_backward_ms": round(ms32, 3),
+            "f64_keep_only_f_sigma_r_ms": round(ms_nokeep, 3)}
 
 
 def bench_joint(bf, f, f64, sigma_s, sigma_r, N, steps, log):

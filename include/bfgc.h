@@ -287,8 +287,10 @@ bf_status bf_gc_backward(const float *f, const float *grad_out, float *grad_f, d
  * doubles, count x 6 x height x width, [count][6][height][width],
  * caller-allocated): P' = sum b_n s^n Hbar_{n+1}, Q = sum b_n s^n Hbar_n,
  * their derivatives in the explicit powers of s, and the same sums with
- * db_n/dmu. Inputs outside [0, 255] set BF_DEVFLAG_RANGE in the workspace's
- * flag word. out and saved must overlap neither f nor each other.
+ * db_n/dmu. Either of out and saved may be null (y only, for a forward that
+ * keeps nothing; the sums only, to recompute them in a backward), not both.
+ * Inputs outside [0, 255] set BF_DEVFLAG_RANGE in the workspace's flag word.
+ * out and saved must overlap neither f nor each other.
  *
  * bf_gc_backward_saving: for L = sum_z sum_i grad_out_{z,i} y_{z,i}, grad_f =
  * dL/df (FP32, layout of f) and *grad_sigma_r = dL/dsigma_r summed over the

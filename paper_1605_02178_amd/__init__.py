@@ -406,20 +406,26 @@ def _check_batch(x, name):
 
 @_on_stream
 def gc_forward_saving(f, sigma_s: float, sigma_r: float, degree: int | None = None, allow_ill_conditioned=False,
-                      coeffs=None, out=None, saved=None, workspace=None, stream=None):
+                      coeffs=None, out=None, saved=None, keep_sums=True, want_y=True, workspace=None, stream=None):
     """bf_gc_forward_saving on a contiguous (count, H, W) float32 batch: the
     filter with FP64 planes (radius <= ADJ_MAX_RADIUS). Returns (y, saved):
-    y like f, saved the (count, 6, H, W) float64 sums that gc_backward_saving
-    takes."""
+    y like f (None without want_y), saved the (count, 6, H, W) float64 sums
+    that gc_backward_saving takes (None without keep_sums)."""
     import torch
     _check_batch(f, "f")
+    if not (keep_sums or want_y):
+        raise ValueError("gc_forward_saving: nothing to compute (keep_sums and want_y both off)")
     B, H, Wd = f.shape
     N = degree_rule(sigma_r) if degree is None else int(degree)
-    if out is None:
+    if not want_y:
+        out = None
+    elif out is None:
         out = torch.empty_like(f)
     else:
         _check_batch(out, "out")
-    if saved is None:
+    if not keep_sums:
+        saved = None
+    elif saved is None:
         saved = torch.empty((B, 6, H, Wd), dtype=torch.float64, device=f.device)
     elif saved.dtype != torch.float64 or tuple(saved.shape) != (B, 6, H, Wd) or not saved.is_contiguous():
         raise ValueError("saved must be a contiguous (count, 6, H, W) float64 tensor")
@@ -427,8 +433,10 @@ def gc_forward_saving(f, sigma_s: float, sigma_r: float, degree: int | None = No
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=f.device)
     flags = (FLAG_ALLOW_ILL_CONDITIONED if allow_ill_conditioned else 0) | _coeff_flags(coeffs)
-    st = _lib.load().bf_gc_forward_saving(ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(out.data_ptr()),
-                                          ctypes.c_void_p(saved.data_ptr()), B, H * Wd, H, Wd, Wd, float(sigma_s),
+    st = _lib.load().bf_gc_forward_saving(ctypes.c_void_p(f.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr() if out is not None else None),
+                                          ctypes.c_void_p(saved.data_ptr() if saved is not None else None), B, H * Wd,
+                                          H, Wd, Wd, float(sigma_s),
                                           float(sigma_r), N, flags, ctypes.c_void_p(workspace.data_ptr()),
                                           workspace.numel(), _stream_ptr(stream))
     _lib.check(st, "bf_gc_forward_saving")
@@ -486,8 +494,10 @@ def _autograd_class():
 
         stack_dtype "f64" (the default up to radius ADJ_MAX_RADIUS): the whole
         batch in one bf_gc_forward_saving launch, FP64 planes, the six sums
-        per pixel kept for the backward, which is one bf_gc_backward_saving
-        launch. "f32", "f16", "bf16" (the default above that radius): the
+        per pixel (48 B) kept for the backward, which is one
+        bf_gc_backward_saving launch. With keep_sums=False the forward keeps
+        only f and sigma_r and the backward recomputes the sums first (one
+        more launch of the forward tile kernel). "f32", "f16", "bf16" (the default above that radius): the
         batch in one bf_gc_batched launch with that stack, only f and sigma_r
         kept; the backward recomputes the filter in FP64 per image
         (bf_gc_backward), so the gradient is that of the Gauss-Chebyshev
@@ -496,7 +506,8 @@ def _autograd_class():
         approximates."""
 
         @staticmethod
-        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype=None, coeffs=None, sigma_r_host=None):
+        def forward(ctx, f, sigma_r, sigma_s, degree=None, stack_dtype=None, coeffs=None, sigma_r_host=None,
+                    keep_sums=True):
             sr = float(sigma_r_host) if sigma_r_host is not None else float(sigma_r)
             N = degree_rule(sr) if degree is None else int(degree)
             if stack_dtype is None:
@@ -518,8 +529,12 @@ def _autograd_class():
             if ctx.saving:
                 if radius(sigma_s) > ADJ_MAX_RADIUS:
                     raise ValueError(f"GaussChebyshevBF: the f64 form takes radius <= {ADJ_MAX_RADIUS}")
-                y, saved = gc_forward_saving(x, sigma_s, sr, N, coeffs=coeffs)
-                ctx.save_for_backward(f, sigma_r, saved)
+                ctx.keep_sums = bool(keep_sums)
+                y, saved = gc_forward_saving(x, sigma_s, sr, N, coeffs=coeffs, keep_sums=ctx.keep_sums)
+                if ctx.keep_sums:
+                    ctx.save_for_backward(f, sigma_r, saved)
+                else:
+                    ctx.save_for_backward(f, sigma_r)
                 return y.reshape(shape)
             y = torch.empty_like(x)
             B = x.shape[0]
@@ -538,10 +553,14 @@ def _autograd_class():
             x = f.reshape(-1, shape[-2], shape[-1])
             g = grad_y.reshape(-1, shape[-2], shape[-1]).contiguous()
             if ctx.saving:
-                gf, gs = gc_backward_saving(x.contiguous(), g, ctx.saved_tensors[2], ctx.sigma_s, ctx.sigma_r, ctx.N,
-                                            coeffs=ctx.coeffs)
+                xc = x.contiguous()
+                if ctx.keep_sums:
+                    saved = ctx.saved_tensors[2]
+                else:
+                    _, saved = gc_forward_saving(xc, ctx.sigma_s, ctx.sigma_r, ctx.N, coeffs=ctx.coeffs, want_y=False)
+                gf, gs = gc_backward_saving(xc, g, saved, ctx.sigma_s, ctx.sigma_r, ctx.N, coeffs=ctx.coeffs)
                 gs = gs.to(device=sigma_r.device, dtype=sigma_r.dtype).reshape(sigma_r.shape)
-                return gf.reshape(shape), gs, None, None, None, None, None
+                return gf.reshape(shape), gs, None, None, None, None, None, None
             B = x.shape[0]
             gf = torch.empty_like(x)
             gsr = torch.empty(B, dtype=torch.float64, device=f.device)
@@ -551,7 +570,7 @@ def _autograd_class():
                 gc_backward(x[b].contiguous(), g[b], ctx.sigma_s, ctx.sigma_r, ctx.N, workspace=ws,
                             coeffs=ctx.coeffs, grad_f=gf[b], grad_sigma_r=gsr[b])
             gs = gsr.sum().to(device=sigma_r.device, dtype=sigma_r.dtype).reshape(sigma_r.shape)
-            return gf.reshape(shape), gs, None, None, None, None, None
+            return gf.reshape(shape), gs, None, None, None, None, None, None
 
     return GaussChebyshevBF
 _GCBF = None
@@ -566,11 +585,14 @@ def __getattr__(name):
     raise AttributeError(name)
 
 
-def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype=None, coeffs=None, sigma_r_host=None):
+def gc_filter_autograd(f, sigma_r, sigma_s, degree=None, stack_dtype=None, coeffs=None, sigma_r_host=None,
+                       keep_sums=True):
     """Differentiable forward: GaussChebyshevBF.apply with sigma_r a tensor
     (sigma_r_host: its value as a float, which spares a device sync);
-    stack_dtype None = "f64" up to radius ADJ_MAX_RADIUS, else "f32"."""
-    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs, sigma_r_host)
+    stack_dtype None = "f64" up to radius ADJ_MAX_RADIUS, else "f32";
+    keep_sums=False: the f64 form keeps only f and sigma_r."""
+    return __getattr__("GaussChebyshevBF").apply(f, sigma_r, sigma_s, degree, stack_dtype, coeffs, sigma_r_host,
+                                                 keep_sums)
 
 
 def _descs(images, outs, sigmas_s, sigmas_r, degrees):

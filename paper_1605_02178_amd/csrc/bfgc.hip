@@ -1825,16 +1825,20 @@ size_t bf_gc_saving_workspace_bytes(int count, int height, int width, double sig
 }
 
 // Shared argument checks of the two calls; *empty when there is nothing to do.
-static bf_status check_saving(const float *f, const void *out, const void *saved, int count, long long stride,
-                              int height, int width, int ld, double sigma_s, double sigma_r, int N, unsigned flags,
-                              void *ws, size_t ws_bytes, bool *empty) {
+// out (the forward's y, the backward's grad_f) and saved: both required when
+// `both`, else at least one (the forward may keep either).
+static bf_status check_saving(const float *f, const void *out, const void *saved, bool both, int count,
+                              long long stride, int height, int width, int ld, double sigma_s, double sigma_r, int N,
+                              unsigned flags, void *ws, size_t ws_bytes, bool *empty) {
     bf_status st = check_common(height, width, sigma_s, sigma_r, N, BF_STACK_F32);
     if (st != BF_OK) return st;
     if (count < 0 || count > 65535) return fail(BF_ERR_INVALID_ARG, "count out of [0, 65535]");
     if (radius_of(sigma_s) > kAdjMaxRadius) return fail(BF_ERR_UNSUPPORTED, "radius W above BF_ADJ_MAX_RADIUS");
     *empty = count == 0 || height == 0 || width == 0;
     if (*empty) return BF_OK;
-    if (!f || !out || !saved) return fail(BF_ERR_INVALID_ARG, "image, output and saved pointers must be non-null");
+    if (!f || (both ? !out || !saved : !out && !saved))
+        return fail(BF_ERR_INVALID_ARG, both ? "image, output and saved pointers must be non-null"
+                                             : "f must be non-null, and out or saved");
     if (ld < width) return fail(BF_ERR_INVALID_ARG, "ld must be >= width");
     const long long img = (long long)(height - 1) * ld + width;
     if (count > 1 && stride < img) return fail(BF_ERR_INVALID_ARG, "image_stride smaller than one image");
@@ -1848,12 +1852,13 @@ bf_status bf_gc_forward_saving(const float *f, float *out, double *saved, int co
                                int height, int width, int ld, double sigma_s, double sigma_r, int N, unsigned flags,
                                void *ws, size_t ws_bytes, void *stream) {
     bool empty = false;
-    bf_status st = check_saving(f, out, saved, count, image_stride, height, width, ld, sigma_s, sigma_r, N, flags,
-                                ws, ws_bytes, &empty);
+    bf_status st = check_saving(f, out, saved, false, count, image_stride, height, width, ld, sigma_s, sigma_r, N,
+                                flags, ws, ws_bytes, &empty);
     if (st != BF_OK || empty) return st;
     const size_t span = ((size_t)(count - 1) * image_stride + (size_t)(height - 1) * ld + width) * sizeof(float);
     const size_t sbytes = (size_t)count * 6 * height * width * sizeof(double);
-    if (overlaps(f, span, out, span) || overlaps(saved, sbytes, f, span) || overlaps(saved, sbytes, out, span))
+    if ((out && overlaps(f, span, out, span)) || (saved && overlaps(saved, sbytes, f, span)) ||
+        (out && saved && overlaps(saved, sbytes, out, span)))
         return fail(BF_ERR_INVALID_ARG, "out, saved and f overlap");
     hipStream_t s = (hipStream_t)stream;
     unsigned *flag = (unsigned *)ws;
@@ -1870,8 +1875,8 @@ bf_status bf_gc_backward_saving(const float *f, const float *grad_out, const dou
                                 size_t ws_bytes, void *stream) {
     if (!grad_sigma_r) return fail(BF_ERR_INVALID_ARG, "grad_sigma_r must be non-null");
     bool empty = false;
-    bf_status st = check_saving(f, grad_f, saved, count, image_stride, height, width, ld, sigma_s, sigma_r, N, flags,
-                                ws, ws_bytes, &empty);
+    bf_status st = check_saving(f, grad_f, saved, true, count, image_stride, height, width, ld, sigma_s, sigma_r, N,
+                                flags, ws, ws_bytes, &empty);
     if (st != BF_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     if (empty) {   // dL/dsigma_r = 0 (a kernel, so the call can be graph-captured)

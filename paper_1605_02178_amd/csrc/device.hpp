@@ -1242,8 +1242,9 @@ __device__ __forceinline__ void adj_split_row(const AdjLds &S, const AdjTaps<W> 
 //   P' = sum cp_{n-1} s^{n-1} Hbar_n,  Q = sum cq_n s^n Hbar_n,
 //   dP'/ds, dQ/ds (the explicit powers only),
 //   Pm = sum bd_{n-1} s^{n-1} Hbar_n,  Qm = sum bd_n s^n Hbar_n,
-// written to saved ([6][H][Wd] per image, FP64), and y = t_c + t_h P'/Q to
-// out when out is non-null. Image z = blockIdx.z of a strided batch.
+// written to saved ([6][H][Wd] per image, FP64) when saved is non-null, and
+// y = t_c + t_h P'/Q to out when out is non-null. Image z = blockIdx.z of a
+// strided batch.
 template <int W>
 __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adj_forward_tile(
     const float *__restrict__ f, float *__restrict__ out, double *__restrict__ saved, int H, int Wd, int ld,
@@ -1254,7 +1255,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
     const long long npx = (long long)H * Wd;
     f += blockIdx.z * image_stride;
     if (out) out += blockIdx.z * image_stride;
-    saved += blockIdx.z * 6 * npx;
+    if (saved) saved += blockIdx.z * 6 * npx;
     const AdjTaps<W> w(taps);   // taps points at the tap of offset -W
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1337,12 +1338,14 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
             const int c = c0 + j0 + q;
             if (r < H && c < Wd) {
                 const long long o = (long long)r * Wd + c;
-                saved[o] = Pa[q];
-                saved[npx + o] = Qa[q];
-                saved[2 * npx + o] = dP[q];
-                saved[3 * npx + o] = dQ[q];
-                saved[4 * npx + o] = Pm[q];
-                saved[5 * npx + o] = Qm[q];
+                if (saved) {
+                    saved[o] = Pa[q];
+                    saved[npx + o] = Qa[q];
+                    saved[2 * npx + o] = dP[q];
+                    saved[3 * npx + o] = dQ[q];
+                    saved[4 * npx + o] = Pm[q];
+                    saved[5 * npx + o] = Qm[q];
+                }
                 if (out) out[(long long)r * ld + c] = (float)(kTc + kTh * (Pa[q] / Qa[q]));   // eq. 10
                 const float fv = f[(long long)r * ld + c];
                 bad |= !(fv >= 0.0f && fv <= 255.0f);

@@ -289,3 +289,21 @@ def test_saving_errors_and_empty(torch_cuda):
     # the autograd function's f64 form refuses radii above 16, like the call
     with pytest.raises(ValueError):
         bf.gc_filter_autograd(x, torch.tensor(30.0, dtype=torch.float64), 5.4, 28, stack_dtype="f64")
+
+
+def test_autograd_keep_sums_false_recomputes_identically(torch_cuda):
+    """The f64 form with keep_sums=False keeps only f and sigma_r and
+    recomputes the sums in the backward with the same kernel: outputs and
+    gradients equal the default's bit for bit."""
+    import paper_1605_02178_amd as bf
+    from synth import edge_rich
+    torch = torch_cuda
+    imgs = np.stack([edge_rich(70, 90, seed=140 + b) for b in range(3)]).astype(np.float32)
+    res = []
+    for keep in (True, False):
+        f = _gpu(torch, imgs[:, None]).requires_grad_(True)
+        sr = torch.tensor(30.0, dtype=torch.float64, device="cuda:0", requires_grad=True)
+        y = bf.gc_filter_autograd(f, sr, 3.0, 28, sigma_r_host=30.0, keep_sums=keep)
+        (y * y).sum().backward()
+        res.append((y.detach(), f.grad, sr.grad))
+    assert all(torch.equal(a, b) for a, b in zip(res[0], res[1]))
