@@ -307,3 +307,52 @@ def test_autograd_keep_sums_false_recomputes_identically(torch_cuda):
         (y * y).sum().backward()
         res.append((y.detach(), f.grad, sr.grad))
     assert all(torch.equal(a, b) for a, b in zip(res[0], res[1]))
+
+
+def test_saving_pair_row_stride_and_image_stride(torch_cuda):
+    """Through the C ABI with ld > width and an image stride beyond one image:
+    the same outputs, sums and gradients as the contiguous batch, bit for bit;
+    the padding columns are left untouched."""
+    import ctypes
+    import paper_1605_02178_amd as bf
+    from paper_1605_02178_amd import _lib
+    torch = torch_cuda
+    B, H, Wd, ld, gap = 3, 70, 45, 53, 4 * 53
+    stride = H * ld + gap
+    imgs = _batch((H, Wd), B, 160)
+    ybar = np.random.default_rng(161).uniform(-1, 1, size=imgs.shape).astype(np.float32)
+    x, g = _gpu(torch, imgs), _gpu(torch, ybar)
+    y_ref, saved_ref = bf.gc_forward_saving(x, 4.0, 30.0, 28)
+    gf_ref, gs_ref = bf.gc_backward_saving(x, g, saved_ref, 4.0, 30.0, 28)
+
+    def strided(a, fill):
+        buf = torch.full((B * stride,), fill, dtype=torch.float32, device="cuda:0")
+        view = torch.as_strided(buf, (B, H, Wd), (stride, ld, 1))
+        if a is not None:
+            view.copy_(a)
+        return buf, view
+
+    fbuf, _ = strided(x, 7.0)
+    gbuf, _ = strided(g, 0.0)
+    ybuf, yv = strided(None, -5.0)
+    gfbuf, gfv = strided(None, -6.0)
+    saved = torch.empty((B, 6, H, Wd), dtype=torch.float64, device="cuda:0")
+    gs = torch.empty((), dtype=torch.float64, device="cuda:0")
+    nbytes = bf.saving_workspace_bytes(B, H, Wd, 4.0, 28)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    lib = _lib.load()
+    vp = lambda t: ctypes.c_void_p(t.data_ptr())
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.bf_gc_forward_saving(vp(fbuf), vp(ybuf), vp(saved), B, stride, H, Wd, ld, 4.0, 30.0, 28, 0, vp(ws),
+                                    nbytes, stream) == 0
+    assert lib.bf_gc_backward_saving(vp(fbuf), vp(gbuf), vp(saved), vp(gfbuf), vp(gs), B, stride, H, Wd, ld, 4.0,
+                                     30.0, 28, 0, vp(ws), nbytes, stream) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(yv, y_ref) and torch.equal(saved, saved_ref)
+    assert torch.equal(gfv, gf_ref) and torch.equal(gs.reshape(()), gs_ref.reshape(()))
+    pad = torch.ones(B * stride, dtype=torch.bool, device="cuda:0")
+    pad[torch.as_strided(torch.arange(B * stride, device="cuda:0"), (B, H, Wd), (stride, ld, 1)).reshape(-1)] = False
+    assert bool((ybuf[pad] == -5.0).all()) and bool((gfbuf[pad] == -6.0).all())
+    # an image stride smaller than one image ((H - 1) ld + W elements) is refused
+    assert lib.bf_gc_forward_saving(vp(fbuf), vp(ybuf), vp(saved), B, (H - 1) * ld + Wd - 1, H, Wd, ld, 4.0, 30.0,
+                                    28, 0, vp(ws), nbytes, stream) == 1
