@@ -41,6 +41,8 @@ METRIC = "Mpixel/s at 4096², σs=10 (FP32 vs FP16 stack, same error); HBM GB/s 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP64_VALU_TFS = 78.6      # 256 CU x 64 lanes x 2 flop x 2.4 GHz, FP64 FMA at full rate
 PEAK_F16_MFMA_TFS = 2500.0     # dense FP16 / BF16 matrix peak
+# the single-image fused kernels: one block per tile, or strips of tiles
+FUSED_KERNELS = ("k_fused_mfma", "k_fused_strip")
 
 
 def log(msg):
@@ -75,7 +77,7 @@ def kernel_roofline(name, H, Wd, W, P, esize, ms_per_launch, stack="f32"):
     stack bytes: esize per pixel and plane for each write or read."""
     px = H * Wd
     taps = 2 * W + 1
-    if name == "k_fused_mfma":
+    if name in FUSED_KERNELS:
         flops = 2.0 * 2.0 * taps * P * px
         issued = fused_mfma_count(H, Wd, W, P, stack) * 16 * 16 * 32 * 2.0
         return {"bound": "mfma", "achieved": flops / ms_per_launch / 1e9, "peak": PEAK_F16_MFMA_TFS,
@@ -125,7 +127,8 @@ def measured_traffic(kernel, stack_tag, profile_name, counters=None):
     if counters is not None:
         counters.update(rec.get("sq", {}))
     base = {"k_hpass_combine": "k_hpass<", "k_hpass": "k_hpass<", "k_vpass": "k_vpass<",
-            "k_stack_build": "k_stack_build<", "k_combine": "k_combine<", "k_fused_mfma": "k_fused_mfma<"}[kernel]
+            "k_stack_build": "k_stack_build<", "k_combine": "k_combine<", "k_fused_mfma": "k_fused_mfma<",
+            "k_fused_strip": "k_fused_strip<"}[kernel]
     for name, v in rec["kernels"].items():
         if name.startswith(base + stack_tag) and (kernel != "k_hpass_combine" or name.endswith("true>")) \
                 and (kernel != "k_hpass" or name.endswith("false>")):
@@ -634,7 +637,7 @@ def main():
         prof_name = f"forward_{H}_s{ss:g}_n{n}_{stack}"
         sq = {}
         roof["traffic"] = measured_traffic(dom, {"f32": "StF32", "f16": "MmaF16", "bf16": "MmaBF16"}[stack]
-                                           if dom == "k_fused_mfma" else {"f32": "StF32", "f16": "StF16",
+                                           if dom in FUSED_KERNELS else {"f32": "StF32", "f16": "StF16",
                                                                           "bf16": "StBF16"}[stack], prof_name, sq)
         roof["traffic_source"] = f"profiles/{prof_name}.md"
         roof["avg_ms"] = kernels[dom]["avg_ms"]
@@ -681,7 +684,7 @@ def main():
         sys.exit(2)
     head_stack, head = max(cands, key=lambda c: c[1]["value"])
     path = ("fused matrix-core kernel: planes in registers, both passes as banded Toeplitz MFMA "
-            "(FP16 x FP16, FP32 accumulation), combine folded in" if head["roofline"]["kernel"] == "k_fused_mfma"
+            "(FP16 x FP16, FP32 accumulation), combine folded in" if head["roofline"]["kernel"] in FUSED_KERNELS
             else "build | column pass | row pass + combine, FP64 accumulation")
     result = {
         "metric": METRIC, "value": head["value"], "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,

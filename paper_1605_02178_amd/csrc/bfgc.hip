@@ -334,9 +334,60 @@ static int resident_blocks(const void *kernel, int *cache) {
     return *cache;
 }
 
+// Strip length of k_fused_strip (one block per CU): the longest strip among
+// those that give the fewest tile rounds, a round being one tile on every CU
+// (ceil(strips / CUs) strips per CU, of at most L tiles each).
+static int strip_length(int tiles_x, int tiles_y) {
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    cus = std::max(cus, 1);
+    long long best = LLONG_MAX;
+    int len = 1;
+    for (int L = 1; L <= tiles_y; ++L) {
+        const long long strips = (long long)tiles_x * ((tiles_y + L - 1) / L);
+        const long long rounds = (strips + cus - 1) / cus * L;
+        if (rounds <= best) {
+            best = rounds;
+            len = L;
+        }
+    }
+    return len;
+}
+
+// Whether a single-image fused geometry runs on strips (k_fused_strip): the
+// FP16 64-row tiles on 16 waves whose registers leave room for the prefetch.
+template <class M, int Q, int NW, int TR>
+__host__ __device__ constexpr bool fused_strips() { return M::kHalfPlanes && NW == 16 && TR == 64 && Q <= 4; }
+
+template <class M, int Q, int TC, int QA, int NW, int TR>
+static bf_status launch_fused_tiles(const float *f, float *out, int H, int Wd, int ld, const FusedConsts &C, int W,
+                                    int N, float mu, char *ws, hipStream_t stream);
+
 template <class M, int Q, int TC, int QA, int NW = 8, int TR = kFusedRows>
 static bf_status launch_fused_q(const float *f, float *out, int H, int Wd, int ld, const FusedConsts &C, int W,
                                 int N, float mu, char *ws, hipStream_t stream) {
+    if constexpr (fused_strips<M, Q, NW, TR>()) {
+        if (W >= H || W >= Wd || (long long)H * ld >= (1LL << 29))
+            return launch_fused_tiles<M, Q, TC, QA, NW, TR>(f, out, H, Wd, ld, C, W, N, mu, ws, stream);
+        const int tiles_x = (Wd + TC - 1) / TC, tiles_y = (H + TR - 1) / TR;
+        const long long tiles = (long long)tiles_x * tiles_y;
+        if (tiles > INT_MAX / 16) return fail(BF_ERR_UNSUPPORTED, "fused path: too many tiles");
+        const int len = strip_length(tiles_x, tiles_y);
+        const int grid = tiles_x * ((tiles_y + len - 1) / len);
+        note_range_words(ws, (long long)NW * tiles);
+        ProfScope prof_("k_fused_strip", stream);
+        hipLaunchKernelGGL((k_fused_strip<M, Q, TC, QA>), dim3(grid), dim3(1024), 0, stream, f, out, H, Wd, ld, C, W,
+                           N, mu, M::kPrescale, (unsigned *)(ws + kFlagBytes), tiles_x, tiles_y, len);
+        return check_launch("k_fused_strip");
+    } else {
+        return launch_fused_tiles<M, Q, TC, QA, NW, TR>(f, out, H, Wd, ld, C, W, N, mu, ws, stream);
+    }
+}
+
+template <class M, int Q, int TC, int QA, int NW, int TR>
+static bf_status launch_fused_tiles(const float *f, float *out, int H, int Wd, int ld, const FusedConsts &C, int W,
+                                    int N, float mu, char *ws, hipStream_t stream) {
     static int resident = 0;
     const void *kernel = (const void *)k_fused_mfma<M, Q, TC, QA, NW, TR>;
     const int tiles_x = (Wd + TC - 1) / TC;

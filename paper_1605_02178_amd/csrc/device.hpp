@@ -805,6 +805,23 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// The lane index, made where it is used: the compiler cannot hoist it out of
+// a loop and hold it in a register across the loop.
+__device__ __forceinline__ int fresh_lane_id() {
+    int l;
+    asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(l));
+    return l;
+}
+
+// Block barrier for LDS traffic only: the fences are limited to the local
+// address space, so outstanding global loads (a prefetch) stay in flight
+// across it; __syncthreads would wait for them as well.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Rows: one wave per block owns 64 rows; 64 x 32 tiles of the line are staged
 // through LDS (coalesced loads and stores, row pitch 33 so a lane walking its
 // row hits its own bank), and each lane runs the recursion along its row. The
@@ -1621,7 +1638,7 @@ struct FusedConsts {
 __device__ __forceinline__ void report_range(bool bad, unsigned *flag, unsigned *slot) {
     if (slot) {
         const bool any = __any(bad);
-        if ((threadIdx.x & 63) == 0) slot[threadIdx.x >> 6] = any ? BF_DEVFLAG_RANGE : 0u;
+        if ((threadIdx.x & 63) == 0) slot[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)] = any ? BF_DEVFLAG_RANGE : 0u;
     } else if (flag && __any(bad) && (threadIdx.x & 63) == __ffsll((unsigned long long)__ballot(bad)) - 1) {
         atomicOr(flag, BF_DEVFLAG_RANGE);
     }
@@ -1683,7 +1700,9 @@ struct FusedTile {
     // halo columns the row pass reads: column blocks up to kNCB - 1 from
     // their 32-column chunk base, QB + 1 chunks each
     static constexpr int kNCW = kNCB + 2 * QB;
-    static constexpr int kPitch = 16 * NW + 12;  // LDS row pitch (elements): 6 words mod 32
+    // LDS row pitch (elements): the 16 kNCW columns the column waves write,
+    // rounded up to 6 words mod 32
+    static constexpr int kPitch = 2 * (8 * kNCW + ((6 - 8 * kNCW) % 32 + 32) % 32);
     static constexpr int kYElems = TR * kPitch;
     static constexpr int kSlots = NW;            // range words per tile (one per wave)
     // LDS buffers of the column-pass result: with four, two planes per
@@ -1803,6 +1822,21 @@ struct FusedTile {
         }
     }
 
+    // The lane's output pixels alone (Raw::c, the same values load() gives),
+    // by 32-bit byte offsets: H ld < 2^29.
+    // ln: the lane index (threadIdx.x mod 64).
+    __device__ __forceinline__ void load_pixels(int r0, int c0, float (&c)[JB][4], int ln) const {
+        const char *base = (const char *)f;
+        const int cr = r0 + 16 * rb + 4 * (ln >> 4);
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+            const int col = min(c0 + 16 * (jc0 + b) + (ln & 15), Wd - 1);
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                c[b][v] = *(const float *)(base + 4u * (unsigned)(min(cr + v, H - 1) * ld + col));
+        }
+    }
+
     // Range check on the lane's own output pixels: every pixel of the image
     // is the output of exactly one lane of one tile.
     __device__ __forceinline__ void check_range(const Raw &R, unsigned *__restrict__ flag,
@@ -1815,6 +1849,46 @@ struct FusedTile {
         report_range(bad, flag, slot);
     }
 
+    // Column-pass A operand state of one centring: s and the running 2^K H_n
+    // for the lane's 8Q halo values (one scale 2^K for every plane keeps FP16
+    // planes normal: it cancels in P/Q), with 2^K e^{-nu s^2/2} =
+    // 2^{e2 s^2 + k2}. FP32 state (BF16), rounded once per plane; or (FP16,
+    // kHalfPlanes) s and H_n held in FP16 and H_{n+1} = H_n s as packed FP16
+    // products, which halves the state and needs no conversion per plane.
+    // There H_0 is taken at the FP16 value of s too, so every plane is that of
+    // one halo value moved by about |f - t| 2^-12 (one FP16 ulp of s), plus one
+    // rounding per product; at 4096^2, sigma_s = 10, sigma_r = 30, N = 32 the
+    // error against the direct filter stays 0.11 max-abs, 98.7 dB PSNR (98.8
+    // with the FP32 recursion).
+    static constexpr bool kH16 = M::kHalfPlanes;
+    struct State {
+        float sv[kH16 ? 1 : Q][8], hv[kH16 ? 1 : Q][8];
+        V sv16[kH16 ? Q : 1], hv16[kH16 ? Q : 1];
+    };
+    static __device__ __forceinline__ float h0_of(float s, const FusedCentre &C) {
+        return __builtin_amdgcn_exp2f(fmaf(C.e2 * s, s, C.k2));                  // 2^K H_0
+    }
+    // FP16 s of one halo value f (eq. 17).
+    static __device__ __forceinline__ E s16_of(float f, const FusedCentre &C) { return M::cvt(fmaf(f, C.sb, C.ob)); }
+
+    // State from the halo values h (the lane's Raw::h).
+    __device__ __forceinline__ void build_state(const float (&h)[Q][8], const FusedCentre &C, State &S) const {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                if constexpr (kH16) {
+                    const E s16 = s16_of(h[q][jj], C);
+                    S.sv16[q][jj] = s16;
+                    S.hv16[q][jj] = M::cvt(h0_of((float)s16, C));
+                } else {
+                    const float s = fmaf(h[q][jj], C.sb, C.ob);                  // eq. (17)
+                    S.sv[q][jj] = s;
+                    S.hv[q][jj] = h0_of(s, C);
+                }
+            }
+        }
+    }
     // Filters the N+2 planes of one centring (coefficients bt[n], n = 0..N+1,
     // with bt[N+1] = 0) and leaves the lane's outputs (rows 16 rb + 4 lg + v,
     // columns 16 (jc0 + b) + li) in y.
@@ -1824,35 +1898,25 @@ struct FusedTile {
     // buffer the last row pass did not read and needs no barrier before it.
     __device__ __forceinline__ void filter(const Raw &R, const FusedCentre &C, const float *__restrict__ bt, int N,
                                            int base, float (&y)[JB][4]) {
+        State S;
+        build_state(R.h, C, S);
+        planes(S, R.c, C, bt, N, base, y, nullptr, nullptr, [](int) {});
+    }
+
+    // The plane loop of filter() on a built state (H advances; s is kept).
+    // cpx: the lane's output pixels (Raw::c), first read after the first
+    // barrier, where their range check goes to flag / slot (none if both are
+    // null). hook(k) runs at the start of each barrier phase k >= 1, all waves
+    // together (k uniform).
+    // kLateH (FP16 state): H_n is the MFMA operand in place and becomes
+    // H_{n+1} after the column pass's products (fewer registers; the same
+    // values), and cpx is first read after the first barrier.
+    template <bool kLateH = false, class Hook>
+    __device__ __forceinline__ void planes(State &S, const float (&cpx)[JB][4], const FusedCentre &C,
+                                           const float *__restrict__ bt, int N, int base, float (&y)[JB][4],
+                                           unsigned *__restrict__ flag, unsigned *__restrict__ slot, Hook &&hook) {
+        static_assert(!kLateH || kH16, "in-place operand: FP16 plane state only");
         const int P = N + 2;
-        // Column-pass A operand state: s and the running 2^K H_n (one scale
-        // 2^K for every plane keeps FP16 planes normal: it cancels in P/Q),
-        // with 2^K e^{-nu s^2/2} = 2^{e2 s^2 + k2}. FP32 state (BF16), rounded
-        // once per plane; or (FP16, kHalfPlanes) s and H_n held in FP16 and
-        // H_{n+1} = H_n s as packed FP16 products, which halves the state and
-        // needs no conversion per plane. The extra rounding is one FP16 ulp of
-        // s (the same for every plane of a pixel, i.e. its value moves by
-        // about |f - t| 2^-12) and one rounding per product; at 4096^2,
-        // sigma_s = 10, sigma_r = 30, N = 32 the error against the direct filter
-        // stays 0.11 max-abs, 98.7 dB PSNR (98.8 with the FP32 recursion).
-        constexpr bool kH16 = M::kHalfPlanes;
-        float sv[kH16 ? 1 : Q][8], hv[kH16 ? 1 : Q][8];
-        V sv16[kH16 ? Q : 1], hv16[kH16 ? Q : 1];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-#pragma unroll
-            for (int jj = 0; jj < 8; ++jj) {
-                const float s = fmaf(R.h[q][jj], C.sb, C.ob);                     // eq. (17)
-                const float h0 = __builtin_amdgcn_exp2f(fmaf(C.e2 * s, s, C.k2)); // 2^K H_0
-                if constexpr (kH16) {
-                    sv16[q][jj] = M::cvt(s);
-                    hv16[q][jj] = M::cvt(h0);
-                } else {
-                    sv[q][jj] = s;
-                    hv[q][jj] = h0;
-                }
-            }
-        }
 
         // With u_n = s^n Hbar_n the sums are accumulated as
         //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
@@ -1860,35 +1924,44 @@ struct FusedTile {
         // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
         // up to terms 2^-64 smaller, and Q moves by as little. (Where b_0 2^-64
         // Hbar_1 underflows, P/Q lies far below FP32 resolution: the pixel's own
-        // term keeps Q >= w_0 b_0 2^K.)
+        // term keeps Q >= w_0 b_0 2^K.) Set in first().
         float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4];
-#pragma unroll
-        for (int b = 0; b < JB; ++b) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const float s = fmaf(R.c[b][v], C.sc, C.oc);
-                sc[b][v] = s != 0.0f ? s : 0x1p-64f;
-                pw[b][v] = sc[b][v];
-                Ps[b][v] = 0.0f;
-                Qa[b][v] = 0.0f;
-            }
-        }
 
-        // Column pass of plane n into ybuf[n & 1]; advances H to plane n+1.
+        // Column pass of plane n into its LDS buffer; advances H to plane n+1.
         // Waves past kNCW hold no halo columns the row pass reads.
         auto column_pass = [&](int n) {
             if (kNCW < NW && wave >= kNCW) return;
+            if constexpr (kLateH) {
+                // H_n as the operand in place, H_{n+1} after the products
+                E *yb = ybuf + ((n + base) & (kBufs - 1)) * kYElems;
+                __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+                for (int j = 0; j < kNRB; ++j) {
+                    const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
+                    mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int q = j / 2; q <= qlast; ++q) acc = M::mma(S.hv16[q], tf[2 * q - j + 1], acc);
+                    typename M::V4 o;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
+                    *(typename M::V4 *)(yb + (16 * j + li) * kPitch + 16 * wave + 4 * lg) = o;
+                }
+                __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+                for (int q = 0; q < Q; ++q) S.hv16[q] = S.hv16[q] * S.sv16[q];      // H_{n+1} = H_n s
+                return;
+            }
             V a[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if constexpr (kH16) {
-                    a[q] = hv16[q];
-                    hv16[q] = hv16[q] * sv16[q];                          // H_{n+1} = H_n s
+                    a[q] = S.hv16[q];
+                    S.hv16[q] = S.hv16[q] * S.sv16[q];                        // H_{n+1} = H_n s
                 } else {
 #pragma unroll
                     for (int jj = 0; jj < 8; ++jj) {
-                        a[q][jj] = M::cvt(hv[q][jj]);
-                        hv[q][jj] *= sv[q][jj];                           // H_{n+1} = H_n s
+                        a[q][jj] = M::cvt(S.hv[q][jj]);
+                        S.hv[q][jj] *= S.sv[q][jj];                           // H_{n+1} = H_n s
                     }
                 }
             }
@@ -1951,8 +2024,29 @@ struct FusedTile {
             }
         };
 
+        // The sums' start and the range check of the lane's output pixels
+        // (every pixel of the image is the output of exactly one lane of one
+        // tile): before the loop, or (kLateH) in first(), so that the pixels'
+        // loads may still be in flight during the first barrier phase.
+        auto start = [&]() {
+            bool bad = false;
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    bad |= !(cpx[b][v] >= 0.0f && cpx[b][v] <= 255.0f);
+                    const float s = fmaf(cpx[b][v], C.sc, C.oc);
+                    sc[b][v] = s != 0.0f ? s : 0x1p-64f;
+                    pw[b][v] = sc[b][v];
+                    Ps[b][v] = 0.0f;
+                }
+            }
+            report_range(bad, flag, slot);
+        };
+        if constexpr (!kLateH) start();
         // Eq. 9's first term (plane 0).
         auto first = [&](const mf_f4 (&z)[JB]) {
+            if constexpr (kLateH) start();
             const float b0 = bt[0];
 #pragma unroll
             for (int b = 0; b < JB; ++b)
@@ -1966,8 +2060,9 @@ struct FusedTile {
             // barriers of a 16-wave block.
             column_pass(0);
             column_pass(1);
-            __syncthreads();
+            lds_barrier();
             for (int k = 1; 2 * k - 2 < P; ++k) {
+                hook(k);
                 if (2 * k < P) column_pass(2 * k);
                 if (2 * k + 1 < P) column_pass(2 * k + 1);
                 {
@@ -1981,26 +2076,28 @@ struct FusedTile {
                     row_pass(2 * k - 1, z);
                     combine(2 * k - 1, z);
                 }
-                if (2 * k < P) __syncthreads();
+                if (2 * k < P) lds_barrier();
             }
         } else {
             // Software pipeline: the row pass of plane n-1 and the column pass of
             // plane n sit between the same two barriers (different LDS buffers).
             column_pass(0);
-            __syncthreads();
+            lds_barrier();
+            hook(1);
             column_pass(1);
             {
                 mf_f4 z[JB];
                 row_pass(0, z);
                 first(z);
             }
-            __syncthreads();
+            lds_barrier();
             for (int n = 2; n < P; ++n) {
+                hook(n);
                 column_pass(n);
                 mf_f4 z[JB];
                 row_pass(n - 1, z);
                 combine(n - 1, z);
-                __syncthreads();
+                lds_barrier();
             }
             {
                 mf_f4 z[JB];
@@ -2032,10 +2129,23 @@ struct FusedTile {
             }
         }
     }
+    // store() by 32-bit byte offsets: H ld < 2^29. ln: the lane index.
+    __device__ __forceinline__ void store32(int r0, int c0, const float (&y)[JB][4], int ln) const {
+        char *base = (char *)out;
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+            const int c = c0 + 16 * (jc0 + b) + (ln & 15);
+            if (c >= Wd) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = r0 + 16 * rb + 4 * (ln >> 4) + v;
+                if (r < H) *(float *)(base + 4u * (unsigned)(r * ld + c)) = y[b][v];
+            }
+        }
+    }
 
     // The filter of eqs. (6)-(10) centred at t_c with half range t_h.
-    __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
-                                        unsigned *__restrict__ slot, int base = 0) {
+    __device__ __forceinline__ FusedCentre plain_centre() const {
         FusedCentre C;
         C.sb = C.sc = (float)(1.0 / kTh);
         C.ob = C.oc = (float)(-kTc / kTh);
@@ -2043,9 +2153,15 @@ struct FusedTile {
         C.k2 = __log2f(prescale);
         C.ys = (float)kTh;
         C.yo = (float)kTc;
-        check_range(R, flag, slot);
+        return C;
+    }
+    __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
+                                        unsigned *__restrict__ slot, int base = 0) {
+        const FusedCentre C = plain_centre();
+        State S;
+        build_state(R.h, C, S);
         float y[JB][4];
-        filter(R, C, bt, N, base, y);
+        planes(S, R.c, C, bt, N, base, y, flag, slot, [](int) {});
         store(r0, c0, y);
     }
 
@@ -2152,6 +2268,153 @@ __global__ __launch_bounds__(NW * 64) void k_fused_mfma(const float *__restrict_
             if (tn < tiles) tile.load((tn / tiles_x) * kFusedRows, (tn % tiles_x) * TC, next);
             tile.run(r0, c0, cur, nullptr, slots + kFusedSlots * t, base);
             base += N + 2;
+        }
+    }
+}
+
+// Single-image fused kernel on vertical strips of tiles (FP16 plane state,
+// 64-row tiles on 16 waves, four LDS buffers): block b filters up to
+// strip_len tiles of one tile column, top to bottom. Consecutive tiles share
+// 2W halo rows, and with 64-row tiles and 32-row chunks the next tile's
+// chunks 0..Q-3 are this tile's chunks 2..Q-1: each lane keeps their s (FP16)
+// in its registers and their H_0 in its own LDS slots (written when the tile
+// starts, before H advances), and loads only the two new chunks, 64 halo rows.
+// Those loads go out in eight slices of two values during the plane loop,
+// each one barrier phase before its s is written to the lane's LDS slots (no
+// other lane reads any of them); the loop's barriers do not wait for them.
+// (Where those rows reach the image's last row, the loads wait for the
+// tile's end.)
+// When the next tile starts the lane reads them back and takes H_0 of the
+// new s: the state build_state gives for the same halo. Its output pixels
+// are loaded then and first read after its first barrier. The strip's first
+// tile loads its whole halo, before the tap setup. Images with W < H and
+// W < Wd (one reflection at the edges) and H ld < 2^29 (32-bit byte offsets)
+// only.
+template <class M, int Q, int TC, int QA>
+__global__ __launch_bounds__(1024) void k_fused_strip(const float *__restrict__ f, float *__restrict__ out, int H,
+                                                      int Wd, int ld, FusedConsts C, int W, int N, float mu,
+                                                      float prescale, unsigned *__restrict__ slots, int tiles_x,
+                                                      int tiles_y, int strip_len) {
+    typedef typename M::E E;
+    typedef typename M::V V;
+    typedef typename M::E E2 __attribute__((ext_vector_type(2)));
+    typedef FusedTile<M, Q, TC, QA, 16, kFusedRows> T;
+    static_assert(M::kHalfPlanes && T::kBufs == 4 && Q >= 3, "FP16 plane state, 64-row tiles on 16 waves");
+    constexpr int kLanes = T::kNCW * 64;         // column-wave lanes
+    constexpr int kSlices = 8;                   // two values each: new chunk sl / 4, rows 2 (sl % 4), +1
+    constexpr int kKept = Q - 2;                 // chunks the next tile takes over
+    __shared__ __align__(16) E ybuf[T::kBufs * T::kYElems];
+    __shared__ E tab[fused_tab_len(Q)];
+    __shared__ __align__(16) E2 s_new[kSlices * kLanes];
+    __shared__ __align__(16) V h_kept[kKept * kLanes];
+    T tile(f, out, H, Wd, ld, W, N, mu, prescale, C.b, ybuf);
+    tile.one_ref = true;                         // W < H and W < Wd here
+    const int cx = blockIdx.x % tiles_x;
+    const int ty0 = (blockIdx.x / tiles_x) * strip_len;
+    const int ty1 = min(ty0 + strip_len, tiles_y);
+    const int c0 = cx * TC;
+    const bool colw = tile.wave < T::kNCW;       // uniform
+    typename T::Raw R;
+    tile.load(ty0 * kFusedRows, c0, R);
+    tile.setup(C.taps, tab);
+    const FusedCentre Cn = tile.plain_centre();
+    typename T::State S;
+    tile.build_state(R.h, Cn, S);
+    int base = 0;
+    for (int ty = ty0; ty < ty1; ++ty) {
+        const int r0 = ty * kFusedRows;
+        const bool more = ty + 1 < ty1;
+        // The lane's indices, from a copy of threadIdx.x the compiler cannot
+        // see through: they are made again for each tile instead of being
+        // held in registers across the plane loop.
+        unsigned tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63;
+        const int lg = lane >> 4;
+        if (more && colw) {
+#pragma unroll
+            for (int q = 0; q < kKept; ++q) h_kept[q * kLanes + tid] = S.hv16[q + 2];
+        }
+        // halo column of a lane (lane index l)
+        auto col_of = [&](int l) { return halo_index(c0 - W + 16 * tile.wave + (l & 15), Wd, W, true); };
+        // first new halo row of the next tile; all its new rows inside the image or not (uniform)
+        const int rb0 = r0 + kFusedRows - W + 32 * (Q - 2);
+        const bool inside = rb0 + 63 < H;
+        const unsigned lane_off = 4u * (unsigned)(8 * lg * ld + col_of(lane));
+        float pf[2];
+        int issued = 0, written = 0;
+        auto load_slice = [&](int sl) {
+            const int r = rb0 + 32 * (sl >> 2) + 2 * (sl & 3);
+            if (inside) {
+                const char *row = (const char *)f + 4u * (unsigned)(r * ld);
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+                    pf[jj] = *(const float *)(row + 4u * (unsigned)(jj * ld) + lane_off);
+            } else {
+                const int l = fresh_lane_id();
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+                    pf[jj] = *(const float *)((const char *)f +
+                                              4u * (unsigned)(halo_index(r + 8 * (l >> 4) + jj, H, W, true) * ld +
+                                                              col_of(l)));
+            }
+        };
+        auto write_slice = [&](int sl) {
+            E2 o;
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) o[jj] = T::s16_of(pf[jj], Cn);
+            s_new[sl * kLanes + 64 * tile.wave + fresh_lane_id()] = o;
+        };
+        // (where the next tile's new rows reach the image's last row, all the
+        // loads wait for the tile's end)
+        auto hook = [&](int k) {
+            if (!more || !colw || !inside) return;
+            if (issued > written) {
+                write_slice(written);
+                ++written;
+            }
+            if (k >= 2 && issued < kSlices) {
+                load_slice(issued);
+                ++issued;
+            }
+        };
+        float y[T::JB][4];
+        tile.template planes<true>(S, R.c, Cn, tile.bt, N, base, y, nullptr, slots + T::kSlots * (ty * tiles_x + cx),
+                                   hook);
+        {
+            unsigned t2 = threadIdx.x;
+            asm volatile("" : "+v"(t2));
+            tile.store32(r0, c0, y, t2 & 63);
+        }
+        base += N + 2;
+        if (more) {
+            if (colw) {
+                for (; written < kSlices; ++written) {
+                    if (issued == written) {
+                        load_slice(issued);
+                        ++issued;
+                    }
+                    write_slice(written);
+                }
+                unsigned t3 = threadIdx.x;
+                asm volatile("" : "+v"(t3));
+#pragma unroll
+                for (int q = 0; q < kKept; ++q) {
+                    S.sv16[q] = S.sv16[q + 2];
+                    S.hv16[q] = h_kept[q * kLanes + t3];
+                }
+#pragma unroll
+                for (int sl = 0; sl < kSlices; ++sl) {
+                    const E2 v = s_new[sl * kLanes + t3];
+#pragma unroll
+                    for (int jj = 0; jj < 2; ++jj) {
+                        const int q = kKept + (sl >> 2), e = 2 * (sl & 3) + jj;
+                        S.sv16[q][e] = v[jj];
+                        S.hv16[q][e] = M::cvt(T::h0_of((float)v[jj], Cn));
+                    }
+                }
+            }
+            tile.load_pixels(r0 + kFusedRows, c0, R.c, lane);
         }
     }
 }
@@ -2371,8 +2634,9 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
         }
     }
     // s (eq. 17 on the guide) by one fma, 2^K e^{-mu s^2/2} by one exp2. FP16
-    // (kHalfPlanes, as in FusedTile::filter): s, ft and the running A_n held
-    // in FP16, A_{n+1} = A_n s and B_n = A_n ft as packed FP16 products.
+    // (kHalfPlanes, as in FusedTile::State): s, ft and the running A_n held
+    // in FP16, A_0 taken at the FP16 s, A_{n+1} = A_n s and B_n = A_n ft as
+    // packed FP16 products.
     constexpr bool kH16 = M::kHalfPlanes;
     const float e2 = -0.5f * mu * 1.4426950408889634f, k2 = __log2f(prescale);
     float sv[kH16 ? 1 : Q][8], hv[kH16 ? 1 : Q][8], fv[kH16 ? 1 : Q][8];
@@ -2382,13 +2646,14 @@ __device__ __forceinline__ void fused_joint_tile(const float *__restrict__ g, co
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
             const float s = fmaf(gx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
-            const float h0 = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));
             const float ft = fmaf(vx[q][jj], (float)(1.0 / kTh), (float)(-kTc / kTh));
             if constexpr (kH16) {
                 sv16[q][jj] = M::cvt(s);
-                hv16[q][jj] = M::cvt(h0);
+                const float sr = (float)sv16[q][jj];
+                hv16[q][jj] = M::cvt(__builtin_amdgcn_exp2f(fmaf(e2 * sr, sr, k2)));
                 fv16[q][jj] = M::cvt(ft);
             } else {
+                const float h0 = __builtin_amdgcn_exp2f(fmaf(e2 * s, s, k2));
                 sv[q][jj] = s;
                 hv[q][jj] = h0;
                 fv[q][jj] = ft;

@@ -34,7 +34,8 @@ def test_tile_geometry(NW, TR, TC, Q, W):
     WPR = NW // NRB
     JB = NCB // WPR
     NCW = NCB + 2 * QB
-    pitch = 16 * NW + 12
+    pitch = 2 * (8 * NCW + (6 - 8 * NCW) % 32)
+    assert pitch >= 16 * NCW and (pitch // 2) % 32 == 6 and pitch % 2 == 0
     assert QA in (QB - 1, QB)
     assert JB in (1, 2) and NCB % WPR == 0
     assert NCW <= NW

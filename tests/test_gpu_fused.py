@@ -230,6 +230,68 @@ def test_fused_f16_wide_radius_sampled(torch_cuda, shape, seed):
         assert err <= BOUND[("f16", 30.0, 32)]
 
 
+# Images with many more 64-row tiles than CUs: the single-image FP16 kernel
+# then runs strips of several tiles per block (each tile after a strip's
+# first reuses two halo chunks of the tile above and loads the other two
+# during that tile's planes). (shape, sigma_s): Q = 4 (W = 30) and Q = 3
+# (W = 12), ragged in both directions.
+STRIP_SHAPES = [((4096, 2048), 10.0), ((4000, 2100), 10.0), ((4030, 2000), 4.0)]
+
+
+@pytest.mark.parametrize("shape,sigma_s", STRIP_SHAPES)
+def test_fused_strips_equal_one_block_per_tile_bitwise(torch_cuda, shape, sigma_s):
+    """The strip kernel against the batched fused kernel (one block per tile,
+    every tile's halo loaded whole) on the same image: bit for bit, also with
+    a row stride; the oracle on crops at the first and last tile rows and
+    across a strip seam."""
+    import paper_1605_02178_amd as bf
+    from oracle import native as C
+    from synth import edge_rich
+    torch = torch_cuda
+    H, Wd = shape
+    f64 = edge_rich(H, Wd, seed=H + Wd).astype(np.float32).astype(np.float64)
+    f = _gpu(torch, f64)
+    y = bf.gc_filter(f, sigma_s, 30.0, 30, stack_dtype="f16", tile_config=bf.TILE_FUSED)
+    outs, status = bf.gc_filter_batched([f], [sigma_s], [30.0], [30], stack_dtype="f16", graph=False,
+                                        tile_config=bf.TILE_FUSED)
+    assert status == [0]
+    diff = float((outs[0] - y).abs().max())
+    _log(f"strips {shape} sigma_s={sigma_s}: against one block per tile {diff:.3e}")
+    assert torch.equal(outs[0], y)
+    big = torch.full((H, Wd + 40), -1.0, device="cuda:0")
+    big[:, :Wd] = f
+    out = torch.full((H, Wd + 40), -5.0, device="cuda:0")
+    bf.gc_filter(big[:, :Wd], sigma_s, 30.0, 30, stack_dtype="f16", tile_config=bf.TILE_FUSED, out=out[:, :Wd])
+    assert torch.equal(out[:, :Wd], y)
+    assert bool((out[:, Wd:] == -5.0).all())
+    yn = _np(y)
+    for reg in ((0, 40, 0, 60), (H - 40, H, Wd - 60, Wd), (H // 2 - 70, H // 2 + 70, 100, 140),
+                (1000, 1100, Wd // 2 - 20, Wd // 2 + 20)):
+        ref = C.gcf(f64, sigma_s, 30.0, 30, region=reg)
+        err = np.abs(yn[reg[0]:reg[1], reg[2]:reg[3]] - ref).max()
+        _log(f"strips {shape} sigma_s={sigma_s} crop {reg}: {err:.3e}")
+        assert err <= BOUND[("f16", 30.0, 30)]
+
+
+def test_fused_strips_range_flag_in_later_tiles(torch_cuda):
+    """Out-of-range pixels in the second and the last tile of a strip raise
+    the range flag; a clean image after them clears it."""
+    import paper_1605_02178_amd as bf
+    from synth import ramp_rectangles
+    torch = torch_cuda
+    f = _gpu(torch, ramp_rectangles(4096, 1024, seed=6))
+    ws = torch.empty(bf.workspace_bytes(4096, 1024, 10.0, 30, "f16"), dtype=torch.uint8, device="cuda:0")
+    bf.gc_filter(f, 10.0, 30.0, 30, stack_dtype="f16", workspace=ws, tile_config=bf.TILE_FUSED)
+    assert bf.read_flags(ws) == 0
+    for r, c in ((70, 5), (4095, 1023), (2100, 600)):
+        g = f.clone()
+        g[r, c] = -0.5
+        bf.gc_filter(g, 10.0, 30.0, 30, stack_dtype="f16", workspace=ws, tile_config=bf.TILE_FUSED)
+        assert bf.read_flags(ws) & bf.DEVFLAG_RANGE, (r, c)
+    bf.gc_filter(f, 10.0, 30.0, 30, stack_dtype="f16", workspace=ws, tile_config=bf.TILE_FUSED)
+    assert bf.read_flags(ws) == 0
+
+
 def test_fused_centre_value_pixels(torch_cuda):
     """Pixels equal to t_c = 127.5 have s = 0 (up to the rounding of s), where
     P = (s P)/s would be 0/0; the kernel takes s = 2^-64 there: a constant
