@@ -2309,8 +2309,13 @@ __global__ __launch_bounds__(1024) void k_fused_strip(const float *__restrict__ 
     __shared__ __align__(16) V h_kept[kKept * kLanes];
     T tile(f, out, H, Wd, ld, W, N, mu, prescale, C.b, ybuf);
     tile.one_ref = true;                         // W < H and W < Wd here
-    const int cx = blockIdx.x % tiles_x;
-    const int ty0 = (blockIdx.x / tiles_x) * strip_len;
+    // Strip order: blocks go to the 8 XCDs in turn (block b to XCD b mod 8);
+    // each XCD takes a contiguous range of strips in row-major order, so
+    // strips side by side, which share 2W halo columns, run in one L2.
+    const int G = gridDim.x, gq = G / 8, gr = G % 8, xcd = blockIdx.x % 8;
+    const int strip = xcd * gq + min(xcd, gr) + blockIdx.x / 8;
+    const int cx = strip % tiles_x;
+    const int ty0 = (strip / tiles_x) * strip_len;
     const int ty1 = min(ty0 + strip_len, tiles_y);
     const int c0 = cx * TC;
     const bool colw = tile.wave < T::kNCW;       // uniform

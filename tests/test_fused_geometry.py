@@ -98,3 +98,39 @@ def test_tile_geometry(NW, TR, TC, Q, W):
                         assert not tap(base + 32 * q + k - c)
     # column pass LDS writes: row 16 j + li, column 16 wave + 4 lg + v
     assert (16 * (NRB - 1) + 15) * pitch + 16 * (NCW - 1) + 4 * 3 + 3 < TR * pitch
+
+
+def _strip_length(tiles_x, tiles_y, cus):
+    # the launcher's choice: the longest strip among those with the fewest tile rounds
+    best, length = None, 1
+    for L in range(1, tiles_y + 1):
+        strips = tiles_x * -(-tiles_y // L)
+        rounds = -(-strips // cus) * L
+        if best is None or rounds <= best:
+            best, length = rounds, L
+    return length
+
+
+@pytest.mark.parametrize("H,Wd,cus", [(4096, 4096, 256), (4000, 2100, 256), (1100, 4200, 256), (64, 128, 256),
+                                      (4096, 4096, 304), (3000, 3000, 80), (700, 130, 7), (4096, 512, 256)])
+def test_strip_order_covers_every_tile_once(H, Wd, cus):
+    """Strips of the single-image FP16 kernel (64 x 128 tiles): the XCD-aware
+    order of blocks (block b to XCD b mod 8, each XCD a contiguous range of
+    strips in row-major order) gives every tile to exactly one block, and
+    each block's tiles form one column, top to bottom."""
+    tiles_x, tiles_y = -(-Wd // 128), -(-H // 64)
+    L = _strip_length(tiles_x, tiles_y, cus)
+    G = tiles_x * -(-tiles_y // L)
+    gq, gr = G // 8, G % 8
+    owner = {}
+    for b in range(G):
+        x = b % 8
+        strip = x * gq + min(x, gr) + b // 8
+        assert 0 <= strip < G
+        cx, ty0 = strip % tiles_x, (strip // tiles_x) * L
+        for ty in range(ty0, min(ty0 + L, tiles_y)):
+            assert (ty, cx) not in owner
+            owner[(ty, cx)] = b
+    assert len(owner) == tiles_x * tiles_y
+    if tiles_x * tiles_y > cus:
+        assert L >= 1 and -(-G // cus) * L <= -(-(tiles_x * tiles_y) // cus)
