@@ -1898,25 +1898,26 @@ struct FusedTile {
     // buffer the last row pass did not read and needs no barrier before it.
     __device__ __forceinline__ void filter(const Raw &R, const FusedCentre &C, const float *__restrict__ bt, int N,
                                            int base, float (&y)[JB][4]) {
-        State S;
-        build_state(R.h, C, S);
-        planes(S, R.c, C, bt, N, base, y, nullptr, nullptr, [](int) {});
-    }
-
-    // The plane loop of filter() on a built state (H advances; s is kept).
-    // cpx: the lane's output pixels (Raw::c), first read after the first
-    // barrier, where their range check goes to flag / slot (none if both are
-    // null). hook(k) runs at the start of each barrier phase k >= 1, all waves
-    // together (k uniform).
-    // kLateH (FP16 state): H_n is the MFMA operand in place and becomes
-    // H_{n+1} after the column pass's products (fewer registers; the same
-    // values), and cpx is first read after the first barrier.
-    template <bool kLateH = false, class Hook>
-    __device__ __forceinline__ void planes(State &S, const float (&cpx)[JB][4], const FusedCentre &C,
-                                           const float *__restrict__ bt, int N, int base, float (&y)[JB][4],
-                                           unsigned *__restrict__ flag, unsigned *__restrict__ slot, Hook &&hook) {
-        static_assert(!kLateH || kH16, "in-place operand: FP16 plane state only");
         const int P = N + 2;
+        // The column-pass A operand state of State, built as build_state does
+        // (local arrays: the other geometries keep fewer registers so).
+        float sv[kH16 ? 1 : Q][8], hv[kH16 ? 1 : Q][8];
+        V sv16[kH16 ? Q : 1], hv16[kH16 ? Q : 1];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+#pragma unroll
+            for (int jj = 0; jj < 8; ++jj) {
+                if constexpr (kH16) {
+                    const E s16 = s16_of(R.h[q][jj], C);
+                    sv16[q][jj] = s16;
+                    hv16[q][jj] = M::cvt(h0_of((float)s16, C));
+                } else {
+                    const float s = fmaf(R.h[q][jj], C.sb, C.ob);                 // eq. (17)
+                    sv[q][jj] = s;
+                    hv[q][jj] = h0_of(s, C);
+                }
+            }
+        }
 
         // With u_n = s^n Hbar_n the sums are accumulated as
         //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
@@ -1924,44 +1925,35 @@ struct FusedTile {
         // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
         // up to terms 2^-64 smaller, and Q moves by as little. (Where b_0 2^-64
         // Hbar_1 underflows, P/Q lies far below FP32 resolution: the pixel's own
-        // term keeps Q >= w_0 b_0 2^K.) Set in first().
+        // term keeps Q >= w_0 b_0 2^K.)
         float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4];
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float s = fmaf(R.c[b][v], C.sc, C.oc);
+                sc[b][v] = s != 0.0f ? s : 0x1p-64f;
+                pw[b][v] = sc[b][v];
+                Ps[b][v] = 0.0f;
+                Qa[b][v] = 0.0f;
+            }
+        }
 
         // Column pass of plane n into its LDS buffer; advances H to plane n+1.
         // Waves past kNCW hold no halo columns the row pass reads.
         auto column_pass = [&](int n) {
             if (kNCW < NW && wave >= kNCW) return;
-            if constexpr (kLateH) {
-                // H_n as the operand in place, H_{n+1} after the products
-                E *yb = ybuf + ((n + base) & (kBufs - 1)) * kYElems;
-                __builtin_amdgcn_s_setprio(1);
-#pragma unroll
-                for (int j = 0; j < kNRB; ++j) {
-                    const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
-                    mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int q = j / 2; q <= qlast; ++q) acc = M::mma(S.hv16[q], tf[2 * q - j + 1], acc);
-                    typename M::V4 o;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
-                    *(typename M::V4 *)(yb + (16 * j + li) * kPitch + 16 * wave + 4 * lg) = o;
-                }
-                __builtin_amdgcn_s_setprio(0);
-#pragma unroll
-                for (int q = 0; q < Q; ++q) S.hv16[q] = S.hv16[q] * S.sv16[q];      // H_{n+1} = H_n s
-                return;
-            }
             V a[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if constexpr (kH16) {
-                    a[q] = S.hv16[q];
-                    S.hv16[q] = S.hv16[q] * S.sv16[q];                        // H_{n+1} = H_n s
+                    a[q] = hv16[q];
+                    hv16[q] = hv16[q] * sv16[q];                          // H_{n+1} = H_n s
                 } else {
 #pragma unroll
                     for (int jj = 0; jj < 8; ++jj) {
-                        a[q][jj] = M::cvt(S.hv[q][jj]);
-                        S.hv[q][jj] *= S.sv[q][jj];                           // H_{n+1} = H_n s
+                        a[q][jj] = M::cvt(hv[q][jj]);
+                        hv[q][jj] *= sv[q][jj];                           // H_{n+1} = H_n s
                     }
                 }
             }
@@ -2024,29 +2016,8 @@ struct FusedTile {
             }
         };
 
-        // The sums' start and the range check of the lane's output pixels
-        // (every pixel of the image is the output of exactly one lane of one
-        // tile): before the loop, or (kLateH) in first(), so that the pixels'
-        // loads may still be in flight during the first barrier phase.
-        auto start = [&]() {
-            bool bad = false;
-#pragma unroll
-            for (int b = 0; b < JB; ++b) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    bad |= !(cpx[b][v] >= 0.0f && cpx[b][v] <= 255.0f);
-                    const float s = fmaf(cpx[b][v], C.sc, C.oc);
-                    sc[b][v] = s != 0.0f ? s : 0x1p-64f;
-                    pw[b][v] = sc[b][v];
-                    Ps[b][v] = 0.0f;
-                }
-            }
-            report_range(bad, flag, slot);
-        };
-        if constexpr (!kLateH) start();
         // Eq. 9's first term (plane 0).
         auto first = [&](const mf_f4 (&z)[JB]) {
-            if constexpr (kLateH) start();
             const float b0 = bt[0];
 #pragma unroll
             for (int b = 0; b < JB; ++b)
@@ -2062,7 +2033,6 @@ struct FusedTile {
             column_pass(1);
             lds_barrier();
             for (int k = 1; 2 * k - 2 < P; ++k) {
-                hook(k);
                 if (2 * k < P) column_pass(2 * k);
                 if (2 * k + 1 < P) column_pass(2 * k + 1);
                 {
@@ -2083,7 +2053,6 @@ struct FusedTile {
             // plane n sit between the same two barriers (different LDS buffers).
             column_pass(0);
             lds_barrier();
-            hook(1);
             column_pass(1);
             {
                 mf_f4 z[JB];
@@ -2092,7 +2061,6 @@ struct FusedTile {
             }
             lds_barrier();
             for (int n = 2; n < P; ++n) {
-                hook(n);
                 column_pass(n);
                 mf_f4 z[JB];
                 row_pass(n - 1, z);
@@ -2104,6 +2072,160 @@ struct FusedTile {
                 row_pass(P - 1, z);
                 combine(P - 1, z);
             }
+        }
+
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // a reduced-precision stack: the reciprocal's ulp is far below its error
+                const float ratio = Ps[b][v] * __frcp_rn(sc[b][v] * Qa[b][v]);
+                y[b][v] = C.yo + C.ys * ratio;                                   // eq. (10)
+            }
+        }
+    }
+
+    // The sums' start from the lane's output pixels cpx (s, the running s^n,
+    // Ps = 0), and their range check (every pixel of the image is the output
+    // of exactly one lane of one tile) to flag / slot.
+    __device__ __forceinline__ void start_sums(const float (&cpx)[JB][4], const FusedCentre &C, float (&sc)[JB][4],
+                                               float (&pw)[JB][4], float (&Ps)[JB][4], unsigned *__restrict__ flag,
+                                               unsigned *__restrict__ slot) const {
+        bool bad = false;
+#pragma unroll
+        for (int b = 0; b < JB; ++b) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                bad |= !(cpx[b][v] >= 0.0f && cpx[b][v] <= 255.0f);
+                const float s = fmaf(cpx[b][v], C.sc, C.oc);
+                sc[b][v] = s != 0.0f ? s : 0x1p-64f;
+                pw[b][v] = sc[b][v];
+                Ps[b][v] = 0.0f;
+            }
+        }
+        report_range(bad, flag, slot);
+    }
+
+    // filter() for the strip kernel (FP16 state, four LDS buffers), on a
+    // state S it keeps between tiles (H advances, s is kept), with three
+    // changes that leave every value as filter() has it: H_n is the MFMA
+    // operand in place and becomes H_{n+1} after the column pass's products
+    // (fewer registers); the lane's output pixels cpx are first read after
+    // the first barrier, where their range check goes to flag / slot; and
+    // hook(k) runs at the start of each barrier phase k >= 1, all waves
+    // together (k uniform). (A separate function: as one body with filter(),
+    // the other geometries lose registers.)
+    template <class Hook>
+    __device__ __forceinline__ void strip_planes(State &S, const float (&cpx)[JB][4], const FusedCentre &C,
+                                                 const float *__restrict__ bt, int N, int base, float (&y)[JB][4],
+                                                 unsigned *__restrict__ flag, unsigned *__restrict__ slot,
+                                                 Hook &&hook) {
+        static_assert(kH16 && kBufs == 4, "FP16 plane state, four LDS buffers");
+        const int P = N + 2;
+
+        // With u_n = s^n Hbar_n the sums are accumulated as
+        //   Q = sum_n b_n u_n,   Ps = sum_n b_{n-1} u_n = s P,
+        // so one product serves both, and P = Ps / s. Where s = 0 the sums take
+        // s = 2^-64 instead: Ps / s is then b_0 Hbar_1, the value of P at s = 0,
+        // up to terms 2^-64 smaller, and Q moves by as little. (Where b_0 2^-64
+        // Hbar_1 underflows, P/Q lies far below FP32 resolution: the pixel's own
+        // term keeps Q >= w_0 b_0 2^K.) Set in first().
+        float sc[JB][4], pw[JB][4], Ps[JB][4], Qa[JB][4];
+
+        // Column pass of plane n into its LDS buffer; advances H to plane n+1.
+        // Waves past kNCW hold no halo columns the row pass reads.
+        auto column_pass = [&](int n) {
+            if (kNCW < NW && wave >= kNCW) return;
+            E *yb = ybuf + ((n + base) & (kBufs - 1)) * kYElems;
+            __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+            for (int j = 0; j < kNRB; ++j) {
+                const int qlast = min(Q - 1, j / 2 + ((j & 1) ? QB : QA));
+                mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = j / 2; q <= qlast; ++q) acc = M::mma(S.hv16[q], tf[2 * q - j + 1], acc);
+                typename M::V4 o;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] = M::cvt(acc[v]);
+                *(typename M::V4 *)(yb + (16 * j + li) * kPitch + 16 * wave + 4 * lg) = o;
+            }
+            __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) S.hv16[q] = S.hv16[q] * S.sv16[q];          // H_{n+1} = H_n s
+        };
+        // Row pass of plane n from ybuf[n & 1]: the lane's filtered values z.
+        auto row_pass = [&](int n, mf_f4 (&z)[JB]) {
+            const E *src = ybuf + ((n + base) & (kBufs - 1)) * kYElems + (16 * rb + li) * kPitch + 8 * lg;
+            if constexpr (JB == 2) {
+                V ya[QB + 1];
+#pragma unroll
+                for (int q = 0; q <= QB; ++q) ya[q] = ld_frag<M>(src + 32 * (q + p));
+                mf_f4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int q = 0; q <= QA; ++q) acc0 = M::mma(ya[q], tf[2 * q + 1], acc0);
+#pragma unroll
+                for (int q = 0; q <= QB; ++q) acc1 = M::mma(ya[q], tf[2 * q], acc1);
+                z[0] = acc0;
+                z[JB - 1] = acc1;
+            } else {
+                // p is uniform: one branch per wave, no fragment selected per lane
+                src += 32 * (p >> 1);
+                mf_f4 acc = {0.f, 0.f, 0.f, 0.f};
+                if ((p & 1) == 0) {
+#pragma unroll
+                    for (int q = 0; q <= QA; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q + 1], acc);
+                } else {
+#pragma unroll
+                    for (int q = 0; q <= QB; ++q) acc = M::mma(ld_frag<M>(src + 32 * q), tf[2 * q], acc);
+                }
+                z[0] = acc;
+            }
+        };
+        // Eqs. 8-9 for plane n >= 1 (pw = s^n on entry).
+        auto combine = [&](int n, const mf_f4 (&z)[JB]) {
+            const float bp = bt[n - 1];
+            const float bq = bt[n];
+#pragma unroll
+            for (int b = 0; b < JB; ++b) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float u = pw[b][v] * z[b][v];
+                    Ps[b][v] = fmaf(bp, u, Ps[b][v]);
+                    Qa[b][v] = fmaf(bq, u, Qa[b][v]);
+                    pw[b][v] *= sc[b][v];
+                }
+            }
+        };
+
+        // Eq. 9's first term (plane 0).
+        auto first = [&](const mf_f4 (&z)[JB]) {
+            start_sums(cpx, C, sc, pw, Ps, flag, slot);
+            const float b0 = bt[0];
+#pragma unroll
+            for (int b = 0; b < JB; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Qa[b][v] = b0 * z[b][v];
+        };
+        // Software pipeline, two planes per phase, as in filter().
+        column_pass(0);
+        column_pass(1);
+        lds_barrier();
+        for (int k = 1; 2 * k - 2 < P; ++k) {
+            hook(k);
+            if (2 * k < P) column_pass(2 * k);
+            if (2 * k + 1 < P) column_pass(2 * k + 1);
+            {
+                mf_f4 z[JB];
+                row_pass(2 * k - 2, z);
+                if (k == 1) first(z);
+                else combine(2 * k - 2, z);
+            }
+            if (2 * k - 1 < P) {
+                mf_f4 z[JB];
+                row_pass(2 * k - 1, z);
+                combine(2 * k - 1, z);
+            }
+            if (2 * k < P) lds_barrier();
         }
 
 #pragma unroll
@@ -2158,10 +2280,9 @@ struct FusedTile {
     __device__ __forceinline__ void run(int r0, int c0, const Raw &R, unsigned *__restrict__ flag,
                                         unsigned *__restrict__ slot, int base = 0) {
         const FusedCentre C = plain_centre();
-        State S;
-        build_state(R.h, C, S);
+        check_range(R, flag, slot);
         float y[JB][4];
-        planes(S, R.c, C, bt, N, base, y, flag, slot, [](int) {});
+        filter(R, C, bt, N, base, y);
         store(r0, c0, y);
     }
 
@@ -2384,8 +2505,7 @@ __global__ __launch_bounds__(1024) void k_fused_strip(const float *__restrict__ 
             }
         };
         float y[T::JB][4];
-        tile.template planes<true>(S, R.c, Cn, tile.bt, N, base, y, nullptr, slots + T::kSlots * (ty * tiles_x + cx),
-                                   hook);
+        tile.strip_planes(S, R.c, Cn, tile.bt, N, base, y, nullptr, slots + T::kSlots * (ty * tiles_x + cx), hook);
         {
             unsigned t2 = threadIdx.x;
             asm volatile("" : "+v"(t2));
