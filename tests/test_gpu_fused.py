@@ -17,7 +17,8 @@ pytestmark = pytest.mark.gpu
 BOUND = {
     ("f16", 30.0, 28): 2.4,     # measured 0.78 (65 x 129, sigma_s = 10); 0.44 on the 4096^2 centre crop
     ("f16", 30.0, 30): 0.7,     # measured 0.23 (4096^2 centre crop)
-    ("f16", 30.0, 32): 0.35,    # measured 0.108 (4096^2 centre crop, the benchmark's FP16 configuration)
+    ("f16", 30.0, 31): 0.35,    # measured 0.105 (4096^2 centre crop, the benchmark's FP16 configuration)
+    ("f16", 30.0, 32): 0.35,    # measured 0.097 (4096^2 centre crop)
     ("f16", 50.0, 11): 0.05,    # measured 0.0156
     ("bf16", 50.0, 11): 1.0,    # measured 0.34 (1100 x 2050 corner)
 }
@@ -169,7 +170,7 @@ def test_fused_range_flag_follows_the_last_call(torch_cuda):
         assert bool(got) == flagged, (k, cfg, flagged)
 
 
-@pytest.mark.parametrize("N", [28, 30, 32])
+@pytest.mark.parametrize("N", [28, 30, 31, 32])
 def test_fused_headline_size_sampled(torch_cuda, N):
     """4096^2 edge-rich, sigma_s = 10, sigma_r = 30, FP16 stack, fused tile (the
     configuration the benchmark times for the FP16 stack): the oracle on a
