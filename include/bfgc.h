@@ -102,9 +102,9 @@ typedef enum {
 #define BF_TILE_FUSED   4
 #define BF_FUSED_MAX_RADIUS 48
 /* bf_gc_forward and bf_gc_forward_noalloc run FP16 stacks on the fused tile up
- * to this radius (64 x 128 tiles on 16 waves up to radius 32, 64 x 64 up to
- * 48, 32 x 128 above); BF16 stacks, and the other entry points, up to
- * BF_FUSED_MAX_RADIUS. */
+ * to this radius (64 x 128 tiles on 16 waves up to radius 32, one block per
+ * CU walking a vertical strip of tiles; 64 x 64 up to 48, 32 x 128 above);
+ * BF16 stacks, and the other entry points, up to BF_FUSED_MAX_RADIUS. */
 #define BF_FUSED_F16_MAX_RADIUS 64
 #define BF_FLAG_TILE(c)               ((((unsigned)(c)) + 1u) << 8)
 
